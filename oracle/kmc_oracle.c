@@ -1,0 +1,405 @@
+/*
+ * Plain CPU oracle for the rail kinetic Monte Carlo (KMC) hop step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load this library.  The product path (the
+ * HIP library under paper_2511_09413_amd/) never calls it, and this file shares
+ * no code, header, table or constant generator with it.
+ *
+ * What is computed (paper: Supplementary Information S1-S2; main text
+ * section 3 "Mapping to the code"):
+ *   - rails of sites, each site empty or holding one cation; ions hop only
+ *     along their rail, never between rails (SI S2.1, "Step-by-step"; the
+ *     number of ions per rail is fixed);
+ *   - hard-core exclusion: a hop goes only into an empty neighbour site
+ *     (SI S2.1, "Random sampling and exclusion rules");
+ *   - thermally activated hop rate nu0*exp(-Em/kT) (main text, Eq. hop_rate)
+ *     whose barrier is shifted by half the energy change of the hop, so that
+ *     forward/backward rates keep detailed balance (main text, Eq. 2 and the
+ *     paragraph after it);
+ *   - the energy change is the applied-bias drop (SI Eq. S1, grounded bottom
+ *     electrode and biased top electrode, SI S1.3) plus the Coulomb energy of
+ *     nearby ions (main text section 3), here a screened Coulomb kernel with an
+ *     inclusive cutoff along the rail and a neighbourhood of rails, periodic
+ *     in the rail index (SI S1.4 "periodic lateral edges");
+ *   - accept when the uniform draw is below the hop probability (SI S2.1,
+ *     movement masks), the update being a pair (bond) checkerboard: even bonds
+ *     then odd bonds, each half-step deciding every bond from the state at the
+ *     start of the half-step; this is the conflict-free reading of the paper's
+ *     "all ions at once" update.
+ *
+ * Randomness: Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random
+ * numbers: as easy as 1, 2, 3", SC'11), written here from that publication.
+ *   hop draw of bond (s, s+1) of rail r, device d, step n, half-step h = s&1:
+ *     counter = (s>>3, r, n, d<<4 | 0<<1 | h), key = (seed lo, seed hi),
+ *     word (s>>1)&3 of the output block;
+ *   placement draw of site s: counter = (s>>2, r, 0, d<<4 | 1<<1), word s&3.
+ *
+ * Two precision paths: binary64 everywhere, or binary32 for the energy, the
+ * exponent and the probability (tables rounded once from binary64).  Build
+ * with -O2 -ffp-contract=off and no fast-math.
+ */
+#include "kmc_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11): multipliers, Weyl key increments, 10 rounds. */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t prod0 = (uint64_t)PHILOX_M0 * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)PHILOX_M1 * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(prod1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)prod1;
+        uint32_t y2 = (uint32_t)(prod0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)prod0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+static uint32_t philox_word(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2,
+                            uint32_t c3, int word)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[word];
+}
+
+uint32_t orc_hop_word(uint64_t seed, int d, int64_t n, int r, int s)
+{
+    int h = s & 1;
+    return philox_word(seed, (uint32_t)(s >> 3), (uint32_t)r, (uint32_t)n,
+                       ((uint32_t)d << 4) | (0u << 1) | (uint32_t)h, (s >> 1) & 3);
+}
+
+uint32_t orc_place_word(uint64_t seed, int d, int r, int s)
+{
+    return philox_word(seed, (uint32_t)(s >> 2), (uint32_t)r, 0u,
+                       ((uint32_t)d << 4) | (1u << 1), s & 3);
+}
+
+/* ------------------------------------------------------------------ */
+/* Geometry helpers                                                    */
+/* ------------------------------------------------------------------ */
+static int64_t dev_offset(const orc_params *P, int d)
+{
+    int64_t off = 0;
+    for (int i = 0; i < d; ++i) off += (int64_t)P->rails[i] * P->sites[i];
+    return off;
+}
+
+/* minimal-image rail distance on a ring of R rails */
+static int rail_dist(int r, int rp, int R)
+{
+    int a = ((rp - r) % R + R) % R;
+    return a < R - a ? a : R - a;
+}
+
+/* Distinct rails within rail_range of rail r (each counted once), with their
+ * minimal-image distance.  Returns the count. */
+static int neighbour_rails(const orc_params *P, int R, int r, int *rail_out, int *dist_out)
+{
+    int cnt = 0;
+    for (int k = 0; k <= 2 * P->rail_range; ++k) {
+        /* visit offsets in the order 0, +1, -1, +2, -2, ... */
+        int delta = (k == 0) ? 0 : ((k & 1) ? (k + 1) / 2 : -(k / 2));
+        int rp = ((r + delta) % R + R) % R;
+        int seen = 0;
+        for (int i = 0; i < cnt; ++i)
+            if (rail_out[i] == rp) seen = 1;
+        if (seen) continue;
+        rail_out[cnt] = rp;
+        dist_out[cnt] = rail_dist(r, rp, R);
+        ++cnt;
+    }
+    return cnt;
+}
+
+/* Interaction kernel K(ds, dr) in volts (eV per elementary charge), binary64.
+ * Screened Coulomb kappa*exp(-d/lambda)/d, or kappa/d when lambda == 0, with
+ * d = sqrt(ds^2 + dr^2); zero at (0,0), beyond |ds| > cutoff or dr > rail_range. */
+double orc_kernel(const orc_params *P, int ds, int dr)
+{
+    if (ds == 0 && dr == 0) return 0.0;
+    if (abs(ds) > P->cutoff) return 0.0;
+    if (dr > P->rail_range) return 0.0;
+    double dist = sqrt((double)ds * (double)ds + (double)dr * (double)dr);
+    if (P->lambda > 0.0) return P->kappa * exp(-dist / P->lambda) / dist;
+    return P->kappa / dist;
+}
+
+/* ------------------------------------------------------------------ */
+/* Protocol: piecewise-linear V(t), right-continuous, constant outside. */
+/* ------------------------------------------------------------------ */
+double orc_protocol_voltage(const double *t_k, const double *v_k, int n_knots, double t_rel)
+{
+    if (n_knots <= 0) return 0.0;
+    if (t_rel < t_k[0]) return v_k[0];
+    int k = 0;
+    for (int i = 0; i < n_knots; ++i)
+        if (t_k[i] <= t_rel) k = i;
+    if (k == n_knots - 1) return v_k[n_knots - 1];
+    double slope_num = (v_k[k + 1] - v_k[k]) * (t_rel - t_k[k]);
+    return v_k[k] + slope_num / (t_k[k + 1] - t_k[k]);
+}
+
+static double device_voltage(const orc_protocol *pr, int d, int64_t n, double dt)
+{
+    const orc_protocol *p = &pr[d];
+    double t_rel = (double)(n - p->n_set) * dt;
+    return orc_protocol_voltage(p->t, p->v, p->n_knots, t_rel);
+}
+
+/* ------------------------------------------------------------------ */
+/* Energy change of the hop o -> t on rail r (occupancy snapshot S of   */
+/* one device, R x L).  Binary64 and binary32 paths.                    */
+/* ------------------------------------------------------------------ */
+double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
+                            int r, int o, int t, double V)
+{
+    double e_app = ((P->alpha * V) * (double)(t - o)) / (double)L;
+    int rails[64], dists[64];
+    int nr = neighbour_rails(P, R, r, rails, dists);
+    int lo = (o < t ? o : t) - P->cutoff;
+    int hi = (o > t ? o : t) + P->cutoff;
+    if (lo < 0) lo = 0;
+    if (hi > L - 1) hi = L - 1;
+    double e_coul = 0.0;
+    for (int i = 0; i < nr; ++i) {
+        const int8_t *row = S + (int64_t)rails[i] * L;
+        for (int j = lo; j <= hi; ++j) {
+            if (rails[i] == r && (j == o || j == t)) continue;
+            if (!row[j]) continue;
+            e_coul += orc_kernel(P, t - j, dists[i]) - orc_kernel(P, o - j, dists[i]);
+        }
+    }
+    return e_app + e_coul;
+}
+
+float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
+                           int r, int o, int t, double V)
+{
+    float a = (float)P->alpha, v = (float)V;
+    float e_app = ((a * v) * (float)(t - o)) / (float)L;
+    int rails[64], dists[64];
+    int nr = neighbour_rails(P, R, r, rails, dists);
+    int lo = (o < t ? o : t) - P->cutoff;
+    int hi = (o > t ? o : t) + P->cutoff;
+    if (lo < 0) lo = 0;
+    if (hi > L - 1) hi = L - 1;
+    float e_coul = 0.0f;
+    for (int i = 0; i < nr; ++i) {
+        const int8_t *row = S + (int64_t)rails[i] * L;
+        for (int j = lo; j <= hi; ++j) {
+            if (rails[i] == r && (j == o || j == t)) continue;
+            if (!row[j]) continue;
+            float kt = (float)orc_kernel(P, t - j, dists[i]);
+            float ko = (float)orc_kernel(P, o - j, dists[i]);
+            e_coul += kt - ko;
+        }
+    }
+    return e_app + e_coul;
+}
+
+/* hop probability p = min(nu0*dt*exp(-beta*(Ea + dE/2)), 1) */
+double orc_hop_prob_f64(const orc_params *P, double ea, double dE)
+{
+    double beta = 1.0 / P->kT;
+    double c0 = P->nu0 * P->dt;
+    double p = c0 * exp(-beta * (ea + 0.5 * dE));
+    return p < 1.0 ? p : 1.0;
+}
+
+float orc_hop_prob_f32(const orc_params *P, double ea, float dE)
+{
+    float beta = (float)(1.0 / P->kT);
+    float c0 = (float)(P->nu0 * P->dt);
+    float p = c0 * expf(-beta * ((float)ea + 0.5f * dE));
+    return p < 1.0f ? p : 1.0f;
+}
+
+/* ------------------------------------------------------------------ */
+/* Initial placement: floor(f*L + 1/2) ions per rail on the sites with  */
+/* the smallest (placement word, site index) keys.                      */
+/* ------------------------------------------------------------------ */
+typedef struct { uint32_t w; int s; } place_key;
+
+static int cmp_place(const void *a, const void *b)
+{
+    const place_key *x = (const place_key *)a, *y = (const place_key *)b;
+    if (x->w != y->w) return x->w < y->w ? -1 : 1;
+    return x->s < y->s ? -1 : (x->s > y->s ? 1 : 0);
+}
+
+int orc_ions_per_rail(double filling, int L)
+{
+    return (int)floor(filling * (double)L + 0.5);
+}
+
+void orc_fill(const orc_params *P, const double *filling, int8_t *occ)
+{
+    for (int d = 0; d < P->n_devices; ++d) {
+        int R = P->rails[d], L = P->sites[d];
+        int8_t *dev = occ + dev_offset(P, d);
+        int nion = orc_ions_per_rail(filling[d], L);
+        place_key *keys = (place_key *)malloc(sizeof(place_key) * (size_t)L);
+        for (int r = 0; r < R; ++r) {
+            for (int s = 0; s < L; ++s) {
+                keys[s].w = orc_place_word(P->seed, d, r, s);
+                keys[s].s = s;
+            }
+            qsort(keys, (size_t)L, sizeof(place_key), cmp_place);
+            int8_t *row = dev + (int64_t)r * L;
+            memset(row, 0, (size_t)L);
+            for (int i = 0; i < nion; ++i) row[keys[i].s] = 1;
+        }
+        free(keys);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* The step loop                                                         */
+/* ------------------------------------------------------------------ */
+static void log_event(orc_log_entry *log, int64_t cap, int64_t *n_log, int d, int h,
+                      int64_t n, int r, int s, double u, double p)
+{
+    if (log && *n_log < cap) {
+        orc_log_entry *e = &log[*n_log];
+        e->d = d; e->h = h; e->n = n; e->r = r; e->s = s; e->u = u; e->p = p;
+    }
+    ++*n_log;
+}
+
+/* A permutation of 0..m-1 drawn from a 64-bit LCG (only used to prove that the
+ * order in which bonds are visited inside a half-step does not matter). */
+static void permutation(int64_t m, uint64_t seed, int64_t *perm)
+{
+    for (int64_t i = 0; i < m; ++i) perm[i] = i;
+    uint64_t x = seed * 6364136223846793005ull + 1442695040888963407ull;
+    for (int64_t i = m - 1; i > 0; --i) {
+        x = x * 6364136223846793005ull + 1442695040888963407ull;
+        int64_t j = (int64_t)((x >> 33) % (uint64_t)(i + 1));
+        int64_t tmp = perm[i]; perm[i] = perm[j]; perm[j] = tmp;
+    }
+}
+
+int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
+            int64_t n0, int64_t n_steps, int32_t *net_out, int32_t *dec_out,
+            int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,
+            const orc_run_opts *opts)
+{
+    int D = P->n_devices;
+    if (n0 < 0 || n0 + n_steps > (int64_t)0xffffffffLL) return -1;
+    int64_t total = dev_offset(P, D);
+    int8_t *S = (int8_t *)malloc((size_t)total);
+    int64_t dummy_log = 0;
+    if (!n_log) n_log = &dummy_log;
+    double *V = (double *)malloc(sizeof(double) * (size_t)D);
+    int32_t *n_down = (int32_t *)calloc((size_t)D, sizeof(int32_t));
+    int32_t *n_up = (int32_t *)calloc((size_t)D, sizeof(int32_t));
+
+    for (int64_t k = 0; k < n_steps; ++k) {
+        int64_t n = n0 + k;
+        for (int d = 0; d < D; ++d) {
+            V[d] = device_voltage(protocols, d, n, P->dt);
+            n_down[d] = 0;
+            n_up[d] = 0;
+        }
+        for (int h = 0; h < 2; ++h) {
+            memcpy(S, occ, (size_t)total); /* Jacobi snapshot */
+            for (int d = 0; d < D; ++d) {
+                int R = P->rails[d], L = P->sites[d];
+                int64_t off = dev_offset(P, d);
+                const int8_t *Sd = S + off;
+                int8_t *Od = occ + off;
+                int r_lo = 0, r_hi = R;
+                if (opts && opts->rail_hi > opts->rail_lo) {
+                    r_lo = opts->rail_lo;
+                    r_hi = opts->rail_hi;
+                }
+                int n_bonds = (L - 1 - h + 1) / 2; /* s = h, h+2, ..., <= L-2 */
+                if (n_bonds < 0) n_bonds = 0;
+                int64_t m = (int64_t)(r_hi - r_lo) * n_bonds;
+                int64_t *perm = NULL;
+                if (opts && opts->shuffle_seed) {
+                    perm = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m > 0 ? m : 1));
+                    permutation(m, opts->shuffle_seed ^ (uint64_t)(n * 2 + h) ^ ((uint64_t)d << 40), perm);
+                }
+                for (int64_t idx = 0; idx < m; ++idx) {
+                    int64_t b = perm ? perm[idx] : idx;
+                    int r = r_lo + (int)(b / n_bonds);
+                    int s = h + 2 * (int)(b % n_bonds);
+                    int8_t a0 = Sd[(int64_t)r * L + s], a1 = Sd[(int64_t)r * L + s + 1];
+                    if (a0 == a1) continue;
+                    int o = a0 ? s : s + 1;
+                    int t = a0 ? s + 1 : s;
+                    double ea = P->ea_site ? P->ea_site[off + (int64_t)r * L + o] : P->ea;
+                    uint32_t w = orc_hop_word(P->seed, d, n, r, s);
+                    int accept;
+                    double u_log, p_log;
+                    if (P->fp32) {
+                        float dE = orc_delta_energy_f32(P, R, L, Sd, r, o, t, V[d]);
+                        float p = orc_hop_prob_f32(P, ea, dE);
+                        float u = ldexpf((float)w, -32);
+                        accept = u < p;
+                        u_log = u; p_log = p;
+                        if (fabsf(u - p) < 1e-6f)
+                            log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
+                    } else {
+                        double dE = orc_delta_energy_f64(P, R, L, Sd, r, o, t, V[d]);
+                        double p = orc_hop_prob_f64(P, ea, dE);
+                        double u = ldexp((double)w, -32);
+                        accept = u < p;
+                        u_log = u; p_log = p;
+                        if (fabs(u - p) < 1e-6)
+                            log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
+                    }
+                    if (accept) {
+                        Od[(int64_t)r * L + o] = 0;
+                        Od[(int64_t)r * L + t] = 1;
+                        if (t < o) ++n_down[d];
+                        else ++n_up[d];
+                    }
+                }
+                free(perm);
+            }
+        }
+        for (int d = 0; d < D; ++d) {
+            int32_t net = n_down[d] - n_up[d];
+            if (net_out) net_out[k * D + d] = net;
+            if (net_total) net_total[d] += net;
+            if (dec_out) {
+                int R = P->rails[d], L = P->sites[d];
+                const int8_t *Od = occ + dev_offset(P, d);
+                int32_t *dk = dec_out + (k * D + d) * 10;
+                for (int q = 0; q < 10; ++q) dk[q] = 0;
+                for (int r = 0; r < R; ++r)
+                    for (int s = 0; s < L; ++s)
+                        if (Od[(int64_t)r * L + s]) dk[(10 * s) / L] += 1;
+            }
+        }
+    }
+    free(S);
+    free(V);
+    free(n_down);
+    free(n_up);
+    return 0;
+}

@@ -1,0 +1,64 @@
+/*
+ * Plain CPU oracle for the rail-KMC hop step: declarations.
+ * TEST INFRASTRUCTURE ONLY (see kmc_oracle.c).  Private to oracle/.
+ */
+#ifndef KMC_ORACLE_H
+#define KMC_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    int n_devices;
+    const int *rails;      /* [n_devices] */
+    const int *sites;      /* [n_devices] */
+    double nu0;            /* attempt frequency, Hz */
+    double ea;             /* barrier, eV (used when ea_site == NULL) */
+    double kT;             /* eV */
+    double dt;             /* s */
+    double alpha;          /* field coupling (dimensionless) */
+    double kappa;          /* Coulomb amplitude, V */
+    double lambda;         /* screening length in sites; 0 = unscreened */
+    int cutoff;            /* inclusive cutoff along the rail, sites */
+    int rail_range;        /* rails within this minimal-image distance interact */
+    int fp32;              /* 0 = binary64 path, 1 = binary32 path */
+    uint64_t seed;
+    const double *ea_site; /* NULL or per-site barrier, devices concatenated */
+} orc_params;
+
+typedef struct {
+    const double *t;   /* knot times, s, nondecreasing */
+    const double *v;   /* knot voltages, V */
+    int n_knots;
+    int64_t n_set;     /* step at which the protocol was installed */
+} orc_protocol;
+
+typedef struct {
+    int32_t d, h;
+    int64_t n;
+    int32_t r, s;
+    double u, p;
+} orc_log_entry;
+
+typedef struct {
+    uint64_t shuffle_seed; /* nonzero: visit bonds in a random order */
+    int rail_lo, rail_hi;  /* rail_hi > rail_lo: update only these rails */
+} orc_run_opts;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+uint32_t orc_hop_word(uint64_t seed, int d, int64_t n, int r, int s);
+uint32_t orc_place_word(uint64_t seed, int d, int r, int s);
+double orc_kernel(const orc_params *P, int ds, int dr);
+double orc_protocol_voltage(const double *t_k, const double *v_k, int n_knots, double t_rel);
+double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
+                            int r, int o, int t, double V);
+float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
+                           int r, int o, int t, double V);
+double orc_hop_prob_f64(const orc_params *P, double ea, double dE);
+float orc_hop_prob_f32(const orc_params *P, double ea, float dE);
+int orc_ions_per_rail(double filling, int L);
+void orc_fill(const orc_params *P, const double *filling, int8_t *occ);
+int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
+            int64_t n0, int64_t n_steps, int32_t *net_out, int32_t *dec_out,
+            int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,
+            const orc_run_opts *opts);
+
+#endif
