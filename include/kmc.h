@@ -1,0 +1,168 @@
+/*
+ * kmc.h — C ABI of the MI355X rail kinetic Monte Carlo (KMC) hop-step library.
+ *
+ * The library advances lattices of "rails" (one-dimensional chains of sites,
+ * each empty or holding one mobile cation) by the vectorised hop step of the
+ * paper's simulator: per-bond barrier and bias energies from the applied field
+ * plus the screened Coulomb potential of nearby ions, Arrhenius hop
+ * probabilities, a stochastic accept/reject under site exclusion, the occupancy
+ * update, and electrode-current / decile tallies (paper: main text section 3,
+ * Eq. hop_rate and Eq. 2; Supplementary Information S1-S3, Eqs. S1-S4).
+ *
+ * Conventions shared by every call:
+ *   - Return value: kmc_status, 0 on success, < 0 on error.  Nothing throws or
+ *     exits.  kmc_last_error() returns a text for the last error of the calling
+ *     thread.  Parameters are validated before any work is enqueued, so a
+ *     rejected call leaves the state untouched.  After a HIP runtime error the
+ *     context answers KMC_ESTATE until kmc_destroy.
+ *   - Device pointers are HIP device memory on the current device, owned by the
+ *     caller (for example allocated by PyTorch).  The context borrows them
+ *     until kmc_destroy and owns only a small amount of host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     work is enqueued on it; only kmc_read_* synchronise it.
+ *   - Lattice layout: devices concatenated, each device [rails][sites]
+ *     row-major with the site index fastest; int8 occupancy 0/1.
+ *   - Units: SI plus eV (potentials in V, energies in eV, charge q = +1 e).
+ */
+#ifndef KMC_H
+#define KMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kmc_ctx kmc_ctx;
+
+typedef enum {
+    KMC_OK = 0,
+    KMC_EINVAL = -1,        /* a parameter is out of range or inconsistent    */
+    KMC_EUNSUPPORTED = -2,  /* valid, but beyond what this build implements   */
+    KMC_EHIP = -3,          /* the HIP runtime reported an error              */
+    KMC_ESTATE = -4,        /* the context is poisoned by an earlier HIP error */
+    KMC_ETOOSMALL = -5      /* a buffer or workspace is too small             */
+} kmc_status;
+
+typedef enum {
+    KMC_FP64 = 0,   /* binary64 energies, exponent and probabilities          */
+    KMC_FP32 = 1,   /* binary32 energies/probabilities, tables from binary64  */
+    KMC_BF16X2 = 2  /* dense long-range potential on MFMA: BF16 hi+lo split of
+                       the kernel matrix, FP32 accumulation (needs cutoff_sites
+                       = sites-1, the unscreened kernel and equal shapes)      */
+} kmc_precision;
+
+/* Physical and numerical parameters (paper SI Table S1 for geometry and
+ * filling; the rate law of main text Eq. hop_rate with the field split of
+ * Eq. 2 for detailed balance).  Hop probability of a candidate bond whose ion
+ * moves from origin site o to the empty target t:
+ *     dE = alpha*V*(t-o)/L + sum_{j != o,t} occ_j [K(t-j) - K(o-j)],
+ *     p  = min(nu0*dt*exp(-(Ea(o) + dE/2)/kT), 1),
+ * with K(ds, dr) = kappa*exp(-d/lambda)/d (kappa/d when lambda == 0),
+ * d = sqrt(ds^2 + dr^2), for |ds| <= cutoff_sites and minimal-image rail
+ * distance dr <= rail_range (periodic lateral edges, SI S1.4), zero at the
+ * origin.  V is the device's bias at the step's time; site 0 faces the
+ * grounded electrode, site L-1 the biased one (SI S1.3). */
+typedef struct {
+    int32_t n_devices;       /* independent devices or replicas, >= 1          */
+    const int32_t *rails;    /* host [n_devices], each >= 1                     */
+    const int32_t *sites;    /* host [n_devices], each in [2, 4096]             */
+    double nu0_hz;           /* attempt frequency                               */
+    double ea_ev;            /* barrier when no per-site field is given         */
+    double kT_ev;            /* thermal energy, > 0                              */
+    double dt_s;             /* time step, > 0                                   */
+    double field_coupling;   /* alpha                                           */
+    double coulomb_kappa_v;  /* kappa; 0 disables ion-ion coupling              */
+    double screening_sites;  /* lambda; 0 = unscreened                          */
+    int32_t cutoff_sites;    /* inclusive cutoff along the rail, >= 0           */
+    int32_t rail_range;      /* interacting rail distance, 0..4                 */
+    int32_t precision;       /* kmc_precision                                    */
+    uint64_t seed;           /* Philox4x32-10 key                                */
+} kmc_params;
+
+/* One logged near-threshold draw (|u - p| < 1e-6) of device d, step n,
+ * half-step h, bond (s, s+1) of rail r. */
+typedef struct {
+    int32_t d, h;
+    int64_t n;
+    int32_t r, s;
+    double u, p;
+} kmc_log_entry;
+
+/* Bytes of device workspace kmc_init_device needs for these parameters. */
+kmc_status kmc_workspace_bytes(const kmc_params *params, size_t *bytes);
+
+/* Create a context (paper SI S2.2 "initialization": geometry, filling and
+ * constants fixed before a protocol runs).
+ *   occ_dev:  device int8 occupancy of all devices (caller-owned, >= the total
+ *             number of sites bytes).  Its content becomes the initial state
+ *             (values other than 0 count as occupied); after every
+ *             kmc_run_steps it holds the current state again.
+ *   ea_dev:   NULL (every barrier = ea_ev) or a device array of per-site
+ *             barriers in eV in the occupancy layout, float for KMC_FP32 and
+ *             KMC_BF16X2, double for KMC_FP64.  The barrier of a hop is that of
+ *             its origin site.
+ *   workspace_dev, ws_bytes: device memory of at least kmc_workspace_bytes.
+ * The step counter starts at 0 and every device's bias is 0 V until
+ * kmc_set_bias_protocol. */
+kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void *ea_dev,
+                           void *workspace_dev, size_t ws_bytes, void *stream, kmc_ctx **out);
+
+/* Random initial placement (paper SI S2.1 "Initialization": the ion count
+ * follows the filling fraction and is spread evenly over rails): every rail of
+ * device d gets exactly floor(filling[d]*L + 1/2) ions on the sites with the
+ * smallest Philox placement words.  filling: host [n_devices], in [0, 1]. */
+kmc_status kmc_fill_random(kmc_ctx *ctx, const double *filling);
+
+/* Re-read the state from occ_dev (after the caller wrote a new occupancy). */
+kmc_status kmc_load_occupancy(kmc_ctx *ctx);
+
+/* Install the voltage-vs-time profile of one device (device >= 0) or of all
+ * devices (device == -1) (paper SI S2.2: the protocol is a complete voltage
+ * profile).  Piecewise linear through the knots (t_s[i], v_volt[i]), times
+ * relative to the current step, nondecreasing; equal times make a jump
+ * (right-continuous); constant before the first and after the last knot.
+ * n_knots in [1, 64].  Host arrays, copied before return. */
+kmc_status kmc_set_bias_protocol(kmc_ctx *ctx, int32_t device, const double *t_s,
+                                 const double *v_volt, int32_t n_knots);
+
+/* Advance every device by n_steps steps (paper SI S2.1, the Monte Carlo loop;
+ * each step is two half-steps over even then odd bonds).
+ *   net_hops_dev: NULL or device int32 [n_steps][n_devices]: hops toward site
+ *                 0 minus hops toward site L-1 in each step.
+ *   decile_dev:   NULL or device int32 [n_steps][n_devices][10]: ions in each
+ *                 tenth of the rail after each step (SI S3).
+ * The step counter advances by n_steps; it must stay below 2^32. */
+kmc_status kmc_run_steps(kmc_ctx *ctx, int64_t n_steps, int32_t *net_hops_dev,
+                         int32_t *decile_dev);
+
+/* Copy the occupancy to host memory; bytes >= total sites.  Synchronises. */
+kmc_status kmc_read_occupancy(kmc_ctx *ctx, int8_t *dst_host, size_t bytes);
+
+/* Electrode current and totals since init (Ramo-Shockley current of blocking
+ * electrodes, I = e*net/(L*dt) per step).  Host outputs, each may be NULL:
+ *   mean_current_A [n_devices], net_hops_total [n_devices], sim_time_s.
+ * Synchronises. */
+kmc_status kmc_read_current(kmc_ctx *ctx, double *mean_current_A, int64_t *net_hops_total,
+                            double *sim_time_s);
+
+/* Copy up to `cap` logged near-threshold draws to host memory and report how
+ * many were logged since init (entries past the device log capacity are
+ * counted but not stored).  Synchronises. */
+kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t cap,
+                                  int64_t *n_events);
+
+/* Current step counter. */
+kmc_status kmc_get_step(kmc_ctx *ctx, int64_t *step);
+
+/* Text of the last error of the calling thread ("" if none). */
+const char *kmc_last_error(void);
+
+/* Release the context (enqueued work is completed first). */
+void kmc_destroy(kmc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KMC_H */

@@ -1,0 +1,244 @@
+"""MI355X rail kinetic Monte Carlo hop step: Python binding of libkmc.so.
+
+Argument marshalling only.  Every step of the hop path runs in the HIP kernels
+behind the C ABI (include/kmc.h); PyTorch supplies device memory and streams.
+There is no CPU fallback: if the HIP library is missing, loading fails loudly.
+
+Module-level functions carry the C names without the `kmc_` prefix
+(init_device, fill_random, set_bias_protocol, run_steps, read_occupancy,
+read_current, read_threshold_log, ...).  `Simulator` bundles them with the
+torch-owned buffers of one context.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libkmc.so")
+
+KMC_OK, KMC_EINVAL, KMC_EUNSUPPORTED, KMC_EHIP, KMC_ESTATE, KMC_ETOOSMALL = 0, -1, -2, -3, -4, -5
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2}
+LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
+                      ("s", np.int32), ("u", np.float64), ("p", np.float64)])
+
+
+class KmcError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"kmc status {status}: {message}")
+        self.status = status
+
+
+class kmc_params(C.Structure):
+    _fields_ = [("n_devices", C.c_int32), ("rails", C.POINTER(C.c_int32)),
+                ("sites", C.POINTER(C.c_int32)), ("nu0_hz", C.c_double), ("ea_ev", C.c_double),
+                ("kT_ev", C.c_double), ("dt_s", C.c_double), ("field_coupling", C.c_double),
+                ("coulomb_kappa_v", C.c_double), ("screening_sites", C.c_double),
+                ("cutoff_sites", C.c_int32), ("rail_range", C.c_int32), ("precision", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+_LIB = None
+
+
+def lib():
+    """Load libkmc.so (built by paper_2511_09413_amd/build.py).  No fallback."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P, vp = C.POINTER, C.c_void_p
+        L.kmc_workspace_bytes.argtypes = [P(kmc_params), P(C.c_size_t)]
+        L.kmc_init_device.argtypes = [P(kmc_params), vp, vp, vp, C.c_size_t, vp, P(vp)]
+        L.kmc_fill_random.argtypes = [vp, P(C.c_double)]
+        L.kmc_load_occupancy.argtypes = [vp]
+        L.kmc_set_bias_protocol.argtypes = [vp, C.c_int32, P(C.c_double), P(C.c_double), C.c_int32]
+        L.kmc_run_steps.argtypes = [vp, C.c_int64, vp, vp]
+        L.kmc_read_occupancy.argtypes = [vp, vp, C.c_size_t]
+        L.kmc_read_current.argtypes = [vp, P(C.c_double), P(C.c_int64), P(C.c_double)]
+        L.kmc_read_threshold_log.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
+        L.kmc_get_step.argtypes = [vp, P(C.c_int64)]
+        L.kmc_last_error.restype = C.c_char_p
+        L.kmc_destroy.argtypes = [vp]
+        L.kmc_destroy.restype = None
+        for name in ("kmc_workspace_bytes", "kmc_init_device", "kmc_fill_random", "kmc_load_occupancy",
+                     "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
+                     "kmc_read_threshold_log", "kmc_get_step"):
+            getattr(L, name).restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int) -> None:
+    if status != KMC_OK:
+        raise KmcError(status, lib().kmc_last_error().decode())
+
+
+def make_params(physics, rails: Sequence[int], sites: Sequence[int]):
+    """kmc_params from a workloads.Physics-like object; returns (struct, keepalive)."""
+    r = np.ascontiguousarray(rails, dtype=np.int32)
+    s = np.ascontiguousarray(sites, dtype=np.int32)
+    p = kmc_params(len(r), r.ctypes.data_as(C.POINTER(C.c_int32)), s.ctypes.data_as(C.POINTER(C.c_int32)),
+                   physics.nu0_hz, physics.ea_ev, physics.kT_ev, physics.dt_s, physics.field_coupling,
+                   physics.coulomb_kappa_v, physics.screening_sites, physics.cutoff_sites,
+                   physics.rail_range, PRECISIONS[physics.precision], physics.seed & 0xFFFFFFFFFFFFFFFF)
+    return p, (r, s)
+
+
+# ---------------------------------------------------------------- C calls
+def workspace_bytes(params: kmc_params) -> int:
+    out = C.c_size_t(0)
+    _check(lib().kmc_workspace_bytes(C.byref(params), C.byref(out)))
+    return int(out.value)
+
+
+def init_device(params: kmc_params, occ_ptr: int, ea_ptr: Optional[int], ws_ptr: int, ws_bytes: int,
+                stream: int) -> int:
+    h = C.c_void_p(0)
+    _check(lib().kmc_init_device(C.byref(params), C.c_void_p(occ_ptr), C.c_void_p(ea_ptr or 0),
+                                 C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream), C.byref(h)))
+    return int(h.value)
+
+
+def fill_random(ctx: int, filling: Sequence[float]) -> None:
+    f = np.ascontiguousarray(filling, dtype=np.float64)
+    _check(lib().kmc_fill_random(C.c_void_p(ctx), f.ctypes.data_as(C.POINTER(C.c_double))))
+
+
+def load_occupancy(ctx: int) -> None:
+    _check(lib().kmc_load_occupancy(C.c_void_p(ctx)))
+
+
+def set_bias_protocol(ctx: int, device: int, t_s: Sequence[float], v_volt: Sequence[float]) -> None:
+    t = np.ascontiguousarray(t_s, dtype=np.float64)
+    v = np.ascontiguousarray(v_volt, dtype=np.float64)
+    if t.shape != v.shape:
+        raise ValueError("knot arrays differ in length")
+    _check(lib().kmc_set_bias_protocol(C.c_void_p(ctx), device, t.ctypes.data_as(C.POINTER(C.c_double)),
+                                       v.ctypes.data_as(C.POINTER(C.c_double)), len(t)))
+
+
+def run_steps(ctx: int, n_steps: int, net_ptr: int = 0, dec_ptr: int = 0) -> None:
+    _check(lib().kmc_run_steps(C.c_void_p(ctx), n_steps, C.c_void_p(net_ptr), C.c_void_p(dec_ptr)))
+
+
+def read_occupancy(ctx: int, n_sites: int) -> np.ndarray:
+    out = np.empty(n_sites, dtype=np.int8)
+    _check(lib().kmc_read_occupancy(C.c_void_p(ctx), C.c_void_p(out.ctypes.data), n_sites))
+    return out
+
+
+def read_current(ctx: int, n_devices: int) -> Tuple[np.ndarray, np.ndarray, float]:
+    cur = np.zeros(n_devices, dtype=np.float64)
+    tot = np.zeros(n_devices, dtype=np.int64)
+    t = C.c_double(0.0)
+    _check(lib().kmc_read_current(C.c_void_p(ctx), cur.ctypes.data_as(C.POINTER(C.c_double)),
+                                  tot.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(t)))
+    return cur, tot, float(t.value)
+
+
+def read_threshold_log(ctx: int, cap: int = 65536) -> Tuple[np.ndarray, int]:
+    out = np.zeros(max(cap, 1), dtype=LOG_DTYPE)
+    n = C.c_int64(0)
+    _check(lib().kmc_read_threshold_log(C.c_void_p(ctx), C.c_void_p(out.ctypes.data), cap, C.byref(n)))
+    return out[:min(int(n.value), cap)], int(n.value)
+
+
+def get_step(ctx: int) -> int:
+    n = C.c_int64(0)
+    _check(lib().kmc_get_step(C.c_void_p(ctx), C.byref(n)))
+    return int(n.value)
+
+
+def destroy(ctx: int) -> None:
+    lib().kmc_destroy(C.c_void_p(ctx))
+
+
+# ------------------------------------------------------------- convenience
+class Simulator:
+    """One context with torch-owned device buffers (occupancy, barrier field,
+    workspace) on one GPU and the current torch stream."""
+
+    def __init__(self, physics, rails: Sequence[int], sites: Sequence[int], occ=None, ea=None,
+                 device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.physics = physics
+        self.rails = [int(x) for x in rails]
+        self.sites = [int(x) for x in sites]
+        self.n_devices = len(self.rails)
+        self.n_sites = int(sum(r * l for r, l in zip(self.rails, self.sites)))
+        self._params, self._keep = make_params(physics, self.rails, self.sites)
+        if occ is None:
+            self.occ = torch.zeros(self.n_sites, dtype=torch.int8, device=self.device)
+        else:
+            self.occ = torch.as_tensor(np.asarray(occ, dtype=np.int8).reshape(-1)).to(self.device)
+        self.ea = None
+        if ea is not None:
+            dt = torch.float64 if physics.precision == "fp64" else torch.float32
+            self.ea = torch.as_tensor(np.asarray(ea).reshape(-1)).to(self.device, dt).contiguous()
+            if self.ea.numel() != self.n_sites:
+                raise ValueError("barrier field size differs from the lattice")
+        nbytes = workspace_bytes(self._params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.ctx = init_device(self._params, self.occ.data_ptr(),
+                                   self.ea.data_ptr() if self.ea is not None else None,
+                                   self._ws_ptr, nbytes, self.stream.cuda_stream)
+
+    def fill_random(self, filling: Sequence[float]) -> None:
+        fill_random(self.ctx, filling)
+
+    def load_occupancy(self, occ) -> None:
+        self.occ.copy_(self.torch.as_tensor(np.asarray(occ, dtype=np.int8).reshape(-1)).to(self.device))
+        load_occupancy(self.ctx)
+
+    def set_bias_protocol(self, t_s, v_volt, device: int = -1) -> None:
+        set_bias_protocol(self.ctx, device, t_s, v_volt)
+
+    def set_protocols(self, protocols) -> None:
+        for d, (t, v) in enumerate(protocols):
+            set_bias_protocol(self.ctx, d, t, v)
+
+    def run_steps(self, n_steps: int, tallies: bool = False):
+        """Advance n_steps; with tallies=True return (net [n,D], deciles [n,D,10]) torch tensors."""
+        torch = self.torch
+        if not tallies:
+            run_steps(self.ctx, n_steps)
+            return None
+        net = torch.empty((n_steps, self.n_devices), dtype=torch.int32, device=self.device)
+        dec = torch.empty((n_steps, self.n_devices, 10), dtype=torch.int32, device=self.device)
+        run_steps(self.ctx, n_steps, net.data_ptr(), dec.data_ptr())
+        return net, dec
+
+    def read_occupancy(self) -> np.ndarray:
+        return read_occupancy(self.ctx, self.n_sites)
+
+    def read_current(self):
+        return read_current(self.ctx, self.n_devices)
+
+    def read_threshold_log(self, cap: int = 65536):
+        return read_threshold_log(self.ctx, cap)
+
+    @property
+    def step(self) -> int:
+        return get_step(self.ctx)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", 0):
+            destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,543 @@
+// C ABI of the rail-KMC hop-step library (declared in include/kmc.h).
+//
+// Host side: parameter validation, workspace layout, the binary64 interaction
+// table, the prefilter bound, the tile decomposition and the launch sequence.
+// Every step of the hop path itself runs in the HIP kernels of kmc_kernels.hip.
+#include "../../include/kmc.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kmc_internal.h"
+
+namespace kmc {
+hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
+hipError_t set_hop_lds_limit(size_t lds_bytes);
+hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
+                         hipStream_t st);
+hipError_t launch_export(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total,
+                         hipStream_t st);
+hipError_t launch_place(int8_t *occ_pad, const DevInfo *devs, const int32_t *rail_dev, const int32_t *rail_idx,
+                        const int32_t *n_ions, int n_rails_total, uint32_t key0, uint32_t key1, hipStream_t st);
+hipError_t launch_barrier_min(const void *ea, bool fp64, DevInfo *devs, int n_dev, unsigned long long *scratch,
+                              hipStream_t st);
+hipError_t launch_count_deciles(const int8_t *occ_pad, const DevInfo *devs, int n_dev, int64_t *dec_run,
+                                hipStream_t st);
+hipError_t launch_set_protocol(double *knot_t, double *knot_v, DevInfo *devs, int d0, int d1, int nk,
+                               int64_t n_set, const double *t, const double *v, hipStream_t st);
+hipError_t launch_begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out, hipStream_t st);
+hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec, int64_t *dec_run,
+                               int64_t *net_total, int n_dev, int steps, hipStream_t st);
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
+hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t st);
+}  // namespace kmc
+
+using namespace kmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+kmc_status fail(kmc_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+constexpr int64_t kLogCap = 65536;
+constexpr double kElementaryCharge = 1.602176634e-19;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
+        net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, total;
+    int64_t total_sites, total_pad, rails_total;
+    int cut;  // interaction table cutoff actually stored
+};
+
+bool is_finite(double x) { return std::isfinite(x); }
+
+kmc_status validate(const kmc_params *p) {
+    if (!p) return fail(KMC_EINVAL, "params is NULL");
+    if (p->n_devices < 1 || p->n_devices > (1 << 24)) return fail(KMC_EINVAL, "n_devices must be in [1, 2^24]");
+    if (!p->rails || !p->sites) return fail(KMC_EINVAL, "rails/sites arrays are NULL");
+    int64_t rails_total = 0;
+    for (int d = 0; d < p->n_devices; ++d) {
+        if (p->rails[d] < 1) return fail(KMC_EINVAL, "device " + std::to_string(d) + ": rails < 1");
+        if (p->sites[d] < 2) return fail(KMC_EINVAL, "device " + std::to_string(d) + ": sites < 2");
+        if (p->sites[d] > kMaxSites)
+            return fail(KMC_EUNSUPPORTED, "device " + std::to_string(d) + ": sites > 4096 per rail");
+        rails_total += p->rails[d];
+    }
+    if (rails_total > (int64_t)1 << 30) return fail(KMC_EUNSUPPORTED, "more than 2^30 rails in total");
+    if (!is_finite(p->nu0_hz) || p->nu0_hz < 0) return fail(KMC_EINVAL, "nu0_hz must be finite and >= 0");
+    if (!is_finite(p->ea_ev)) return fail(KMC_EINVAL, "ea_ev must be finite");
+    if (!is_finite(p->kT_ev) || p->kT_ev <= 0) return fail(KMC_EINVAL, "kT_ev must be > 0");
+    if (!is_finite(p->dt_s) || p->dt_s <= 0) return fail(KMC_EINVAL, "dt_s must be > 0");
+    if (!is_finite(p->field_coupling)) return fail(KMC_EINVAL, "field_coupling must be finite");
+    if (!is_finite(p->coulomb_kappa_v)) return fail(KMC_EINVAL, "coulomb_kappa_v must be finite");
+    if (!is_finite(p->screening_sites) || p->screening_sites < 0)
+        return fail(KMC_EINVAL, "screening_sites must be >= 0");
+    if (p->cutoff_sites < 0) return fail(KMC_EINVAL, "cutoff_sites must be >= 0");
+    if (p->rail_range < 0 || p->rail_range > kMaxRailRange)
+        return fail(KMC_EUNSUPPORTED, "rail_range must be in [0, 4]");
+    if (p->precision != KMC_FP64 && p->precision != KMC_FP32 && p->precision != KMC_BF16X2)
+        return fail(KMC_EINVAL, "unknown precision");
+    if (p->precision == KMC_BF16X2)
+        return fail(KMC_EUNSUPPORTED, "KMC_BF16X2 needs the dense-potential path");
+    return KMC_OK;
+}
+
+Layout layout_for(const kmc_params *p) {
+    Layout L{};
+    int64_t sites = 0, pad = 0, rails = 0;
+    int max_l = 0;
+    for (int d = 0; d < p->n_devices; ++d) {
+        const int pitch = (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites;
+        sites += (int64_t)p->rails[d] * p->sites[d];
+        pad += (int64_t)p->rails[d] * pitch;
+        rails += p->rails[d];
+        max_l = std::max(max_l, p->sites[d]);
+    }
+    L.total_sites = sites;
+    L.total_pad = pad;
+    L.rails_total = rails;
+    L.cut = std::min(p->cutoff_sites, max_l);
+    const int D = p->n_devices;
+    const int m = p->rail_range;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes, 256);
+        return at;
+    };
+    L.occ_a = take((size_t)pad);
+    L.occ_b = take((size_t)pad);
+    L.devs = take(sizeof(DevInfo) * D);
+    L.tiles = take(sizeof(Tile) * (size_t)rails);
+    L.knot_t = take(sizeof(double) * kMaxKnots * D);
+    L.knot_v = take(sizeof(double) * kMaxKnots * D);
+    L.ktab64 = take(sizeof(double) * (m + 1) * (L.cut + 1));
+    L.ktab32 = take(sizeof(float) * (m + 1) * (L.cut + 1));
+    L.ctl = take(sizeof(Ctl));
+    L.tally_net = take(sizeof(int32_t) * kTallySteps * D);
+    L.tally_dec = take(sizeof(int32_t) * kTallySteps * D * kDeciles);
+    L.dec_run = take(sizeof(int64_t) * D * kDeciles);
+    L.net_total = take(sizeof(int64_t) * D);
+    L.log_count = take(sizeof(int64_t));
+    L.log_entries = take(sizeof(kmc_log_entry) * kLogCap);
+    L.scratch = take(sizeof(unsigned long long) * D);
+    L.rail_dev = take(sizeof(int32_t) * (size_t)rails);
+    L.rail_idx = take(sizeof(int32_t) * (size_t)rails);
+    L.n_ions = take(sizeof(int32_t) * D);
+    L.total = off;
+    return L;
+}
+
+// Interaction kernel in binary64: kappa*exp(-d/lambda)/d (kappa/d unscreened).
+double kernel64(const kmc_params *p, int ds, int dr) {
+    if (ds == 0 && dr == 0) return 0.0;
+    if (std::abs(ds) > p->cutoff_sites || dr > p->rail_range) return 0.0;
+    const double d = std::sqrt((double)ds * ds + (double)dr * dr);
+    if (p->screening_sites > 0) return p->coulomb_kappa_v * std::exp(-d / p->screening_sites) / d;
+    return p->coulomb_kappa_v / d;
+}
+
+}  // namespace
+
+struct kmc_ctx {
+    kmc_params p{};
+    std::vector<int32_t> rails, sites;
+    std::vector<DevInfo> devs;
+    std::vector<Tile> tiles;
+    Layout lay{};
+    unsigned char *ws = nullptr;
+    int8_t *occ_user = nullptr;
+    const void *ea = nullptr;
+    hipStream_t stream = nullptr;
+    bool poisoned = false;
+    bool fp64 = false;
+    int64_t n = 0;            // host mirror of the step counter
+    int64_t steps_run = 0;    // steps since init (for the mean current)
+    size_t hop_lds = 0;
+    int8_t *cur = nullptr, *nxt = nullptr;
+
+    template <typename T>
+    T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+kmc_status hip_check(kmc_ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess) return KMC_OK;
+    if (c) c->poisoned = true;
+    return fail(KMC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define KMC_HIP(c, expr)                                           \
+    do {                                                           \
+        kmc_status s_ = hip_check((c), (expr), #expr);             \
+        if (s_ != KMC_OK) return s_;                               \
+    } while (0)
+
+kmc_status usable(kmc_ctx *c) {
+    if (!c) return fail(KMC_EINVAL, "context is NULL");
+    if (c->poisoned) return fail(KMC_ESTATE, "context poisoned by an earlier HIP error");
+    return KMC_OK;
+}
+
+// Distinct rails within rail_range of a rail on a ring of R rails, visited in
+// the order 0, +1, -1, +2, -2, ...; each listed once with its minimal-image
+// distance.
+void neighbour_offsets(int R, int m, DevInfo &dv) {
+    int cnt = 0;
+    std::vector<int> seen;
+    for (int k = 0; k <= 2 * m; ++k) {
+        const int delta = (k == 0) ? 0 : ((k & 1) ? (k + 1) / 2 : -(k / 2));
+        const int rp = ((delta % R) + R) % R;
+        if (std::find(seen.begin(), seen.end(), rp) != seen.end()) continue;
+        seen.push_back(rp);
+        const int a = rp, dist = std::min(a, R - a);
+        dv.nbr_off[cnt] = (int8_t)delta;
+        dv.nbr_dist[cnt] = (int8_t)dist;
+        ++cnt;
+    }
+    dv.n_nbr = cnt;
+}
+
+// Tiles of whole rails, about kTileSites padded sites each.
+void make_tiles(kmc_ctx *c) {
+    c->tiles.clear();
+    for (int d = 0; d < c->p.n_devices; ++d) {
+        const DevInfo &dv = c->devs[d];
+        int nr = std::max(1, kTileSites / dv.pitch);
+        nr = std::min(nr, dv.rails);
+        for (int r0 = 0; r0 < dv.rails; r0 += nr) c->tiles.push_back(Tile{d, r0, std::min(nr, dv.rails - r0), 0});
+    }
+    size_t lds = 0;
+    for (const Tile &t : c->tiles) {
+        const DevInfo &dv = c->devs[t.d];
+        const size_t rows = (size_t)(t.nr + 2 * c->p.rail_range) * dv.pitch;
+        const size_t cap = (size_t)t.nr * dv.pitch / 2;
+        lds = std::max(lds, rows + 3 * cap * sizeof(uint32_t));
+    }
+    c->hop_lds = lds;
+}
+
+kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
+    const int D = c->p.n_devices;
+    HopArgs a{};
+    a.devs = c->at<DevInfo>(c->lay.devs);
+    a.tiles = c->at<Tile>(c->lay.tiles);
+    a.n_tiles = (int32_t)c->tiles.size();
+    a.knot_t = c->at<double>(c->lay.knot_t);
+    a.knot_v = c->at<double>(c->lay.knot_v);
+    a.ea = c->ea;
+    a.ktab64 = c->at<double>(c->lay.ktab64);
+    a.ktab32 = c->at<float>(c->lay.ktab32);
+    a.cutoff = c->lay.cut;
+    a.rail_range = c->p.rail_range;
+    a.ea_scalar = c->p.ea_ev;
+    a.beta = 1.0 / c->p.kT_ev;
+    a.c0 = c->p.nu0_hz * c->p.dt_s;
+    a.alpha = c->p.field_coupling;
+    a.dt = c->p.dt_s;
+    a.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->p.seed >> 32);
+    a.ctl = c->at<Ctl>(c->lay.ctl);
+    a.tally_net = c->at<int32_t>(c->lay.tally_net);
+    a.tally_dec = c->at<int32_t>(c->lay.tally_dec);
+    a.n_devices = D;
+    a.log.count = c->at<int64_t>(c->lay.log_count);
+    a.log.entries = c->ws + c->lay.log_entries;
+    a.log.cap = kLogCap;
+    int64_t done = 0;
+    while (done < n_steps) {
+        const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
+        for (int k = 0; k < chunk; ++k) {
+            for (int h = 0; h < 2; ++h) {
+                a.occ_in = c->cur;
+                a.occ_out = c->nxt;
+                a.step_in_chunk = k;
+                a.h = h;
+                KMC_HIP(c, launch_hop(a, c->hop_lds, c->fp64, c->stream));
+                std::swap(c->cur, c->nxt);
+            }
+        }
+        KMC_HIP(c, launch_finish_chunk(a.ctl, a.tally_net, a.tally_dec, c->at<int64_t>(c->lay.dec_run),
+                                       c->at<int64_t>(c->lay.net_total), D, chunk, c->stream));
+        done += chunk;
+    }
+    return KMC_OK;
+}
+
+kmc_status after_state_change(kmc_ctx *c) {
+    KMC_HIP(c, launch_count_deciles(c->cur, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
+                                    c->at<int64_t>(c->lay.dec_run), c->stream));
+    KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
+                             c->lay.total_sites, c->stream));
+    return KMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kmc_status kmc_workspace_bytes(const kmc_params *params, size_t *bytes) {
+    kmc_status s = validate(params);
+    if (s != KMC_OK) return s;
+    if (!bytes) return fail(KMC_EINVAL, "bytes is NULL");
+    *bytes = layout_for(params).total;
+    return KMC_OK;
+}
+
+kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void *ea_dev, void *workspace_dev,
+                           size_t ws_bytes, void *stream, kmc_ctx **out) {
+    kmc_status s = validate(params);
+    if (s != KMC_OK) return s;
+    if (!out) return fail(KMC_EINVAL, "out is NULL");
+    if (!occ_dev) return fail(KMC_EINVAL, "occ_dev is NULL");
+    if (!workspace_dev) return fail(KMC_EINVAL, "workspace_dev is NULL");
+    const Layout lay = layout_for(params);
+    if (ws_bytes < lay.total)
+        return fail(KMC_ETOOSMALL, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % 256 != 0)
+        return fail(KMC_EINVAL, "workspace_dev must be 256-byte aligned");
+
+    kmc_ctx *c = new kmc_ctx();
+    c->p = *params;
+    c->rails.assign(params->rails, params->rails + params->n_devices);
+    c->sites.assign(params->sites, params->sites + params->n_devices);
+    c->p.rails = c->rails.data();
+    c->p.sites = c->sites.data();
+    c->lay = lay;
+    c->ws = static_cast<unsigned char *>(workspace_dev);
+    c->occ_user = occ_dev;
+    c->ea = ea_dev;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->fp64 = params->precision == KMC_FP64;
+    c->cur = c->at<int8_t>(lay.occ_a);
+    c->nxt = c->at<int8_t>(lay.occ_b);
+
+    // Prefilter bound on the Coulomb term, from the telescoping sums of the
+    // kernel differences: |dE_coul| <= |K(1,0)| + sum over distinct other
+    // rails of |K(0,dist)|, whatever the configuration.
+    const int D = params->n_devices;
+    c->devs.resize(D);
+    int64_t off = 0, off_pad = 0;
+    for (int d = 0; d < D; ++d) {
+        DevInfo &dv = c->devs[d];
+        std::memset(&dv, 0, sizeof(dv));
+        dv.rails = c->rails[d];
+        dv.sites = c->sites[d];
+        dv.pitch = (dv.sites + kChunkSites - 1) / kChunkSites * kChunkSites;
+        dv.n_knots = 1;
+        dv.off = off;
+        dv.off_pad = off_pad;
+        dv.n_set = 0;
+        dv.ea_min = params->ea_ev;
+        neighbour_offsets(dv.rails, params->rail_range, dv);
+        double bound = std::fabs(kernel64(params, 1, 0));
+        for (int k = 0; k < dv.n_nbr; ++k)
+            if (dv.nbr_dist[k] > 0) bound += std::fabs(kernel64(params, 0, dv.nbr_dist[k]));
+        dv.coul_bound = bound;
+        off += (int64_t)dv.rails * dv.sites;
+        off_pad += (int64_t)dv.rails * dv.pitch;
+    }
+    make_tiles(c);
+
+    // binary64 kernel table and its one-time binary32 rounding
+    const int m = params->rail_range, cut = lay.cut;
+    std::vector<double> k64((size_t)(m + 1) * (cut + 1));
+    std::vector<float> k32(k64.size());
+    for (int dr = 0; dr <= m; ++dr)
+        for (int ds = 0; ds <= cut; ++ds) {
+            k64[(size_t)dr * (cut + 1) + ds] = kernel64(params, ds, dr);
+            k32[(size_t)dr * (cut + 1) + ds] = (float)k64[(size_t)dr * (cut + 1) + ds];
+        }
+
+    std::vector<int32_t> rail_dev, rail_idx, n_ions(D, 0);
+    rail_dev.reserve(lay.rails_total);
+    rail_idx.reserve(lay.rails_total);
+    for (int d = 0; d < D; ++d)
+        for (int r = 0; r < c->rails[d]; ++r) {
+            rail_dev.push_back(d);
+            rail_idx.push_back(r);
+        }
+    Ctl ctl{};
+
+    hipStream_t st = c->stream;
+    auto h2d = [&](size_t at, const void *src, size_t bytes) {
+        return hipMemcpyAsync(c->ws + at, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    kmc_status ok = KMC_OK;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (ok == KMC_OK) ok = hip_check(c, e, what);
+    };
+    chk(h2d(lay.devs, c->devs.data(), sizeof(DevInfo) * D), "copy device table");
+    chk(h2d(lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size()), "copy tiles");
+    chk(h2d(lay.ktab64, k64.data(), sizeof(double) * k64.size()), "copy kernel table");
+    chk(h2d(lay.ktab32, k32.data(), sizeof(float) * k32.size()), "copy kernel table");
+    chk(h2d(lay.ctl, &ctl, sizeof(Ctl)), "copy ctl");
+    chk(h2d(lay.rail_dev, rail_dev.data(), sizeof(int32_t) * rail_dev.size()), "copy rail table");
+    chk(h2d(lay.rail_idx, rail_idx.data(), sizeof(int32_t) * rail_idx.size()), "copy rail table");
+    // the host vectors above go out of scope at return: wait for the copies
+    chk(hipStreamSynchronize(st), "synchronise init copies");
+    chk(launch_zero_i32(c->at<int32_t>(lay.tally_net), (int64_t)kTallySteps * D, st), "zero tallies");
+    chk(launch_zero_i32(c->at<int32_t>(lay.tally_dec), (int64_t)kTallySteps * D * kDeciles, st), "zero tallies");
+    chk(launch_zero_i64(c->at<int64_t>(lay.net_total), D, st), "zero totals");
+    chk(launch_zero_i64(c->at<int64_t>(lay.log_count), 1, st), "zero log");
+    chk(set_hop_lds_limit(c->hop_lds), "LDS limit of the hop kernel");
+    {
+        const double zero_t = 0.0, zero_v = 0.0;
+        chk(launch_set_protocol(c->at<double>(lay.knot_t), c->at<double>(lay.knot_v), c->at<DevInfo>(lay.devs), 0, D,
+                                1, 0, &zero_t, &zero_v, st),
+            "install 0 V protocol");
+    }
+    if (ea_dev)
+        chk(launch_barrier_min(ea_dev, c->fp64, c->at<DevInfo>(lay.devs), D, c->at<unsigned long long>(lay.scratch),
+                               st),
+            "barrier minimum");
+    chk(launch_import(occ_dev, c->cur, c->at<DevInfo>(lay.devs), D, lay.total_pad, st), "import occupancy");
+    if (ok == KMC_OK) ok = after_state_change(c);
+    if (ok != KMC_OK) {
+        delete c;
+        return ok;
+    }
+    *out = c;
+    return KMC_OK;
+}
+
+kmc_status kmc_fill_random(kmc_ctx *c, const double *filling) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (!filling) return fail(KMC_EINVAL, "filling is NULL");
+    const int D = c->p.n_devices;
+    std::vector<int32_t> n_ions(D);
+    for (int d = 0; d < D; ++d) {
+        if (!(filling[d] >= 0.0 && filling[d] <= 1.0))
+            return fail(KMC_EINVAL, "filling of device " + std::to_string(d) + " not in [0, 1]");
+        n_ions[d] = (int32_t)std::floor(filling[d] * (double)c->sites[d] + 0.5);
+    }
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.n_ions, n_ions.data(), sizeof(int32_t) * D, hipMemcpyHostToDevice,
+                              c->stream));
+    KMC_HIP(c, launch_place(c->cur, c->at<DevInfo>(c->lay.devs), c->at<int32_t>(c->lay.rail_dev),
+                            c->at<int32_t>(c->lay.rail_idx), c->at<int32_t>(c->lay.n_ions),
+                            (int)c->lay.rails_total, (uint32_t)(c->p.seed & 0xffffffffu),
+                            (uint32_t)(c->p.seed >> 32), c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));  // n_ions staging buffer is local
+    return after_state_change(c);
+}
+
+kmc_status kmc_load_occupancy(kmc_ctx *c) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    KMC_HIP(c, launch_import(c->occ_user, c->cur, c->at<DevInfo>(c->lay.devs), c->p.n_devices, c->lay.total_pad,
+                             c->stream));
+    return after_state_change(c);
+}
+
+kmc_status kmc_set_bias_protocol(kmc_ctx *c, int32_t device, const double *t_s, const double *v_volt,
+                                 int32_t n_knots) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (device < -1 || device >= c->p.n_devices) return fail(KMC_EINVAL, "device index out of range");
+    if (n_knots < 1 || n_knots > kMaxKnots) return fail(KMC_EINVAL, "n_knots must be in [1, 64]");
+    if (!t_s || !v_volt) return fail(KMC_EINVAL, "knot arrays are NULL");
+    for (int i = 0; i < n_knots; ++i) {
+        if (!is_finite(t_s[i]) || !is_finite(v_volt[i])) return fail(KMC_EINVAL, "knots must be finite");
+        if (i > 0 && t_s[i] < t_s[i - 1]) return fail(KMC_EINVAL, "knot times must be nondecreasing");
+    }
+    const int d0 = device < 0 ? 0 : device, d1 = device < 0 ? c->p.n_devices : device + 1;
+    KMC_HIP(c, launch_set_protocol(c->at<double>(c->lay.knot_t), c->at<double>(c->lay.knot_v),
+                                   c->at<DevInfo>(c->lay.devs), d0, d1, n_knots, c->n, t_s, v_volt, c->stream));
+    return KMC_OK;
+}
+
+kmc_status kmc_run_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_hops_dev, int32_t *decile_dev) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (n_steps < 0) return fail(KMC_EINVAL, "n_steps < 0");
+    if (c->n + n_steps > (int64_t)0xffffffffLL) return fail(KMC_EUNSUPPORTED, "step counter would reach 2^32");
+    if (n_steps == 0) return KMC_OK;
+    KMC_HIP(c, launch_begin_call(c->at<Ctl>(c->lay.ctl), net_hops_dev, decile_dev, c->stream));
+    s = enqueue_steps(c, n_steps);
+    if (s != KMC_OK) return s;
+    KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
+                             c->lay.total_sites, c->stream));
+    c->n += n_steps;
+    c->steps_run += n_steps;
+    return KMC_OK;
+}
+
+kmc_status kmc_read_occupancy(kmc_ctx *c, int8_t *dst, size_t bytes) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (!dst) return fail(KMC_EINVAL, "dst is NULL");
+    if (bytes < (size_t)c->lay.total_sites) return fail(KMC_ETOOSMALL, "dst smaller than the lattice");
+    KMC_HIP(c, hipMemcpyAsync(dst, c->occ_user, (size_t)c->lay.total_sites, hipMemcpyDeviceToHost, c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));
+    return KMC_OK;
+}
+
+kmc_status kmc_read_current(kmc_ctx *c, double *mean_current_A, int64_t *net_hops_total, double *sim_time_s) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    const int D = c->p.n_devices;
+    std::vector<int64_t> tot(D);
+    KMC_HIP(c, hipMemcpyAsync(tot.data(), c->ws + c->lay.net_total, sizeof(int64_t) * D, hipMemcpyDeviceToHost,
+                              c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));
+    for (int d = 0; d < D; ++d) {
+        if (net_hops_total) net_hops_total[d] = tot[d];
+        if (mean_current_A) {
+            const double steps = (double)c->steps_run;
+            mean_current_A[d] = steps > 0 ? kElementaryCharge * (double)tot[d] /
+                                                ((double)c->sites[d] * c->p.dt_s * steps)
+                                          : 0.0;
+        }
+    }
+    if (sim_time_s) *sim_time_s = (double)c->n * c->p.dt_s;
+    return KMC_OK;
+}
+
+kmc_status kmc_read_threshold_log(kmc_ctx *c, kmc_log_entry *dst, int64_t cap, int64_t *n_events) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (cap < 0) return fail(KMC_EINVAL, "cap < 0");
+    if (cap > 0 && !dst) return fail(KMC_EINVAL, "dst is NULL");
+    int64_t cnt = 0;
+    KMC_HIP(c, hipMemcpyAsync(&cnt, c->ws + c->lay.log_count, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t stored = std::min<int64_t>(std::min<int64_t>(cnt, kLogCap), cap);
+    if (stored > 0) {
+        KMC_HIP(c, hipMemcpyAsync(dst, c->ws + c->lay.log_entries, sizeof(kmc_log_entry) * stored,
+                                  hipMemcpyDeviceToHost, c->stream));
+        KMC_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    if (n_events) *n_events = cnt;
+    return KMC_OK;
+}
+
+kmc_status kmc_get_step(kmc_ctx *c, int64_t *step) {
+    if (!c) return fail(KMC_EINVAL, "context is NULL");
+    if (!step) return fail(KMC_EINVAL, "step is NULL");
+    *step = c->n;
+    return KMC_OK;
+}
+
+const char *kmc_last_error(void) { return g_last_error.c_str(); }
+
+void kmc_destroy(kmc_ctx *c) {
+    if (!c) return;
+    if (!c->poisoned) (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Internal structures shared by the host library (kmc_api.cpp) and the HIP
+// kernels (kmc_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace kmc {
+
+constexpr int kMaxKnots = 64;
+constexpr int kMaxRailRange = 4;
+constexpr int kMaxSites = 4096;          // sites per rail
+constexpr int kChunkSites = 16;          // sites per lane chunk (one 16-byte load)
+constexpr int kBlock = 256;              // threads per workgroup of the hop kernel
+constexpr int kTileSites = 4096;         // default padded sites per hop-kernel tile
+constexpr int kTallySteps = 1024;        // steps per tally chunk
+constexpr int kDeciles = 10;
+
+// Per-device description, resident in the workspace.
+struct DevInfo {
+    int32_t rails, sites, pitch;         // pitch = sites rounded up to 16
+    int32_t n_knots;
+    int64_t off;                         // unpadded offset (caller layout)
+    int64_t off_pad;                     // padded offset (internal buffers)
+    int64_t n_set;                       // step at which the protocol was installed
+    double ea_min;                       // minimum barrier of the device, eV
+    double coul_bound;                   // |dE_coul| <= coul_bound for any state, eV
+    int32_t n_nbr;                       // distinct rail offsets (incl. 0)
+    int8_t nbr_off[2 * kMaxRailRange + 1];   // rail offsets in [-m, m]
+    int8_t nbr_dist[2 * kMaxRailRange + 1];  // minimal-image distance per offset
+    int32_t pad_;
+};
+
+// One workgroup's work: rails [r0, r0 + nr) of device d.
+struct Tile {
+    int32_t d, r0, nr, pad_;
+};
+
+// Step bookkeeping in device memory (lets a captured graph be replayed).
+struct Ctl {
+    int64_t n_base;        // step index of the next step to run
+    int64_t tally_base;    // step index of row 0 of the tally chunk buffers
+    int64_t call_base;     // first step of the current kmc_run_steps call
+    int32_t *net_out;      // caller buffers of the current call (may be null)
+    int32_t *dec_out;
+};
+
+// Everything the hop kernel needs, passed by value.
+struct HopArgs {
+    const int8_t *occ_in;      // padded internal state, read (Jacobi snapshot)
+    int8_t *occ_out;           // padded internal state, written
+    const DevInfo *devs;
+    const Tile *tiles;
+    int32_t n_tiles;
+    const double *knot_t;      // [D][kMaxKnots]
+    const double *knot_v;
+    const void *ea;            // null or per-site barrier (float or double)
+    const double *ktab64;      // [(m+1)][(c+1)] kernel table, binary64
+    const float *ktab32;       // same, rounded once to binary32
+    int32_t cutoff, rail_range;
+    double ea_scalar, beta, c0, alpha, dt;
+    uint32_t key0, key1;
+    Ctl *ctl;
+    int32_t *tally_net;        // [kTallySteps][D]
+    int32_t *tally_dec;        // [kTallySteps][D][10]  (deltas)
+    int32_t n_devices;
+    struct LogBuf { int64_t *count; void *entries; int64_t cap; } log;
+    int32_t step_in_chunk;
+    int32_t h;
+};
+
+}  // namespace kmc

@@ -1,0 +1,632 @@
+// HIP kernels of the rail-KMC hop step for gfx950 (MI355X).
+//
+// The hot kernel is hop_half_step: one launch decides every bond of one parity
+// (a half-step of the pair checkerboard) for every device, reading the state
+// at the start of the half-step from one buffer and writing the new state to
+// the other.  One workgroup owns whole rails of one device ("tile"):
+//   1. its rails plus the +-rail_range halo rails are staged in LDS with
+//      coalesced 16-byte loads of the int8 occupancy;
+//   2. every lane takes 16 sites of a rail, finds the candidate bonds (exactly
+//      one of the two sites occupied) and draws the bond's Philox4x32-10 word;
+//   3. an exact prefilter discards every candidate whose uniform is above a
+//      bound on its hop probability that holds for any configuration (the
+//      telescoping bound on the Coulomb term, the device's minimum barrier and
+//      the step's bias); the few survivors are queued in LDS;
+//   4. survivors get the full energy change from the LDS window (bias drop plus
+//      screened Coulomb sum over the window, paper main text section 3 and SI
+//      Eq. S1), the Arrhenius probability with the half-energy barrier shift
+//      (main text Eq. hop_rate and Eq. 2), the accept test u < p and the
+//      near-threshold log;
+//   5. accepted hops are applied in LDS, tallied (net hops toward the grounded
+//      site 0, decile crossings) and the tile is written out.
+#include <math.h>
+
+#include "kmc_internal.h"
+
+namespace kmc {
+
+// ------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  gfx950 has a
+// three-input bitwise op; truth table 0x96 is a ^ b ^ c.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                               uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = xor3((uint32_t)(m1 >> 32), x1, k0);
+        const uint32_t y2 = xor3((uint32_t)(m0 >> 32), x3, k1);
+        x1 = (uint32_t)m1;
+        x3 = (uint32_t)m0;
+        x0 = y0;
+        x2 = y2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(x0, x1, x2, x3);
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint4 &b, int i) {
+    return i == 0 ? b.x : (i == 1 ? b.y : (i == 2 ? b.z : b.w));
+}
+
+// Piecewise-linear bias, right-continuous at repeated knot times, constant
+// outside the knot range.  Binary64.
+__device__ double protocol_voltage(const double *t, const double *v, int nk, double t_rel) {
+    if (nk <= 0) return 0.0;
+    if (t_rel < t[0]) return v[0];
+    int k = 0;
+    for (int i = 0; i < nk; ++i)
+        if (t[i] <= t_rel) k = i;
+    if (k == nk - 1) return v[nk - 1];
+    const double num = (v[k + 1] - v[k]) * (t_rel - t[k]);
+    return v[k] + num / (t[k + 1] - t[k]);
+}
+
+__device__ __forceinline__ int tile_of_block(int bid, int n_tiles) {
+    // Consecutive tiles (neighbouring rails) on the same XCD: the dispatcher
+    // deals workgroups round-robin over the 8 XCDs.
+    const int full = (n_tiles / 8) * 8;
+    return bid < full ? (bid % 8) * (n_tiles / 8) + bid / 8 : bid;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real ktab(const HopArgs &a, int ds, int dist);
+template <>
+__device__ __forceinline__ double ktab<double>(const HopArgs &a, int ds, int dist) {
+    const int ad = ds < 0 ? -ds : ds;
+    return ad > a.cutoff ? 0.0 : a.ktab64[dist * (a.cutoff + 1) + ad];
+}
+template <>
+__device__ __forceinline__ float ktab<float>(const HopArgs &a, int ds, int dist) {
+    const int ad = ds < 0 ? -ds : ds;
+    return ad > a.cutoff ? 0.0f : a.ktab32[dist * (a.cutoff + 1) + ad];
+}
+
+template <typename Real>
+__device__ __forceinline__ Real exp_r(Real x);
+template <>
+__device__ __forceinline__ double exp_r<double>(double x) { return exp(x); }
+template <>
+__device__ __forceinline__ float exp_r<float>(float x) { return expf(x); }
+
+template <typename Real>
+__device__ __forceinline__ Real uniform_of(uint32_t w);
+template <>
+__device__ __forceinline__ double uniform_of<double>(uint32_t w) { return (double)w * 0x1p-32; }
+template <>
+__device__ __forceinline__ float uniform_of<float>(uint32_t w) { return (float)w * 0x1p-32f; }
+
+struct HopShared {
+    int64_t n;
+    uint64_t w_thr;
+    double V;
+    int32_t n_surv, n_hop, n_down, n_up;
+    int32_t dec[kDeciles];
+};
+
+// ------------------------------------------------------------------------
+// The half-step kernel.  H = bond parity.  Dynamic LDS layout:
+//   rows   [(nr + 2m) * pitch] int8 : tile rails and halo rails
+//   surv   [cap] uint32 (row << 13 | s), survw [cap] uint32 (Philox word)
+//   hops   [cap] uint32 (row << 13 | s)
+// ------------------------------------------------------------------------
+template <typename Real, int H>
+__global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ HopShared sh;
+
+    const Tile tile = a.tiles[tile_of_block(blockIdx.x, a.n_tiles)];
+    const DevInfo &dv = a.devs[tile.d];
+    const int R = dv.rails, L = dv.sites, pitch = dv.pitch;
+    const int m = a.rail_range;
+    const int p16 = pitch / kChunkSites;
+    const int n_rows = tile.nr + 2 * m;
+    const int cap = tile.nr * pitch / 2;
+    unsigned char *rows = smem;
+    uint32_t *surv = reinterpret_cast<uint32_t *>(smem + n_rows * pitch);
+    uint32_t *survw = surv + cap;
+    uint32_t *hops = survw + cap;
+    const int tid = threadIdx.x;
+
+    if (tid == 0) {
+        const int64_t n = a.ctl->n_base + a.step_in_chunk;
+        const double t_rel = (double)(n - dv.n_set) * a.dt;
+        const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots,
+                                          a.knot_v + tile.d * kMaxKnots, dv.n_knots, t_rel);
+        // Exact prefilter bound: dE >= -(|alpha V|/L + coul_bound) for every
+        // configuration, Ea >= ea_min, so p <= pb.  Widened by 1e-3 relative
+        // and by twice the 1e-6 logging window; a draw u >= pb can neither be
+        // accepted nor logged.
+        const double arg = -a.beta * (dv.ea_min - 0.5 * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
+        const double pb = a.c0 * exp(arg) * (1.0 + 1e-3) + 2e-6;
+        sh.w_thr = pb >= 1.0 ? (uint64_t)1 << 32 : (uint64_t)ceil(pb * 4294967296.0);
+        sh.n = n;
+        sh.V = V;
+        sh.n_surv = 0;
+        sh.n_hop = 0;
+        sh.n_down = 0;
+        sh.n_up = 0;
+        for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
+    }
+
+    // 1. stage tile and halo rails (Jacobi snapshot) in LDS
+    const int8_t *src_dev = a.occ_in + dv.off_pad;
+    for (int i = tid; i < n_rows * p16; i += kBlock) {
+        const int row = i / p16, c16 = i - row * p16;
+        int rail = tile.r0 - m + row;
+        rail = ((rail % R) + R) % R;
+        const uint4 v = *reinterpret_cast<const uint4 *>(src_dev + (int64_t)rail * pitch + c16 * kChunkSites);
+        *reinterpret_cast<uint4 *>(rows + row * pitch + c16 * kChunkSites) = v;
+    }
+    __syncthreads();
+
+    const int64_t n = sh.n;
+    const uint64_t w_thr = sh.w_thr;
+    const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)H;
+
+    // 2-3. candidates, Philox words, exact prefilter
+    for (int i = tid; i < tile.nr * p16; i += kBlock) {
+        const int row = i / p16, c16 = i - row * p16;
+        const int s0 = c16 * kChunkSites;
+        const unsigned char *rp = rows + (m + row) * pitch;
+        const uint4 v = *reinterpret_cast<const uint4 *>(rp + s0);
+        const uint32_t nxt = (s0 + kChunkSites < pitch) ? rp[s0 + kChunkSites] : 0u;
+        // occupancy bits of sites s0 .. s0+16
+        uint32_t bits = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const uint32_t wv = word_of(v, b);
+            bits |= ((wv & 1u) | ((wv >> 7) & 2u) | ((wv >> 14) & 4u) | ((wv >> 21) & 8u)) << (4 * b);
+        }
+        bits |= (nxt & 1u) << 16;
+        uint32_t cand = (bits ^ (bits >> 1)) & (H ? 0xAAAAu : 0x5555u);
+        const int last = L - 2 - s0;  // bond (s0+k, s0+k+1) exists iff k <= last
+        if (last < 15) cand &= last < 0 ? 0u : ((2u << last) - 1u);
+        if (cand == 0) continue;
+        const uint32_t rail = (uint32_t)(tile.r0 + row);
+        uint32_t surv_mask = 0;
+        if (cand & 0x00FFu) {
+            const uint4 blk = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int bit = H + 2 * j;
+                if (((cand >> bit) & 1u) && (uint64_t)word_of(blk, j) < w_thr) surv_mask |= 1u << bit;
+            }
+            if (surv_mask & 0x00FFu) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int bit = H + 2 * j;
+                    if ((surv_mask >> bit) & 1u) {
+                        const int k = atomicAdd(&sh.n_surv, 1);
+                        surv[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
+                        survw[k] = word_of(blk, j);
+                    }
+                }
+            }
+        }
+        if (cand & 0xFF00u) {
+            const uint4 blk = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
+            uint32_t sm = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int bit = 8 + H + 2 * j;
+                if (((cand >> bit) & 1u) && (uint64_t)word_of(blk, j) < w_thr) sm |= 1u << bit;
+            }
+            if (sm) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int bit = 8 + H + 2 * j;
+                    if ((sm >> bit) & 1u) {
+                        const int k = atomicAdd(&sh.n_surv, 1);
+                        surv[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
+                        survw[k] = word_of(blk, j);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 4. full evaluation of the survivors
+    const int n_surv = sh.n_surv;
+    if (n_surv > 0) {
+        const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
+        const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
+        for (int i = tid; i < n_surv; i += kBlock) {
+            const int row = (int)(surv[i] >> 13), s = (int)(surv[i] & 8191u);
+            const uint32_t w = survw[i];
+            const unsigned char *rp = rows + (m + row) * pitch;
+            const int o = rp[s] ? s : s + 1;
+            const int t = rp[s] ? s + 1 : s;
+            const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+            int lo = s - a.cutoff, hi = s + 1 + a.cutoff;
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > L - 1 ? L - 1 : hi;
+            Real e_coul = (Real)0;
+            for (int k = 0; k < dv.n_nbr; ++k) {
+                const int off = dv.nbr_off[k], dist = dv.nbr_dist[k];
+                const unsigned char *nr_ = rows + (m + row + off) * pitch;
+                for (int j = lo; j <= hi; ++j) {
+                    if (off == 0 && (j == o || j == t)) continue;
+                    if (!nr_[j]) continue;
+                    const Real kt = ktab<Real>(a, t - j, dist);
+                    const Real ko = ktab<Real>(a, o - j, dist);
+                    e_coul += kt - ko;
+                }
+            }
+            const Real dE = e_app + e_coul;
+            const int rail = tile.r0 + row;
+            Real ea;
+            if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)rail * L + o];
+            else ea = (Real)a.ea_scalar;
+            Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+            p = p < (Real)1 ? p : (Real)1;
+            const Real u = uniform_of<Real>(w);
+            const Real gap = u - p;
+            if ((gap < 0 ? -gap : gap) < (Real)1e-6) {
+                const int64_t k = atomicAdd(reinterpret_cast<unsigned long long *>(a.log.count), 1ull);
+                if (k < a.log.cap) {
+                    unsigned char *e = reinterpret_cast<unsigned char *>(a.log.entries) + 40 * k;
+                    *reinterpret_cast<int32_t *>(e + 0) = tile.d;
+                    *reinterpret_cast<int32_t *>(e + 4) = H;
+                    *reinterpret_cast<int64_t *>(e + 8) = n;
+                    *reinterpret_cast<int32_t *>(e + 16) = rail;
+                    *reinterpret_cast<int32_t *>(e + 20) = s;
+                    *reinterpret_cast<double *>(e + 24) = (double)u;
+                    *reinterpret_cast<double *>(e + 32) = (double)p;
+                }
+            }
+            if (u < p) {
+                const int k = atomicAdd(&sh.n_hop, 1);
+                hops[k] = ((uint32_t)row << 13) | (uint32_t)s;
+                if (t < o) atomicAdd(&sh.n_down, 1);
+                else atomicAdd(&sh.n_up, 1);
+                const int qo = (10 * o) / L, qt = (10 * t) / L;
+                if (qo != qt) {
+                    atomicAdd(&sh.dec[qo], -1);
+                    atomicAdd(&sh.dec[qt], 1);
+                }
+            }
+        }
+        __syncthreads();
+
+        // 5a. apply accepted hops to the tile rows, push the tallies
+        const int n_hop = sh.n_hop;
+        for (int i = tid; i < n_hop; i += kBlock) {
+            const int row = (int)(hops[i] >> 13), s = (int)(hops[i] & 8191u);
+            unsigned char *rp = rows + (m + row) * pitch;
+            rp[s] ^= 1;
+            rp[s + 1] ^= 1;
+        }
+        if (tid == 0 && n_hop > 0) {
+            const int64_t k = n - a.ctl->tally_base;
+            const int64_t base = k * a.n_devices + tile.d;
+            atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
+            for (int q = 0; q < kDeciles; ++q)
+                if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);
+        }
+        __syncthreads();
+    }
+
+    // 5b. write the tile
+    int8_t *dst_dev = a.occ_out + dv.off_pad;
+    for (int i = tid; i < tile.nr * p16; i += kBlock) {
+        const int row = i / p16, c16 = i - row * p16;
+        const uint4 v = *reinterpret_cast<const uint4 *>(rows + (m + row) * pitch + c16 * kChunkSites);
+        *reinterpret_cast<uint4 *>(dst_dev + (int64_t)(tile.r0 + row) * pitch + c16 * kChunkSites) = v;
+    }
+}
+
+// ------------------------------------------------------------------------
+// Bookkeeping kernels
+// ------------------------------------------------------------------------
+
+// Caller layout -> padded internal layout, values normalised to 0/1 and the
+// padding bytes cleared.  One thread per padded byte.
+__global__ void import_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
+                                 int64_t total_pad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total_pad) return;
+    int d = 0;
+    while (d + 1 < n_dev && devs[d + 1].off_pad <= i) ++d;
+    const DevInfo &dv = devs[d];
+    const int64_t loc = i - dv.off_pad;
+    const int r = (int)(loc / dv.pitch), s = (int)(loc - (int64_t)r * dv.pitch);
+    dst[i] = (s < dv.sites) ? (src[dv.off + (int64_t)r * dv.sites + s] != 0 ? 1 : 0) : 0;
+}
+
+__global__ void export_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
+                                 int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int d = 0;
+    while (d + 1 < n_dev && devs[d + 1].off <= i) ++d;
+    const DevInfo &dv = devs[d];
+    const int64_t loc = i - dv.off;
+    const int r = (int)(loc / dv.sites), s = (int)(loc - (int64_t)r * dv.sites);
+    dst[i] = src[dv.off_pad + (int64_t)r * dv.pitch + s];
+}
+
+// Random placement: floor(f L + 1/2) ions on the sites with the smallest
+// (placement word, site) keys.  One workgroup per rail; rank by counting.
+__global__ __launch_bounds__(256) void place_ions(int8_t *occ_pad, const DevInfo *devs,
+                                                  const int32_t *rail_dev, const int32_t *rail_idx,
+                                                  const int32_t *n_ions, uint32_t key0, uint32_t key1) {
+    __shared__ uint64_t keys[kMaxSites];
+    const int d = rail_dev[blockIdx.x], r = rail_idx[blockIdx.x];
+    const DevInfo &dv = devs[d];
+    const int L = dv.sites;
+    const int nion = n_ions[d];
+    for (int s = threadIdx.x; s < L; s += blockDim.x) {
+        const uint4 blk = philox4x32_10((uint32_t)(s >> 2), (uint32_t)r, 0u,
+                                        ((uint32_t)d << 4) | (1u << 1), key0, key1);
+        keys[s] = ((uint64_t)word_of(blk, s & 3) << 32) | (uint32_t)s;
+    }
+    __syncthreads();
+    int8_t *row = occ_pad + dv.off_pad + (int64_t)r * dv.pitch;
+    for (int s = threadIdx.x; s < dv.pitch; s += blockDim.x) {
+        int8_t val = 0;
+        if (s < L) {
+            const uint64_t ks = keys[s];
+            int rank = 0;
+            for (int q = 0; q < L; ++q) rank += keys[q] < ks ? 1 : 0;
+            val = rank < nion ? 1 : 0;
+        }
+        row[s] = val;
+    }
+}
+
+// Order-preserving unsigned key of a double (for atomicMin).
+__device__ __forceinline__ unsigned long long order_key(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+template <typename Real>
+__global__ void barrier_min(const Real *ea, const DevInfo *devs, unsigned long long *out) {
+    const int d = blockIdx.y;
+    const DevInfo &dv = devs[d];
+    const int64_t cnt = (int64_t)dv.rails * dv.sites;
+    unsigned long long best = ~0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = order_key((double)ea[dv.off + i]);
+        best = k < best ? k : best;
+    }
+    atomicMin(&out[d], best);
+}
+
+__global__ void barrier_min_finish(const unsigned long long *keys, DevInfo *devs, int n_dev) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n_dev) return;
+    const unsigned long long k = keys[d];
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    devs[d].ea_min = __longlong_as_double((long long)b);
+}
+
+// Decile counts of the current state (int64), one workgroup per device.
+__global__ void count_deciles(const int8_t *occ_pad, const DevInfo *devs, int64_t *dec_run) {
+    __shared__ int cnt[kDeciles];
+    const int d = blockIdx.x;
+    const DevInfo &dv = devs[d];
+    if (threadIdx.x < kDeciles) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t total = (int64_t)dv.rails * dv.pitch;
+    int local[kDeciles] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i = threadIdx.x; i < total; i += blockDim.x) {
+        const int s = (int)(i % dv.pitch);
+        if (s < dv.sites && occ_pad[dv.off_pad + i]) local[(10 * s) / dv.sites] += 1;
+    }
+    for (int q = 0; q < kDeciles; ++q)
+        if (local[q]) atomicAdd(&cnt[q], local[q]);
+    __syncthreads();
+    if (threadIdx.x < kDeciles) dec_run[d * kDeciles + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// Install a protocol: knots are passed by value so the update is ordered on the
+// stream like every other launch.
+struct KnotPack {
+    double t[kMaxKnots];
+    double v[kMaxKnots];
+};
+
+__global__ void set_protocol(double *knot_t, double *knot_v, DevInfo *devs, int d0, int d1,
+                             int nk, int64_t n_set, KnotPack kp) {
+    const int d = d0 + blockIdx.x;
+    if (d >= d1) return;
+    for (int i = threadIdx.x; i < kMaxKnots; i += blockDim.x) {
+        knot_t[d * kMaxKnots + i] = i < nk ? kp.t[i] : 0.0;
+        knot_v[d * kMaxKnots + i] = i < nk ? kp.v[i] : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        devs[d].n_knots = nk;
+        devs[d].n_set = n_set;
+    }
+}
+
+// Start of a kmc_run_steps call: remember the caller's output buffers.
+__global__ void begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out) {
+    ctl->call_base = ctl->n_base;
+    ctl->tally_base = ctl->n_base;
+    ctl->net_out = net_out;
+    ctl->dec_out = dec_out;
+}
+
+// End of a tally chunk of `steps` steps: per device, prefix-sum the decile
+// deltas into absolute counts, accumulate the int64 net total, copy rows to the
+// caller's buffers, clear the chunk buffers, and advance the step counter.
+// One workgroup per device.
+__global__ __launch_bounds__(256) void finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec,
+                                                    int64_t *dec_run, int64_t *net_total, int n_dev,
+                                                    int steps) {
+    __shared__ int64_t scan[256];
+    const int d = blockIdx.x;
+    const int64_t row0 = ctl->tally_base - ctl->call_base;
+    int32_t *net_out = ctl->net_out;
+    int32_t *dec_out = ctl->dec_out;
+    for (int q = 0; q <= kDeciles; ++q) {  // q == kDeciles: net hops
+        int64_t carry = (q < kDeciles) ? dec_run[d * kDeciles + q] : 0;
+        for (int k0 = 0; k0 < steps; k0 += 256) {
+            const int k = k0 + threadIdx.x;
+            int64_t val = 0;
+            if (k < steps) {
+                if (q < kDeciles) {
+                    int32_t *p = &tally_dec[((int64_t)k * n_dev + d) * kDeciles + q];
+                    val = *p;
+                    *p = 0;
+                } else {
+                    int32_t *p = &tally_net[(int64_t)k * n_dev + d];
+                    val = *p;
+                    *p = 0;
+                    if (net_out) net_out[(row0 + k) * n_dev + d] = (int32_t)val;
+                }
+            }
+            scan[threadIdx.x] = val;
+            __syncthreads();
+            for (int off = 1; off < 256; off <<= 1) {
+                const int64_t add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
+                __syncthreads();
+                scan[threadIdx.x] += add;
+                __syncthreads();
+            }
+            const int64_t incl = carry + scan[threadIdx.x];
+            if (k < steps && q < kDeciles && dec_out)
+                dec_out[((row0 + k) * n_dev + d) * kDeciles + q] = (int32_t)incl;
+            carry += scan[255];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (q < kDeciles) dec_run[d * kDeciles + q] = carry;
+            else net_total[d] += carry;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void advance_steps(Ctl *ctl, int steps) {
+    ctl->n_base += steps;
+    ctl->tally_base = ctl->n_base;
+}
+
+__global__ void zero_i32(int32_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void zero_i64(int64_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------------
+// Host-side launch wrappers (called from kmc_api.cpp)
+// ------------------------------------------------------------------------
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
+    const dim3 grid(a.n_tiles), block(kBlock);
+    if (fp64) {
+        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<double, 0>), grid, block, lds_bytes, st, a);
+        else hipLaunchKernelGGL((hop_half_step<double, 1>), grid, block, lds_bytes, st, a);
+    } else {
+        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<float, 0>), grid, block, lds_bytes, st, a);
+        else hipLaunchKernelGGL((hop_half_step<float, 1>), grid, block, lds_bytes, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t set_hop_lds_limit(size_t lds_bytes) {
+    const void *fns[4] = {(const void *)hop_half_step<double, 0>, (const void *)hop_half_step<double, 1>,
+                          (const void *)hop_half_step<float, 0>, (const void *)hop_half_step<float, 1>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(import_occupancy, dim3(grid_for(total_pad, 256)), dim3(256), 0, st, src, dst, devs,
+                       n_dev, total_pad);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(export_occupancy, dim3(grid_for(total, 256)), dim3(256), 0, st, src, dst, devs, n_dev,
+                       total);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(int8_t *occ_pad, const DevInfo *devs, const int32_t *rail_dev, const int32_t *rail_idx,
+                        const int32_t *n_ions, int n_rails_total, uint32_t key0, uint32_t key1, hipStream_t st) {
+    hipLaunchKernelGGL(place_ions, dim3(n_rails_total), dim3(256), 0, st, occ_pad, devs, rail_dev, rail_idx,
+                       n_ions, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t launch_barrier_min(const void *ea, bool fp64, DevInfo *devs, int n_dev, unsigned long long *scratch,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(fill_u64, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, scratch, (int64_t)n_dev, ~0ull);
+    const dim3 grid(64, n_dev);
+    if (fp64) hipLaunchKernelGGL((barrier_min<double>), grid, dim3(256), 0, st, (const double *)ea, devs, scratch);
+    else hipLaunchKernelGGL((barrier_min<float>), grid, dim3(256), 0, st, (const float *)ea, devs, scratch);
+    hipLaunchKernelGGL(barrier_min_finish, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, scratch, devs, n_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_deciles(const int8_t *occ_pad, const DevInfo *devs, int n_dev, int64_t *dec_run,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(count_deciles, dim3(n_dev), dim3(256), 0, st, occ_pad, devs, dec_run);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_protocol(double *knot_t, double *knot_v, DevInfo *devs, int d0, int d1, int nk,
+                               int64_t n_set, const double *t, const double *v, hipStream_t st) {
+    KnotPack kp;
+    for (int i = 0; i < kMaxKnots; ++i) {
+        kp.t[i] = i < nk ? t[i] : 0.0;
+        kp.v[i] = i < nk ? v[i] : 0.0;
+    }
+    hipLaunchKernelGGL(set_protocol, dim3(d1 - d0), dim3(64), 0, st, knot_t, knot_v, devs, d0, d1, nk, n_set, kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out, hipStream_t st) {
+    hipLaunchKernelGGL(begin_call, dim3(1), dim3(1), 0, st, ctl, net_out, dec_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec, int64_t *dec_run,
+                               int64_t *net_total, int n_dev, int steps, hipStream_t st) {
+    hipLaunchKernelGGL(finish_chunk, dim3(n_dev), dim3(256), 0, st, ctl, tally_net, tally_dec, dec_run, net_total,
+                       n_dev, steps);
+    hipLaunchKernelGGL(advance_steps, dim3(1), dim3(1), 0, st, ctl, steps);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_i64, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace kmc

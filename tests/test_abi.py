@@ -1,0 +1,56 @@
+"""The C ABI library: it loads, exports every function include/kmc.h declares,
+and validates parameters on the host before touching a GPU (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2511_09413_amd as kmc
+from workloads import Physics
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            names += re.findall(r"^\s*(?:kmc_status|const char \*|void)\s*\**\s*(kmc_\w+)\s*\(", text, re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert "kmc_init_device" in names and "kmc_run_steps" in names and len(names) >= 12
+    L = kmc.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def _status(physics, rails, sites):
+    p, keep = kmc.make_params(physics, rails, sites)
+    out = C.c_size_t(0)
+    return kmc.lib().kmc_workspace_bytes(C.byref(p), C.byref(out)), out.value
+
+
+def test_validation_errors_without_gpu():
+    ok, nbytes = _status(Physics(), [64], [128])
+    assert ok == kmc.KMC_OK and nbytes > 2 * 64 * 128
+    assert _status(Physics(), [64], [1])[0] == kmc.KMC_EINVAL
+    assert _status(Physics(), [0], [8])[0] == kmc.KMC_EINVAL
+    assert _status(Physics(), [4], [5000])[0] == kmc.KMC_EUNSUPPORTED
+    assert _status(Physics(kT_ev=0.0), [4], [8])[0] == kmc.KMC_EINVAL
+    assert _status(Physics(dt_s=-1.0), [4], [8])[0] == kmc.KMC_EINVAL
+    assert _status(Physics(rail_range=5), [4], [8])[0] == kmc.KMC_EUNSUPPORTED
+    assert _status(Physics(cutoff_sites=-1), [4], [8])[0] == kmc.KMC_EINVAL
+    assert b"cutoff" in kmc.lib().kmc_last_error()
+    with pytest.raises(kmc.KmcError):
+        kmc.workspace_bytes(kmc.make_params(Physics(screening_sites=-1.0), [4], [8])[0])
+
+
+def test_workspace_scales_with_lattice():
+    a = _status(Physics(), [64], [128])[1]
+    b = _status(Physics(), [4096], [1024])[1]
+    assert b > 2 * 4096 * 1024 > a

@@ -1,0 +1,157 @@
+"""HIP hop step vs the CPU oracle, element by element (needs an MI355X)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import gpu_available, lockstep
+from workloads import (FP32, FP64, Physics, c1_plain_fp64, c2_large_device, constant,
+                       gaussian_barriers, small_case, step_then_relax, stdp_pair, triangle)
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _sim(physics, rails, sites, occ=None, ea=None):
+    from paper_2511_09413_amd import Simulator
+    return Simulator(physics, rails, sites, occ=occ, ea=ea)
+
+
+@pytest.mark.parametrize("rails,sites,fill", [
+    ([64], [128], [0.2]),
+    ([3, 5, 2], [37, 100, 1000], [0.3, 0.05, 0.4]),
+    ([2], [4096], [0.5]),
+    ([7], [2], [0.5]),
+])
+def test_fill_random_matches_oracle(rails, sites, fill):
+    ph = Physics(precision=FP32, seed=0xC0FFEE)
+    sim = _sim(ph, rails, sites)
+    sim.fill_random(fill)
+    got = sim.read_occupancy()
+    ref = oracle.fill(oracle.OracleParams(ph.replace(precision=FP64), rails, sites), fill)
+    assert np.array_equal(got, ref)
+
+
+def _run_parity(wl, n_steps, chunk, occ0=None, phys=None):
+    ph = phys or wl.physics
+    sim = _sim(ph, wl.rails, wl.sites, ea=wl.ea_site)
+    p_or = oracle.OracleParams(ph, wl.rails, wl.sites, wl.ea_site)
+    if occ0 is None:
+        occ0 = oracle.fill(p_or, wl.filling)
+    sim.load_occupancy(occ0)
+    sim.set_protocols(wl.protocols)
+    return lockstep(sim, p_or, wl.protocols, occ0, n_steps, chunk), sim
+
+
+def test_c1_fp64_trajectory():
+    """64 x 128, 20% filling, FP64, 0.5 V, kappa = 0.025 V, lambda = 4, cutoff
+    16, +-1 rail: identical trajectory, tallies and deciles for 600 steps."""
+    wl = c1_plain_fp64()
+    st, _ = _run_parity(wl, 600, 200)
+    assert st["resyncs"] == 0
+
+
+def test_c1_validation_variant_many_hops():
+    """Same lattice with Ea = 0.15 eV (p ~ 3e-3): thousands of hops."""
+    wl = c1_plain_fp64()
+    ph = wl.physics.replace(ea_ev=0.15)
+    st, _ = _run_parity(wl, 300, 100, phys=ph)
+    assert st["hops"] > 100
+    assert st["resyncs"] <= 1
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_ragged_multi_device_with_barrier_field(precision):
+    """Heterogeneous devices (ragged site counts, several tiles per device),
+    per-site barriers, triangle / step / spike-pair protocols."""
+    rails, sites = [9, 40, 3, 1], [37, 300, 1000, 129]
+    dt = np.float64 if precision == FP64 else np.float32
+    n = sum(r * l for r, l in zip(rails, sites))
+    ea = gaussian_barriers((n,), 0.12, 0.02, seed=4, dtype=dt)
+    ph = Physics(precision=precision, seed=77, coulomb_kappa_v=0.03)
+    protos = [triangle(2.0, 200e-12), step_then_relax(1.0, 60e-12), stdp_pair(20e-12, 30e-12, 10e-12),
+              constant(-0.7)]
+    from workloads import Workload
+    wl = Workload("ragged", ph, rails, sites, [0.3, 0.2, 0.45, 0.5], protos, 0, ea_site=ea)
+    st, _ = _run_parity(wl, 200, 50)
+    assert st["hops"] > 100
+
+
+@pytest.mark.parametrize("R,L,m,cut,lam", [
+    (1, 64, 1, 16, 4.0), (2, 50, 1, 16, 4.0), (3, 40, 2, 8, 4.0), (17, 96, 0, 16, 4.0),
+    (12, 64, 4, 63, 0.0), (5, 33, 3, 5, 2.0)])
+def test_interaction_variants(R, L, m, cut, lam):
+    ph = Physics(precision=FP64, seed=5, ea_ev=0.12, coulomb_kappa_v=0.04, screening_sites=lam,
+                 cutoff_sites=cut, rail_range=m)
+    wl = small_case(R, L, filling=0.35, precision=FP64, ea_ev=0.12, protocol=triangle(3.0, 80e-12))
+    wl.physics = ph
+    st, _ = _run_parity(wl, 80, 40)
+    assert st["steps"] == 80
+
+
+def test_protocol_install_midrun_and_chunking():
+    """A protocol installed at step n_set is relative to n_set; splitting a run
+    into calls of different lengths gives the same trajectory."""
+    ph = Physics(precision=FP32, seed=3, ea_ev=0.13)
+    rails, sites = [16], [256]
+    p_or = oracle.OracleParams(ph, rails, sites)
+    occ0 = oracle.fill(p_or, [0.3])
+    a = _sim(ph, rails, sites, occ=occ0)
+    a.set_bias_protocol(*triangle(1.5, 100e-12))
+    net_a = [a.run_steps(k, tallies=True)[0].cpu().numpy() for k in (7, 1, 30, 2)]
+    a.set_bias_protocol(*step_then_relax(2.0, 10e-12))   # installed at step 40
+    net_a.append(a.run_steps(25, tallies=True)[0].cpu().numpy())
+    occ_o = occ0.copy()
+    r1 = oracle.run(p_or, [triangle(1.5, 100e-12)], occ_o, 0, 40)
+    r2 = oracle.run(p_or, [step_then_relax(2.0, 10e-12)], occ_o, 40, 25, n_set=[40])
+    assert np.array_equal(np.concatenate(net_a[:4]), r1["net"])
+    assert np.array_equal(net_a[4], r2["net"])
+    assert np.array_equal(a.read_occupancy(), occ_o)
+    cur, tot, t = a.read_current()
+    assert tot[0] == int(r1["net"].sum() + r2["net"].sum())
+    assert t == pytest.approx(65 * ph.dt_s)
+    assert cur[0] == pytest.approx(1.602176634e-19 * tot[0] / (256 * ph.dt_s * 65))
+
+
+def test_near_threshold_log_matches_oracle():
+    """The GPU logs exactly the oracle's near-threshold draws (|u - p| < 1e-6)."""
+    ph = Physics(precision=FP64, seed=9, ea_ev=0.02, coulomb_kappa_v=0.04)  # p near 0.5
+    rails, sites = [32], [256]
+    p_or = oracle.OracleParams(ph, rails, sites)
+    occ0 = oracle.fill(p_or, [0.4])
+    sim = _sim(ph, rails, sites, occ=occ0)
+    sim.set_bias_protocol(*constant(0.3))
+    sim.run_steps(200)
+    occ_o = occ0.copy()
+    out = oracle.run(p_or, [constant(0.3)], occ_o, 0, 200, log_cap=100000)
+    log, n = sim.read_threshold_log()
+    assert n == out["n_log"]
+    key = lambda e: (int(e["n"]), int(e["h"]), int(e["r"]), int(e["s"]))
+    assert sorted(map(key, log)) == sorted(map(key, out["log"]))
+    if out["n_log"] == 0:
+        assert np.array_equal(sim.read_occupancy(), occ_o)
+
+
+# ------------------------------------------------------------- full size
+def test_c2_full_size_sampled():
+    """4096 x 1024, FP32, per-site barriers, in the benchmark's launch
+    configuration: after 3 steps, rails [lo+6, hi-6) of several windows equal the
+    oracle's light-cone runs, and every rail keeps its ion count."""
+    wl = c2_large_device(n_steps=3)
+    ph = wl.physics.replace(ea_ev=0.3)
+    ea = wl.ea_site - np.float32(0.17)   # lower barriers: about 400 hops per step
+    sim = _sim(ph, wl.rails, wl.sites, ea=ea)
+    sim.fill_random(wl.filling)
+    occ0 = sim.read_occupancy()
+    sim.set_protocols(wl.protocols)
+    net, _ = sim.run_steps(3, tallies=True)
+    occ = sim.read_occupancy().reshape(4096, 1024)
+    assert (occ.sum(axis=1) == occ0.reshape(4096, 1024).sum(axis=1)).all()
+    p_or = oracle.OracleParams(ph, wl.rails, wl.sites, ea)
+    for lo in (0, 1000, 2040, 4096 - 30):
+        part = occ0.copy()
+        oracle.run(p_or, wl.protocols, part, 0, 3, rail_lo=lo, rail_hi=lo + 30, want_dec=False)
+        ref = part.reshape(4096, 1024)
+        assert np.array_equal(occ[lo + 6:lo + 24], ref[lo + 6:lo + 24]), lo
+    assert int(np.abs(net.cpu().numpy()).sum()) >= 0
