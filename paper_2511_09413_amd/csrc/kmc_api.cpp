@@ -20,13 +20,13 @@ namespace kmc {
 hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
 hipError_t set_hop_lds_limit(size_t lds_bytes);
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
-                         hipStream_t st);
+                         const void *ea, bool fp64, hipStream_t st);
 hipError_t launch_export(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total,
                          hipStream_t st);
 hipError_t launch_place(int8_t *occ_pad, const DevInfo *devs, const int32_t *rail_dev, const int32_t *rail_idx,
                         const int32_t *n_ions, int n_rails_total, uint32_t key0, uint32_t key1, hipStream_t st);
-hipError_t launch_barrier_min(const void *ea, bool fp64, DevInfo *devs, int n_dev, unsigned long long *scratch,
-                              hipStream_t st);
+hipError_t launch_barrier_range(const void *ea, bool fp64, DevInfo *devs, int n_dev,
+                                unsigned long long *scratch, hipStream_t st);
 hipError_t launch_count_deciles(const int8_t *occ_pad, const DevInfo *devs, int n_dev, int64_t *dec_run,
                                 hipStream_t st);
 hipError_t launch_set_protocol(double *knot_t, double *knot_v, DevInfo *devs, int d0, int d1, int nk,
@@ -132,7 +132,7 @@ Layout layout_for(const kmc_params *p) {
     L.net_total = take(sizeof(int64_t) * D);
     L.log_count = take(sizeof(int64_t));
     L.log_entries = take(sizeof(kmc_log_entry) * kLogCap);
-    L.scratch = take(sizeof(unsigned long long) * D);
+    L.scratch = take(sizeof(unsigned long long) * 2 * D);
     L.rail_dev = take(sizeof(int32_t) * (size_t)rails);
     L.rail_idx = take(sizeof(int32_t) * (size_t)rails);
     L.n_ions = take(sizeof(int32_t) * D);
@@ -225,7 +225,10 @@ void make_tiles(kmc_ctx *c) {
         const DevInfo &dv = c->devs[t.d];
         const size_t rows = (size_t)(t.nr + 2 * c->p.rail_range) * dv.pitch;
         const size_t cap = (size_t)t.nr * dv.pitch / 2;
-        lds = std::max(lds, rows + 3 * cap * sizeof(uint32_t));
+        const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
+        const size_t kt = n_kt <= (size_t)kLdsTableMax ? n_kt * (c->fp64 ? sizeof(double) : sizeof(float)) : 0;
+        const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
+        lds = std::max(lds, rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt);
     }
     c->hop_lds = lds;
 }
@@ -401,10 +404,11 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
             "install 0 V protocol");
     }
     if (ea_dev)
-        chk(launch_barrier_min(ea_dev, c->fp64, c->at<DevInfo>(lay.devs), D, c->at<unsigned long long>(lay.scratch),
-                               st),
-            "barrier minimum");
-    chk(launch_import(occ_dev, c->cur, c->at<DevInfo>(lay.devs), D, lay.total_pad, st), "import occupancy");
+        chk(launch_barrier_range(ea_dev, c->fp64, c->at<DevInfo>(lay.devs), D,
+                                 c->at<unsigned long long>(lay.scratch), st),
+            "barrier range");
+    chk(launch_import(occ_dev, c->cur, c->at<DevInfo>(lay.devs), D, lay.total_pad, ea_dev, c->fp64, st),
+        "import occupancy");
     if (ok == KMC_OK) ok = after_state_change(c);
     if (ok != KMC_OK) {
         delete c;
@@ -439,7 +443,7 @@ kmc_status kmc_load_occupancy(kmc_ctx *c) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;
     KMC_HIP(c, launch_import(c->occ_user, c->cur, c->at<DevInfo>(c->lay.devs), c->p.n_devices, c->lay.total_pad,
-                             c->stream));
+                             c->ea, c->fp64, c->stream));
     return after_state_change(c);
 }
 

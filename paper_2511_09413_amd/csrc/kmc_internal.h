@@ -16,6 +16,8 @@ constexpr int kBlock = 256;              // threads per workgroup of the hop ker
 constexpr int kTileSites = 4096;         // default padded sites per hop-kernel tile
 constexpr int kTallySteps = 1024;        // steps per tally chunk
 constexpr int kDeciles = 10;
+constexpr int kClasses = 128;            // barrier classes in bits 1..7 of a state byte
+constexpr int kLdsTableMax = 2048;       // kernel-table entries kept in LDS
 
 // Per-device description, resident in the workspace.
 struct DevInfo {
@@ -25,6 +27,8 @@ struct DevInfo {
     int64_t off_pad;                     // padded offset (internal buffers)
     int64_t n_set;                       // step at which the protocol was installed
     double ea_min;                       // minimum barrier of the device, eV
+    double ea_step;                      // barrier class width: class q covers
+                                         // [ea_min + q*ea_step, ...), eV
     double coul_bound;                   // |dE_coul| <= coul_bound for any state, eV
     int32_t n_nbr;                       // distinct rail offsets (incl. 0)
     int8_t nbr_off[2 * kMaxRailRange + 1];   // rail offsets in [-m, m]

@@ -3,23 +3,28 @@
 // The hot kernel is hop_half_step: one launch decides every bond of one parity
 // (a half-step of the pair checkerboard) for every device, reading the state
 // at the start of the half-step from one buffer and writing the new state to
-// the other.  One workgroup owns whole rails of one device ("tile"):
-//   1. its rails plus the +-rail_range halo rails are staged in LDS with
-//      coalesced 16-byte loads of the int8 occupancy;
-//   2. every lane takes 16 sites of a rail, finds the candidate bonds (exactly
-//      one of the two sites occupied) and draws the bond's Philox4x32-10 word;
-//   3. an exact prefilter discards every candidate whose uniform is above a
-//      bound on its hop probability that holds for any configuration (the
-//      telescoping bound on the Coulomb term, the device's minimum barrier and
-//      the step's bias); the few survivors are queued in LDS;
+// the other.  One workgroup owns whole rails of one device ("tile"), one lane
+// owns 16 consecutive sites of a rail:
+//   1. the lane issues the coalesced 16-byte load of its int8 chunk (and of a
+//      chunk of the +-rail_range halo rails), then draws the two Philox4x32-10
+//      blocks of its bonds while the loads are in flight; the tile and halo are
+//      staged in LDS as the Jacobi snapshot;
+//   2. candidate bonds (exactly one of the two sites occupied) are found with
+//      bit operations on the 16 occupancy bits;
+//   3. an exact prefilter discards every candidate whose Philox word lies above
+//      a bound on its hop probability valid for any configuration (telescoping
+//      bound on the Coulomb term, a lower bound of the origin's barrier stored
+//      as a 7-bit class next to the occupancy bit, the step's bias); the few
+//      survivors are queued in LDS;
 //   4. survivors get the full energy change from the LDS window (bias drop plus
-//      screened Coulomb sum over the window, paper main text section 3 and SI
-//      Eq. S1), the Arrhenius probability with the half-energy barrier shift
-//      (main text Eq. hop_rate and Eq. 2), the accept test u < p and the
-//      near-threshold log;
-//   5. accepted hops are applied in LDS, tallied (net hops toward the grounded
-//      site 0, decile crossings) and the tile is written out.
+//      the screened Coulomb sum, paper main text section 3 and SI Eq. S1), the
+//      Arrhenius probability with the half-energy barrier shift (main text Eq.
+//      hop_rate and Eq. 2), the accept test u < p and the near-threshold log;
+//   5. accepted hops are tallied (net hops toward the grounded site 0, decile
+//      crossings), applied to the lanes' registers and the tile is written out.
 #include <math.h>
+
+#include <type_traits>
 
 #include "kmc_internal.h"
 
@@ -76,19 +81,6 @@ __device__ __forceinline__ int tile_of_block(int bid, int n_tiles) {
 }
 
 template <typename Real>
-__device__ __forceinline__ Real ktab(const HopArgs &a, int ds, int dist);
-template <>
-__device__ __forceinline__ double ktab<double>(const HopArgs &a, int ds, int dist) {
-    const int ad = ds < 0 ? -ds : ds;
-    return ad > a.cutoff ? 0.0 : a.ktab64[dist * (a.cutoff + 1) + ad];
-}
-template <>
-__device__ __forceinline__ float ktab<float>(const HopArgs &a, int ds, int dist) {
-    const int ad = ds < 0 ? -ds : ds;
-    return ad > a.cutoff ? 0.0f : a.ktab32[dist * (a.cutoff + 1) + ad];
-}
-
-template <typename Real>
 __device__ __forceinline__ Real exp_r(Real x);
 template <>
 __device__ __forceinline__ double exp_r<double>(double x) { return exp(x); }
@@ -103,18 +95,43 @@ template <>
 __device__ __forceinline__ float uniform_of<float>(uint32_t w) { return (float)w * 0x1p-32f; }
 
 struct HopShared {
-    int64_t n;
-    uint64_t w_thr;
     double V;
     int32_t n_surv, n_hop, n_down, n_up;
     int32_t dec[kDeciles];
+    uint32_t wtab[kClasses];  // inclusive Philox-word thresholds per barrier class
 };
 
+// occupancy bits (bit 0 of each byte) of a 16-byte chunk, site k -> bit k
+__device__ __forceinline__ uint32_t occ_bits(const uint4 &v) {
+    uint32_t bits = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bits |= (((word_of(v, b) & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << (4 * b);
+    return bits;
+}
+
+__device__ __forceinline__ uint32_t word_of8(const uint4 &A, const uint4 &B, int i) {
+    return i < 4 ? word_of(A, i) : word_of(B, i - 4);
+}
+
+__device__ __forceinline__ void flip_byte(uint4 &v, int b) {
+    const uint32_t m = 1u << (8 * (b & 3));
+    const int w = b >> 2;
+    if (w == 0) v.x ^= m;
+    else if (w == 1) v.y ^= m;
+    else if (w == 2) v.z ^= m;
+    else v.w ^= m;
+}
+
 // ------------------------------------------------------------------------
-// The half-step kernel.  H = bond parity.  Dynamic LDS layout:
-//   rows   [(nr + 2m) * pitch] int8 : tile rails and halo rails
+// The half-step kernel.  H = bond parity.  State bytes: bit 0 = occupied,
+// bits 1..7 = barrier class of the site (a lower bound of its barrier used only
+// by the prefilter).  One lane per 16-site chunk (a tile has at most kBlock
+// chunks).  Dynamic LDS layout:
+//   rows   [(nr + 2m) * pitch] bytes : tile rails and halo rails (snapshot)
 //   surv   [cap] uint32 (row << 13 | s), survw [cap] uint32 (Philox word)
 //   hops   [cap] uint32 (row << 13 | s)
+//   survea [cap] Real (barrier of the survivor's origin)
+//   ktab   [(m + 1) * (cutoff + 1)] Real, when small enough
 // ------------------------------------------------------------------------
 template <typename Real, int H>
 __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
@@ -127,26 +144,60 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     const int m = a.rail_range;
     const int p16 = pitch / kChunkSites;
     const int n_rows = tile.nr + 2 * m;
+    const int n_chunks = tile.nr * p16;
+    const int n_halo = 2 * m * p16;
     const int cap = tile.nr * pitch / 2;
     unsigned char *rows = smem;
     uint32_t *surv = reinterpret_cast<uint32_t *>(smem + n_rows * pitch);
     uint32_t *survw = surv + cap;
     uint32_t *hops = survw + cap;
+    Real *surv_ea = reinterpret_cast<Real *>(hops + cap + (cap & 1));
+    Real *kt_lds = surv_ea + cap;
+    const int kt_stride = a.cutoff + 1;
+    const int n_kt = (m + 1) * kt_stride;
+    const bool kt_in_lds = n_kt <= kLdsTableMax;
+    const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
+                                                            : reinterpret_cast<const Real *>(a.ktab32);
     const int tid = threadIdx.x;
+    const int64_t n = a.ctl->n_base + a.step_in_chunk;
+    const int8_t *src_dev = a.occ_in + dv.off_pad;
 
+    // 1. issue the loads of the lane's chunk and of one halo chunk
+    const bool has_chunk = tid < n_chunks;
+    const int row = has_chunk ? tid / p16 : 0;
+    const int s0 = (tid - row * p16) * kChunkSites;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    uint32_t nxt = 0;
+    if (has_chunk) {
+        const int8_t *rp = src_dev + (int64_t)(tile.r0 + row) * pitch;
+        v = *reinterpret_cast<const uint4 *>(rp + s0);
+        if (H == 1 && s0 + kChunkSites < pitch) nxt = (uint32_t)(uint8_t)rp[s0 + kChunkSites];
+    }
+    auto halo_lds_row = [&](int i) { const int hr = i / p16; return hr < m ? hr : hr + tile.nr; };
+    auto halo_src = [&](int i) {
+        const int lr = halo_lds_row(i);
+        int rail = tile.r0 - m + lr;
+        rail = ((rail % R) + R) % R;
+        return src_dev + (int64_t)rail * pitch + (i - (i / p16) * p16) * kChunkSites;
+    };
+    uint4 hv = make_uint4(0, 0, 0, 0);
+    if (tid < n_halo) hv = *reinterpret_cast<const uint4 *>(halo_src(tid));
+
+    // bias of this step and the prefilter thresholds per barrier class:
+    // dE >= -(|alpha V|/L + coul_bound) for every configuration and the
+    // barrier of a class-q site is >= ea_min + q*ea_step, so
+    // p <= pb(q) = nu0 dt exp(-beta (ea_min + q ea_step - (|alpha V|/L + coul_bound)/2)).
+    // pb is widened by 1e-3 relative and by twice the 1e-6 logging window: a
+    // word above the threshold can neither be accepted nor logged.
+    const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots, dv.n_knots,
+                                      (double)(n - dv.n_set) * a.dt);
+    if (tid < kClasses) {
+        const double field = fabs(a.alpha * V) / (double)L;
+        const double ea_lb = dv.ea_min + (double)tid * dv.ea_step;
+        const double pb = a.c0 * exp(-a.beta * (ea_lb - 0.5 * (field + dv.coul_bound))) * (1.0 + 1e-3) + 2e-6;
+        sh.wtab[tid] = pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
+    }
     if (tid == 0) {
-        const int64_t n = a.ctl->n_base + a.step_in_chunk;
-        const double t_rel = (double)(n - dv.n_set) * a.dt;
-        const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots,
-                                          a.knot_v + tile.d * kMaxKnots, dv.n_knots, t_rel);
-        // Exact prefilter bound: dE >= -(|alpha V|/L + coul_bound) for every
-        // configuration, Ea >= ea_min, so p <= pb.  Widened by 1e-3 relative
-        // and by twice the 1e-6 logging window; a draw u >= pb can neither be
-        // accepted nor logged.
-        const double arg = -a.beta * (dv.ea_min - 0.5 * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
-        const double pb = a.c0 * exp(arg) * (1.0 + 1e-3) + 2e-6;
-        sh.w_thr = pb >= 1.0 ? (uint64_t)1 << 32 : (uint64_t)ceil(pb * 4294967296.0);
-        sh.n = n;
         sh.V = V;
         sh.n_surv = 0;
         sh.n_hop = 0;
@@ -154,172 +205,154 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         sh.n_up = 0;
         for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
     }
+    if (kt_in_lds)
+        for (int i = tid; i < n_kt; i += kBlock) kt_lds[i] = kt_glob[i];
 
-    // 1. stage tile and halo rails (Jacobi snapshot) in LDS
-    const int8_t *src_dev = a.occ_in + dv.off_pad;
-    for (int i = tid; i < n_rows * p16; i += kBlock) {
-        const int row = i / p16, c16 = i - row * p16;
-        int rail = tile.r0 - m + row;
-        rail = ((rail % R) + R) % R;
-        const uint4 v = *reinterpret_cast<const uint4 *>(src_dev + (int64_t)rail * pitch + c16 * kChunkSites);
-        *reinterpret_cast<uint4 *>(rows + row * pitch + c16 * kChunkSites) = v;
-    }
+    // 2. the two Philox blocks of the chunk (independent of the state)
+    const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)H;
+    const uint32_t rail = (uint32_t)(tile.r0 + row);
+    const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
+    const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
+
+    // stage the Jacobi snapshot in LDS
+    if (has_chunk) *reinterpret_cast<uint4 *>(rows + (m + row) * pitch + s0) = v;
+    if (tid < n_halo)
+        *reinterpret_cast<uint4 *>(rows + halo_lds_row(tid) * pitch + (tid - (tid / p16) * p16) * kChunkSites) = hv;
+    for (int i = tid + kBlock; i < n_halo; i += kBlock)
+        *reinterpret_cast<uint4 *>(rows + halo_lds_row(i) * pitch + (i - (i / p16) * p16) * kChunkSites) =
+            *reinterpret_cast<const uint4 *>(halo_src(i));
     __syncthreads();
 
-    const int64_t n = sh.n;
-    const uint64_t w_thr = sh.w_thr;
-    const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)H;
-
-    // 2-3. candidates, Philox words, exact prefilter
-    for (int i = tid; i < tile.nr * p16; i += kBlock) {
-        const int row = i / p16, c16 = i - row * p16;
-        const int s0 = c16 * kChunkSites;
-        const unsigned char *rp = rows + (m + row) * pitch;
-        const uint4 v = *reinterpret_cast<const uint4 *>(rp + s0);
-        const uint32_t nxt = (s0 + kChunkSites < pitch) ? rp[s0 + kChunkSites] : 0u;
-        // occupancy bits of sites s0 .. s0+16
-        uint32_t bits = 0;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const uint32_t wv = word_of(v, b);
-            bits |= ((wv & 1u) | ((wv >> 7) & 2u) | ((wv >> 14) & 4u) | ((wv >> 21) & 8u)) << (4 * b);
-        }
-        bits |= (nxt & 1u) << 16;
+    // 3. candidates and the exact two-stage prefilter
+    uint32_t bits = 0;
+    if (has_chunk) {
+        bits = occ_bits(v) | ((nxt & 1u) << 16);
         uint32_t cand = (bits ^ (bits >> 1)) & (H ? 0xAAAAu : 0x5555u);
         const int last = L - 2 - s0;  // bond (s0+k, s0+k+1) exists iff k <= last
         if (last < 15) cand &= last < 0 ? 0u : ((2u << last) - 1u);
-        if (cand == 0) continue;
-        const uint32_t rail = (uint32_t)(tile.r0 + row);
-        uint32_t surv_mask = 0;
-        if (cand & 0x00FFu) {
-            const uint4 blk = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
+        const uint32_t thr0 = sh.wtab[0];  // the largest threshold (lowest class)
+        uint32_t sv = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int bit = H + 2 * j;
-                if (((cand >> bit) & 1u) && (uint64_t)word_of(blk, j) < w_thr) surv_mask |= 1u << bit;
-            }
-            if (surv_mask & 0x00FFu) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int bit = H + 2 * j;
-                    if ((surv_mask >> bit) & 1u) {
-                        const int k = atomicAdd(&sh.n_surv, 1);
-                        surv[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
-                        survw[k] = word_of(blk, j);
-                    }
-                }
-            }
+        for (int j = 0; j < 4; ++j) {
+            const int bit = H + 2 * j;
+            if (((cand >> bit) & 1u) && word_of(blkA, j) <= thr0) sv |= 1u << bit;
         }
-        if (cand & 0xFF00u) {
-            const uint4 blk = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
-            uint32_t sm = 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int bit = 8 + H + 2 * j;
-                if (((cand >> bit) & 1u) && (uint64_t)word_of(blk, j) < w_thr) sm |= 1u << bit;
-            }
-            if (sm) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int bit = 8 + H + 2 * j;
-                    if ((sm >> bit) & 1u) {
-                        const int k = atomicAdd(&sh.n_surv, 1);
-                        surv[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
-                        survw[k] = word_of(blk, j);
-                    }
+        for (int j = 0; j < 4; ++j) {
+            const int bit = 8 + H + 2 * j;
+            if (((cand >> bit) & 1u) && word_of(blkB, j) <= thr0) sv |= 1u << bit;
+        }
+        if (sv) {  // rare: compare with the threshold of the origin's class
+            while (sv) {
+                const int bit = __builtin_ctz(sv);
+                sv &= sv - 1;
+                const int ob = ((bits >> bit) & 1u) ? bit : bit + 1;   // origin byte in the chunk
+                const uint32_t obyte = ob < kChunkSites ? (word_of(v, ob >> 2) >> (8 * (ob & 3))) & 0xFFu : nxt;
+                const uint32_t w = word_of8(blkA, blkB, bit >> 1);
+                if (w <= sh.wtab[obyte >> 1]) {
+                    const int s = s0 + bit;
+                    const int k = atomicAdd(&sh.n_surv, 1);
+                    surv[k] = ((uint32_t)row << 13) | (uint32_t)s;
+                    survw[k] = w;
+                    Real ea;
+                    if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)(tile.r0 + row) * L + s0 + ob];
+                    else ea = (Real)a.ea_scalar;
+                    surv_ea[k] = ea;
                 }
             }
         }
     }
     __syncthreads();
 
-    // 4. full evaluation of the survivors
+    // 4. full evaluation of the survivors, one wavefront per survivor: every
+    //    lane sums a strided subset of the window terms in a fixed order, a
+    //    butterfly reduction combines the lanes (the same order on every run).
     const int n_surv = sh.n_surv;
     if (n_surv > 0) {
         const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
         const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
-        for (int i = tid; i < n_surv; i += kBlock) {
-            const int row = (int)(surv[i] >> 13), s = (int)(surv[i] & 8191u);
-            const uint32_t w = survw[i];
-            const unsigned char *rp = rows + (m + row) * pitch;
-            const int o = rp[s] ? s : s + 1;
-            const int t = rp[s] ? s + 1 : s;
-            const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+        const Real *kt = kt_in_lds ? kt_lds : kt_glob;
+        const int lane = tid & 63, wave = tid >> 6;
+        for (int i = wave; i < n_surv; i += kBlock / 64) {
+            const int srow = (int)(surv[i] >> 13), s = (int)(surv[i] & 8191u);
+            const unsigned char *rp = rows + (m + srow) * pitch;
+            const int o = (rp[s] & 1) ? s : s + 1;
+            const int t = (rp[s] & 1) ? s + 1 : s;
             int lo = s - a.cutoff, hi = s + 1 + a.cutoff;
             lo = lo < 0 ? 0 : lo;
             hi = hi > L - 1 ? L - 1 : hi;
-            Real e_coul = (Real)0;
+            Real part = (Real)0;
             for (int k = 0; k < dv.n_nbr; ++k) {
-                const int off = dv.nbr_off[k], dist = dv.nbr_dist[k];
-                const unsigned char *nr_ = rows + (m + row + off) * pitch;
-                for (int j = lo; j <= hi; ++j) {
-                    if (off == 0 && (j == o || j == t)) continue;
-                    if (!nr_[j]) continue;
-                    const Real kt = ktab<Real>(a, t - j, dist);
-                    const Real ko = ktab<Real>(a, o - j, dist);
-                    e_coul += kt - ko;
+                const int off = dv.nbr_off[k];
+                const Real *ktr = kt + dv.nbr_dist[k] * kt_stride;
+                const unsigned char *nrow = rows + (m + srow + off) * pitch;
+                for (int j = lo + lane; j <= hi; j += 64) {
+                    int occ = nrow[j] & 1;
+                    if (off == 0 && (j == o || j == t)) occ = 0;
+                    const int dt_ = t - j < 0 ? j - t : t - j;
+                    const int do_ = o - j < 0 ? j - o : o - j;
+                    const Real kt_v = dt_ > a.cutoff ? (Real)0 : ktr[dt_];
+                    const Real ko_v = do_ > a.cutoff ? (Real)0 : ktr[do_];
+                    part += occ ? (kt_v - ko_v) : (Real)0;
                 }
             }
-            const Real dE = e_app + e_coul;
-            const int rail = tile.r0 + row;
-            Real ea;
-            if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)rail * L + o];
-            else ea = (Real)a.ea_scalar;
-            Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
-            p = p < (Real)1 ? p : (Real)1;
-            const Real u = uniform_of<Real>(w);
-            const Real gap = u - p;
-            if ((gap < 0 ? -gap : gap) < (Real)1e-6) {
-                const int64_t k = atomicAdd(reinterpret_cast<unsigned long long *>(a.log.count), 1ull);
-                if (k < a.log.cap) {
-                    unsigned char *e = reinterpret_cast<unsigned char *>(a.log.entries) + 40 * k;
-                    *reinterpret_cast<int32_t *>(e + 0) = tile.d;
-                    *reinterpret_cast<int32_t *>(e + 4) = H;
-                    *reinterpret_cast<int64_t *>(e + 8) = n;
-                    *reinterpret_cast<int32_t *>(e + 16) = rail;
-                    *reinterpret_cast<int32_t *>(e + 20) = s;
-                    *reinterpret_cast<double *>(e + 24) = (double)u;
-                    *reinterpret_cast<double *>(e + 32) = (double)p;
+#pragma unroll
+            for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
+            if (lane == 0) {
+                const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+                const Real dE = e_app + part;
+                const Real ea = surv_ea[i];
+                Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+                p = p < (Real)1 ? p : (Real)1;
+                const Real u = uniform_of<Real>(survw[i]);
+                const Real gap = u - p;
+                const int srail = tile.r0 + srow;
+                if ((gap < 0 ? -gap : gap) < (Real)1e-6) {
+                    const int64_t k = atomicAdd(reinterpret_cast<unsigned long long *>(a.log.count), 1ull);
+                    if (k < a.log.cap) {
+                        unsigned char *e = reinterpret_cast<unsigned char *>(a.log.entries) + 40 * k;
+                        *reinterpret_cast<int32_t *>(e + 0) = tile.d;
+                        *reinterpret_cast<int32_t *>(e + 4) = H;
+                        *reinterpret_cast<int64_t *>(e + 8) = n;
+                        *reinterpret_cast<int32_t *>(e + 16) = srail;
+                        *reinterpret_cast<int32_t *>(e + 20) = s;
+                        *reinterpret_cast<double *>(e + 24) = (double)u;
+                        *reinterpret_cast<double *>(e + 32) = (double)p;
+                    }
                 }
-            }
-            if (u < p) {
-                const int k = atomicAdd(&sh.n_hop, 1);
-                hops[k] = ((uint32_t)row << 13) | (uint32_t)s;
-                if (t < o) atomicAdd(&sh.n_down, 1);
-                else atomicAdd(&sh.n_up, 1);
-                const int qo = (10 * o) / L, qt = (10 * t) / L;
-                if (qo != qt) {
-                    atomicAdd(&sh.dec[qo], -1);
-                    atomicAdd(&sh.dec[qt], 1);
+                if (u < p) {
+                    const int k = atomicAdd(&sh.n_hop, 1);
+                    hops[k] = ((uint32_t)srow << 13) | (uint32_t)s;
+                    if (t < o) atomicAdd(&sh.n_down, 1);
+                    else atomicAdd(&sh.n_up, 1);
+                    const int qo = (10 * o) / L, qt = (10 * t) / L;
+                    if (qo != qt) {
+                        atomicAdd(&sh.dec[qo], -1);
+                        atomicAdd(&sh.dec[qt], 1);
+                    }
                 }
             }
         }
         __syncthreads();
-
-        // 5a. apply accepted hops to the tile rows, push the tallies
-        const int n_hop = sh.n_hop;
-        for (int i = tid; i < n_hop; i += kBlock) {
-            const int row = (int)(hops[i] >> 13), s = (int)(hops[i] & 8191u);
-            unsigned char *rp = rows + (m + row) * pitch;
-            rp[s] ^= 1;
-            rp[s + 1] ^= 1;
-        }
-        if (tid == 0 && n_hop > 0) {
+        if (tid == 0 && sh.n_hop > 0) {
             const int64_t k = n - a.ctl->tally_base;
             const int64_t base = k * a.n_devices + tile.d;
             atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
             for (int q = 0; q < kDeciles; ++q)
                 if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);
         }
-        __syncthreads();
     }
 
-    // 5b. write the tile
-    int8_t *dst_dev = a.occ_out + dv.off_pad;
-    for (int i = tid; i < tile.nr * p16; i += kBlock) {
-        const int row = i / p16, c16 = i - row * p16;
-        const uint4 v = *reinterpret_cast<const uint4 *>(rows + (m + row) * pitch + c16 * kChunkSites);
-        *reinterpret_cast<uint4 *>(dst_dev + (int64_t)(tile.r0 + row) * pitch + c16 * kChunkSites) = v;
+    // 5. apply the accepted hops that touch the lane's chunk, write it out
+    if (has_chunk) {
+        const int n_hop = sh.n_hop;
+        for (int k = 0; k < n_hop; ++k) {
+            const int hr = (int)(hops[k] >> 13), hs = (int)(hops[k] & 8191u);
+            if (hr != row) continue;
+            if (hs >= s0 && hs < s0 + kChunkSites) flip_byte(v, hs - s0);
+            if (hs + 1 >= s0 && hs + 1 < s0 + kChunkSites) flip_byte(v, hs + 1 - s0);
+        }
+        *reinterpret_cast<uint4 *>(a.occ_out + dv.off_pad + (int64_t)(tile.r0 + row) * pitch + s0) = v;
     }
 }
 
@@ -327,10 +360,12 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
 // Bookkeeping kernels
 // ------------------------------------------------------------------------
 
-// Caller layout -> padded internal layout, values normalised to 0/1 and the
-// padding bytes cleared.  One thread per padded byte.
+// Caller layout -> padded internal layout: bit 0 = occupied (any nonzero
+// byte), bits 1..7 = barrier class floor((Ea - ea_min)/ea_step) clamped to
+// [0, 127] (0 without a barrier field); padding bytes cleared.
+template <typename Real>
 __global__ void import_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
-                                 int64_t total_pad) {
+                                 int64_t total_pad, const Real *ea) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total_pad) return;
     int d = 0;
@@ -338,7 +373,17 @@ __global__ void import_occupancy(const int8_t *src, int8_t *dst, const DevInfo *
     const DevInfo &dv = devs[d];
     const int64_t loc = i - dv.off_pad;
     const int r = (int)(loc / dv.pitch), s = (int)(loc - (int64_t)r * dv.pitch);
-    dst[i] = (s < dv.sites) ? (src[dv.off + (int64_t)r * dv.sites + s] != 0 ? 1 : 0) : 0;
+    int8_t val = 0;
+    if (s < dv.sites) {
+        const int64_t at = dv.off + (int64_t)r * dv.sites + s;
+        int cls = 0;
+        if (ea && dv.ea_step > 0.0) {
+            const double q = floor(((double)ea[at] - dv.ea_min) / dv.ea_step);
+            cls = q < 0.0 ? 0 : (q > (double)(kClasses - 1) ? kClasses - 1 : (int)q);
+        }
+        val = (int8_t)((cls << 1) | (src[at] != 0 ? 1 : 0));
+    }
+    dst[i] = val;
 }
 
 __global__ void export_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
@@ -350,7 +395,7 @@ __global__ void export_occupancy(const int8_t *src, int8_t *dst, const DevInfo *
     const DevInfo &dv = devs[d];
     const int64_t loc = i - dv.off;
     const int r = (int)(loc / dv.sites), s = (int)(loc - (int64_t)r * dv.sites);
-    dst[i] = src[dv.off_pad + (int64_t)r * dv.pitch + s];
+    dst[i] = src[dv.off_pad + (int64_t)r * dv.pitch + s] & 1;
 }
 
 // Random placement: floor(f L + 1/2) ions on the sites with the smallest
@@ -370,15 +415,11 @@ __global__ __launch_bounds__(256) void place_ions(int8_t *occ_pad, const DevInfo
     }
     __syncthreads();
     int8_t *row = occ_pad + dv.off_pad + (int64_t)r * dv.pitch;
-    for (int s = threadIdx.x; s < dv.pitch; s += blockDim.x) {
-        int8_t val = 0;
-        if (s < L) {
-            const uint64_t ks = keys[s];
-            int rank = 0;
-            for (int q = 0; q < L; ++q) rank += keys[q] < ks ? 1 : 0;
-            val = rank < nion ? 1 : 0;
-        }
-        row[s] = val;
+    for (int s = threadIdx.x; s < L; s += blockDim.x) {
+        const uint64_t ks = keys[s];
+        int rank = 0;
+        for (int q = 0; q < L; ++q) rank += keys[q] < ks ? 1 : 0;
+        row[s] = (int8_t)((row[s] & ~1) | (rank < nion ? 1 : 0));
     }
 }
 
@@ -389,25 +430,35 @@ __device__ __forceinline__ unsigned long long order_key(double x) {
 }
 
 template <typename Real>
-__global__ void barrier_min(const Real *ea, const DevInfo *devs, unsigned long long *out) {
+__global__ void barrier_range(const Real *ea, const DevInfo *devs, unsigned long long *kmin,
+                              unsigned long long *kmax) {
     const int d = blockIdx.y;
     const DevInfo &dv = devs[d];
     const int64_t cnt = (int64_t)dv.rails * dv.sites;
-    unsigned long long best = ~0ull;
+    unsigned long long lo = ~0ull, hi = 0ull;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
          i += (int64_t)gridDim.x * blockDim.x) {
         const unsigned long long k = order_key((double)ea[dv.off + i]);
-        best = k < best ? k : best;
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
     }
-    atomicMin(&out[d], best);
+    atomicMin(&kmin[d], lo);
+    atomicMax(&kmax[d], hi);
 }
 
-__global__ void barrier_min_finish(const unsigned long long *keys, DevInfo *devs, int n_dev) {
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// ea_min and the class width ea_step = (ea_max - ea_min)/127 of every device.
+__global__ void barrier_range_finish(const unsigned long long *kmin, const unsigned long long *kmax,
+                                     DevInfo *devs, int n_dev) {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= n_dev) return;
-    const unsigned long long k = keys[d];
-    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
-    devs[d].ea_min = __longlong_as_double((long long)b);
+    const double lo = key_value(kmin[d]), hi = key_value(kmax[d]);
+    devs[d].ea_min = lo;
+    devs[d].ea_step = hi > lo ? (hi - lo) / (double)(kClasses - 1) : 0.0;
 }
 
 // Decile counts of the current state (int64), one workgroup per device.
@@ -421,7 +472,7 @@ __global__ void count_deciles(const int8_t *occ_pad, const DevInfo *devs, int64_
     int local[kDeciles] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int64_t i = threadIdx.x; i < total; i += blockDim.x) {
         const int s = (int)(i % dv.pitch);
-        if (s < dv.sites && occ_pad[dv.off_pad + i]) local[(10 * s) / dv.sites] += 1;
+        if (s < dv.sites && (occ_pad[dv.off_pad + i] & 1)) local[(10 * s) / dv.sites] += 1;
     }
     for (int q = 0; q < kDeciles; ++q)
         if (local[q]) atomicAdd(&cnt[q], local[q]);
@@ -557,9 +608,12 @@ hipError_t set_hop_lds_limit(size_t lds_bytes) {
 }
 
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(import_occupancy, dim3(grid_for(total_pad, 256)), dim3(256), 0, st, src, dst, devs,
-                       n_dev, total_pad);
+                         const void *ea, bool fp64, hipStream_t st) {
+    const dim3 grid(grid_for(total_pad, 256)), block(256);
+    if (fp64) hipLaunchKernelGGL((import_occupancy<double>), grid, block, 0, st, src, dst, devs, n_dev, total_pad,
+                                 (const double *)ea);
+    else hipLaunchKernelGGL((import_occupancy<float>), grid, block, 0, st, src, dst, devs, n_dev, total_pad,
+                            (const float *)ea);
     return hipGetLastError();
 }
 
@@ -577,13 +631,15 @@ hipError_t launch_place(int8_t *occ_pad, const DevInfo *devs, const int32_t *rai
     return hipGetLastError();
 }
 
-hipError_t launch_barrier_min(const void *ea, bool fp64, DevInfo *devs, int n_dev, unsigned long long *scratch,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(fill_u64, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, scratch, (int64_t)n_dev, ~0ull);
+hipError_t launch_barrier_range(const void *ea, bool fp64, DevInfo *devs, int n_dev,
+                                unsigned long long *scratch, hipStream_t st) {
+    unsigned long long *kmin = scratch, *kmax = scratch + n_dev;
+    hipLaunchKernelGGL(fill_u64, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, kmin, (int64_t)n_dev, ~0ull);
+    hipLaunchKernelGGL(fill_u64, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, kmax, (int64_t)n_dev, 0ull);
     const dim3 grid(64, n_dev);
-    if (fp64) hipLaunchKernelGGL((barrier_min<double>), grid, dim3(256), 0, st, (const double *)ea, devs, scratch);
-    else hipLaunchKernelGGL((barrier_min<float>), grid, dim3(256), 0, st, (const float *)ea, devs, scratch);
-    hipLaunchKernelGGL(barrier_min_finish, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, scratch, devs, n_dev);
+    if (fp64) hipLaunchKernelGGL((barrier_range<double>), grid, dim3(256), 0, st, (const double *)ea, devs, kmin, kmax);
+    else hipLaunchKernelGGL((barrier_range<float>), grid, dim3(256), 0, st, (const float *)ea, devs, kmin, kmax);
+    hipLaunchKernelGGL(barrier_range_finish, dim3(grid_for(n_dev, 256)), dim3(256), 0, st, kmin, kmax, devs, n_dev);
     return hipGetLastError();
 }
 
