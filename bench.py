@@ -31,6 +31,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent"])
+    ap.add_argument("--tile-sites", type=int, default=0)
     return ap.parse_args()
 
 
@@ -63,7 +65,8 @@ def main():
 
     wl = c2_large_device(n_steps=100_000)
     dev = torch.device("cuda:0")
-    sim = kmc.Simulator(wl.physics, wl.rails, wl.sites, ea=wl.ea_site, device="cuda:0")
+    sim = kmc.Simulator(wl.physics, wl.rails, wl.sites, ea=wl.ea_site, device="cuda:0", mode=args.mode,
+                        tile_sites=args.tile_sites)
     sim.fill_random(wl.filling)
     sim.set_protocols(wl.protocols)
     sim.run_steps(args.warmup)
@@ -107,6 +110,7 @@ def main():
         "effective_hbm_gbs": eff_gbs,
         "wall_s": wall,
         "net_hops_total": int(tot[0]),
+        "launch_mode": sim.launch_mode,
         "roofline": {"bound": "hbm", "achieved": bytes_per_site_update / 2 * sites / per_launch_s / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bytes_per_site_update / 2 * sites / per_launch_s / 1e9 / HBM_PEAK_GBS,

@@ -153,6 +153,28 @@ kmc_status kmc_read_current(kmc_ctx *ctx, double *mean_current_A, int64_t *net_h
 kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t cap,
                                   int64_t *n_events);
 
+/* Launch strategy of kmc_run_steps.
+ *   KMC_LAUNCH_HALF_STEP: one kernel launch per half-step; the state makes a
+ *     round trip through device memory every half-step.  Always available.
+ *   KMC_LAUNCH_PERSISTENT: one launch per chunk of up to 1024 steps; every
+ *     workgroup keeps its tile of rails in LDS and exchanges only its edge
+ *     rails with its two neighbouring tiles.  Needs the whole tiling
+ *     co-resident on the GPU (lattices up to tens of MB).
+ *   KMC_LAUNCH_AUTO (default): persistent when it fits, else half-step.
+ * Both give bit-identical trajectories. */
+typedef enum { KMC_LAUNCH_AUTO = 0, KMC_LAUNCH_HALF_STEP = 1, KMC_LAUNCH_PERSISTENT = 2 } kmc_launch_mode;
+
+/* Select the launch strategy; KMC_EUNSUPPORTED if PERSISTENT does not fit. */
+kmc_status kmc_set_launch_mode(kmc_ctx *ctx, int32_t mode);
+
+/* The strategy kmc_run_steps will use now (HALF_STEP or PERSISTENT). */
+kmc_status kmc_get_launch_mode(kmc_ctx *ctx, int32_t *mode);
+
+/* Target number of (padded) sites per workgroup tile, 0 = built-in default,
+ * else in [16, 65536]; tiles are whole rails.  Used by the autotuner.  Waits
+ * for the work already enqueued.  Trajectories do not depend on it. */
+kmc_status kmc_set_tile_sites(kmc_ctx *ctx, int32_t sites);
+
 /* Current step counter. */
 kmc_status kmc_get_step(kmc_ctx *ctx, int64_t *step);
 

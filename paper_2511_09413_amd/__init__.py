@@ -21,6 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_build", "libkmc.so")
 
 KMC_OK, KMC_EINVAL, KMC_EUNSUPPORTED, KMC_EHIP, KMC_ESTATE, KMC_ETOOSMALL = 0, -1, -2, -3, -4, -5
+LAUNCH_MODES = {"auto": 0, "half_step": 1, "persistent": 2}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
                       ("s", np.int32), ("u", np.float64), ("p", np.float64)])
@@ -62,12 +63,16 @@ def lib():
         L.kmc_read_current.argtypes = [vp, P(C.c_double), P(C.c_int64), P(C.c_double)]
         L.kmc_read_threshold_log.argtypes = [vp, vp, C.c_int64, P(C.c_int64)]
         L.kmc_get_step.argtypes = [vp, P(C.c_int64)]
+        L.kmc_set_launch_mode.argtypes = [vp, C.c_int32]
+        L.kmc_get_launch_mode.argtypes = [vp, P(C.c_int32)]
+        L.kmc_set_tile_sites.argtypes = [vp, C.c_int32]
         L.kmc_last_error.restype = C.c_char_p
         L.kmc_destroy.argtypes = [vp]
         L.kmc_destroy.restype = None
         for name in ("kmc_workspace_bytes", "kmc_init_device", "kmc_fill_random", "kmc_load_occupancy",
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
-                     "kmc_read_threshold_log", "kmc_get_step"):
+                     "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
+                     "kmc_set_tile_sites"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -154,6 +159,20 @@ def get_step(ctx: int) -> int:
     return int(n.value)
 
 
+def set_launch_mode(ctx: int, mode: str) -> None:
+    _check(lib().kmc_set_launch_mode(C.c_void_p(ctx), LAUNCH_MODES[mode]))
+
+
+def get_launch_mode(ctx: int) -> str:
+    m = C.c_int32(0)
+    _check(lib().kmc_get_launch_mode(C.c_void_p(ctx), C.byref(m)))
+    return {v: k for k, v in LAUNCH_MODES.items()}[int(m.value)]
+
+
+def set_tile_sites(ctx: int, sites: int) -> None:
+    _check(lib().kmc_set_tile_sites(C.c_void_p(ctx), sites))
+
+
 def destroy(ctx: int) -> None:
     lib().kmc_destroy(C.c_void_p(ctx))
 
@@ -164,7 +183,7 @@ class Simulator:
     workspace) on one GPU and the current torch stream."""
 
     def __init__(self, physics, rails: Sequence[int], sites: Sequence[int], occ=None, ea=None,
-                 device: str = "cuda:0"):
+                 device: str = "cuda:0", mode: str = "auto", tile_sites: int = 0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -193,6 +212,10 @@ class Simulator:
             self.ctx = init_device(self._params, self.occ.data_ptr(),
                                    self.ea.data_ptr() if self.ea is not None else None,
                                    self._ws_ptr, nbytes, self.stream.cuda_stream)
+        if tile_sites:
+            set_tile_sites(self.ctx, tile_sites)
+        if mode != "auto":
+            set_launch_mode(self.ctx, mode)
 
     def fill_random(self, filling: Sequence[float]) -> None:
         fill_random(self.ctx, filling)
@@ -227,6 +250,16 @@ class Simulator:
 
     def read_threshold_log(self, cap: int = 65536):
         return read_threshold_log(self.ctx, cap)
+
+    @property
+    def launch_mode(self) -> str:
+        return get_launch_mode(self.ctx)
+
+    def set_launch_mode(self, mode: str) -> None:
+        set_launch_mode(self.ctx, mode)
+
+    def set_tile_sites(self, sites: int) -> None:
+        set_tile_sites(self.ctx, sites)
 
     @property
     def step(self) -> int:

@@ -35,6 +35,8 @@ hipError_t launch_begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out, hipSt
 hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec, int64_t *dec_run,
                                int64_t *net_total, int n_dev, int steps, hipStream_t st);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
+hipError_t launch_persistent(const PArgs &a, int block, size_t lds, bool fp64, hipStream_t st);
+hipError_t persistent_capacity(int block, size_t lds, bool fp64, int *blocks_per_cu);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t st);
 }  // namespace kmc
 
@@ -50,13 +52,17 @@ kmc_status fail(kmc_status s, const std::string &msg) {
 }
 
 constexpr int64_t kLogCap = 65536;
+constexpr int64_t kMaxPTiles = 2048;
 constexpr double kElementaryCharge = 1.602176634e-19;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
-        net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, total;
+        net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, progress, pub, status,
+        total;
+    int64_t max_ptiles, pub_stride;  // persistent kernel: tile capacity, publication words per tile
+    int max_pitch;
     int64_t total_sites, total_pad, rails_total;
     int cut;  // interaction table cutoff actually stored
 };
@@ -136,6 +142,18 @@ Layout layout_for(const kmc_params *p) {
     L.rail_dev = take(sizeof(int32_t) * (size_t)rails);
     L.rail_idx = take(sizeof(int32_t) * (size_t)rails);
     L.n_ions = take(sizeof(int32_t) * D);
+    // persistent kernel: tiles, progress counters (one cache line each) and the
+    // edge-rail publication rings, capped at 64 MiB
+    int max_pitch = 0;
+    for (int d = 0; d < D; ++d) max_pitch = std::max(max_pitch, (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites);
+    L.max_pitch = max_pitch;
+    L.pub_stride = (int64_t)kRing * 2 * std::max(m, 1) * max_pitch / 8;
+    const int64_t pub_cap = ((int64_t)64 << 20) / (8 * L.pub_stride);
+    L.max_ptiles = std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap);
+    L.ptiles = take(sizeof(PTile) * (size_t)L.max_ptiles);
+    L.progress = take(sizeof(uint64_t) * 8 * (size_t)L.max_ptiles);
+    L.pub = take(sizeof(uint64_t) * (size_t)(L.pub_stride * L.max_ptiles));
+    L.status = take(sizeof(int32_t) * 4);
     L.total = off;
     return L;
 }
@@ -167,6 +185,13 @@ struct kmc_ctx {
     int64_t steps_run = 0;    // steps since init (for the mean current)
     size_t hop_lds = 0;
     int8_t *cur = nullptr, *nxt = nullptr;
+    int tile_sites = 0;                // target padded sites per tile (0 = default)
+    std::vector<PTile> ptiles;         // persistent tiling
+    int p_block = 0;
+    size_t p_lds = 0;
+    bool p_ok = false;                 // persistent tiling fits co-resident on this GPU
+    int mode = 0;                      // KMC_LAUNCH_AUTO / _HALF_STEP / _PERSISTENT
+    uint64_t epoch = 0;
 
     template <typename T>
     T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -214,9 +239,10 @@ void neighbour_offsets(int R, int m, DevInfo &dv) {
 // Tiles of whole rails, about kTileSites padded sites each.
 void make_tiles(kmc_ctx *c) {
     c->tiles.clear();
+    const int target = c->tile_sites > 0 ? std::min(c->tile_sites, kTileSites) : kTileSites;
     for (int d = 0; d < c->p.n_devices; ++d) {
         const DevInfo &dv = c->devs[d];
-        int nr = std::max(1, kTileSites / dv.pitch);
+        int nr = std::max(1, target / dv.pitch);
         nr = std::min(nr, dv.rails);
         for (int r0 = 0; r0 < dv.rails; r0 += nr) c->tiles.push_back(Tile{d, r0, std::min(nr, dv.rails - r0), 0});
     }
@@ -231,6 +257,54 @@ void make_tiles(kmc_ctx *c) {
         lds = std::max(lds, rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt);
     }
     c->hop_lds = lds;
+}
+
+// Persistent tiling: every device cut into n_t >= 1 tiles of consecutive rails,
+// sizes within one rail of each other and at least max(rail_range, 1) rails
+// unless the device is a single tile; prev/next are the cyclic neighbours.
+void make_ptiles(kmc_ctx *c) {
+    c->ptiles.clear();
+    const int m = std::max(c->p.rail_range, 1);
+    const int target = c->tile_sites > 0 ? c->tile_sites : 8192;
+    int max_chunks = 0;
+    size_t lds = 0;
+    const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
+    const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
+    const size_t kt = n_kt <= (size_t)kLdsTableMax ? n_kt * real : 0;
+    for (int d = 0; d < c->p.n_devices; ++d) {
+        const DevInfo &dv = c->devs[d];
+        const int want = std::max(m, target / dv.pitch);
+        int n_t = std::max(1, dv.rails / want);
+        if (n_t > 1 && dv.rails / n_t < m) n_t = 1;
+        const int first = (int)c->ptiles.size();
+        const int base = dv.rails / n_t, extra = dv.rails % n_t;
+        int r0 = 0;
+        for (int i = 0; i < n_t; ++i) {
+            const int nr = base + (i < extra ? 1 : 0);
+            const int prev = first + (i + n_t - 1) % n_t, next = first + (i + 1) % n_t;
+            c->ptiles.push_back(PTile{d, r0, nr, prev, next, 0});
+            r0 += nr;
+            max_chunks = std::max(max_chunks, nr * dv.pitch / kChunkSites);
+            const size_t cap = (size_t)nr * dv.pitch / 2;
+            lds = std::max(lds, 2 * (size_t)nr * dv.pitch + cap * (2 * sizeof(uint32_t) + real) + kt);
+        }
+    }
+    c->p_block = std::min(kPMaxBlock, (max_chunks + 63) / 64 * 64);
+    c->p_lds = lds;
+    c->p_ok = false;
+    if ((int64_t)c->ptiles.size() > c->lay.max_ptiles || lds > 160 * 1024) return;
+    int per_cu = 0, dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
+    if (persistent_capacity(c->p_block, lds, c->fp64, &per_cu) != hipSuccess) return;
+    c->p_ok = (int64_t)per_cu * prop.multiProcessorCount >= (int64_t)c->ptiles.size();
+}
+
+bool use_persistent(const kmc_ctx *c) {
+    if (c->mode == 1) return false;
+    if (c->mode == 2) return c->p_ok;
+    // automatic: persistent whenever the whole lattice fits co-resident in LDS
+    return c->p_ok;
 }
 
 kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
@@ -260,10 +334,47 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
     a.log.count = c->at<int64_t>(c->lay.log_count);
     a.log.entries = c->ws + c->lay.log_entries;
     a.log.cap = kLogCap;
+    const bool persistent = use_persistent(c);
+    PArgs pa{};
+    if (persistent) {
+        pa.occ = c->cur;
+        pa.devs = a.devs;
+        pa.tiles = c->at<PTile>(c->lay.ptiles);
+        pa.n_tiles = (int32_t)c->ptiles.size();
+        pa.knot_t = a.knot_t;
+        pa.knot_v = a.knot_v;
+        pa.ea = a.ea;
+        pa.ktab64 = a.ktab64;
+        pa.ktab32 = a.ktab32;
+        pa.cutoff = a.cutoff;
+        pa.rail_range = a.rail_range;
+        pa.ea_scalar = a.ea_scalar;
+        pa.beta = a.beta;
+        pa.c0 = a.c0;
+        pa.alpha = a.alpha;
+        pa.dt = a.dt;
+        pa.key0 = a.key0;
+        pa.key1 = a.key1;
+        pa.ctl = a.ctl;
+        pa.tally_net = a.tally_net;
+        pa.tally_dec = a.tally_dec;
+        pa.n_devices = D;
+        pa.log = a.log;
+        pa.progress = c->at<uint64_t>(c->lay.progress);
+        pa.pub = c->at<uint64_t>(c->lay.pub);
+        pa.pub_stride = c->lay.pub_stride;
+        pa.max_pitch = c->lay.max_pitch;
+        pa.status = c->at<int32_t>(c->lay.status);
+    }
     int64_t done = 0;
     while (done < n_steps) {
         const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
-        for (int k = 0; k < chunk; ++k) {
+        if (persistent) {
+            pa.epoch = ++c->epoch;
+            pa.n_steps = chunk;
+            KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
+        }
+        for (int k = 0; k < chunk && !persistent; ++k) {
             for (int h = 0; h < 2; ++h) {
                 a.occ_in = c->cur;
                 a.occ_out = c->nxt;
@@ -276,6 +387,18 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         KMC_HIP(c, launch_finish_chunk(a.ctl, a.tally_net, a.tally_dec, c->at<int64_t>(c->lay.dec_run),
                                        c->at<int64_t>(c->lay.net_total), D, chunk, c->stream));
         done += chunk;
+    }
+    return KMC_OK;
+}
+
+// Raised by the persistent kernel when a neighbour wait timed out.
+kmc_status check_status(kmc_ctx *c) {
+    int32_t st = 0;
+    KMC_HIP(c, hipMemcpyAsync(&st, c->ws + c->lay.status, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));
+    if (st != 0) {
+        c->poisoned = true;
+        return fail(KMC_EHIP, "persistent hop kernel: a neighbour wait timed out; state is invalid");
     }
     return KMC_OK;
 }
@@ -354,6 +477,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
         off_pad += (int64_t)dv.rails * dv.pitch;
     }
     make_tiles(c);
+    make_ptiles(c);
 
     // binary64 kernel table and its one-time binary32 rounding
     const int m = params->rail_range, cut = lay.cut;
@@ -385,6 +509,8 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     };
     chk(h2d(lay.devs, c->devs.data(), sizeof(DevInfo) * D), "copy device table");
     chk(h2d(lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size()), "copy tiles");
+    if ((int64_t)c->ptiles.size() <= lay.max_ptiles)
+        chk(h2d(lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size()), "copy persistent tiles");
     chk(h2d(lay.ktab64, k64.data(), sizeof(double) * k64.size()), "copy kernel table");
     chk(h2d(lay.ktab32, k32.data(), sizeof(float) * k32.size()), "copy kernel table");
     chk(h2d(lay.ctl, &ctl, sizeof(Ctl)), "copy ctl");
@@ -396,6 +522,8 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i32(c->at<int32_t>(lay.tally_dec), (int64_t)kTallySteps * D * kDeciles, st), "zero tallies");
     chk(launch_zero_i64(c->at<int64_t>(lay.net_total), D, st), "zero totals");
     chk(launch_zero_i64(c->at<int64_t>(lay.log_count), 1, st), "zero log");
+    chk(launch_zero_i64(c->at<int64_t>(lay.progress), 8 * lay.max_ptiles, st), "zero progress counters");
+    chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
     chk(set_hop_lds_limit(c->hop_lds), "LDS limit of the hop kernel");
     {
         const double zero_t = 0.0, zero_v = 0.0;
@@ -483,6 +611,8 @@ kmc_status kmc_run_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_hops_dev, int
 kmc_status kmc_read_occupancy(kmc_ctx *c, int8_t *dst, size_t bytes) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;
+    s = check_status(c);
+    if (s != KMC_OK) return s;
     if (!dst) return fail(KMC_EINVAL, "dst is NULL");
     if (bytes < (size_t)c->lay.total_sites) return fail(KMC_ETOOSMALL, "dst smaller than the lattice");
     KMC_HIP(c, hipMemcpyAsync(dst, c->occ_user, (size_t)c->lay.total_sites, hipMemcpyDeviceToHost, c->stream));
@@ -492,6 +622,8 @@ kmc_status kmc_read_occupancy(kmc_ctx *c, int8_t *dst, size_t bytes) {
 
 kmc_status kmc_read_current(kmc_ctx *c, double *mean_current_A, int64_t *net_hops_total, double *sim_time_s) {
     kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    s = check_status(c);
     if (s != KMC_OK) return s;
     const int D = c->p.n_devices;
     std::vector<int64_t> tot(D);
@@ -514,6 +646,8 @@ kmc_status kmc_read_current(kmc_ctx *c, double *mean_current_A, int64_t *net_hop
 kmc_status kmc_read_threshold_log(kmc_ctx *c, kmc_log_entry *dst, int64_t cap, int64_t *n_events) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;
+    s = check_status(c);
+    if (s != KMC_OK) return s;
     if (cap < 0) return fail(KMC_EINVAL, "cap < 0");
     if (cap > 0 && !dst) return fail(KMC_EINVAL, "dst is NULL");
     int64_t cnt = 0;
@@ -533,6 +667,42 @@ kmc_status kmc_get_step(kmc_ctx *c, int64_t *step) {
     if (!c) return fail(KMC_EINVAL, "context is NULL");
     if (!step) return fail(KMC_EINVAL, "step is NULL");
     *step = c->n;
+    return KMC_OK;
+}
+
+kmc_status kmc_set_launch_mode(kmc_ctx *c, int32_t mode) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (mode < KMC_LAUNCH_AUTO || mode > KMC_LAUNCH_PERSISTENT) return fail(KMC_EINVAL, "unknown launch mode");
+    if (mode == KMC_LAUNCH_PERSISTENT && !c->p_ok)
+        return fail(KMC_EUNSUPPORTED, "the persistent tiling does not fit co-resident on this GPU");
+    c->mode = mode;
+    return KMC_OK;
+}
+
+kmc_status kmc_get_launch_mode(kmc_ctx *c, int32_t *mode) {
+    if (!c) return fail(KMC_EINVAL, "context is NULL");
+    if (!mode) return fail(KMC_EINVAL, "mode is NULL");
+    *mode = use_persistent(c) ? KMC_LAUNCH_PERSISTENT : KMC_LAUNCH_HALF_STEP;
+    return KMC_OK;
+}
+
+kmc_status kmc_set_tile_sites(kmc_ctx *c, int32_t sites) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (sites != 0 && (sites < kChunkSites || sites > (1 << 16)))
+        return fail(KMC_EINVAL, "tile sites must be 0 (default) or in [16, 65536]");
+    KMC_HIP(c, hipStreamSynchronize(c->stream));  // launches in flight use the old tiles
+    c->tile_sites = sites;
+    make_tiles(c);
+    make_ptiles(c);
+    KMC_HIP(c, hipMemcpy(c->ws + c->lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(),
+                         hipMemcpyHostToDevice));
+    if ((int64_t)c->ptiles.size() <= c->lay.max_ptiles)
+        KMC_HIP(c, hipMemcpy(c->ws + c->lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size(),
+                             hipMemcpyHostToDevice));
+    KMC_HIP(c, set_hop_lds_limit(c->hop_lds));
+    if (c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) c->mode = KMC_LAUNCH_AUTO;
     return KMC_OK;
 }
 

@@ -41,6 +41,16 @@ struct Tile {
     int32_t d, r0, nr, pad_;
 };
 
+// Tile of the persistent kernel: rails [r0, r0 + nr) of device d, and the
+// tiles owning the rails just below and just above it (itself when the device
+// is a single tile).
+struct PTile {
+    int32_t d, r0, nr, prev, next, pad_;
+};
+
+constexpr int kRing = 8;                 // publication slots per tile
+constexpr int kPMaxBlock = 1024;         // threads per workgroup, persistent kernel
+
 // Step bookkeeping in device memory (lets a captured graph be replayed).
 struct Ctl {
     int64_t n_base;        // step index of the next step to run
@@ -72,6 +82,36 @@ struct HopArgs {
     struct LogBuf { int64_t *count; void *entries; int64_t cap; } log;
     int32_t step_in_chunk;
     int32_t h;
+};
+
+// Arguments of the persistent kernel (several steps per launch, each
+// workgroup keeps its tile in LDS and talks to its two neighbours only).
+struct PArgs {
+    int8_t *occ;               // padded state: read at launch start, written at the end
+    const DevInfo *devs;
+    const PTile *tiles;
+    int32_t n_tiles;
+    const double *knot_t;
+    const double *knot_v;
+    const void *ea;
+    const double *ktab64;
+    const float *ktab32;
+    int32_t cutoff, rail_range;
+    double ea_scalar, beta, c0, alpha, dt;
+    uint32_t key0, key1;
+    Ctl *ctl;
+    int32_t *tally_net;
+    int32_t *tally_dec;
+    int32_t n_devices;
+    HopArgs::LogBuf log;
+    uint64_t *progress;        // [n_tiles * 8]: (epoch << 40) | half-steps completed
+    uint64_t *pub;             // edge-rail publications, pub_stride words per tile
+    int64_t pub_stride;        // kRing * 2m * max_pitch / 8
+    int32_t max_pitch;
+    uint64_t epoch;
+    int32_t n_steps;
+    int32_t max_nr;            // largest tile (LDS sizing)
+    int32_t *status;           // nonzero: a neighbour wait timed out
 };
 
 }  // namespace kmc

@@ -26,73 +26,10 @@
 
 #include <type_traits>
 
+#include "kmc_device.h"
 #include "kmc_internal.h"
 
 namespace kmc {
-
-// ------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  gfx950 has a
-// three-input bitwise op; truth table 0x96 is a ^ b ^ c.
-// ------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-
-__device__ __forceinline__ uint4 philox4x32_10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
-                                               uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        const uint64_t m0 = (uint64_t)0xD2511F53u * x0;
-        const uint64_t m1 = (uint64_t)0xCD9E8D57u * x2;
-        const uint32_t y0 = xor3((uint32_t)(m1 >> 32), x1, k0);
-        const uint32_t y2 = xor3((uint32_t)(m0 >> 32), x3, k1);
-        x1 = (uint32_t)m1;
-        x3 = (uint32_t)m0;
-        x0 = y0;
-        x2 = y2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(x0, x1, x2, x3);
-}
-
-__device__ __forceinline__ uint32_t word_of(const uint4 &b, int i) {
-    return i == 0 ? b.x : (i == 1 ? b.y : (i == 2 ? b.z : b.w));
-}
-
-// Piecewise-linear bias, right-continuous at repeated knot times, constant
-// outside the knot range.  Binary64.
-__device__ double protocol_voltage(const double *t, const double *v, int nk, double t_rel) {
-    if (nk <= 0) return 0.0;
-    if (t_rel < t[0]) return v[0];
-    int k = 0;
-    for (int i = 0; i < nk; ++i)
-        if (t[i] <= t_rel) k = i;
-    if (k == nk - 1) return v[nk - 1];
-    const double num = (v[k + 1] - v[k]) * (t_rel - t[k]);
-    return v[k] + num / (t[k + 1] - t[k]);
-}
-
-__device__ __forceinline__ int tile_of_block(int bid, int n_tiles) {
-    // Consecutive tiles (neighbouring rails) on the same XCD: the dispatcher
-    // deals workgroups round-robin over the 8 XCDs.
-    const int full = (n_tiles / 8) * 8;
-    return bid < full ? (bid % 8) * (n_tiles / 8) + bid / 8 : bid;
-}
-
-template <typename Real>
-__device__ __forceinline__ Real exp_r(Real x);
-template <>
-__device__ __forceinline__ double exp_r<double>(double x) { return exp(x); }
-template <>
-__device__ __forceinline__ float exp_r<float>(float x) { return expf(x); }
-
-template <typename Real>
-__device__ __forceinline__ Real uniform_of(uint32_t w);
-template <>
-__device__ __forceinline__ double uniform_of<double>(uint32_t w) { return (double)w * 0x1p-32; }
-template <>
-__device__ __forceinline__ float uniform_of<float>(uint32_t w) { return (float)w * 0x1p-32f; }
 
 struct HopShared {
     double V;
@@ -100,27 +37,6 @@ struct HopShared {
     int32_t dec[kDeciles];
     uint32_t wtab[kClasses];  // inclusive Philox-word thresholds per barrier class
 };
-
-// occupancy bits (bit 0 of each byte) of a 16-byte chunk, site k -> bit k
-__device__ __forceinline__ uint32_t occ_bits(const uint4 &v) {
-    uint32_t bits = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) bits |= (((word_of(v, b) & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << (4 * b);
-    return bits;
-}
-
-__device__ __forceinline__ uint32_t word_of8(const uint4 &A, const uint4 &B, int i) {
-    return i < 4 ? word_of(A, i) : word_of(B, i - 4);
-}
-
-__device__ __forceinline__ void flip_byte(uint4 &v, int b) {
-    const uint32_t m = 1u << (8 * (b & 3));
-    const int w = b >> 2;
-    if (w == 0) v.x ^= m;
-    else if (w == 1) v.y ^= m;
-    else if (w == 2) v.z ^= m;
-    else v.w ^= m;
-}
 
 // ------------------------------------------------------------------------
 // The half-step kernel.  H = bond parity.  State bytes: bit 0 = occupied,
@@ -183,20 +99,11 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     uint4 hv = make_uint4(0, 0, 0, 0);
     if (tid < n_halo) hv = *reinterpret_cast<const uint4 *>(halo_src(tid));
 
-    // bias of this step and the prefilter thresholds per barrier class:
-    // dE >= -(|alpha V|/L + coul_bound) for every configuration and the
-    // barrier of a class-q site is >= ea_min + q*ea_step, so
-    // p <= pb(q) = nu0 dt exp(-beta (ea_min + q ea_step - (|alpha V|/L + coul_bound)/2)).
-    // pb is widened by 1e-3 relative and by twice the 1e-6 logging window: a
-    // word above the threshold can neither be accepted nor logged.
+    // bias of this step and the prefilter thresholds per barrier class
     const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots, dv.n_knots,
                                       (double)(n - dv.n_set) * a.dt);
-    if (tid < kClasses) {
-        const double field = fabs(a.alpha * V) / (double)L;
-        const double ea_lb = dv.ea_min + (double)tid * dv.ea_step;
-        const double pb = a.c0 * exp(-a.beta * (ea_lb - 0.5 * (field + dv.coul_bound))) * (1.0 + 1e-3) + 2e-6;
-        sh.wtab[tid] = pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
-    }
+    for (int q = tid; q < kClasses; q += kBlock)
+        sh.wtab[q] = class_threshold(a.c0, a.beta, a.alpha, V, L, dv.ea_min, dv.ea_step, dv.coul_bound, q);
     if (tid == 0) {
         sh.V = V;
         sh.n_surv = 0;
@@ -301,26 +208,10 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
             if (lane == 0) {
                 const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
                 const Real dE = e_app + part;
-                const Real ea = surv_ea[i];
-                Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
-                p = p < (Real)1 ? p : (Real)1;
-                const Real u = uniform_of<Real>(survw[i]);
-                const Real gap = u - p;
                 const int srail = tile.r0 + srow;
-                if ((gap < 0 ? -gap : gap) < (Real)1e-6) {
-                    const int64_t k = atomicAdd(reinterpret_cast<unsigned long long *>(a.log.count), 1ull);
-                    if (k < a.log.cap) {
-                        unsigned char *e = reinterpret_cast<unsigned char *>(a.log.entries) + 40 * k;
-                        *reinterpret_cast<int32_t *>(e + 0) = tile.d;
-                        *reinterpret_cast<int32_t *>(e + 4) = H;
-                        *reinterpret_cast<int64_t *>(e + 8) = n;
-                        *reinterpret_cast<int32_t *>(e + 16) = srail;
-                        *reinterpret_cast<int32_t *>(e + 20) = s;
-                        *reinterpret_cast<double *>(e + 24) = (double)u;
-                        *reinterpret_cast<double *>(e + 32) = (double)p;
-                    }
-                }
-                if (u < p) {
+                const bool accept = decide_hop<Real>(dE, surv_ea[i], survw[i], beta_r, c0_r, a.log, tile.d, H, n,
+                                                     srail, s);
+                if (accept) {
                     const int k = atomicAdd(&sh.n_hop, 1);
                     hops[k] = ((uint32_t)srow << 13) | (uint32_t)s;
                     if (t < o) atomicAdd(&sh.n_down, 1);

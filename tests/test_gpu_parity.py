@@ -13,9 +13,15 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 
-def _sim(physics, rails, sites, occ=None, ea=None):
+MODES = [("half_step", 0), ("persistent", 0), ("persistent", 512)]
+
+
+def _sim(physics, rails, sites, occ=None, ea=None, mode="auto", tile_sites=0):
     from paper_2511_09413_amd import Simulator
-    return Simulator(physics, rails, sites, occ=occ, ea=ea)
+    sim = Simulator(physics, rails, sites, occ=occ, ea=ea, tile_sites=tile_sites)
+    if mode != "auto":
+        sim.set_launch_mode(mode)
+    return sim
 
 
 @pytest.mark.parametrize("rails,sites,fill", [
@@ -33,9 +39,9 @@ def test_fill_random_matches_oracle(rails, sites, fill):
     assert np.array_equal(got, ref)
 
 
-def _run_parity(wl, n_steps, chunk, occ0=None, phys=None):
+def _run_parity(wl, n_steps, chunk, occ0=None, phys=None, mode="auto", tile_sites=0):
     ph = phys or wl.physics
-    sim = _sim(ph, wl.rails, wl.sites, ea=wl.ea_site)
+    sim = _sim(ph, wl.rails, wl.sites, ea=wl.ea_site, mode=mode, tile_sites=tile_sites)
     p_or = oracle.OracleParams(ph, wl.rails, wl.sites, wl.ea_site)
     if occ0 is None:
         occ0 = oracle.fill(p_or, wl.filling)
@@ -44,25 +50,30 @@ def _run_parity(wl, n_steps, chunk, occ0=None, phys=None):
     return lockstep(sim, p_or, wl.protocols, occ0, n_steps, chunk), sim
 
 
-def test_c1_fp64_trajectory():
+@pytest.mark.parametrize("mode,tile", MODES)
+def test_c1_fp64_trajectory(mode, tile):
     """64 x 128, 20% filling, FP64, 0.5 V, kappa = 0.025 V, lambda = 4, cutoff
     16, +-1 rail: identical trajectory, tallies and deciles for 600 steps."""
     wl = c1_plain_fp64()
-    st, _ = _run_parity(wl, 600, 200)
+    st, sim = _run_parity(wl, 600, 200, mode=mode, tile_sites=tile)
     assert st["resyncs"] == 0
+    assert sim.launch_mode == mode
 
 
-def test_c1_validation_variant_many_hops():
-    """Same lattice with Ea = 0.15 eV (p ~ 3e-3): thousands of hops."""
+@pytest.mark.parametrize("mode,tile", MODES)
+def test_c1_validation_variant_many_hops(mode, tile):
+    """Same lattice with Ea = 0.15 eV (p ~ 3e-3): thousands of hops; with
+    512-site tiles the persistent kernel exchanges edge rails between 16 tiles."""
     wl = c1_plain_fp64()
     ph = wl.physics.replace(ea_ev=0.15)
-    st, _ = _run_parity(wl, 300, 100, phys=ph)
+    st, _ = _run_parity(wl, 300, 100, phys=ph, mode=mode, tile_sites=tile)
     assert st["hops"] > 100
     assert st["resyncs"] <= 1
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-def test_ragged_multi_device_with_barrier_field(precision):
+@pytest.mark.parametrize("mode,tile", MODES)
+def test_ragged_multi_device_with_barrier_field(precision, mode, tile):
     """Heterogeneous devices (ragged site counts, several tiles per device),
     per-site barriers, triangle / step / spike-pair protocols."""
     rails, sites = [9, 40, 3, 1], [37, 300, 1000, 129]
@@ -74,19 +85,20 @@ def test_ragged_multi_device_with_barrier_field(precision):
               constant(-0.7)]
     from workloads import Workload
     wl = Workload("ragged", ph, rails, sites, [0.3, 0.2, 0.45, 0.5], protos, 0, ea_site=ea)
-    st, _ = _run_parity(wl, 200, 50)
+    st, _ = _run_parity(wl, 200, 50, mode=mode, tile_sites=tile)
     assert st["hops"] > 100
 
 
+@pytest.mark.parametrize("mode,tile", MODES)
 @pytest.mark.parametrize("R,L,m,cut,lam", [
     (1, 64, 1, 16, 4.0), (2, 50, 1, 16, 4.0), (3, 40, 2, 8, 4.0), (17, 96, 0, 16, 4.0),
-    (12, 64, 4, 63, 0.0), (5, 33, 3, 5, 2.0)])
-def test_interaction_variants(R, L, m, cut, lam):
+    (12, 64, 4, 63, 0.0), (5, 33, 3, 5, 2.0), (40, 48, 2, 16, 4.0), (24, 160, 4, 30, 0.0)])
+def test_interaction_variants(R, L, m, cut, lam, mode, tile):
     ph = Physics(precision=FP64, seed=5, ea_ev=0.12, coulomb_kappa_v=0.04, screening_sites=lam,
                  cutoff_sites=cut, rail_range=m)
     wl = small_case(R, L, filling=0.35, precision=FP64, ea_ev=0.12, protocol=triangle(3.0, 80e-12))
     wl.physics = ph
-    st, _ = _run_parity(wl, 80, 40)
+    st, _ = _run_parity(wl, 80, 40, mode=mode, tile_sites=tile)
     assert st["steps"] == 80
 
 
@@ -134,14 +146,15 @@ def test_near_threshold_log_matches_oracle():
 
 
 # ------------------------------------------------------------- full size
-def test_c2_full_size_sampled():
+@pytest.mark.parametrize("mode", ["half_step", "persistent"])
+def test_c2_full_size_sampled(mode):
     """4096 x 1024, FP32, per-site barriers, in the benchmark's launch
     configuration: after 3 steps, rails [lo+6, hi-6) of several windows equal the
     oracle's light-cone runs, and every rail keeps its ion count."""
     wl = c2_large_device(n_steps=3)
     ph = wl.physics.replace(ea_ev=0.3)
-    ea = wl.ea_site - np.float32(0.17)   # lower barriers: about 400 hops per step
-    sim = _sim(ph, wl.rails, wl.sites, ea=ea)
+    ea = wl.ea_site - np.float32(0.17)   # lower barriers: thousands of hops per step
+    sim = _sim(ph, wl.rails, wl.sites, ea=ea, mode=mode)
     sim.fill_random(wl.filling)
     occ0 = sim.read_occupancy()
     sim.set_protocols(wl.protocols)
