@@ -103,8 +103,12 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     if (tid == 0) sh.stop = 0;
     __syncthreads();
 
-    // publish the edge rails of `state` as state j
-    auto publish = [&](const unsigned char *state, int64_t j) {
+    // Publication of the edge rails of `state` as state j, in two parts: the
+    // stores are issued at the end of half-step j-1 and completed (s_waitcnt on
+    // every counter: a workgroup-scope fence does not wait for global stores on
+    // gfx950, then a barrier) during half-step j, just before the progress
+    // counter announces state j; the store latency overlaps the Philox work.
+    auto publish_issue = [&](const unsigned char *state, int64_t j) {
         uint64_t *slot = a.pub + (int64_t)ti * a.pub_stride + (int64_t)(j % kRing) * slot_words;
         for (int i = tid; i < slot_words; i += bdim) {
             const int b = i / band_words, wd = i - b * band_words;
@@ -112,15 +116,18 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
             const uint64_t word = *reinterpret_cast<const uint64_t *>(state + row * P + wd * 8);
             __hip_atomic_store(slot + i, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        // wait until this thread's stores have completed (all counters zero):
-        // a workgroup-scope fence does not wait for global stores on gfx950
+    };
+    auto publish_complete = [&](int64_t j) {  // contains a workgroup barrier
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (tid == 0)
             __hip_atomic_store(&a.progress[(int64_t)ti * 8], progress_tag(epoch, j), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
     };
-    if (!single) publish(S0, j0);
+    if (!single) {
+        publish_issue(S0, j0);
+        publish_complete(j0);
+    }
 
     for (int js = 0; js < 2 * a.n_steps; ++js) {
         const int64_t j = j0 + js;
@@ -200,7 +207,11 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
-        __syncthreads();
+        if (!single && js > 0) {
+            publish_complete(j);  // state j (issued at the end of half-step j-1); includes the barrier
+        } else {
+            __syncthreads();
+        }
 
         // survivors: one wavefront each; window rows from the snapshot in LDS or
         // from the neighbours' publications of state j
@@ -276,7 +287,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         __syncthreads();
         if (sh.stop) break;
 
-        if (!single) publish(nxt, j + 1);
+        if (!single) publish_issue(nxt, j + 1);
         if (h == 1 && tid == 0 && (sh.n_down | sh.n_up)) {
             const int64_t base = (n - a.ctl->tally_base) * a.n_devices + tile.d;
             atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
@@ -285,7 +296,9 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         }
     }
 
-    // write the tile back (an even number of half-steps ends in S0)
+    // announce the last state, write the tile back (an even number of
+    // half-steps ends in S0)
+    if (!single && !sh.stop) publish_complete(j0 + 2 * (int64_t)a.n_steps);
     __syncthreads();
     for (int c = tid; c < n_chunks; c += bdim) {
         const int row = c / p16, col = c - row * p16;
