@@ -147,7 +147,7 @@ Layout layout_for(const kmc_params *p) {
     int max_pitch = 0;
     for (int d = 0; d < D; ++d) max_pitch = std::max(max_pitch, (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites);
     L.max_pitch = max_pitch;
-    L.pub_stride = (int64_t)kRing * 2 * std::max(m, 1) * max_pitch / 8;
+    L.pub_stride = (int64_t)kRing * 2 * std::max(m, 1) * ((max_pitch + 31) / 32);
     const int64_t pub_cap = ((int64_t)64 << 20) / (8 * L.pub_stride);
     L.max_ptiles = std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap);
     L.ptiles = take(sizeof(PTile) * (size_t)L.max_ptiles);
@@ -285,14 +285,18 @@ void make_ptiles(kmc_ctx *c) {
             c->ptiles.push_back(PTile{d, r0, nr, prev, next, 0});
             r0 += nr;
             max_chunks = std::max(max_chunks, nr * dv.pitch / kChunkSites);
+            // occupancy bits (two buffers), barrier classes, survivor lists, kernel table
+            const size_t words = (size_t)nr * ((dv.pitch + 63) / 64);
             const size_t cap = (size_t)nr * dv.pitch / 2;
-            lds = std::max(lds, 2 * (size_t)nr * dv.pitch + cap * (2 * sizeof(uint32_t) + real) + kt);
+            lds = std::max(lds, 2 * words * sizeof(uint64_t) + (size_t)nr * dv.pitch +
+                                    (2 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt);
         }
     }
     c->p_block = std::min(kPMaxBlock, (max_chunks + 63) / 64 * 64);
     c->p_lds = lds;
     c->p_ok = false;
-    if ((int64_t)c->ptiles.size() > c->lay.max_ptiles || lds > 160 * 1024) return;
+    // one lane per 16-site chunk: a tile holds at most kPMaxBlock chunks
+    if (max_chunks > kPMaxBlock || (int64_t)c->ptiles.size() > c->lay.max_ptiles || lds > 160 * 1024) return;
     int per_cu = 0, dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
@@ -370,7 +374,14 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
     while (done < n_steps) {
         const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
         if (persistent) {
-            pa.epoch = ++c->epoch;
+            // publication tags carry the low 20 bits of the epoch: at every wrap
+            // the ring is cleared so that no stale word can match a new tag
+            if ((++c->epoch & 0xFFFFFu) == 0) {
+                KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.pub), c->lay.pub_stride * c->lay.max_ptiles,
+                                           c->stream));
+                ++c->epoch;
+            }
+            pa.epoch = c->epoch;
             pa.n_steps = chunk;
             KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
         }
@@ -523,6 +534,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i64(c->at<int64_t>(lay.net_total), D, st), "zero totals");
     chk(launch_zero_i64(c->at<int64_t>(lay.log_count), 1, st), "zero log");
     chk(launch_zero_i64(c->at<int64_t>(lay.progress), 8 * lay.max_ptiles, st), "zero progress counters");
+    chk(launch_zero_i64(c->at<int64_t>(lay.pub), lay.pub_stride * lay.max_ptiles, st), "zero publication ring");
     chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
     chk(set_hop_lds_limit(c->hop_lds), "LDS limit of the hop kernel");
     {

@@ -1,28 +1,31 @@
-// Persistent hop-step kernel: one launch runs a chunk of steps.
+// Persistent hop-step kernel: one launch runs a chunk of up to 1024 steps.
 //
-// Each workgroup owns a tile (whole rails of one device) and keeps the tile's
-// int8 state in LDS for the whole launch, double-buffered: every half-step
-// reads the snapshot buffer and writes the other (Jacobi update of the pair
-// checkerboard).  The only data that crosses workgroups are the tile's first
-// and last rail_range rails, which the Coulomb windows of the neighbouring
-// tiles need.  After each half-step a workgroup publishes those edge rails into
-// a ring of kRing slots in global memory and bumps its progress counter; a
-// neighbour waits for that counter only when one of its survivors has a window
-// reaching into the tile, or when it is about to reuse a ring slot the tile may
-// still read.  There is no grid-wide barrier, so a workgroup delayed by a
-// survivor evaluation does not stall the chip.
+// Each workgroup owns a tile (whole rails of one device) and keeps it in LDS
+// for the whole launch: the occupancy as bits (double-buffered: every
+// half-step reads the snapshot and writes the other buffer, the Jacobi update
+// of the pair checkerboard) and the barrier class of every site as a byte.
+// One lane owns 16 consecutive sites of a rail for the whole launch, so its
+// coordinates and Philox counter words stay in registers.
 //
-// Cross-workgroup data (publications, progress counters) is accessed only with
-// relaxed agent-scope atomics, which gfx950 executes as coherent (sc1) loads and
-// stores; a writer waits for its stores to complete (s_waitcnt on every
-// counter, then a workgroup barrier) before one thread stores the counter, and
-// a reader loads the data only after it has observed the counter.  Every wait is bounded: on time-out
-// the kernel raises a status flag, every workgroup leaves its loop, and the
-// host reports the error.
+// Only the tile's first and last rail_range rails cross workgroups: the
+// Coulomb windows of the neighbouring tiles reach into them.  After every
+// half-step the workgroup writes those rails into a ring of kRing slots in
+// global memory as 64-bit words, 32 occupancy bits plus a 32-bit tag naming
+// the state (launch epoch, half-step).  Data and tag travel in one store, so
+// a writer never waits for its stores; a reader that needs a neighbour's rail
+// (a survivor whose window crosses the tile edge, which is rare) polls the
+// words it needs until their tags name the state it wants.  Before a slot is
+// overwritten, the writer checks, with one load issued a half-step ahead, that
+// both neighbours have published the state that proves they finished reading
+// it.  There is no grid-wide barrier.  Every wait is bounded: on time-out the
+// kernel raises a status flag, all workgroups leave their loops and the host
+// reports the error.  Cross-workgroup words are accessed only with relaxed
+// agent-scope atomics, which gfx950 executes as coherent (sc1) loads and
+// stores.
 //
-// The per-bond work (Philox4x32-10 draw, candidate test, exact prefilter,
-// survivor energy, Arrhenius probability and accept test) is the same as in
-// hop_half_step.
+// Per bond the work is that of hop_half_step: Philox4x32-10 draw, candidate
+// test, exact two-stage prefilter, survivor energy (wavefront-cooperative
+// window sum), Arrhenius probability and accept test.
 #include "kmc_device.h"
 #include "kmc_internal.h"
 
@@ -31,34 +34,29 @@ namespace kmc {
 constexpr int kSpinLimit = 1 << 20;  // about a second of polling
 
 struct PShared {
-    double V;
+    double V, g;                  // bias of the step, exp(beta (|alpha V|/L + coul_bound)/2)
+    uint32_t thr0;                // stage-0 threshold (lowest barrier class)
     int32_t n_surv, n_down, n_up, stop;
     int32_t dec[kDeciles];
-    uint32_t wtab[kClasses];
+    int64_t ver_prev, ver_next;   // neighbour progress verified so far (half-steps, relative)
 };
 
-__device__ __forceinline__ uint64_t progress_tag(uint64_t epoch, int64_t j) { return (epoch << 40) | (uint64_t)j; }
+__device__ __forceinline__ uint32_t pub_tag(uint64_t epoch, int64_t j_rel) {
+    return ((uint32_t)(epoch & 0xFFFFFu) << 12) | (uint32_t)j_rel;
+}
 
-// Wait until tile t has published state j (completed half-steps < j) in this
-// launch.  Returns false when the wait timed out or another workgroup did.
-__device__ bool wait_progress(const PArgs &a, int t, int64_t j) {
-    const uint64_t want = progress_tag(a.epoch, j);
-    int spins = 0;
-    while (__hip_atomic_load(&a.progress[(int64_t)t * 8], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-        if (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-        if (++spins > kSpinLimit) {
-            __hip_atomic_store(a.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return true;
+// Inclusive threshold of a Philox word for a class with static factor
+// A = exp(-beta ea_lb) (see class_threshold), widened like class_threshold.
+__device__ __forceinline__ uint32_t threshold_of(double c0, double A, double g) {
+    const double pb = c0 * A * g * (1.0 + 1e-3) + 2e-6;
+    return pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
 }
 
 template <typename Real>
 __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ PShared sh;
+    __shared__ double cls_A[kClasses];
 
     const int ti = tile_of_block(blockIdx.x, a.n_tiles);
     const PTile tile = a.tiles[ti];
@@ -66,18 +64,22 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     const int R = dv.rails, L = dv.sites, P = dv.pitch;
     const int m = a.rail_range;
     const int p16 = P / kChunkSites;
+    const int W = (P + 63) / 64;             // 64-bit occupancy words per rail in LDS
+    const int W32 = (P + 31) / 32;           // 32-bit data words per published rail
     const int nr = tile.nr;
-    const int n_chunks = nr * p16;
+    const int n_chunks = nr * p16;           // <= blockDim.x (host guarantees)
     const int cap = nr * P / 2;
     const int tid = threadIdx.x, bdim = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, n_waves = bdim >> 6;
     const bool single = tile.prev == ti && tile.next == ti;
+    const bool isolated = single || a.rail_range == 0;  // no rail of another tile is ever read
 
-    unsigned char *S0 = smem;
-    unsigned char *S1 = smem + nr * P;
-    uint32_t *sv_pos = reinterpret_cast<uint32_t *>(smem + 2 * nr * P);
+    uint64_t *B0 = reinterpret_cast<uint64_t *>(smem);
+    uint64_t *B1 = B0 + nr * W;
+    unsigned char *cls = reinterpret_cast<unsigned char *>(B1 + nr * W);
+    uint32_t *sv_pos = reinterpret_cast<uint32_t *>(cls + nr * P);
     uint32_t *sv_w = sv_pos + cap;
-    Real *sv_ea = reinterpret_cast<Real *>(sv_w + cap);
+    Real *sv_ea = reinterpret_cast<Real *>(sv_w + cap + (cap & 1));
     Real *kt_lds = sv_ea + cap;
     const int kt_stride = a.cutoff + 1;
     const int n_kt = (m + 1) * kt_stride;
@@ -85,186 +87,188 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
                                                             : reinterpret_cast<const Real *>(a.ktab32);
     const Real *kt = kt_in_lds ? kt_lds : kt_glob;
-    const int band_words = P / 8;                 // 64-bit words per published rail
-    const int slot_words = 2 * m * band_words;    // one ring slot
+    const int slot_words = 2 * m * W32;      // 64-bit words of one ring slot
     const uint64_t epoch = a.epoch;
     const int64_t j0 = 2 * a.ctl->n_base;
     const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0, alpha_r = (Real)a.alpha;
 
-    // load the tile and the kernel table
+    // the lane's chunk, fixed for the launch
+    const bool has_chunk = tid < n_chunks;
+    const int row = has_chunk ? tid / p16 : 0;
+    const int s0 = has_chunk ? (tid - row * p16) * kChunkSites : 0;
+    const int wi = row * W + (s0 >> 6), sb = s0 & 63;
+    const uint32_t rail = (uint32_t)(tile.r0 + row);
+    const int last = L - 2 - s0;
+    const uint32_t valid = last >= 15 ? 0xFFFFu : (last < 0 ? 0u : ((2u << last) - 1u));
+    const bool nx_here = sb < 48;                       // bit s0+16 in the same word
+    const bool nx_exists = s0 + kChunkSites < P;
+
+    // load the tile: occupancy bits and barrier classes
     int8_t *gstate = a.occ + dv.off_pad + (int64_t)tile.r0 * P;
-    for (int c = tid; c < n_chunks; c += bdim) {
-        const int row = c / p16, col = c - row * p16;
-        *reinterpret_cast<uint4 *>(S0 + row * P + col * kChunkSites) =
-            *reinterpret_cast<const uint4 *>(gstate + (int64_t)row * P + col * kChunkSites);
+    for (int i = tid; i < nr * W; i += bdim) B0[i] = 0;  // padding bits stay 0
+    __syncthreads();
+    if (has_chunk) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(gstate + (int64_t)row * P + s0);
+        reinterpret_cast<uint16_t *>(B0)[row * W * 4 + (s0 >> 4)] = (uint16_t)occ_bits(v);
+        *reinterpret_cast<uint4 *>(cls + row * P + s0) =
+            make_uint4((v.x >> 1) & 0x7F7F7F7Fu, (v.y >> 1) & 0x7F7F7F7Fu, (v.z >> 1) & 0x7F7F7F7Fu,
+                       (v.w >> 1) & 0x7F7F7F7Fu);
     }
     if (kt_in_lds)
         for (int i = tid; i < n_kt; i += bdim) kt_lds[i] = kt_glob[i];
-    if (tid == 0) sh.stop = 0;
+    for (int q = tid; q < kClasses; q += bdim) cls_A[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
+    if (tid == 0) {
+        sh.stop = 0;
+        sh.ver_prev = -1;
+        sh.ver_next = -1;
+    }
     __syncthreads();
 
-    // Publication of the edge rails of `state` as state j, in two parts: the
-    // stores are issued at the end of half-step j-1 and completed (s_waitcnt on
-    // every counter: a workgroup-scope fence does not wait for global stores on
-    // gfx950, then a barrier) during half-step j, just before the progress
-    // counter announces state j; the store latency overlaps the Philox work.
-    auto publish_issue = [&](const unsigned char *state, int64_t j) {
+    // the edge rails of `state` as state j (no wait: tags validate the data)
+    auto publish = [&](const uint64_t *state, int64_t j) {
         uint64_t *slot = a.pub + (int64_t)ti * a.pub_stride + (int64_t)(j % kRing) * slot_words;
+        const uint64_t tag = (uint64_t)pub_tag(epoch, j - j0) << 32;
         for (int i = tid; i < slot_words; i += bdim) {
-            const int b = i / band_words, wd = i - b * band_words;
-            const int row = b < m ? b : nr - 2 * m + b;
-            const uint64_t word = *reinterpret_cast<const uint64_t *>(state + row * P + wd * 8);
-            __hip_atomic_store(slot + i, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int b = i / W32, q = i - b * W32;
+            const int rrow = b < m ? b : nr - 2 * m + b;
+            const uint32_t data = (uint32_t)(state[rrow * W + (q >> 1)] >> (32 * (q & 1)));
+            __hip_atomic_store(slot + i, tag | data, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
-    auto publish_complete = [&](int64_t j) {  // contains a workgroup barrier
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (tid == 0)
-            __hip_atomic_store(&a.progress[(int64_t)ti * 8], progress_tag(epoch, j), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+    // Wait until word `i` of tile t's slot for state j carries state j's tag
+    // (or a later one when `at_least`) and store it in *out; false on time-out.
+    auto fetch = [&](int t, int64_t j, int i, bool at_least, uint64_t *out) -> bool {
+        const uint64_t *w = a.pub + (int64_t)t * a.pub_stride + (int64_t)(j % kRing) * slot_words + i;
+        const uint32_t want = pub_tag(epoch, j - j0);
+        for (int spins = 0;; ++spins) {
+            const uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t tag = (uint32_t)(v >> 32);
+            if (tag == want || (at_least && (tag >> 12) == (want >> 12) && tag > want)) {
+                *out = v;
+                return true;
+            }
+            if (spins > kSpinLimit) {
+                __hip_atomic_store(a.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            if (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+            __builtin_amdgcn_s_sleep(2);
+        }
     };
-    if (!single) {
-        publish_issue(S0, j0);
-        publish_complete(j0);
-    }
+    if (!isolated) publish(B0, j0);
 
     for (int js = 0; js < 2 * a.n_steps; ++js) {
         const int64_t j = j0 + js;
         const int64_t n = j >> 1;
         const int h = (int)(j & 1);
-        unsigned char *cur = (js & 1) ? S1 : S0;
-        unsigned char *nxt = (js & 1) ? S0 : S1;
-        if (h == 0) {
-            const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots,
-                                              dv.n_knots, (double)(n - dv.n_set) * a.dt);
-            for (int q = tid; q < kClasses; q += bdim)
-                sh.wtab[q] = class_threshold(a.c0, a.beta, a.alpha, V, L, dv.ea_min, dv.ea_step, dv.coul_bound, q);
-            if (tid == 0) {
+        const uint64_t *cur = (js & 1) ? B1 : B0;
+        uint64_t *nxt = (js & 1) ? B0 : B1;
+        if (tid == 0) {
+            if (h == 0) {
+                const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots,
+                                                  dv.n_knots, (double)(n - dv.n_set) * a.dt);
                 sh.V = V;
+                sh.g = exp(0.5 * a.beta * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
                 sh.n_down = 0;
                 sh.n_up = 0;
                 for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
             }
-        }
-        if (tid == 0) {
+            sh.thr0 = threshold_of(a.c0, cls_A[0], sh.g);
             sh.n_surv = 0;
-            // the slot this half-step will write held state j+1-kRing, which the
-            // neighbours read during their half-step j+1-kRing
-            const int64_t need = j + 2 - kRing;
-            if (!single && need > j0) {
-                bool ok = wait_progress(a, tile.prev, need);
-                if (ok && tile.next != tile.prev) ok = wait_progress(a, tile.next, need);
-                if (!ok) sh.stop = 1;
-            }
         }
-        for (int c = tid; c < n_chunks; c += bdim) {
-            const int off = (c / p16) * P + (c - (c / p16) * p16) * kChunkSites;
-            *reinterpret_cast<uint4 *>(nxt + off) = *reinterpret_cast<const uint4 *>(cur + off);
-        }
+        for (int i = tid; i < nr * W; i += bdim) nxt[i] = cur[i];
         __syncthreads();
         if (sh.stop) break;
 
         // candidates, Philox words, exact two-stage prefilter
-        const uint32_t thr0 = sh.wtab[0];
-        const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
-        const uint32_t pmask = h ? 0xAAAAu : 0x5555u;
-        for (int c = tid; c < n_chunks; c += bdim) {
-            const int row = c / p16;
-            const int s0 = (c - row * p16) * kChunkSites;
-            const unsigned char *rp = cur + row * P;
-            const uint4 v = *reinterpret_cast<const uint4 *>(rp + s0);
-            const uint32_t nx = (h && s0 + kChunkSites < P) ? (uint32_t)rp[s0 + kChunkSites] : 0u;
-            const uint32_t bits = occ_bits(v) | ((nx & 1u) << 16);
-            uint32_t cand = (bits ^ (bits >> 1)) & pmask;
-            const int last = L - 2 - s0;
-            if (last < 15) cand &= last < 0 ? 0u : ((2u << last) - 1u);
-            if (cand == 0) continue;
-            const uint32_t rail = (uint32_t)(tile.r0 + row);
-            const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
-            const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
-            uint32_t sv = 0;
+        if (has_chunk) {
+            const uint64_t word = cur[wi];
+            uint32_t bits = (uint32_t)(word >> sb) & 0xFFFFu;
+            if (h && nx_exists) bits |= (uint32_t)((nx_here ? (word >> (sb + 16)) : cur[wi + 1]) & 1u) << 16;
+            const uint32_t cand = (bits ^ (bits >> 1)) & (h ? 0xAAAAu : 0x5555u) & valid;
+            if (cand) {
+                const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
+                const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
+                const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
+                const uint32_t thr0 = sh.thr0;
+                uint32_t sv = 0;
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int bit = h + 2 * jj;
-                if (((cand >> bit) & 1u) && word_of(blkA, jj) <= thr0) sv |= 1u << bit;
-                if (((cand >> (bit + 8)) & 1u) && word_of(blkB, jj) <= thr0) sv |= 1u << (bit + 8);
-            }
-            while (sv) {  // rare: the threshold of the origin's barrier class
-                const int bit = __builtin_ctz(sv);
-                sv &= sv - 1;
-                const int ob = ((bits >> bit) & 1u) ? bit : bit + 1;
-                const uint32_t obyte = ob < kChunkSites ? (word_of(v, ob >> 2) >> (8 * (ob & 3))) & 0xFFu : nx;
-                const uint32_t w = word_of8(blkA, blkB, bit >> 1);
-                if (w <= sh.wtab[obyte >> 1]) {
-                    const int k = atomicAdd(&sh.n_surv, 1);
-                    sv_pos[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
-                    sv_w[k] = w;
-                    Real ea;
-                    if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)rail * L + s0 + ob];
-                    else ea = (Real)a.ea_scalar;
-                    sv_ea[k] = ea;
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int bit = h + 2 * jj;
+                    if (((cand >> bit) & 1u) && word_of(blkA, jj) <= thr0) sv |= 1u << bit;
+                    if (((cand >> (bit + 8)) & 1u) && word_of(blkB, jj) <= thr0) sv |= 1u << (bit + 8);
+                }
+                while (sv) {  // rare: the threshold of the origin's barrier class
+                    const int bit = __builtin_ctz(sv);
+                    sv &= sv - 1;
+                    const int o = s0 + (((bits >> bit) & 1u) ? bit : bit + 1);
+                    const uint32_t w = word_of8(blkA, blkB, bit >> 1);
+                    if (w <= threshold_of(a.c0, cls_A[cls[row * P + o]], sh.g)) {
+                        const int k = atomicAdd(&sh.n_surv, 1);
+                        sv_pos[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
+                        sv_w[k] = w;
+                        Real ea;
+                        if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)rail * L + o];
+                        else ea = (Real)a.ea_scalar;
+                        sv_ea[k] = ea;
+                    }
                 }
             }
         }
-        if (!single && js > 0) {
-            publish_complete(j);  // state j (issued at the end of half-step j-1); includes the barrier
-        } else {
-            __syncthreads();
-        }
+        __syncthreads();
 
-        // survivors: one wavefront each; window rows from the snapshot in LDS or
-        // from the neighbours' publications of state j
+        // slot check for the publication at the end of this half-step: the slot
+        // of state j+1 held state j+1-kRing, which the neighbours read during
+        // their half-step j+1-kRing; they finished it once they published
+        // state j+2-kRing.  The load is issued now and consumed after the survivors.
+        const int64_t need = j + 2 - kRing - j0;
+        uint64_t probe_p = 0, probe_n = 0;
+        const bool check = !isolated && tid == 0 && need > 0;
+        bool check_p = check && sh.ver_prev < need, check_n = check && sh.ver_next < need;
+        if (tile.next == tile.prev) check_n = false;
+
+        // survivors: one wavefront each
         const int n_surv = sh.n_surv;
-        const int slot = (int)(j % kRing);
         for (int i = wave; i < n_surv; i += n_waves) {
             const int srow = (int)(sv_pos[i] >> 13), s = (int)(sv_pos[i] & 8191u);
-            const unsigned char *rp = cur + srow * P;
-            const int o = (rp[s] & 1) ? s : s + 1;
-            const int t = (rp[s] & 1) ? s + 1 : s;
-            int ok = 1;
-            if (!single && lane == 0) {
-                if (srow - m < 0) ok = wait_progress(a, tile.prev, j);
-                if (ok && srow + m >= nr) ok = wait_progress(a, tile.next, j);
-                if (!ok) sh.stop = 1;
-            }
-            ok = __shfl(ok, 0, 64);
-            if (!ok) break;
+            const int o = ((cur[srow * W + (s >> 6)] >> (s & 63)) & 1u) ? s : s + 1;
+            const int t = (o == s) ? s + 1 : s;
             int lo = s - a.cutoff, hi = s + 1 + a.cutoff;
             lo = lo < 0 ? 0 : lo;
             hi = hi > L - 1 ? L - 1 : hi;
             Real part = (Real)0;
-            for (int k = 0; k < dv.n_nbr; ++k) {
+            bool ok = true;
+            for (int k = 0; k < dv.n_nbr && ok; ++k) {
                 const int off = dv.nbr_off[k];
                 const Real *ktr = kt + dv.nbr_dist[k] * kt_stride;
                 int rho = srow + off;
-                const unsigned char *lrow = nullptr;
-                const uint64_t *prow = nullptr;
-                if (single) {
-                    rho = ((rho % R) + R) % R;
-                    lrow = cur + rho * P;
-                } else if (rho >= 0 && rho < nr) {
-                    lrow = cur + rho * P;
-                } else if (rho < 0) {
-                    prow = a.pub + (int64_t)tile.prev * a.pub_stride + (int64_t)slot * slot_words +
-                           (2 * m + rho) * band_words;
-                } else {
-                    prow = a.pub + (int64_t)tile.next * a.pub_stride + (int64_t)slot * slot_words +
-                           (rho - nr) * band_words;
-                }
+                int nb = -1, band = 0;
+                if (single) rho = ((rho % R) + R) % R;
+                else if (rho < 0) { nb = tile.prev; band = 2 * m + rho; }
+                else if (rho >= nr) { nb = tile.next; band = rho - nr; }
                 for (int jj = lo + lane; jj <= hi; jj += 64) {
-                    uint32_t byte;
-                    if (lrow) byte = lrow[jj];
-                    else byte = (uint32_t)(__hip_atomic_load(prow + (jj >> 3), __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT) >> (8 * (jj & 7)));
-                    int occ = byte & 1;
-                    if (off == 0 && (jj == o || jj == t)) occ = 0;
+                    uint32_t bit;
+                    if (nb < 0) {
+                        bit = (uint32_t)(cur[rho * W + (jj >> 6)] >> (jj & 63)) & 1u;
+                    } else {
+                        uint64_t v = 0;
+                        if (!fetch(nb, j, band * W32 + (jj >> 5), false, &v)) {
+                            ok = false;
+                            break;
+                        }
+                        bit = (uint32_t)(v >> (jj & 31)) & 1u;
+                    }
+                    if (off == 0 && (jj == o || jj == t)) bit = 0;
                     const int dt_ = t - jj < 0 ? jj - t : t - jj;
                     const int do_ = o - jj < 0 ? jj - o : o - jj;
                     const Real kt_v = dt_ > a.cutoff ? (Real)0 : ktr[dt_];
                     const Real ko_v = do_ > a.cutoff ? (Real)0 : ktr[do_];
-                    part += occ ? (kt_v - ko_v) : (Real)0;
+                    part += bit ? (kt_v - ko_v) : (Real)0;
                 }
+            }
+            if (__any(!ok)) {
+                if (lane == 0) sh.stop = 1;
+                break;
             }
 #pragma unroll
             for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
@@ -272,8 +276,9 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 const Real e_app = ((alpha_r * (Real)sh.V) * (Real)(t - o)) / (Real)L;
                 const int srail = tile.r0 + srow;
                 if (decide_hop<Real>(e_app + part, sv_ea[i], sv_w[i], beta_r, c0_r, a.log, tile.d, h, n, srail, s)) {
-                    nxt[srow * P + s] ^= 1;
-                    nxt[srow * P + s + 1] ^= 1;
+                    atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + (s >> 6)]), 1ull << (s & 63));
+                    atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + ((s + 1) >> 6)]),
+                              1ull << ((s + 1) & 63));
                     if (t < o) atomicAdd(&sh.n_down, 1);
                     else atomicAdd(&sh.n_up, 1);
                     const int qo = (10 * o) / L, qt = (10 * t) / L;
@@ -284,10 +289,22 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
+        if (check_p || check_n) {  // thread 0: consume the slot check
+            bool ok = true;
+            if (check_p) {
+                ok = fetch(tile.prev, j + 2 - kRing, 0, true, &probe_p);
+                if (ok) sh.ver_prev = (int64_t)((uint32_t)(probe_p >> 32) & 0xFFFu);
+            }
+            if (ok && check_n) {
+                ok = fetch(tile.next, j + 2 - kRing, 0, true, &probe_n);
+                if (ok) sh.ver_next = (int64_t)((uint32_t)(probe_n >> 32) & 0xFFFu);
+            }
+            if (!ok) sh.stop = 1;
+        }
         __syncthreads();
         if (sh.stop) break;
 
-        if (!single) publish_issue(nxt, j + 1);
+        if (!isolated) publish(nxt, j + 1);
         if (h == 1 && tid == 0 && (sh.n_down | sh.n_up)) {
             const int64_t base = (n - a.ctl->tally_base) * a.n_devices + tile.d;
             atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
@@ -296,14 +313,17 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         }
     }
 
-    // announce the last state, write the tile back (an even number of
-    // half-steps ends in S0)
-    if (!single && !sh.stop) publish_complete(j0 + 2 * (int64_t)a.n_steps);
+    // write the tile back (an even number of half-steps ends in B0)
     __syncthreads();
-    for (int c = tid; c < n_chunks; c += bdim) {
-        const int row = c / p16, col = c - row * p16;
-        *reinterpret_cast<uint4 *>(gstate + (int64_t)row * P + col * kChunkSites) =
-            *reinterpret_cast<const uint4 *>(S0 + row * P + col * kChunkSites);
+    if (has_chunk) {
+        const uint32_t bits = (uint32_t)(B0[wi] >> sb) & 0xFFFFu;
+        const uint4 c = *reinterpret_cast<const uint4 *>(cls + row * P + s0);
+        uint4 v;
+        v.x = (((bits >> 0) & 0xFu) * 0x00204081u & 0x01010101u) | (c.x << 1);
+        v.y = (((bits >> 4) & 0xFu) * 0x00204081u & 0x01010101u) | (c.y << 1);
+        v.z = (((bits >> 8) & 0xFu) * 0x00204081u & 0x01010101u) | (c.z << 1);
+        v.w = (((bits >> 12) & 0xFu) * 0x00204081u & 0x01010101u) | (c.w << 1);
+        *reinterpret_cast<uint4 *>(gstate + (int64_t)row * P + s0) = v;
     }
 }
 
