@@ -289,7 +289,8 @@ void make_ptiles(kmc_ctx *c) {
             const size_t words = (size_t)nr * ((dv.pitch + 63) / 64);
             const size_t cap = (size_t)nr * dv.pitch / 2;
             lds = std::max(lds, 2 * words * sizeof(uint64_t) + (size_t)nr * dv.pitch +
-                                    (2 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt);
+                                    (2 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + ((kt + 7) & ~(size_t)7) +
+                                    (size_t)kTallySteps * (2 * sizeof(double) + sizeof(uint32_t)));
         }
     }
     c->p_block = std::min(kPMaxBlock, (max_chunks + 63) / 64 * 64);

@@ -34,8 +34,6 @@ namespace kmc {
 constexpr int kSpinLimit = 1 << 20;  // about a second of polling
 
 struct PShared {
-    double V, g;                  // bias of the step, exp(beta (|alpha V|/L + coul_bound)/2)
-    uint32_t thr0;                // stage-0 threshold (lowest barrier class)
     int32_t n_surv, n_down, n_up, stop;
     int32_t dec[kDeciles];
     int64_t ver_prev, ver_next;   // neighbour progress verified so far (half-steps, relative)
@@ -84,6 +82,12 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     const int kt_stride = a.cutoff + 1;
     const int n_kt = (m + 1) * kt_stride;
     const bool kt_in_lds = n_kt <= kLdsTableMax;
+    // per-step tables of the launch: bias V, g = exp(beta (|alpha V|/L + coul_bound)/2)
+    // and the stage-0 threshold
+    double *step_V = reinterpret_cast<double *>(
+        reinterpret_cast<unsigned char *>(kt_lds) + (kt_in_lds ? ((n_kt * (int)sizeof(Real) + 7) & ~7) : 0));
+    double *step_g = step_V + a.n_steps;
+    uint32_t *step_thr0 = reinterpret_cast<uint32_t *>(step_g + a.n_steps);
     const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
                                                             : reinterpret_cast<const Real *>(a.ktab32);
     const Real *kt = kt_in_lds ? kt_lds : kt_glob;
@@ -117,6 +121,14 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     if (kt_in_lds)
         for (int i = tid; i < n_kt; i += bdim) kt_lds[i] = kt_glob[i];
     for (int q = tid; q < kClasses; q += bdim) cls_A[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
+    for (int k = tid; k < a.n_steps; k += bdim) {
+        const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots,
+                                          dv.n_knots, (double)((j0 >> 1) + k - dv.n_set) * a.dt);
+        const double g = exp(0.5 * a.beta * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
+        step_V[k] = V;
+        step_g[k] = g;
+        step_thr0[k] = threshold_of(a.c0, exp(-a.beta * dv.ea_min), g);
+    }
     if (tid == 0) {
         sh.stop = 0;
         sh.ver_prev = -1;
@@ -163,17 +175,24 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         const int h = (int)(j & 1);
         const uint64_t *cur = (js & 1) ? B1 : B0;
         uint64_t *nxt = (js & 1) ? B0 : B1;
+        const int kstep = js >> 1;
+        // thread 0: progress probe of the neighbours, issued now, read after the
+        // survivors (see the slot check below)
+        const int64_t need = j + 2 - kRing - j0;
+        const bool probe = !isolated && tid == 0 && js > 0 && (sh.ver_prev < need + 2 || sh.ver_next < need + 2);
+        uint64_t pv_prev = 0, pv_next = 0;
+        if (probe) {
+            pv_prev = __hip_atomic_load(a.pub + (int64_t)tile.prev * a.pub_stride + ((j - 1) % kRing) * slot_words,
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pv_next = __hip_atomic_load(a.pub + (int64_t)tile.next * a.pub_stride + ((j - 1) % kRing) * slot_words,
+                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
         if (tid == 0) {
             if (h == 0) {
-                const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots,
-                                                  dv.n_knots, (double)(n - dv.n_set) * a.dt);
-                sh.V = V;
-                sh.g = exp(0.5 * a.beta * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
                 sh.n_down = 0;
                 sh.n_up = 0;
                 for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
             }
-            sh.thr0 = threshold_of(a.c0, cls_A[0], sh.g);
             sh.n_surv = 0;
         }
         for (int i = tid; i < nr * W; i += bdim) nxt[i] = cur[i];
@@ -190,7 +209,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
                 const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
                 const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
-                const uint32_t thr0 = sh.thr0;
+                const uint32_t thr0 = step_thr0[kstep];
                 uint32_t sv = 0;
 #pragma unroll
                 for (int jj = 0; jj < 4; ++jj) {
@@ -203,7 +222,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                     sv &= sv - 1;
                     const int o = s0 + (((bits >> bit) & 1u) ? bit : bit + 1);
                     const uint32_t w = word_of8(blkA, blkB, bit >> 1);
-                    if (w <= threshold_of(a.c0, cls_A[cls[row * P + o]], sh.g)) {
+                    if (w <= threshold_of(a.c0, cls_A[cls[row * P + o]], step_g[kstep])) {
                         const int k = atomicAdd(&sh.n_surv, 1);
                         sv_pos[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
                         sv_w[k] = w;
@@ -220,12 +239,8 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         // slot check for the publication at the end of this half-step: the slot
         // of state j+1 held state j+1-kRing, which the neighbours read during
         // their half-step j+1-kRing; they finished it once they published
-        // state j+2-kRing.  The load is issued now and consumed after the survivors.
-        const int64_t need = j + 2 - kRing - j0;
-        uint64_t probe_p = 0, probe_n = 0;
+        // state j+2-kRing.  `ver_*` hold the latest state seen published.
         const bool check = !isolated && tid == 0 && need > 0;
-        bool check_p = check && sh.ver_prev < need, check_n = check && sh.ver_next < need;
-        if (tile.next == tile.prev) check_n = false;
 
         // survivors: one wavefront each
         const int n_surv = sh.n_surv;
@@ -273,7 +288,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
 #pragma unroll
             for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
             if (lane == 0) {
-                const Real e_app = ((alpha_r * (Real)sh.V) * (Real)(t - o)) / (Real)L;
+                const Real e_app = ((alpha_r * (Real)step_V[kstep]) * (Real)(t - o)) / (Real)L;
                 const int srail = tile.r0 + srow;
                 if (decide_hop<Real>(e_app + part, sv_ea[i], sv_w[i], beta_r, c0_r, a.log, tile.d, h, n, srail, s)) {
                     atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + (s >> 6)]), 1ull << (s & 63));
@@ -289,15 +304,22 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
-        if (check_p || check_n) {  // thread 0: consume the slot check
+        if (probe) {  // thread 0: the probe issued at the top of the half-step
+            const uint32_t want = pub_tag(epoch, j - 1 - j0);
+            const uint32_t tp = (uint32_t)(pv_prev >> 32), tn = (uint32_t)(pv_next >> 32);
+            if ((tp >> 12) == (want >> 12) && tp >= want) sh.ver_prev = max(sh.ver_prev, (int64_t)(tp & 0xFFFu));
+            if ((tn >> 12) == (want >> 12) && tn >= want) sh.ver_next = max(sh.ver_next, (int64_t)(tn & 0xFFFu));
+        }
+        if (check && (sh.ver_prev < need || (tile.next != tile.prev && sh.ver_next < need))) {
+            uint64_t v = 0;
             bool ok = true;
-            if (check_p) {
-                ok = fetch(tile.prev, j + 2 - kRing, 0, true, &probe_p);
-                if (ok) sh.ver_prev = (int64_t)((uint32_t)(probe_p >> 32) & 0xFFFu);
+            if (sh.ver_prev < need) {
+                ok = fetch(tile.prev, j + 2 - kRing, 0, true, &v);
+                if (ok) sh.ver_prev = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
             }
-            if (ok && check_n) {
-                ok = fetch(tile.next, j + 2 - kRing, 0, true, &probe_n);
-                if (ok) sh.ver_next = (int64_t)((uint32_t)(probe_n >> 32) & 0xFFFu);
+            if (ok && tile.next != tile.prev && sh.ver_next < need) {
+                ok = fetch(tile.next, j + 2 - kRing, 0, true, &v);
+                if (ok) sh.ver_next = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
             }
             if (!ok) sh.stop = 1;
         }
