@@ -94,6 +94,16 @@ __device__ __forceinline__ int tile_of_block(int bid, int n_tiles) {
     return bid < full ? (bid % 8) * (n_tiles / 8) + bid / 8 : bid;
 }
 
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() also waits
+// for every global load and store the wavefront has in flight; inside the
+// persistent loop that would make every barrier wait for the edge-rail
+// publications and the neighbour probes.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Arrhenius hop probability with the half-energy barrier shift (paper main
 // text Eq. hop_rate and Eq. 2), p = min(nu0 dt exp(-beta (Ea + dE/2)), 1);
 // accept when u < p; draws with |u - p| < 1e-6 are appended to the log.

@@ -48,7 +48,7 @@ struct PTile {
     int32_t d, r0, nr, prev, next, pad_;
 };
 
-constexpr int kRing = 8;                 // publication slots per tile
+constexpr int kRing = 32;                // publication slots per tile
 constexpr int kPMaxBlock = 1024;         // threads per workgroup, persistent kernel
 
 // Step bookkeeping in device memory (lets a captured graph be replayed).

@@ -136,11 +136,16 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     }
     __syncthreads();
 
-    // the edge rails of `state` as state j (no wait: tags validate the data)
+    // The edge rails of `state` as state j (no wait: tags validate the data).
+    // The stores are issued by the last wavefronts: on gfx950 one counter
+    // tracks a wavefront's loads and stores, so a wavefront that later waits
+    // for a load (thread 0's progress probes) must not have stores in flight.
+    const int pub_first = bdim - ((slot_words + 63) / 64) * 64;
     auto publish = [&](const uint64_t *state, int64_t j) {
         uint64_t *slot = a.pub + (int64_t)ti * a.pub_stride + (int64_t)(j % kRing) * slot_words;
         const uint64_t tag = (uint64_t)pub_tag(epoch, j - j0) << 32;
-        for (int i = tid; i < slot_words; i += bdim) {
+        for (int i = tid - (pub_first > 0 ? pub_first : 0); i >= 0 && i < slot_words;
+             i += (pub_first > 0 ? slot_words : bdim)) {
             const int b = i / W32, q = i - b * W32;
             const int rrow = b < m ? b : nr - 2 * m + b;
             const uint32_t data = (uint32_t)(state[rrow * W + (q >> 1)] >> (32 * (q & 1)));
@@ -176,17 +181,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         const uint64_t *cur = (js & 1) ? B1 : B0;
         uint64_t *nxt = (js & 1) ? B0 : B1;
         const int kstep = js >> 1;
-        // thread 0: progress probe of the neighbours, issued now, read after the
-        // survivors (see the slot check below)
         const int64_t need = j + 2 - kRing - j0;
-        const bool probe = !isolated && tid == 0 && js > 0 && (sh.ver_prev < need + 2 || sh.ver_next < need + 2);
-        uint64_t pv_prev = 0, pv_next = 0;
-        if (probe) {
-            pv_prev = __hip_atomic_load(a.pub + (int64_t)tile.prev * a.pub_stride + ((j - 1) % kRing) * slot_words,
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            pv_next = __hip_atomic_load(a.pub + (int64_t)tile.next * a.pub_stride + ((j - 1) % kRing) * slot_words,
-                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         if (tid == 0) {
             if (h == 0) {
                 sh.n_down = 0;
@@ -196,7 +191,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
             sh.n_surv = 0;
         }
         for (int i = tid; i < nr * W; i += bdim) nxt[i] = cur[i];
-        __syncthreads();
+        lds_barrier();
         if (sh.stop) break;
 
         // candidates, Philox words, exact two-stage prefilter
@@ -234,13 +229,28 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
 
-        // slot check for the publication at the end of this half-step: the slot
+        // Slot check for the publication at the end of this half-step: the slot
         // of state j+1 held state j+1-kRing, which the neighbours read during
         // their half-step j+1-kRing; they finished it once they published
-        // state j+2-kRing.  `ver_*` hold the latest state seen published.
-        const bool check = !isolated && tid == 0 && need > 0;
+        // state j+2-kRing.  Thread 0 learns the neighbours' progress with one
+        // blocking probe every 16 half-steps (the ring is deep enough that the
+        // probe stays ahead of the need); wavefront 0 is delayed by one load
+        // latency while the other wavefronts work on their survivors.
+        if (!isolated && tid == 0 && js > 0 && ((js & 15) == 0 || sh.ver_prev < need || sh.ver_next < need)) {
+            const int64_t target = max(need, j - 4 - j0) + j0;
+            uint64_t v = 0;
+            bool ok = fetch(tile.prev, target, 0, true, &v);
+            if (ok) sh.ver_prev = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
+            if (ok && tile.next != tile.prev) {
+                ok = fetch(tile.next, target, 0, true, &v);
+                if (ok) sh.ver_next = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
+            } else if (ok) {
+                sh.ver_next = sh.ver_prev;
+            }
+            if (!ok) sh.stop = 1;
+        }
 
         // survivors: one wavefront each
         const int n_surv = sh.n_surv;
@@ -304,26 +314,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
-        if (probe) {  // thread 0: the probe issued at the top of the half-step
-            const uint32_t want = pub_tag(epoch, j - 1 - j0);
-            const uint32_t tp = (uint32_t)(pv_prev >> 32), tn = (uint32_t)(pv_next >> 32);
-            if ((tp >> 12) == (want >> 12) && tp >= want) sh.ver_prev = max(sh.ver_prev, (int64_t)(tp & 0xFFFu));
-            if ((tn >> 12) == (want >> 12) && tn >= want) sh.ver_next = max(sh.ver_next, (int64_t)(tn & 0xFFFu));
-        }
-        if (check && (sh.ver_prev < need || (tile.next != tile.prev && sh.ver_next < need))) {
-            uint64_t v = 0;
-            bool ok = true;
-            if (sh.ver_prev < need) {
-                ok = fetch(tile.prev, j + 2 - kRing, 0, true, &v);
-                if (ok) sh.ver_prev = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
-            }
-            if (ok && tile.next != tile.prev && sh.ver_next < need) {
-                ok = fetch(tile.next, j + 2 - kRing, 0, true, &v);
-                if (ok) sh.ver_next = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
-            }
-            if (!ok) sh.stop = 1;
-        }
-        __syncthreads();
+        lds_barrier();
         if (sh.stop) break;
 
         if (!isolated) publish(nxt, j + 1);
