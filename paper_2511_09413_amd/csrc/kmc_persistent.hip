@@ -234,20 +234,32 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         // Slot check for the publication at the end of this half-step: the slot
         // of state j+1 held state j+1-kRing, which the neighbours read during
         // their half-step j+1-kRing; they finished it once they published
-        // state j+2-kRing.  Thread 0 learns the neighbours' progress with one
-        // blocking probe every 16 half-steps (the ring is deep enough that the
-        // probe stays ahead of the need); wavefront 0 is delayed by one load
-        // latency while the other wavefronts work on their survivors.
-        if (!isolated && tid == 0 && js > 0 && ((js & 15) == 0 || sh.ver_prev < need || sh.ver_next < need)) {
-            const int64_t target = max(need, j - 4 - j0) + j0;
+        // state j+2-kRing (`need`, relative to the launch).  Thread 0 keeps the
+        // latest published state it has seen of each neighbour and refreshes
+        // it only when it comes within 8 half-steps of the need: both
+        // neighbours' slots of state j-1 are loaded together (their tags name
+        // the state they hold), and only if a neighbour is truly behind does
+        // thread 0 poll for state `need`.  In steady state that is one load
+        // latency every twenty-odd half-steps for wavefront 0 alone.
+        if (!isolated && tid == 0 && js > 0 && (sh.ver_prev < need + 8 || sh.ver_next < need + 8)) {
+            const int64_t slot_prev = (int64_t)tile.prev * a.pub_stride + ((j - 1) % kRing) * slot_words;
+            const int64_t slot_next = (int64_t)tile.next * a.pub_stride + ((j - 1) % kRing) * slot_words;
+            const uint64_t vp = __hip_atomic_load(a.pub + slot_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t vn = __hip_atomic_load(a.pub + slot_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t epoch_bits = pub_tag(epoch, 0) >> 12;
+            const uint32_t tp = (uint32_t)(vp >> 32), tn = (uint32_t)(vn >> 32);
+            if ((tp >> 12) == epoch_bits) sh.ver_prev = max(sh.ver_prev, (int64_t)(tp & 0xFFFu));
+            if ((tn >> 12) == epoch_bits) sh.ver_next = max(sh.ver_next, (int64_t)(tn & 0xFFFu));
+            if (tile.next == tile.prev) sh.ver_next = sh.ver_prev = max(sh.ver_prev, sh.ver_next);
+            bool ok = true;
             uint64_t v = 0;
-            bool ok = fetch(tile.prev, target, 0, true, &v);
-            if (ok) sh.ver_prev = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
-            if (ok && tile.next != tile.prev) {
-                ok = fetch(tile.next, target, 0, true, &v);
+            if (need > 0 && sh.ver_prev < need) {
+                ok = fetch(tile.prev, j0 + need, 0, true, &v);
+                if (ok) sh.ver_prev = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
+            }
+            if (ok && need > 0 && sh.ver_next < need) {
+                ok = fetch(tile.next, j0 + need, 0, true, &v);
                 if (ok) sh.ver_next = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
-            } else if (ok) {
-                sh.ver_next = sh.ver_prev;
             }
             if (!ok) sh.stop = 1;
         }
