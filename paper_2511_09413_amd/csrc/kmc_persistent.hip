@@ -237,13 +237,15 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         // state j+2-kRing (`need`, relative to the launch).  Thread 0 keeps the
         // latest published state it has seen of each neighbour and refreshes
         // it only when it comes within 8 half-steps of the need: both
-        // neighbours' slots of state j-1 are loaded together (their tags name
-        // the state they hold), and only if a neighbour is truly behind does
-        // thread 0 poll for state `need`.  In steady state that is one load
+        // neighbours' slots of state j-4 are loaded together (their tags name
+        // the state they hold; a store takes about a half-step to become
+        // visible, so a state published a few half-steps ago is read back
+        // reliably), and only if a neighbour is truly behind does thread 0
+        // poll for state `need`.  In steady state that is one load
         // latency every twenty-odd half-steps for wavefront 0 alone.
-        if (!isolated && tid == 0 && js > 0 && (sh.ver_prev < need + 8 || sh.ver_next < need + 8)) {
-            const int64_t slot_prev = (int64_t)tile.prev * a.pub_stride + ((j - 1) % kRing) * slot_words;
-            const int64_t slot_next = (int64_t)tile.next * a.pub_stride + ((j - 1) % kRing) * slot_words;
+        if (!isolated && tid == 0 && js >= 4 && (sh.ver_prev < need + 8 || sh.ver_next < need + 8)) {
+            const int64_t slot_prev = (int64_t)tile.prev * a.pub_stride + ((j - 4) % kRing) * slot_words;
+            const int64_t slot_next = (int64_t)tile.next * a.pub_stride + ((j - 4) % kRing) * slot_words;
             const uint64_t vp = __hip_atomic_load(a.pub + slot_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint64_t vn = __hip_atomic_load(a.pub + slot_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t epoch_bits = pub_tag(epoch, 0) >> 12;
