@@ -1,34 +1,46 @@
 """Benchmark of the rail-KMC hop step on one MI355X.
 
-Workload (default): a single large device, 4096 rails x 1024 sites, 30% filling,
+Workload: a single large device, 4096 rails x 1024 sites, 30% filling,
 per-site barriers Ea ~ N(0.3, 0.02) eV (binary32), a +-2 V triangular sweep over
 1e5 steps of 1 ps, screened Coulomb (lambda = 4 sites, cutoff 16, +-1 rail),
-binary32 rates.  A "step" is one full hop step (both bond parities) of the whole
-lattice.  Inputs are resident in HBM before the timed region.
+binary32 rates.  A step is one full hop step (both bond parities) of the whole
+lattice.  Inputs are resident in device memory before the timed region.
 
-Prints one JSON line: site-updates/s (value), effective HBM GB/s of the
-algorithmic traffic, the roofline of the dominant kernel and the CPU oracle
-timed on a bounded sample of the same workload.
+Prints one JSON line: site-updates/s (value), the roofline of the dominant
+kernel (the hop kernel: VALU-bound by the Philox4x32-10 stream), the effective
+HBM rate of the method's algorithmic traffic, and the CPU oracle timed on a
+bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz = one wave64 VALU instruction
+# per SIMD every 4 cycles = 3.93e13 32-bit lane-operations per second.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-N_CU, CLOCK_GHZ = 256, 2.4
+# one Philox4x32-10 block = 10 rounds x (2 v_mad_u64_u32 + 2 v_bitop3_b32)
+OPS_PER_PHILOX_BLOCK = 40
+# algorithmic bytes per site-update of the method (occupancy 1 B and the
+# binary32 barrier 4 B per half-step pass)
+BYTES_PER_SITE_UPDATE = 10.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_persistent_c2_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2511_09413_amd", "csrc", f)
+                  for f in ("kmc_persistent.hip", "kmc_device.h", "kmc_internal.h")]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100_000)
-    ap.add_argument("--warmup", type=int, default=2_000)
+    ap.add_argument("--warmup", type=int, default=2_048)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent"])
@@ -36,10 +48,35 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_sha1() -> str:
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the hop kernel from the counter profile summary
+    (its json block), or None when there is none."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_FILE).read(), re.S)
+    return json.loads(m.group(1)) if m else None
+
+
+def philox_blocks_per_step(rails, sites) -> int:
+    """One 32-bit Philox word per bond and half-step, four words per block."""
+    total = 0
+    for R, L in zip(rails, sites):
+        for h in (0, 1):
+            bonds = max(0, (L - h) // 2)
+            total += R * ((bonds + 3) // 4)
+    return total
+
+
 def cpu_baseline(wl, budget_s):
     """The oracle as it stands (single thread) on whole steps of the same
     device, stopping once budget_s of CPU time is spent."""
-    import numpy as np
     import oracle
     p = oracle.params_for(wl)
     occ = oracle.fill(p, wl.filling)
@@ -49,16 +86,15 @@ def cpu_baseline(wl, budget_s):
         steps += 1
     el = time.perf_counter() - t0
     return {"value": wl.n_sites * steps / el, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} full steps of the 4096x1024 device (single-threaded C oracle, {el:.1f} s)"}
+            "sample": f"{steps} whole steps of the 4096x1024 device, single-threaded C oracle, {el:.1f} s"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding is a "
-              f"design in DESIGN.md, not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU (asked for {args.gpus}): the multi-GPU sharding is a design "
+              f"note only, nothing here uses a second GPU", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import paper_2511_09413_amd as kmc
     from workloads import c2_large_device
@@ -73,24 +109,33 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t_wall = time.perf_counter()
     e0.record(stream)
     sim.run_steps(args.steps)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_wall
-    ms = e0.elapsed_time(e1)
-    sec = ms / 1e3
-    sites = wl.n_sites
-    value = sites * args.steps / sec
-    # algorithmic HBM traffic per site-update: occupancy 1 B per half-step pass
-    # and the binary32 barrier 4 B per half-step pass
-    bytes_per_site_update = 10.0
-    eff_gbs = bytes_per_site_update * value / 1e9
-    launches = 2 * args.steps
+    sec = e0.elapsed_time(e1) / 1e3
+    value = wl.n_sites * args.steps / sec
+    cur, tot, t_sim = sim.read_current()   # also checks the kernel status
+    mode = sim.launch_mode
+
+    # dominant kernel: hop_persistent (one launch per 1024 steps) or
+    # hop_half_step (one launch per half-step)
+    if mode == "persistent":
+        launches = (args.steps + 1023) // 1024
+        kernel = "hop_persistent"
+    else:
+        launches = 2 * args.steps
+        kernel = "hop_half_step"
     per_launch_s = sec / launches
-    cur, tot, t_sim = sim.read_current()
+    blocks_per_launch = philox_blocks_per_step(wl.rails, wl.sites) * args.steps / launches
+    achieved = OPS_PER_PHILOX_BLOCK * blocks_per_launch / per_launch_s / 1e12
+    traffic = None
+    if mode == "persistent":
+        t = measured_traffic()
+        if t is not None and t.get("kernel_sha1") == kernel_sha1():
+            traffic = t["hbm_bytes_per_launch"]
     out = {
         "metric": "site-updates/s (4096x1024 rails)",
         "value": value,
@@ -98,23 +143,23 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": sec * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": wl.name, "rails": 4096, "sites": 1024, "filling": 0.3,
-                   "protocol": "triangle +-2 V over 1e5 steps", "ea": "N(0.3,0.02) eV per site",
-                   "coulomb": "lambda=4, cutoff=16, +-1 rail", "parallelism": "single GPU"},
-        "effective_hbm_gbs": eff_gbs,
+                   "protocol": "triangle +-2 V over 1e5 steps", "barriers": "N(0.3,0.02) eV per site",
+                   "coulomb": "lambda=4, cutoff=16, +-1 rail", "launch_mode": mode},
+        "effective_hbm_gbs": BYTES_PER_SITE_UPDATE * value / 1e9,
+        "effective_hbm_frac": BYTES_PER_SITE_UPDATE * value / 1e9 / HBM_PEAK_GBS,
+        "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                     "avg_launch_us": per_launch_s * 1e6, "launches": launches},
         "wall_s": wall,
         "net_hops_total": int(tot[0]),
-        "launch_mode": sim.launch_mode,
-        "roofline": {"bound": "hbm", "achieved": bytes_per_site_update / 2 * sites / per_launch_s / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": bytes_per_site_update / 2 * sites / per_launch_s / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None},
+        "mean_current_A": float(cur[0]),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

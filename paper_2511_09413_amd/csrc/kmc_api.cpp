@@ -4,6 +4,7 @@
 // table, the prefilter bound, the tile decomposition and the launch sequence.
 // Every step of the hop path itself runs in the HIP kernels of kmc_kernels.hip.
 #include "../../include/kmc.h"
+#include "../../include/kmc_calib.h"
 
 #include <hip/hip_runtime.h>
 
@@ -38,6 +39,7 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 hipError_t launch_persistent(const PArgs &a, int block, size_t lds, bool fp64, hipStream_t st);
 hipError_t persistent_capacity(int block, size_t lds, bool fp64, int *blocks_per_cu);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t st);
+hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st);
 }  // namespace kmc
 
 using namespace kmc;
@@ -716,6 +718,15 @@ kmc_status kmc_set_tile_sites(kmc_ctx *c, int32_t sites) {
                              hipMemcpyHostToDevice));
     KMC_HIP(c, set_hop_lds_limit(c->hop_lds));
     if (c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) c->mode = KMC_LAUNCH_AUTO;
+    return KMC_OK;
+}
+
+kmc_status kmc_calib_copy(const void *src, void *dst, size_t bytes, void *stream) {
+    if (!src || !dst) return fail(KMC_EINVAL, "NULL pointer");
+    if (bytes % 16 != 0 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return fail(KMC_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    const hipError_t e = launch_copy_bytes(src, dst, bytes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(KMC_EHIP, std::string("copy launch: ") + hipGetErrorString(e));
     return KMC_OK;
 }
 

@@ -471,6 +471,12 @@ __global__ void fill_u64(unsigned long long *p, int64_t n, unsigned long long v)
     if (i < n) p[i] = v;
 }
 
+// Plain streaming copy (16 bytes per lane per iteration), for counter calibration.
+__global__ void copy_bytes(const uint4 *src, uint4 *dst, int64_t n16) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------------
 // Host-side launch wrappers (called from kmc_api.cpp)
 // ------------------------------------------------------------------------
@@ -567,6 +573,12 @@ hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec,
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_i32, dim3(grid_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    hipLaunchKernelGGL(copy_bytes, dim3(2048), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16);
     return hipGetLastError();
 }
 
