@@ -33,7 +33,9 @@ class _Protocol(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("shuffle_seed", C.c_uint64), ("rail_lo", C.c_int), ("rail_hi", C.c_int)]
+    _fields_ = [("shuffle_seed", C.c_uint64), ("rail_lo", C.c_int), ("rail_hi", C.c_int),
+                ("score_w", C.POINTER(C.c_double)), ("score_grad", C.POINTER(C.c_double)),
+                ("score_mag", C.POINTER(C.c_double)), ("score_sens", C.POINTER(C.c_double))]
 
 
 LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
@@ -191,7 +193,7 @@ def run(p: OracleParams, protocols, occ: np.ndarray, n0: int, n_steps: int,
     tot = net_total if net_total is not None else np.zeros(D, dtype=np.int64)
     log = np.zeros(max(log_cap, 1), dtype=LOG_DTYPE)
     n_log = C.c_int64(0)
-    opts = _Opts(shuffle_seed, rail_lo, rail_hi)
+    opts = _Opts(shuffle_seed, rail_lo, rail_hi, None, None, None, None)
     rc = lib().orc_run(C.byref(p.s), prot.arr, _ptr(occ_c, C.c_int8), n0, n_steps,
                        _ptr(net, C.c_int32), _ptr(dec, C.c_int32), _ptr(tot, C.c_int64),
                        log.ctypes.data_as(C.c_void_p), log_cap, C.byref(n_log), C.byref(opts))
@@ -202,3 +204,32 @@ def run(p: OracleParams, protocols, occ: np.ndarray, n0: int, n_steps: int,
     n_ev = int(n_log.value)
     return {"occ": occ_c, "net": net, "dec": dec, "net_total": tot,
             "log": log[:min(n_ev, log_cap)], "n_log": n_ev}
+
+
+def score_replay(p: OracleParams, protocols, occ0: np.ndarray, n0: int, weights: np.ndarray,
+                 n_set: Optional[Sequence[int]] = None) -> Dict[str, np.ndarray]:
+    """Replay the steps [n0, n0 + len(weights)) from occ0 (not modified) and sum,
+    per device, the score-function terms of every hop decision weighted by
+    weights[k][d] (k = step - n0).  Returns grad, mag (sum of |term|) and sens
+    (sum of |W g| p/(1-p)^2), each [D][4] over theta = (Ea shift, nu0, kappa,
+    alpha), and the replayed final occupancy."""
+    D = len(p.rails)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    n_steps = w.shape[0]
+    if w.shape != (n_steps, D):
+        raise ValueError("weights must be [n_steps][n_devices]")
+    occ = np.ascontiguousarray(occ0, dtype=np.int8).reshape(-1).copy()
+    prot = Protocols(protocols, n_set if n_set is not None else [0] * D)
+    grad = np.zeros((D, 4))
+    mag = np.zeros((D, 4))
+    sens = np.zeros((D, 4))
+    opts = _Opts(0, 0, 0, _ptr(w, C.c_double), _ptr(grad, C.c_double), _ptr(mag, C.c_double),
+                 _ptr(sens, C.c_double))
+    n_log = C.c_int64(0)
+    rc = lib().orc_run(C.byref(p.s), prot.arr, _ptr(occ, C.c_int8), n0, n_steps, None, None, None,
+                       None, 0, C.byref(n_log), C.byref(opts))
+    if rc == -2:
+        raise ValueError("score replay needs kappa != 0 and nu0 > 0")
+    if rc != 0:
+        raise ValueError("oracle rejected the run (step counter out of range)")
+    return {"grad": grad, "mag": mag, "sens": sens, "occ": occ}

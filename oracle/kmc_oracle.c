@@ -172,8 +172,12 @@ static double device_voltage(const orc_protocol *pr, int d, int64_t n, double dt
 /* Energy change of the hop o -> t on rail r (occupancy snapshot S of   */
 /* one device, R x L).  Binary64 and binary32 paths.                    */
 /* ------------------------------------------------------------------ */
-double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
-                            int r, int o, int t, double V)
+/* The two parts of the energy change: the applied-bias drop e_app and the
+ * Coulomb sum e_coul over the snapshot (window terms visited rail by rail in
+ * the neighbour order, sites in increasing order). */
+static void delta_energy_parts_f64(const orc_params *P, int R, int L, const int8_t *S,
+                                   int r, int o, int t, double V, double *e_app_out,
+                                   double *e_coul_out)
 {
     double e_app = ((P->alpha * V) * (double)(t - o)) / (double)L;
     int rails[64], dists[64];
@@ -191,11 +195,13 @@ double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
             e_coul += orc_kernel(P, t - j, dists[i]) - orc_kernel(P, o - j, dists[i]);
         }
     }
-    return e_app + e_coul;
+    *e_app_out = e_app;
+    *e_coul_out = e_coul;
 }
 
-float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
-                           int r, int o, int t, double V)
+static void delta_energy_parts_f32(const orc_params *P, int R, int L, const int8_t *S,
+                                   int r, int o, int t, double V, float *e_app_out,
+                                   float *e_coul_out)
 {
     float a = (float)P->alpha, v = (float)V;
     float e_app = ((a * v) * (float)(t - o)) / (float)L;
@@ -216,6 +222,23 @@ float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
             e_coul += kt - ko;
         }
     }
+    *e_app_out = e_app;
+    *e_coul_out = e_coul;
+}
+
+double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
+                            int r, int o, int t, double V)
+{
+    double e_app, e_coul;
+    delta_energy_parts_f64(P, R, L, S, r, o, t, V, &e_app, &e_coul);
+    return e_app + e_coul;
+}
+
+float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
+                           int r, int o, int t, double V)
+{
+    float e_app, e_coul;
+    delta_energy_parts_f32(P, R, L, S, r, o, t, V, &e_app, &e_coul);
     return e_app + e_coul;
 }
 
@@ -301,6 +324,36 @@ static void permutation(int64_t m, uint64_t seed, int64_t *perm)
     }
 }
 
+/* Score-function (likelihood-ratio) term of one Bernoulli hop decision.
+ * The decision y ~ Bernoulli(p) with p = nu0 dt exp(-beta (Ea + dE/2)) (main
+ * text Eq. hop_rate with the half-energy shift of Eq. 2) has
+ *     d log P(y) / d theta = (d log p / d theta) (y - p) / (1 - p)
+ * while p < 1, and 0 once p is clamped at 1.  The log-derivatives of p for
+ * theta = (Ea shift of every barrier, nu0, kappa, alpha) are
+ *     -beta,  1/nu0,  -(beta/2) e_coul/kappa,  -(beta/2) V (t - o)/L ,
+ * since e_coul is linear in kappa and e_app = alpha V (t - o)/L.  The term is
+ * weighted by W[k][d] (the caller's weight of the decision's step) and summed
+ * per device.  Also summed: |term| (magnitude) and |W g| p/(1-p)^2, the
+ * sensitivity of the term to a relative change of p (its derivative in p
+ * times p). */
+static void add_score(const orc_params *P, const orc_run_opts *opts, int64_t k, int d,
+                      int accept, double p, double e_coul, double V, int o, int t, int L)
+{
+    if (!(p < 1.0)) return;
+    const int D = P->n_devices;
+    const double beta = 1.0 / P->kT;
+    const double W = opts->score_w[k * D + d];
+    const double g[4] = {-beta, 1.0 / P->nu0, -0.5 * beta * e_coul / P->kappa,
+                         -0.5 * beta * V * (double)(t - o) / (double)L};
+    const double ratio = ((double)accept - p) / (1.0 - p);
+    for (int q = 0; q < 4; ++q) {
+        const double term = W * g[q] * ratio;
+        opts->score_grad[d * 4 + q] += term;
+        if (opts->score_mag) opts->score_mag[d * 4 + q] += fabs(term);
+        if (opts->score_sens) opts->score_sens[d * 4 + q] += fabs(W * g[q]) * p / ((1.0 - p) * (1.0 - p));
+    }
+}
+
 int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
             int64_t n0, int64_t n_steps, int32_t *net_out, int32_t *dec_out,
             int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,
@@ -308,6 +361,7 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
 {
     int D = P->n_devices;
     if (n0 < 0 || n0 + n_steps > (int64_t)0xffffffffLL) return -1;
+    if (opts && opts->score_grad && (P->kappa == 0.0 || !(P->nu0 > 0.0))) return -2;
     int64_t total = dev_offset(P, D);
     int8_t *S = (int8_t *)malloc((size_t)total);
     int64_t dummy_log = 0;
@@ -355,23 +409,32 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                     uint32_t w = orc_hop_word(P->seed, d, n, r, s);
                     int accept;
                     double u_log, p_log;
+                    double p_score, e_coul_score;
                     if (P->fp32) {
-                        float dE = orc_delta_energy_f32(P, R, L, Sd, r, o, t, V[d]);
+                        float e_app, e_coul;
+                        delta_energy_parts_f32(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul);
+                        float dE = e_app + e_coul;
                         float p = orc_hop_prob_f32(P, ea, dE);
                         float u = ldexpf((float)w, -32);
                         accept = u < p;
                         u_log = u; p_log = p;
+                        p_score = p; e_coul_score = e_coul;
                         if (fabsf(u - p) < 1e-6f)
                             log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
                     } else {
-                        double dE = orc_delta_energy_f64(P, R, L, Sd, r, o, t, V[d]);
+                        double e_app, e_coul;
+                        delta_energy_parts_f64(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul);
+                        double dE = e_app + e_coul;
                         double p = orc_hop_prob_f64(P, ea, dE);
                         double u = ldexp((double)w, -32);
                         accept = u < p;
                         u_log = u; p_log = p;
+                        p_score = p; e_coul_score = e_coul;
                         if (fabs(u - p) < 1e-6)
                             log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
                     }
+                    if (opts && opts->score_grad)
+                        add_score(P, opts, k, d, accept, p_score, e_coul_score, V[d], o, t, L);
                     if (accept) {
                         Od[(int64_t)r * L + o] = 0;
                         Od[(int64_t)r * L + t] = 1;

@@ -41,6 +41,14 @@ typedef struct {
 typedef struct {
     uint64_t shuffle_seed; /* nonzero: visit bonds in a random order */
     int rail_lo, rail_hi;  /* rail_hi > rail_lo: update only these rails */
+    /* score-function accumulation (all NULL: none).  score_w [n_steps][D]
+     * weights of the decisions of each step; score_grad, score_mag and
+     * score_sens [D][4] are accumulated into (theta = Ea shift, nu0, kappa,
+     * alpha).  Needs kappa != 0 and nu0 > 0. */
+    const double *score_w;
+    double *score_grad;
+    double *score_mag;
+    double *score_sens;
 } orc_run_opts;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
