@@ -153,6 +153,34 @@ kmc_status kmc_read_current(kmc_ctx *ctx, double *mean_current_A, int64_t *net_h
 kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t cap,
                                   int64_t *n_events);
 
+/* Score-function (likelihood-ratio) gradient of a weighted observable, by
+ * replaying the steps [step0, step0 + n_steps) from the state occ0.  Every hop
+ * decision y ~ Bernoulli(p) of the replay, with p of the rate law above (main
+ * text Eq. hop_rate with the half-energy shift of Eq. 2), contributes
+ *     W[k][d] * g_theta * (y - p)/(1 - p)     (0 when p is clamped at 1)
+ * to grad[d][theta], k = step - step0, where g_theta = d log p / d theta for
+ *     theta = 0: a common shift of every barrier Ea   g = -1/kT
+ *             1: nu0                                 g = 1/nu0
+ *             2: kappa                               g = -(dE_coul/kappa)/(2 kT)
+ *             3: alpha (field_coupling)              g = -V (t - o)/(2 L kT).
+ * With W[k][d] = sum_{k' >= k} w[k'] (f_d(k') - b(k')) for an observable f
+ * measured after each step, a weight w and a baseline b independent of the
+ * replica, the sum is an unbiased estimate of d E[sum_k w[k] f(k)] / d theta.
+ *   occ0_dev:   device int8 [total sites], caller layout: the state before
+ *               step step0 (for example a copy taken before kmc_run_steps).
+ *   weight_dev: device binary64 [n_steps][n_devices].
+ *   grad_dev:   device binary64 [n_devices][4], overwritten.
+ * The replay uses the protocol installed now (its knots and install step)
+ * and the context's parameters; it takes the same decisions as kmc_run_steps
+ * from the same state and steps (the Philox stream is a function of the step
+ * index).  The context's own state, step counter and tallies are not touched.
+ * The hop probability of every candidate is evaluated in full in the path's
+ * precision and the terms are summed in binary64 (sum order not fixed).
+ * Errors: KMC_EINVAL for NULL pointers, negative indices, coulomb_kappa_v == 0
+ * or nu0_hz <= 0; KMC_EUNSUPPORTED if step0 + n_steps exceeds 2^32 - 1. */
+kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                            const double *weight_dev, double *grad_dev);
+
 /* Launch strategy of kmc_run_steps.
  *   KMC_LAUNCH_HALF_STEP: one kernel launch per half-step; the state makes a
  *     round trip through device memory every half-step.  Always available.

@@ -66,13 +66,14 @@ def lib():
         L.kmc_set_launch_mode.argtypes = [vp, C.c_int32]
         L.kmc_get_launch_mode.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_tile_sites.argtypes = [vp, C.c_int32]
+        L.kmc_score_replay.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
         L.kmc_last_error.restype = C.c_char_p
         L.kmc_destroy.argtypes = [vp]
         L.kmc_destroy.restype = None
         for name in ("kmc_workspace_bytes", "kmc_init_device", "kmc_fill_random", "kmc_load_occupancy",
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
-                     "kmc_set_tile_sites"):
+                     "kmc_set_tile_sites", "kmc_score_replay"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -173,6 +174,11 @@ def set_tile_sites(ctx: int, sites: int) -> None:
     _check(lib().kmc_set_tile_sites(C.c_void_p(ctx), sites))
 
 
+def score_replay(ctx: int, occ0_ptr: int, step0: int, n_steps: int, weight_ptr: int, grad_ptr: int) -> None:
+    _check(lib().kmc_score_replay(C.c_void_p(ctx), C.c_void_p(occ0_ptr), step0, n_steps, C.c_void_p(weight_ptr),
+                                  C.c_void_p(grad_ptr)))
+
+
 def destroy(ctx: int) -> None:
     lib().kmc_destroy(C.c_void_p(ctx))
 
@@ -241,6 +247,25 @@ class Simulator:
         dec = torch.empty((n_steps, self.n_devices, 10), dtype=torch.int32, device=self.device)
         run_steps(self.ctx, n_steps, net.data_ptr(), dec.data_ptr())
         return net, dec
+
+    def snapshot(self):
+        """Device copy of the current occupancy (the start state of a later replay)."""
+        return self.occ.clone()
+
+    def score_replay(self, occ0, step0: int, weights):
+        """Score-function terms of the steps [step0, step0 + len(weights)) replayed
+        from occ0 (device int8 tensor), weighted by weights [n_steps, D]; returns
+        grad [D, 4] (float64, device) over (Ea shift, nu0, kappa, alpha)."""
+        torch = self.torch
+        occ0 = torch.as_tensor(occ0).to(self.device, torch.int8).contiguous()
+        if occ0.numel() != self.n_sites:
+            raise ValueError("occ0 size differs from the lattice")
+        w = torch.as_tensor(weights).to(self.device, torch.float64).contiguous()
+        if w.dim() != 2 or w.shape[1] != self.n_devices:
+            raise ValueError("weights must be [n_steps, n_devices]")
+        grad = torch.empty((self.n_devices, 4), dtype=torch.float64, device=self.device)
+        score_replay(self.ctx, occ0.data_ptr(), step0, w.shape[0], w.data_ptr(), grad.data_ptr())
+        return grad
 
     def read_occupancy(self) -> np.ndarray:
         return read_occupancy(self.ctx, self.n_sites)

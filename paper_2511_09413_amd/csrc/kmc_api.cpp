@@ -19,7 +19,8 @@
 
 namespace kmc {
 hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
-hipError_t set_hop_lds_limit(size_t lds_bytes);
+hipError_t launch_score(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
+hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes);
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
                          const void *ea, bool fp64, hipStream_t st);
 hipError_t launch_export(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total,
@@ -62,7 +63,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, progress, pub, status,
-        total;
+        rp_a, rp_b, score_log, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tile capacity, publication words per tile
     int max_pitch;
     int64_t total_sites, total_pad, rails_total;
@@ -156,6 +157,10 @@ Layout layout_for(const kmc_params *p) {
     L.progress = take(sizeof(uint64_t) * 8 * (size_t)L.max_ptiles);
     L.pub = take(sizeof(uint64_t) * (size_t)(L.pub_stride * L.max_ptiles));
     L.status = take(sizeof(int32_t) * 4);
+    // score replay: its own pair of state planes and a discarded event count
+    L.rp_a = take((size_t)pad);
+    L.rp_b = take((size_t)pad);
+    L.score_log = take(sizeof(int64_t));
     L.total = off;
     return L;
 }
@@ -186,6 +191,7 @@ struct kmc_ctx {
     int64_t n = 0;            // host mirror of the step counter
     int64_t steps_run = 0;    // steps since init (for the mean current)
     size_t hop_lds = 0;
+    size_t score_lds = 0;              // hop_lds plus the occupancy bit rows
     int8_t *cur = nullptr, *nxt = nullptr;
     int tile_sites = 0;                // target padded sites per tile (0 = default)
     std::vector<PTile> ptiles;         // persistent tiling
@@ -248,7 +254,7 @@ void make_tiles(kmc_ctx *c) {
         nr = std::min(nr, dv.rails);
         for (int r0 = 0; r0 < dv.rails; r0 += nr) c->tiles.push_back(Tile{d, r0, std::min(nr, dv.rails - r0), 0});
     }
-    size_t lds = 0;
+    size_t lds = 0, score_lds = 0;
     for (const Tile &t : c->tiles) {
         const DevInfo &dv = c->devs[t.d];
         const size_t rows = (size_t)(t.nr + 2 * c->p.rail_range) * dv.pitch;
@@ -256,9 +262,12 @@ void make_tiles(kmc_ctx *c) {
         const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
         const size_t kt = n_kt <= (size_t)kLdsTableMax ? n_kt * (c->fp64 ? sizeof(double) : sizeof(float)) : 0;
         const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
-        lds = std::max(lds, rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt);
+        const size_t base = rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt;
+        lds = std::max(lds, base);
+        score_lds = std::max(score_lds, base + rows / kChunkSites * sizeof(uint16_t));
     }
     c->hop_lds = lds;
+    c->score_lds = score_lds;
 }
 
 // Persistent tiling: every device cut into n_t >= 1 tiles of consecutive rails,
@@ -314,7 +323,7 @@ bool use_persistent(const kmc_ctx *c) {
     return c->p_ok;
 }
 
-kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
+HopArgs hop_args(kmc_ctx *c) {
     const int D = c->p.n_devices;
     HopArgs a{};
     a.devs = c->at<DevInfo>(c->lay.devs);
@@ -341,6 +350,14 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
     a.log.count = c->at<int64_t>(c->lay.log_count);
     a.log.entries = c->ws + c->lay.log_entries;
     a.log.cap = kLogCap;
+    a.nu0 = c->p.nu0_hz;
+    a.kappa = c->p.coulomb_kappa_v;
+    return a;
+}
+
+kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
+    const int D = c->p.n_devices;
+    HopArgs a = hop_args(c);
     const bool persistent = use_persistent(c);
     PArgs pa{};
     if (persistent) {
@@ -539,7 +556,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i64(c->at<int64_t>(lay.progress), 8 * lay.max_ptiles, st), "zero progress counters");
     chk(launch_zero_i64(c->at<int64_t>(lay.pub), lay.pub_stride * lay.max_ptiles, st), "zero publication ring");
     chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
-    chk(set_hop_lds_limit(c->hop_lds), "LDS limit of the hop kernel");
+    chk(set_hop_lds_limit(c->hop_lds, c->score_lds), "LDS limit of the hop kernel");
     {
         const double zero_t = 0.0, zero_v = 0.0;
         chk(launch_set_protocol(c->at<double>(lay.knot_t), c->at<double>(lay.knot_v), c->at<DevInfo>(lay.devs), 0, D,
@@ -716,8 +733,43 @@ kmc_status kmc_set_tile_sites(kmc_ctx *c, int32_t sites) {
     if ((int64_t)c->ptiles.size() <= c->lay.max_ptiles)
         KMC_HIP(c, hipMemcpy(c->ws + c->lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size(),
                              hipMemcpyHostToDevice));
-    KMC_HIP(c, set_hop_lds_limit(c->hop_lds));
+    KMC_HIP(c, set_hop_lds_limit(c->hop_lds, c->score_lds));
     if (c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) c->mode = KMC_LAUNCH_AUTO;
+    return KMC_OK;
+}
+
+kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                            const double *weight_dev, double *grad_dev) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (!occ0_dev || !grad_dev) return fail(KMC_EINVAL, "occ0_dev/grad_dev is NULL");
+    if (n_steps < 0 || step0 < 0) return fail(KMC_EINVAL, "step0 and n_steps must be >= 0");
+    if (n_steps > 0 && !weight_dev) return fail(KMC_EINVAL, "weight_dev is NULL");
+    if (step0 + n_steps > (int64_t)0xffffffffLL) return fail(KMC_EUNSUPPORTED, "step index would reach 2^32");
+    if (c->p.coulomb_kappa_v == 0.0)
+        return fail(KMC_EINVAL, "score replay needs coulomb_kappa_v != 0 (the kappa score is dE_coul/kappa)");
+    if (!(c->p.nu0_hz > 0.0)) return fail(KMC_EINVAL, "score replay needs nu0_hz > 0");
+    const int D = c->p.n_devices;
+    KMC_HIP(c, launch_zero_i64(reinterpret_cast<int64_t *>(grad_dev), 4 * (int64_t)D, c->stream));
+    if (n_steps == 0) return KMC_OK;
+    int8_t *cur = c->at<int8_t>(c->lay.rp_a), *nxt = c->at<int8_t>(c->lay.rp_b);
+    KMC_HIP(c, launch_import(occ0_dev, cur, c->at<DevInfo>(c->lay.devs), D, c->lay.total_pad, c->ea, c->fp64,
+                             c->stream));
+    HopArgs a = hop_args(c);
+    a.log.count = c->at<int64_t>(c->lay.score_log);
+    a.log.cap = 0;
+    a.score_grad = grad_dev;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        a.n_abs = step0 + k;
+        a.score_w = weight_dev + k * D;
+        for (int h = 0; h < 2; ++h) {
+            a.occ_in = cur;
+            a.occ_out = nxt;
+            a.h = h;
+            KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
+            std::swap(cur, nxt);
+        }
+    }
     return KMC_OK;
 }
 

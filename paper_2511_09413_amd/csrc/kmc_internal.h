@@ -82,6 +82,11 @@ struct HopArgs {
     struct LogBuf { int64_t *count; void *entries; int64_t cap; } log;
     int32_t step_in_chunk;
     int32_t h;
+    // score replay only (hop_half_step<..., true>)
+    int64_t n_abs;             // step index of the launch
+    double nu0, kappa;
+    const double *score_w;     // [D] weights of this step's decisions
+    double *score_grad;        // [D][4] accumulators (Ea shift, nu0, kappa, alpha)
 };
 
 // Arguments of the persistent kernel (several steps per launch, each

@@ -22,6 +22,14 @@
 //      hop_rate and Eq. 2), the accept test u < p and the near-threshold log;
 //   5. accepted hops are tallied (net hops toward the grounded site 0, decile
 //      crossings), applied to the lanes' registers and the tile is written out.
+//
+// With kScore the same kernel replays a half-step for the score-function
+// gradient: the decisions are taken exactly as above (so the replay follows the
+// forward trajectory), and in addition every candidate bond gets its hop
+// probability from a lane-serial Coulomb sum over the occupied sites of the
+// window (rails in neighbour order, sites ascending) and contributes
+// W g (y - p)/(1 - p) to the device's four accumulators, g being the
+// log-derivative of p in (Ea shift, nu0, kappa, alpha).
 #include <math.h>
 
 #include <type_traits>
@@ -32,11 +40,50 @@
 namespace kmc {
 
 struct HopShared {
+    double score[kBlock / 64][4];  // score replay: per-wave partial sums
     double V;
     int32_t n_surv, n_hop, n_down, n_up;
     int32_t dec[kDeciles];
     uint32_t wtab[kClasses];  // inclusive Philox-word thresholds per barrier class
 };
+
+// Coulomb part of the energy change of the hop o -> t (bond (s, s+1)) summed by
+// one lane: occupied sites j of the window [s - cutoff, s + 1 + cutoff] on each
+// distinct neighbour rail (neighbour order), in increasing j, adding
+// K(t - j) - K(o - j); the moving ion's own sites are skipped.  rbits holds the
+// occupancy of the tile rows as 16-bit words (site k of a chunk -> bit k).
+template <typename Real>
+__device__ inline Real coulomb_serial(const uint16_t *rbits, int p16, int base_row, const DevInfo &dv,
+                                      const Real *kt, int kt_stride, int cutoff, int o, int t, int s, int L) {
+    int lo = s - cutoff, hi = s + 1 + cutoff;
+    lo = lo < 0 ? 0 : lo;
+    hi = hi > L - 1 ? L - 1 : hi;
+    Real e = (Real)0;
+    for (int k = 0; k < dv.n_nbr; ++k) {
+        const int off = dv.nbr_off[k];
+        const Real *ktr = kt + dv.nbr_dist[k] * kt_stride;
+        const uint16_t *rb = rbits + (base_row + off) * p16;
+        for (int wi = lo >> 4; wi <= (hi >> 4); ++wi) {
+            uint32_t b = rb[wi];
+            if (wi == (lo >> 4)) b &= 0xFFFFu << (lo & 15);
+            if (wi == (hi >> 4)) b &= 0xFFFFu >> (15 - (hi & 15));
+            if (off == 0) {
+                if ((o >> 4) == wi) b &= ~(1u << (o & 15));
+                if ((t >> 4) == wi) b &= ~(1u << (t & 15));
+            }
+            while (b) {
+                const int j = wi * 16 + __builtin_ctz(b);
+                b &= b - 1;
+                const int dt_ = t - j < 0 ? j - t : t - j;
+                const int do_ = o - j < 0 ? j - o : o - j;
+                const Real kt_v = dt_ > cutoff ? (Real)0 : ktr[dt_];
+                const Real ko_v = do_ > cutoff ? (Real)0 : ktr[do_];
+                e += kt_v - ko_v;
+            }
+        }
+    }
+    return e;
+}
 
 // ------------------------------------------------------------------------
 // The half-step kernel.  H = bond parity.  State bytes: bit 0 = occupied,
@@ -48,8 +95,9 @@ struct HopShared {
 //   hops   [cap] uint32 (row << 13 | s)
 //   survea [cap] Real (barrier of the survivor's origin)
 //   ktab   [(m + 1) * (cutoff + 1)] Real, when small enough
+//   rbits  [(nr + 2m) * pitch / 16] uint16 occupancy bits (score replay only)
 // ------------------------------------------------------------------------
-template <typename Real, int H>
+template <typename Real, int H, bool kScore>
 __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ HopShared sh;
@@ -72,10 +120,12 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     const int kt_stride = a.cutoff + 1;
     const int n_kt = (m + 1) * kt_stride;
     const bool kt_in_lds = n_kt <= kLdsTableMax;
+    uint16_t *rbits = reinterpret_cast<uint16_t *>(kt_lds + (kt_in_lds ? n_kt : 0));
     const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
                                                             : reinterpret_cast<const Real *>(a.ktab32);
     const int tid = threadIdx.x;
-    const int64_t n = a.ctl->n_base + a.step_in_chunk;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t n = kScore ? a.n_abs : a.ctl->n_base + a.step_in_chunk;
     const int8_t *src_dev = a.occ_in + dv.off_pad;
 
     // 1. issue the loads of the lane's chunk and of one halo chunk
@@ -129,14 +179,19 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         *reinterpret_cast<uint4 *>(rows + halo_lds_row(i) * pitch + (i - (i / p16) * p16) * kChunkSites) =
             *reinterpret_cast<const uint4 *>(halo_src(i));
     __syncthreads();
+    if constexpr (kScore) {
+        for (int i = tid; i < n_rows * p16; i += kBlock)
+            rbits[i] = (uint16_t)occ_bits(*reinterpret_cast<const uint4 *>(rows + i * kChunkSites));
+    }
 
     // 3. candidates and the exact two-stage prefilter
-    uint32_t bits = 0;
+    uint32_t bits = 0, cand_all = 0;
     if (has_chunk) {
         bits = occ_bits(v) | ((nxt & 1u) << 16);
         uint32_t cand = (bits ^ (bits >> 1)) & (H ? 0xAAAAu : 0x5555u);
         const int last = L - 2 - s0;  // bond (s0+k, s0+k+1) exists iff k <= last
         if (last < 15) cand &= last < 0 ? 0u : ((2u << last) - 1u);
+        cand_all = cand;
         const uint32_t thr0 = sh.wtab[0];  // the largest threshold (lowest class)
         uint32_t sv = 0;
 #pragma unroll
@@ -179,7 +234,6 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
         const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
         const Real *kt = kt_in_lds ? kt_lds : kt_glob;
-        const int lane = tid & 63, wave = tid >> 6;
         for (int i = wave; i < n_surv; i += kBlock / 64) {
             const int srow = (int)(surv[i] >> 13), s = (int)(surv[i] & 8191u);
             const unsigned char *rp = rows + (m + srow) * pitch;
@@ -225,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
             }
         }
         __syncthreads();
-        if (tid == 0 && sh.n_hop > 0) {
+        if (!kScore && tid == 0 && sh.n_hop > 0) {
             const int64_t k = n - a.ctl->tally_base;
             const int64_t base = k * a.n_devices + tile.d;
             atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
@@ -235,15 +289,76 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     }
 
     // 5. apply the accepted hops that touch the lane's chunk, write it out
+    uint32_t acc = 0;  // accepted bonds starting in the chunk
     if (has_chunk) {
         const int n_hop = sh.n_hop;
         for (int k = 0; k < n_hop; ++k) {
             const int hr = (int)(hops[k] >> 13), hs = (int)(hops[k] & 8191u);
             if (hr != row) continue;
-            if (hs >= s0 && hs < s0 + kChunkSites) flip_byte(v, hs - s0);
+            if (hs >= s0 && hs < s0 + kChunkSites) {
+                flip_byte(v, hs - s0);
+                acc |= 1u << (hs - s0);
+            }
             if (hs + 1 >= s0 && hs + 1 < s0 + kChunkSites) flip_byte(v, hs + 1 - s0);
         }
         *reinterpret_cast<uint4 *>(a.occ_out + dv.off_pad + (int64_t)(tile.r0 + row) * pitch + s0) = v;
+    }
+
+    // 6. score replay: every candidate's term W g (y - p)/(1 - p), binary64
+    if constexpr (kScore) {
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        if (has_chunk && cand_all) {
+            const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
+            const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
+            const Real *kt = kt_in_lds ? kt_lds : kt_glob;
+            const double W = a.score_w[tile.d];
+            const double beta = a.beta, V = sh.V;
+            const double g_ea = -beta, g_nu = 1.0 / a.nu0;
+            const int64_t row_at = dv.off + (int64_t)(tile.r0 + row) * L;
+            uint32_t cm = cand_all;
+            while (cm) {
+                const int bit = __builtin_ctz(cm);
+                cm &= cm - 1;
+                const int s = s0 + bit;
+                const bool first = (bits >> bit) & 1u;
+                const int o = first ? s : s + 1, t = first ? s + 1 : s;
+                const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[row_at + o] : (Real)a.ea_scalar;
+                const Real ec = coulomb_serial<Real>(rbits, p16, m + row, dv, kt, kt_stride, a.cutoff, o, t, s, L);
+                const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+                const Real dE = e_app + ec;
+                Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+                p = p < (Real)1 ? p : (Real)1;
+                if (p < (Real)1) {
+                    const double pd = (double)p;
+                    const double ratio = ((double)((acc >> bit) & 1u) - pd) / (1.0 - pd);
+                    const double g_k = -0.5 * beta * (double)ec / a.kappa;
+                    const double g_a = -0.5 * beta * V * (double)(t - o) / (double)L;
+                    g0 += W * g_ea * ratio;
+                    g1 += W * g_nu * ratio;
+                    g2 += W * g_k * ratio;
+                    g3 += W * g_a * ratio;
+                }
+            }
+        }
+#pragma unroll
+        for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) {
+            g0 += __shfl_xor(g0, sh_, 64);
+            g1 += __shfl_xor(g1, sh_, 64);
+            g2 += __shfl_xor(g2, sh_, 64);
+            g3 += __shfl_xor(g3, sh_, 64);
+        }
+        if (lane == 0) {
+            sh.score[wave][0] = g0;
+            sh.score[wave][1] = g1;
+            sh.score[wave][2] = g2;
+            sh.score[wave][3] = g3;
+        }
+        __syncthreads();
+        if (tid < 4) {
+            double sum = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) sum += sh.score[w][tid];
+            if (sum != 0.0) atomicAdd(&a.score_grad[tile.d * 4 + tid], sum);
+        }
     }
 }
 
@@ -482,23 +597,35 @@ __global__ void copy_bytes(const uint4 *src, uint4 *dst, int64_t n16) {
 // ------------------------------------------------------------------------
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
+template <bool kScore>
+static hipError_t launch_half_step(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
     const dim3 grid(a.n_tiles), block(kBlock);
     if (fp64) {
-        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<double, 0>), grid, block, lds_bytes, st, a);
-        else hipLaunchKernelGGL((hop_half_step<double, 1>), grid, block, lds_bytes, st, a);
+        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<double, 0, kScore>), grid, block, lds_bytes, st, a);
+        else hipLaunchKernelGGL((hop_half_step<double, 1, kScore>), grid, block, lds_bytes, st, a);
     } else {
-        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<float, 0>), grid, block, lds_bytes, st, a);
-        else hipLaunchKernelGGL((hop_half_step<float, 1>), grid, block, lds_bytes, st, a);
+        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<float, 0, kScore>), grid, block, lds_bytes, st, a);
+        else hipLaunchKernelGGL((hop_half_step<float, 1, kScore>), grid, block, lds_bytes, st, a);
     }
     return hipGetLastError();
 }
 
-hipError_t set_hop_lds_limit(size_t lds_bytes) {
-    const void *fns[4] = {(const void *)hop_half_step<double, 0>, (const void *)hop_half_step<double, 1>,
-                          (const void *)hop_half_step<float, 0>, (const void *)hop_half_step<float, 1>};
-    for (const void *f : fns) {
-        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
+    return launch_half_step<false>(a, lds_bytes, fp64, st);
+}
+
+hipError_t launch_score(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
+    return launch_half_step<true>(a, lds_bytes, fp64, st);
+}
+
+hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes) {
+    const void *fns[8] = {(const void *)hop_half_step<double, 0, false>, (const void *)hop_half_step<double, 1, false>,
+                          (const void *)hop_half_step<float, 0, false>,  (const void *)hop_half_step<float, 1, false>,
+                          (const void *)hop_half_step<double, 0, true>,  (const void *)hop_half_step<double, 1, true>,
+                          (const void *)hop_half_step<float, 0, true>,   (const void *)hop_half_step<float, 1, true>};
+    for (int i = 0; i < 8; ++i) {
+        const int bytes = (int)(i < 4 ? lds_bytes : score_lds_bytes);
+        hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

@@ -1,0 +1,166 @@
+"""Score-function replay on the GPU (kmc_score_replay) against the oracle's
+replay on the same seeds, and the autograd bridge (needs an MI355X).
+
+Tolerance.  Both sides take the same decisions and sum the same terms
+W g (y - p)/(1 - p) in binary64, in different orders.  The Coulomb part of
+the energy is summed in the same order on both sides, so p differs only
+through the exponential (device libm vs glibc, a few units in the last place
+of the path's precision, eps).  A relative change dp/p = eps moves a term by
+|W g| p/(1 - p)^2 eps, so
+    |grad_gpu - grad_oracle| <= 4 eps sens + 1e-9 mag
+with sens = sum |W g| p/(1-p)^2 and mag = sum |term| from the oracle; the
+second part covers the binary64 summation order."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import gpu_available
+from workloads import FP32, FP64, Physics, c5_gradient, constant, small_case, step_then_relax, triangle
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+EPS = {FP64: 2.0 ** -52, FP32: 2.0 ** -23}
+
+
+def _tolerance(ref, precision):
+    return 4 * EPS[precision] * ref["sens"] + 1e-9 * ref["mag"]
+
+
+def _forward_and_replay(ph, rails, sites, filling, protocols, n_steps, weights_seed, ea=None, mode="auto",
+                        tile_sites=0):
+    import torch
+    from paper_2511_09413_amd import Simulator
+    sim = Simulator(ph, rails, sites, ea=ea, mode=mode, tile_sites=tile_sites)
+    sim.fill_random(filling)
+    sim.set_protocols(protocols)
+    occ0 = sim.snapshot()
+    occ0_h = occ0.cpu().numpy()
+    net_g, _ = sim.run_steps(n_steps, tallies=True)
+    D = len(rails)
+    W = np.random.default_rng(weights_seed).normal(size=(n_steps, D))
+    grad = sim.score_replay(occ0, 0, torch.from_numpy(W)).cpu().numpy()
+    p_or = oracle.OracleParams(ph, rails, sites, ea)
+    fwd = oracle.run(p_or, protocols, occ0_h.copy(), 0, n_steps, want_dec=False)
+    ref = oracle.score_replay(p_or, protocols, occ0_h, 0, W)
+    return sim, grad, ref, net_g.cpu().numpy(), fwd
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("mode,tile", [("half_step", 0), ("persistent", 0), ("half_step", 512)])
+def test_replay_matches_oracle_ragged(precision, mode, tile):
+    """Two devices of different shapes, validation barrier (many hops), a bias
+    sweep: the GPU replay's four sums per device equal the oracle's."""
+    ph = Physics(precision=precision, seed=77, ea_ev=0.15)
+    rails, sites = [24, 5], [128, 77]
+    protos = [triangle(1.0, 300e-12), constant(-0.4)]
+    sim, grad, ref, net_g, fwd = _forward_and_replay(ph, rails, sites, [0.3, 0.45], protos, 300, 5, mode=mode,
+                                                     tile_sites=tile)
+    assert np.array_equal(net_g, fwd["net"])      # forward trajectory identical to the oracle's
+    assert np.abs(fwd["net"]).sum() > 100
+    tol = _tolerance(ref, precision)
+    assert np.all(np.abs(grad - ref["grad"]) <= tol), (grad, ref["grad"], tol)
+    assert np.all(ref["mag"] > 0)
+
+
+def test_replay_with_barrier_field_and_wide_interaction():
+    """Per-site barriers (origin-site barrier), +-2 rails, unscreened, cutoff 40."""
+    R, L = 16, 96
+    ph = Physics(precision=FP64, seed=5, ea_ev=0.15, screening_sites=0.0, cutoff_sites=40, rail_range=2)
+    ea = np.random.default_rng(3).normal(0.15, 0.02, size=R * L)
+    sim, grad, ref, net_g, fwd = _forward_and_replay(ph, [R], [L], [0.3], [constant(0.6)], 120, 9, ea=ea)
+    assert np.array_equal(net_g, fwd["net"])
+    assert np.all(np.abs(grad - ref["grad"]) <= _tolerance(ref, FP64))
+
+
+def test_replay_leaves_the_context_alone():
+    """Replaying does not change the state, the step counter or the tallies:
+    continuing afterwards gives the same trajectory as a context that never
+    replayed."""
+    import torch
+    from paper_2511_09413_amd import Simulator
+    ph = Physics(precision=FP32, seed=3, ea_ev=0.15)
+    a = Simulator(ph, [12], [64])
+    b = Simulator(ph, [12], [64])
+    for s in (a, b):
+        s.fill_random([0.3])
+        s.set_protocols([constant(0.5)])
+    occ0 = a.snapshot()
+    a.run_steps(40)
+    b.run_steps(40)
+    a.score_replay(occ0, 0, torch.ones((40, 1), dtype=torch.float64))
+    assert a.step == b.step == 40
+    na, _ = a.run_steps(60, tallies=True)
+    nb, _ = b.run_steps(60, tallies=True)
+    assert torch.equal(na, nb)
+    assert np.array_equal(a.read_occupancy(), b.read_occupancy())
+    assert np.array_equal(a.read_current()[1], b.read_current()[1])
+
+
+def test_replay_rejects_kappa_zero():
+    import torch
+    from paper_2511_09413_amd import KmcError, Simulator
+    sim = Simulator(Physics(precision=FP32, coulomb_kappa_v=0.0), [4], [32])
+    with pytest.raises(KmcError):
+        sim.score_replay(sim.snapshot(), 0, torch.ones((2, 1), dtype=torch.float64))
+
+
+def test_autograd_backward_equals_oracle_estimator():
+    """decile_observable's backward = the same estimator computed on the CPU:
+    oracle forward for f, leave-one-out baseline, reverse cumulative weights,
+    oracle replay, summed over replicas."""
+    import torch
+    from paper_2511_09413_amd.autograd import THETA, ObservableSpec, decile_observable
+    ph = Physics(precision=FP64, seed=12, ea_ev=0.15)
+    D, R, L, n = 6, 8, 40, 80
+    protos = [step_then_relax(1.0, 40e-12)] * D
+    spec = ObservableSpec(ph, [R] * D, [L] * D, [0.3] * D, protos, n, decile=0)
+    theta = torch.tensor([getattr(ph, k) for k in THETA], dtype=torch.float64, requires_grad=True)
+    w = torch.linspace(0.5, 1.5, n, dtype=torch.float64)
+    f = decile_observable(theta, spec)
+    (f * w.to(f.device)[:, None]).sum().backward()
+    g_gpu = theta.grad.numpy()
+
+    p_or = oracle.OracleParams(ph, [R] * D, [L] * D)
+    occ0 = oracle.fill(p_or, [0.3] * D)
+    out = oracle.run(p_or, protos, occ0.copy(), 0, n)
+    ions = out["dec"][0].sum(axis=1).astype(np.float64)
+    fo = out["dec"][:, :, 0] / ions
+    assert np.allclose(f.detach().cpu().numpy(), fo, rtol=0, atol=0)
+    base = (fo.sum(axis=1, keepdims=True) - fo) / (D - 1)
+    W = np.cumsum((w.numpy()[:, None] * (fo - base))[::-1], axis=0)[::-1]
+    ref = oracle.score_replay(p_or, protos, occ0, 0, W)
+    tol = _tolerance(ref, FP64).sum(axis=0)
+    assert np.all(np.abs(g_gpu - ref["grad"].sum(axis=0)) <= tol), (g_gpu, ref["grad"].sum(axis=0), tol)
+
+
+def test_c5_full_size_sampled():
+    """512 replicas x 256 x 512 (FP32), the gradient workload's shape: replay 30
+    steps on the GPU; for sampled replicas the oracle computes the same replica
+    alone (the replicas before it shrunk to 1 x 2 sites with zero weight, so the
+    replica index of the random stream is unchanged)."""
+    import torch
+    from paper_2511_09413_amd import Simulator
+    wl = c5_gradient(n_steps=30)
+    ph = wl.physics.replace(ea_ev=0.2)
+    D = len(wl.rails)
+    sim = Simulator(ph, wl.rails, wl.sites)
+    sim.fill_random(wl.filling)
+    sim.set_protocols(wl.protocols)
+    occ0 = sim.snapshot()
+    sim.run_steps(30)
+    W = np.random.default_rng(1).normal(size=(30, D))
+    grad = sim.score_replay(occ0, 0, torch.from_numpy(W)).cpu().numpy()
+    occ0_h = occ0.cpu().numpy().reshape(D, -1)
+    for d in (0, 137, D - 1):
+        rails = [1] * d + [wl.rails[d]]
+        sites = [2] * d + [wl.sites[d]]
+        p_or = oracle.OracleParams(ph, rails, sites)
+        occ = np.concatenate([np.zeros(2 * d, dtype=np.int8), occ0_h[d]])
+        Wd = np.zeros((30, d + 1))
+        Wd[:, d] = W[:, d]
+        ref = oracle.score_replay(p_or, [wl.protocols[d]] * (d + 1), occ, 0, Wd)
+        tol = _tolerance(ref, FP32)[d]
+        assert np.all(np.abs(grad[d] - ref["grad"][d]) <= tol), (d, grad[d], ref["grad"][d], tol)

@@ -98,3 +98,30 @@ def test_score_needs_kappa():
     p = oracle.OracleParams(ph, [1], [4])
     with pytest.raises(ValueError):
         oracle.score_replay(p, [constant(0.0)], np.array([1, 0, 0, 1], dtype=np.int8), 0, np.ones((2, 1)))
+
+
+def test_crn_fd_harness_matches_exact_derivative():
+    """The common-random-numbers finite-difference harness of the package,
+    driven by the oracle as simulator, agrees with the exact derivative."""
+    from paper_2511_09413_amd.autograd import crn_fd
+    R, L, ions = 1, 6, [3]
+    protocol = triangle(0.9, 8e-12)
+    ph = _physics(ea_ev=0.06)
+    lat = Lattice(R, L, ions, ph)
+    occ0 = lat.states[len(lat.states) // 3]
+    n_steps, D = 5, 20000
+    volts = [oracle.protocol_voltage(protocol[0], protocol[1], n * ph.dt_s) for n in range(n_steps)]
+    w = np.array([0.2, 0.5, 1.0, -0.3, 0.8])
+    exact = _exact_gradient(ph, R, L, ions, occ0, volts, w)
+
+    def simulate(theta):
+        phx = ph.replace(**dict(zip(THETA, theta)))
+        p = oracle.OracleParams(phx, [R] * D, [L] * D)
+        out = oracle.run(p, [protocol] * D, np.tile(occ0.reshape(-1), D), 0, n_steps)
+        return (out["dec"][:, :, 0] * w[:, None]).sum(axis=0)
+
+    theta = [getattr(ph, k) for k in THETA]
+    mean, per = crn_fd(simulate, theta, h=1e-2)
+    se = per.std(axis=1) / math.sqrt(D)
+    for q in range(4):
+        assert abs(mean[q] - exact[q]) < 4.5 * se[q] + 1e-3 * abs(exact[q]), (THETA[q], mean[q], exact[q], se[q])
