@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent"])
     ap.add_argument("--tile-sites", type=int, default=0)
+    ap.add_argument("--workload", default="large-device", choices=["large-device", "batch", "gradient"],
+                    help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
+                         "gradient: forward + score replay of 512 replicas x 256 x 512")
     return ap.parse_args()
 
 
@@ -95,6 +98,10 @@ def main():
         print(f"bench.py runs on one GPU (asked for {args.gpus}): the multi-GPU sharding is a design "
               f"note only, nothing here uses a second GPU", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "gradient":
+        return bench_gradient(args)
     import torch
     import paper_2511_09413_amd as kmc
     from workloads import c2_large_device
@@ -163,6 +170,99 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+def _timed(fn, stream):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def bench_batch(args):
+    """256 heterogeneous devices (rails U{32..1024}, sites U{64..2048}, filling
+    U[0.05,0.4], step / triangle / STDP protocols), all advanced by one call."""
+    import torch
+    import paper_2511_09413_amd as kmc
+    from workloads import c3_batched
+    steps = args.steps if args.steps != 100_000 else 8192
+    wl = c3_batched(n_steps=100_000)
+    sim = kmc.Simulator(wl.physics, wl.rails, wl.sites, device="cuda:0", mode=args.mode,
+                        tile_sites=args.tile_sites)
+    sim.fill_random(wl.filling)
+    sim.set_protocols(wl.protocols)
+    sim.run_steps(args.warmup)
+    stream = torch.cuda.current_stream()
+    sec = _timed(lambda: sim.run_steps(steps), stream)
+    sim.read_current()
+    mode = sim.launch_mode
+    value = wl.n_sites * steps / sec
+    chunks = (steps + 1023) // 1024
+    launches = chunks * sim.n_groups if mode == "persistent" else 2 * steps
+    per_launch_s = sec / launches
+    achieved = OPS_PER_PHILOX_BLOCK * philox_blocks_per_step(wl.rails, wl.sites) * steps / sec / 1e12
+    out = {
+        "metric": "site-updates/s (256-device batch)", "value": value, "unit": "site-updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": sec * 1e3 / steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": wl.name, "devices": len(wl.rails), "sites_total": wl.n_sites,
+                   "launch_mode": mode, "groups": sim.n_groups},
+        "effective_hbm_gbs": BYTES_PER_SITE_UPDATE / 5 * 2 * value / 1e9,
+        "roofline": {"bound": "alu", "kernel": "hop_persistent" if mode == "persistent" else "hop_half_step",
+                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "avg_launch_us": per_launch_s * 1e6, "launches": launches},
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+def bench_gradient(args):
+    """Forward steps and the score-function replay of 512 replicas of a
+    256 x 512 device (1 V for the first half of the run, then 0 V), FP32 step,
+    binary64 accumulators."""
+    import numpy as np
+    import torch
+    import paper_2511_09413_amd as kmc
+    from workloads import c5_gradient
+    steps = args.steps if args.steps != 100_000 else 20_000
+    wl = c5_gradient(n_steps=20_000)
+    sim = kmc.Simulator(wl.physics, wl.rails, wl.sites, device="cuda:0", mode=args.mode,
+                        tile_sites=args.tile_sites)
+    sim.fill_random(wl.filling)
+    sim.set_protocols(wl.protocols)
+    occ0 = sim.snapshot()
+    stream = torch.cuda.current_stream()
+    D = len(wl.rails)
+    W = torch.ones((steps, D), dtype=torch.float64, device="cuda:0")
+    sim.score_replay(occ0, 0, W[:min(steps, 64)])      # warm-up of the replay kernels
+    t_fwd = _timed(lambda: sim.run_steps(steps), stream)
+    grads = []
+    t_rep = _timed(lambda: grads.append(sim.score_replay(occ0, 0, W)), stream)
+    g = grads[0].cpu().numpy()
+    value = wl.n_sites * steps / (t_fwd + t_rep)
+    achieved = OPS_PER_PHILOX_BLOCK * philox_blocks_per_step(wl.rails, wl.sites) * steps / t_rep / 1e12
+    out = {
+        "metric": "gradient site-updates/s (forward + score replay)", "value": value, "unit": "site-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": (t_fwd + t_rep) * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+f64acc",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "replicas": D, "theta": ["Ea", "nu0", "kappa", "alpha"],
+                   "forward_launch_mode": sim.launch_mode},
+        "forward_site_updates_per_s": wl.n_sites * steps / t_fwd,
+        "replay_site_updates_per_s": wl.n_sites * steps / t_rep,
+        "replay_over_forward_time": t_rep / t_fwd,
+        "roofline": {"bound": "alu", "kernel": "hop_half_step<float,h,score>", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": None, "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps},
+        "grad_mean_over_replicas": [float(x) for x in g.mean(axis=0)],
+    }
     print(json.dumps(out), flush=True)
     sim.close()
 

@@ -184,10 +184,11 @@ kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0,
 /* Launch strategy of kmc_run_steps.
  *   KMC_LAUNCH_HALF_STEP: one kernel launch per half-step; the state makes a
  *     round trip through device memory every half-step.  Always available.
- *   KMC_LAUNCH_PERSISTENT: one launch per chunk of up to 1024 steps; every
- *     workgroup keeps its tile of rails in LDS and exchanges only its edge
- *     rails with its two neighbouring tiles.  Needs the whole tiling
- *     co-resident on the GPU (lattices up to tens of MB).
+ *   KMC_LAUNCH_PERSISTENT: one launch per chunk of up to 1024 steps and group
+ *     of devices; every workgroup keeps its tile of rails in LDS and exchanges
+ *     only its edge rails with its two neighbouring tiles.  Needs every single
+ *     device's tiling co-resident on the GPU; larger batches of devices run as
+ *     several launches per chunk, one per group of whole devices.
  *   KMC_LAUNCH_AUTO (default): persistent when it fits, else half-step.
  * Both give bit-identical trajectories. */
 typedef enum { KMC_LAUNCH_AUTO = 0, KMC_LAUNCH_HALF_STEP = 1, KMC_LAUNCH_PERSISTENT = 2 } kmc_launch_mode;
@@ -197,6 +198,16 @@ kmc_status kmc_set_launch_mode(kmc_ctx *ctx, int32_t mode);
 
 /* The strategy kmc_run_steps will use now (HALF_STEP or PERSISTENT). */
 kmc_status kmc_get_launch_mode(kmc_ctx *ctx, int32_t *mode);
+
+/* Number of persistent launches per 1024-step chunk: the devices are split
+ * into groups of whole devices whose tiles are co-resident on the GPU
+ * (0 when the persistent strategy does not fit). */
+kmc_status kmc_get_persistent_groups(kmc_ctx *ctx, int32_t *groups);
+
+/* Cap the number of workgroup tiles of one persistent launch (0 = as many as
+ * are co-resident), for example to leave room for other work on the GPU.
+ * Waits for the work already enqueued.  Trajectories do not depend on it. */
+kmc_status kmc_set_persistent_group_limit(kmc_ctx *ctx, int32_t max_tiles);
 
 /* Target number of (padded) sites per workgroup tile, 0 = built-in default,
  * else in [16, 65536]; tiles are whole rails.  Used by the autotuner.  Waits

@@ -67,13 +67,16 @@ def lib():
         L.kmc_get_launch_mode.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_tile_sites.argtypes = [vp, C.c_int32]
         L.kmc_score_replay.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
+        L.kmc_get_persistent_groups.argtypes = [vp, P(C.c_int32)]
+        L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
         L.kmc_last_error.restype = C.c_char_p
         L.kmc_destroy.argtypes = [vp]
         L.kmc_destroy.restype = None
         for name in ("kmc_workspace_bytes", "kmc_init_device", "kmc_fill_random", "kmc_load_occupancy",
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
-                     "kmc_set_tile_sites", "kmc_score_replay"):
+                     "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
+                     "kmc_set_persistent_group_limit"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -275,6 +278,17 @@ class Simulator:
 
     def read_threshold_log(self, cap: int = 65536):
         return read_threshold_log(self.ctx, cap)
+
+    def set_group_limit(self, max_tiles: int) -> None:
+        """At most max_tiles workgroup tiles per persistent launch (0 = what fits)."""
+        _check(lib().kmc_set_persistent_group_limit(C.c_void_p(self.ctx), max_tiles))
+
+    @property
+    def n_groups(self) -> int:
+        """Persistent launches per 1024-step chunk (groups of whole devices)."""
+        out = C.c_int32(0)
+        _check(lib().kmc_get_persistent_groups(C.c_void_p(self.ctx), C.byref(out)))
+        return int(out.value)
 
     @property
     def launch_mode(self) -> str:

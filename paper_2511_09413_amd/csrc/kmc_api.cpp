@@ -63,11 +63,12 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, progress, pub, status,
-        rp_a, rp_b, score_log, total;
-    int64_t max_ptiles, pub_stride;  // persistent kernel: tile capacity, publication words per tile
+        rp_a, rp_b, score_log, dtab64, dtab32, total;
+    int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int max_pitch;
     int64_t total_sites, total_pad, rails_total;
-    int cut;  // interaction table cutoff actually stored
+    int cut;     // interaction table cutoff actually stored
+    int dpitch;  // entries per row of the window-difference tables
 };
 
 bool is_finite(double x) { return std::isfinite(x); }
@@ -153,7 +154,7 @@ Layout layout_for(const kmc_params *p) {
     L.pub_stride = (int64_t)kRing * 2 * std::max(m, 1) * ((max_pitch + 31) / 32);
     const int64_t pub_cap = ((int64_t)64 << 20) / (8 * L.pub_stride);
     L.max_ptiles = std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap);
-    L.ptiles = take(sizeof(PTile) * (size_t)L.max_ptiles);
+    L.ptiles = take(sizeof(PTile) * (size_t)rails);  // every tile is at least one rail
     L.progress = take(sizeof(uint64_t) * 8 * (size_t)L.max_ptiles);
     L.pub = take(sizeof(uint64_t) * (size_t)(L.pub_stride * L.max_ptiles));
     L.status = take(sizeof(int32_t) * 4);
@@ -161,6 +162,9 @@ Layout layout_for(const kmc_params *p) {
     L.rp_a = take((size_t)pad);
     L.rp_b = take((size_t)pad);
     L.score_log = take(sizeof(int64_t));
+    L.dpitch = (2 * L.cut + 2 + 15) / 16 * 16;
+    L.dtab64 = take(sizeof(double) * 2 * (m + 1) * (size_t)L.dpitch);
+    L.dtab32 = take(sizeof(float) * 2 * (m + 1) * (size_t)L.dpitch);
     L.total = off;
     return L;
 }
@@ -194,7 +198,9 @@ struct kmc_ctx {
     size_t score_lds = 0;              // hop_lds plus the occupancy bit rows
     int8_t *cur = nullptr, *nxt = nullptr;
     int tile_sites = 0;                // target padded sites per tile (0 = default)
-    std::vector<PTile> ptiles;         // persistent tiling
+    int group_limit = 0;               // max tiles per persistent launch (0 = what fits)
+    std::vector<PTile> ptiles;         // persistent tiling (prev/next relative to the tile's group)
+    std::vector<std::pair<int, int>> pgroups;  // (first tile, tiles): devices run together in one launch
     int p_block = 0;
     size_t p_lds = 0;
     bool p_ok = false;                 // persistent tiling fits co-resident on this GPU
@@ -264,7 +270,9 @@ void make_tiles(kmc_ctx *c) {
         const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
         const size_t base = rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt;
         lds = std::max(lds, base);
-        score_lds = std::max(score_lds, base + rows / kChunkSites * sizeof(uint16_t));
+        const size_t n_dt = (size_t)2 * (c->p.rail_range + 1) * c->lay.dpitch;
+        const size_t dt = n_dt <= (size_t)kLdsTableMax ? n_dt * real : 0;
+        score_lds = std::max(score_lds, align_up(base + rows / kChunkSites * sizeof(uint16_t), 16) + dt);
     }
     c->hop_lds = lds;
     c->score_lds = score_lds;
@@ -307,13 +315,40 @@ void make_ptiles(kmc_ctx *c) {
     c->p_block = std::min(kPMaxBlock, (max_chunks + 63) / 64 * 64);
     c->p_lds = lds;
     c->p_ok = false;
+    c->pgroups.clear();
     // one lane per 16-site chunk: a tile holds at most kPMaxBlock chunks
-    if (max_chunks > kPMaxBlock || (int64_t)c->ptiles.size() > c->lay.max_ptiles || lds > 160 * 1024) return;
+    if (max_chunks > kPMaxBlock || lds > 160 * 1024) return;
     int per_cu = 0, dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
     if (persistent_capacity(c->p_block, lds, c->fp64, &per_cu) != hipSuccess) return;
-    c->p_ok = (int64_t)per_cu * prop.multiProcessorCount >= (int64_t)c->ptiles.size();
+    // Devices are independent: a lattice larger than what is co-resident runs
+    // as a sequence of launches over groups of whole devices, each group small
+    // enough to be co-resident (and within the ring slots).
+    int64_t cap = std::min<int64_t>((int64_t)per_cu * prop.multiProcessorCount, c->lay.max_ptiles);
+    if (c->group_limit > 0) cap = std::min<int64_t>(cap, c->group_limit);
+    if (cap < 1) return;
+    int first = 0, count = 0;
+    for (int i = 0; i < (int)c->ptiles.size();) {
+        const int d = c->ptiles[i].d;
+        int n_d = 0;
+        while (i + n_d < (int)c->ptiles.size() && c->ptiles[i + n_d].d == d) ++n_d;
+        if (n_d > cap) return;
+        if (count + n_d > cap) {
+            c->pgroups.emplace_back(first, count);
+            first = i;
+            count = 0;
+        }
+        count += n_d;
+        i += n_d;
+    }
+    if (count > 0) c->pgroups.emplace_back(first, count);
+    for (const auto &g : c->pgroups)
+        for (int i = g.first; i < g.first + g.second; ++i) {
+            c->ptiles[i].prev -= g.first;
+            c->ptiles[i].next -= g.first;
+        }
+    c->p_ok = true;
 }
 
 bool use_persistent(const kmc_ctx *c) {
@@ -352,6 +387,8 @@ HopArgs hop_args(kmc_ctx *c) {
     a.log.cap = kLogCap;
     a.nu0 = c->p.nu0_hz;
     a.kappa = c->p.coulomb_kappa_v;
+    a.dtab = c->fp64 ? (const void *)c->at<double>(c->lay.dtab64) : (const void *)c->at<float>(c->lay.dtab32);
+    a.dpitch = c->lay.dpitch;
     return a;
 }
 
@@ -364,7 +401,7 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.occ = c->cur;
         pa.devs = a.devs;
         pa.tiles = c->at<PTile>(c->lay.ptiles);
-        pa.n_tiles = (int32_t)c->ptiles.size();
+        pa.n_tiles = 0;
         pa.knot_t = a.knot_t;
         pa.knot_v = a.knot_v;
         pa.ea = a.ea;
@@ -394,16 +431,20 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
     while (done < n_steps) {
         const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
         if (persistent) {
-            // publication tags carry the low 20 bits of the epoch: at every wrap
-            // the ring is cleared so that no stale word can match a new tag
-            if ((++c->epoch & 0xFFFFFu) == 0) {
-                KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.pub), c->lay.pub_stride * c->lay.max_ptiles,
-                                           c->stream));
-                ++c->epoch;
+            for (const auto &g : c->pgroups) {
+                // publication tags carry the low 20 bits of the epoch: at every
+                // wrap the ring is cleared so that no stale word can match a new tag
+                if ((++c->epoch & 0xFFFFFu) == 0) {
+                    KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.pub), c->lay.pub_stride * c->lay.max_ptiles,
+                                               c->stream));
+                    ++c->epoch;
+                }
+                pa.tiles = c->at<PTile>(c->lay.ptiles) + g.first;
+                pa.n_tiles = g.second;
+                pa.epoch = c->epoch;
+                pa.n_steps = chunk;
+                KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
             }
-            pa.epoch = c->epoch;
-            pa.n_steps = chunk;
-            KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
         }
         for (int k = 0; k < chunk && !persistent; ++k) {
             for (int h = 0; h < 2; ++h) {
@@ -520,6 +561,28 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
             k32[(size_t)dr * (cut + 1) + ds] = (float)k64[(size_t)dr * (cut + 1) + ds];
         }
 
+    // Window differences for the score replay: row (dir, dist), entry x is
+    // site j = s - cut + x of the rail at that distance, for the bond (s, s+1)
+    // with the ion moving up (dir 0: o = s, t = s+1) or down (dir 1); the
+    // moving ion's own two sites are zero on its own rail.  Each precision's
+    // entry is the difference of that precision's two table values.
+    const int dp = lay.dpitch;
+    std::vector<double> d64((size_t)2 * (m + 1) * dp, 0.0);
+    std::vector<float> d32(d64.size(), 0.0f);
+    for (int dir = 0; dir < 2; ++dir)
+        for (int dist = 0; dist <= m; ++dist)
+            for (int x = 0; x <= 2 * cut + 1; ++x) {
+                const int jr = x - cut, orl = dir ? 1 : 0, trl = dir ? 0 : 1;
+                if (dist == 0 && (jr == 0 || jr == 1)) continue;
+                const int dt = std::abs(trl - jr), dO = std::abs(orl - jr);
+                const size_t at = ((size_t)dir * (m + 1) + dist) * dp + x;
+                const size_t row = (size_t)dist * (cut + 1);
+                const double kt64 = dt <= cut ? k64[row + dt] : 0.0, ko64 = dO <= cut ? k64[row + dO] : 0.0;
+                const float kt32 = dt <= cut ? k32[row + dt] : 0.0f, ko32 = dO <= cut ? k32[row + dO] : 0.0f;
+                d64[at] = kt64 - ko64;
+                d32[at] = kt32 - ko32;
+            }
+
     std::vector<int32_t> rail_dev, rail_idx, n_ions(D, 0);
     rail_dev.reserve(lay.rails_total);
     rail_idx.reserve(lay.rails_total);
@@ -540,10 +603,11 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     };
     chk(h2d(lay.devs, c->devs.data(), sizeof(DevInfo) * D), "copy device table");
     chk(h2d(lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size()), "copy tiles");
-    if ((int64_t)c->ptiles.size() <= lay.max_ptiles)
-        chk(h2d(lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size()), "copy persistent tiles");
+    chk(h2d(lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size()), "copy persistent tiles");
     chk(h2d(lay.ktab64, k64.data(), sizeof(double) * k64.size()), "copy kernel table");
     chk(h2d(lay.ktab32, k32.data(), sizeof(float) * k32.size()), "copy kernel table");
+    chk(h2d(lay.dtab64, d64.data(), sizeof(double) * d64.size()), "copy window differences");
+    chk(h2d(lay.dtab32, d32.data(), sizeof(float) * d32.size()), "copy window differences");
     chk(h2d(lay.ctl, &ctl, sizeof(Ctl)), "copy ctl");
     chk(h2d(lay.rail_dev, rail_dev.data(), sizeof(int32_t) * rail_dev.size()), "copy rail table");
     chk(h2d(lay.rail_idx, rail_idx.data(), sizeof(int32_t) * rail_idx.size()), "copy rail table");
@@ -719,23 +783,48 @@ kmc_status kmc_get_launch_mode(kmc_ctx *c, int32_t *mode) {
     return KMC_OK;
 }
 
+kmc_status kmc_get_persistent_groups(kmc_ctx *c, int32_t *groups) {
+    if (!c) return fail(KMC_EINVAL, "context is NULL");
+    if (!groups) return fail(KMC_EINVAL, "groups is NULL");
+    *groups = c->p_ok ? (int32_t)c->pgroups.size() : 0;
+    return KMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Rebuild both tilings after a tuning change and upload them.
+kmc_status retile(kmc_ctx *c) {
+    KMC_HIP(c, hipStreamSynchronize(c->stream));  // launches in flight use the old tiles
+    make_tiles(c);
+    make_ptiles(c);
+    KMC_HIP(c, hipMemcpy(c->ws + c->lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(),
+                         hipMemcpyHostToDevice));
+    KMC_HIP(c, hipMemcpy(c->ws + c->lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size(),
+                         hipMemcpyHostToDevice));
+    KMC_HIP(c, set_hop_lds_limit(c->hop_lds, c->score_lds));
+    if (c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) c->mode = KMC_LAUNCH_AUTO;
+    return KMC_OK;
+}
+}  // namespace
+
+extern "C" {
+
 kmc_status kmc_set_tile_sites(kmc_ctx *c, int32_t sites) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;
     if (sites != 0 && (sites < kChunkSites || sites > (1 << 16)))
         return fail(KMC_EINVAL, "tile sites must be 0 (default) or in [16, 65536]");
-    KMC_HIP(c, hipStreamSynchronize(c->stream));  // launches in flight use the old tiles
     c->tile_sites = sites;
-    make_tiles(c);
-    make_ptiles(c);
-    KMC_HIP(c, hipMemcpy(c->ws + c->lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(),
-                         hipMemcpyHostToDevice));
-    if ((int64_t)c->ptiles.size() <= c->lay.max_ptiles)
-        KMC_HIP(c, hipMemcpy(c->ws + c->lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size(),
-                             hipMemcpyHostToDevice));
-    KMC_HIP(c, set_hop_lds_limit(c->hop_lds, c->score_lds));
-    if (c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) c->mode = KMC_LAUNCH_AUTO;
-    return KMC_OK;
+    return retile(c);
+}
+
+kmc_status kmc_set_persistent_group_limit(kmc_ctx *c, int32_t max_tiles) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (max_tiles < 0) return fail(KMC_EINVAL, "max_tiles must be >= 0");
+    c->group_limit = max_tiles;
+    return retile(c);
 }
 
 kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,

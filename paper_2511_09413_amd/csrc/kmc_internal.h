@@ -85,6 +85,8 @@ struct HopArgs {
     // score replay only (hop_half_step<..., true>)
     int64_t n_abs;             // step index of the launch
     double nu0, kappa;
+    const void *dtab;          // [2][m+1][dpitch] window differences K(t-j) - K(o-j), path precision
+    int32_t dpitch;            // entries per row, >= 2*cutoff + 2, multiple of 16
     const double *score_w;     // [D] weights of this step's decisions
     double *score_grad;        // [D][4] accumulators (Ea shift, nu0, kappa, alpha)
 };

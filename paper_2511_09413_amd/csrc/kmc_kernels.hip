@@ -42,47 +42,18 @@ namespace kmc {
 struct HopShared {
     double score[kBlock / 64][4];  // score replay: per-wave partial sums
     double V;
-    int32_t n_surv, n_hop, n_down, n_up;
+    int32_t n_surv, n_hop, n_down, n_up, n_cand;
     int32_t dec[kDeciles];
     uint32_t wtab[kClasses];  // inclusive Philox-word thresholds per barrier class
 };
 
-// Coulomb part of the energy change of the hop o -> t (bond (s, s+1)) summed by
-// one lane: occupied sites j of the window [s - cutoff, s + 1 + cutoff] on each
-// distinct neighbour rail (neighbour order), in increasing j, adding
-// K(t - j) - K(o - j); the moving ion's own sites are skipped.  rbits holds the
-// occupancy of the tile rows as 16-bit words (site k of a chunk -> bit k).
-template <typename Real>
-__device__ inline Real coulomb_serial(const uint16_t *rbits, int p16, int base_row, const DevInfo &dv,
-                                      const Real *kt, int kt_stride, int cutoff, int o, int t, int s, int L) {
-    int lo = s - cutoff, hi = s + 1 + cutoff;
-    lo = lo < 0 ? 0 : lo;
-    hi = hi > L - 1 ? L - 1 : hi;
-    Real e = (Real)0;
-    for (int k = 0; k < dv.n_nbr; ++k) {
-        const int off = dv.nbr_off[k];
-        const Real *ktr = kt + dv.nbr_dist[k] * kt_stride;
-        const uint16_t *rb = rbits + (base_row + off) * p16;
-        for (int wi = lo >> 4; wi <= (hi >> 4); ++wi) {
-            uint32_t b = rb[wi];
-            if (wi == (lo >> 4)) b &= 0xFFFFu << (lo & 15);
-            if (wi == (hi >> 4)) b &= 0xFFFFu >> (15 - (hi & 15));
-            if (off == 0) {
-                if ((o >> 4) == wi) b &= ~(1u << (o & 15));
-                if ((t >> 4) == wi) b &= ~(1u << (t & 15));
-            }
-            while (b) {
-                const int j = wi * 16 + __builtin_ctz(b);
-                b &= b - 1;
-                const int dt_ = t - j < 0 ? j - t : t - j;
-                const int do_ = o - j < 0 ? j - o : o - j;
-                const Real kt_v = dt_ > cutoff ? (Real)0 : ktr[dt_];
-                const Real ko_v = do_ > cutoff ? (Real)0 : ktr[do_];
-                e += kt_v - ko_v;
-            }
-        }
-    }
-    return e;
+// Sixteen occupancy bits of sites j0 .. j0+15 of a tile row (bit k = site
+// j0 + k), zero outside the row.  rbits holds each row as 16-bit words.
+__device__ __forceinline__ uint32_t window_bits(const uint16_t *rb, int p16, int j0) {
+    const int w = j0 >> 4, sh = j0 & 15;
+    const uint32_t lo = (w >= 0 && w < p16) ? rb[w] : 0u;
+    const uint32_t hi = (w + 1 >= 0 && w + 1 < p16) ? rb[w + 1] : 0u;
+    return ((hi << 16 | lo) >> sh) & 0xFFFFu;
 }
 
 // ------------------------------------------------------------------------
@@ -96,6 +67,7 @@ __device__ inline Real coulomb_serial(const uint16_t *rbits, int p16, int base_r
 //   survea [cap] Real (barrier of the survivor's origin)
 //   ktab   [(m + 1) * (cutoff + 1)] Real, when small enough
 //   rbits  [(nr + 2m) * pitch / 16] uint16 occupancy bits (score replay only)
+//   dtab   [2][m + 1][dpitch] Real window differences (score replay only)
 // ------------------------------------------------------------------------
 template <typename Real, int H, bool kScore>
 __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
@@ -157,6 +129,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     if (tid == 0) {
         sh.V = V;
         sh.n_surv = 0;
+        sh.n_cand = 0;
         sh.n_hop = 0;
         sh.n_down = 0;
         sh.n_up = 0;
@@ -304,40 +277,79 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         *reinterpret_cast<uint4 *>(a.occ_out + dv.off_pad + (int64_t)(tile.r0 + row) * pitch + s0) = v;
     }
 
-    // 6. score replay: every candidate's term W g (y - p)/(1 - p), binary64
+    // 6. score replay: every candidate's term W g (y - p)/(1 - p), binary64.
+    //    The candidates of the tile are listed in LDS (the survivor list is free
+    //    now) and shared round-robin by all lanes.  The Coulomb part of dE is
+    //    the sum over the window sites j = s - cutoff .. s + 1 + cutoff, rail by
+    //    rail in neighbour order and j ascending, of occ_j D(j - s), with D the
+    //    precomputed difference K(t - j) - K(o - j) in the path precision (zero
+    //    at the moving ion's two sites): the same terms in the same order as a
+    //    serial sum over the occupied sites, the empty ones adding an exact 0.
     if constexpr (kScore) {
-        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-        if (has_chunk && cand_all) {
-            const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
-            const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
-            const Real *kt = kt_in_lds ? kt_lds : kt_glob;
-            const double W = a.score_w[tile.d];
-            const double beta = a.beta, V = sh.V;
-            const double g_ea = -beta, g_nu = 1.0 / a.nu0;
-            const int64_t row_at = dv.off + (int64_t)(tile.r0 + row) * L;
+        uint32_t *clist = surv;
+        if (has_chunk) {
             uint32_t cm = cand_all;
             while (cm) {
                 const int bit = __builtin_ctz(cm);
                 cm &= cm - 1;
-                const int s = s0 + bit;
-                const bool first = (bits >> bit) & 1u;
-                const int o = first ? s : s + 1, t = first ? s + 1 : s;
-                const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[row_at + o] : (Real)a.ea_scalar;
-                const Real ec = coulomb_serial<Real>(rbits, p16, m + row, dv, kt, kt_stride, a.cutoff, o, t, s, L);
-                const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
-                const Real dE = e_app + ec;
-                Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
-                p = p < (Real)1 ? p : (Real)1;
-                if (p < (Real)1) {
-                    const double pd = (double)p;
-                    const double ratio = ((double)((acc >> bit) & 1u) - pd) / (1.0 - pd);
-                    const double g_k = -0.5 * beta * (double)ec / a.kappa;
-                    const double g_a = -0.5 * beta * V * (double)(t - o) / (double)L;
-                    g0 += W * g_ea * ratio;
-                    g1 += W * g_nu * ratio;
-                    g2 += W * g_k * ratio;
-                    g3 += W * g_a * ratio;
+                const uint32_t dir = ((bits >> bit) & 1u) ? 0u : 1u;  // 0: ion at s moves up
+                const uint32_t y = (acc >> bit) & 1u;
+                const int k = atomicAdd(&sh.n_cand, 1);
+                clist[k] = ((uint32_t)row << 14) | (y << 13) | (dir << 12) | (uint32_t)(s0 + bit);
+            }
+        }
+        const size_t dt_at = (reinterpret_cast<unsigned char *>(rbits + n_rows * p16) - smem + 15) & ~(size_t)15;
+        Real *dt_lds = reinterpret_cast<Real *>(smem + dt_at);
+        const int n_dt = 2 * (m + 1) * a.dpitch;
+        const bool dt_in_lds = n_dt <= kLdsTableMax;
+        if (dt_in_lds)
+            for (int i = tid; i < n_dt; i += kBlock) dt_lds[i] = reinterpret_cast<const Real *>(a.dtab)[i];
+        __syncthreads();
+        const Real *dtab = dt_in_lds ? dt_lds : reinterpret_cast<const Real *>(a.dtab);
+        const int n_cand = sh.n_cand;
+        const int wn = 2 * a.cutoff + 2;   // window length
+        const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
+        const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
+        const double W = a.score_w[tile.d];
+        const double beta = a.beta, V = sh.V;
+        const double g_ea = -beta, g_nu = 1.0 / a.nu0;
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        for (int i = tid; i < n_cand; i += kBlock) {
+            const uint32_t e = clist[i];
+            const int crow = (int)(e >> 14), s = (int)(e & 4095u);
+            const int dir = (int)((e >> 12) & 1u);
+            const uint32_t y = (e >> 13) & 1u;
+            const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
+            const int j0 = s - a.cutoff;
+            Real ec = (Real)0;
+            for (int k = 0; k < dv.n_nbr; ++k) {
+                const Real *drow = dtab + (dir * (m + 1) + dv.nbr_dist[k]) * a.dpitch;
+                const uint16_t *rb = rbits + (m + crow + dv.nbr_off[k]) * p16;
+                for (int x0 = 0; x0 < wn; x0 += 16) {
+                    const uint32_t wb = window_bits(rb, p16, j0 + x0);
+                    if (x0 + 16 <= wn) {
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) ec += ((wb >> q) & 1u) ? drow[x0 + q] : (Real)0;
+                    } else {
+                        for (int q = 0; q < wn - x0; ++q) ec += ((wb >> q) & 1u) ? drow[x0 + q] : (Real)0;
+                    }
                 }
+            }
+            const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
+            const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[rail_at + o] : (Real)a.ea_scalar;
+            const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+            const Real dE = e_app + ec;
+            Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+            p = p < (Real)1 ? p : (Real)1;
+            if (p < (Real)1) {
+                const double pd = (double)p;
+                const double ratio = ((double)y - pd) / (1.0 - pd);
+                const double g_k = -0.5 * beta * (double)ec / a.kappa;
+                const double g_a = -0.5 * beta * V * (double)(t - o) / (double)L;
+                g0 += W * g_ea * ratio;
+                g1 += W * g_nu * ratio;
+                g2 += W * g_k * ratio;
+                g3 += W * g_a * ratio;
             }
         }
 #pragma unroll

@@ -1,0 +1,96 @@
+"""Batches of heterogeneous devices in one call (needs an MI355X): persistent
+launches over groups of whole devices against the oracle, and the full
+256-device batch sampled device by device."""
+import numpy as np
+import pytest
+
+import oracle
+from parity_util import gpu_available, lockstep
+from workloads import FP32, FP64, Physics, c3_batched, constant, step_then_relax, stdp_pair, triangle
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+RAILS = [5, 9, 3, 16, 1, 7, 12, 2, 6, 10, 4, 8]
+SITES = [64, 130, 33, 96, 257, 48, 80, 500, 17, 112, 75, 40]
+FILL = [0.3, 0.1, 0.45, 0.2, 0.5, 0.35, 0.25, 0.05, 0.4, 0.3, 0.15, 0.3]
+
+
+def _protocols(n):
+    kinds = [constant(0.6), triangle(1.0, 200e-12), step_then_relax(1.0, 60e-12), stdp_pair(20e-12, 30e-12),
+             constant(-0.4)]
+    return [kinds[i % len(kinds)] for i in range(n)]
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("limit,tile_sites", [(3, 512), (5, 512), (0, 0)])
+def test_grouped_persistent_batch_matches_oracle(precision, limit, tile_sites):
+    """12 devices of different shapes, fillings and protocols; the persistent
+    strategy split into groups of at most `limit` tiles (several launches per
+    chunk) follows the oracle step by step."""
+    from paper_2511_09413_amd import Simulator
+    ph = Physics(precision=precision, seed=99, ea_ev=0.15)
+    protos = _protocols(len(RAILS))
+    sim = Simulator(ph, RAILS, SITES, tile_sites=tile_sites)
+    if limit:
+        sim.set_group_limit(limit)
+    sim.set_launch_mode("persistent")
+    if limit:
+        assert sim.n_groups > 1
+    p_or = oracle.OracleParams(ph, RAILS, SITES)
+    occ0 = oracle.fill(p_or, FILL)
+    sim.load_occupancy(occ0)
+    sim.set_protocols(protos)
+    st = lockstep(sim, p_or, protos, occ0, 400, 150)
+    assert st["resyncs"] == 0 and st["hops"] > 100
+
+
+def test_batch_strategies_agree():
+    """Half-step launches, one persistent group and many small groups give the
+    same per-step tallies and final state."""
+    import torch
+    from paper_2511_09413_amd import Simulator
+    ph = Physics(precision=FP32, seed=5, ea_ev=0.15)
+    protos = _protocols(len(RAILS))
+    outs = []
+    for mode, limit in (("half_step", 0), ("persistent", 0), ("persistent", 3)):
+        sim = Simulator(ph, RAILS, SITES, tile_sites=512)
+        sim.set_group_limit(limit)
+        sim.set_launch_mode(mode)
+        sim.fill_random(FILL)
+        sim.set_protocols(protos)
+        net, dec = sim.run_steps(700, tallies=True)
+        outs.append((net.cpu(), dec.cpu(), sim.read_occupancy()))
+        sim.close()
+    for o in outs[1:]:
+        assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1])
+        assert np.array_equal(o[2], outs[0][2])
+
+
+def test_c3_full_batch_sampled():
+    """The 256-device batch (1.4e8 sites) in the automatic strategy: after 4
+    steps, sampled devices equal the oracle's run of that device alone (the
+    devices before it shrunk to 1 x 2 empty sites so its random stream index is
+    unchanged), and every rail keeps its ion count."""
+    from paper_2511_09413_amd import Simulator
+    wl = c3_batched(n_steps=100_000)
+    ph = wl.physics.replace(ea_ev=0.2)   # more hops per step than at 0.3 eV
+    sim = Simulator(ph, wl.rails, wl.sites)
+    assert sim.launch_mode == "persistent" and sim.n_groups > 1
+    sim.fill_random(wl.filling)
+    occ0 = sim.read_occupancy()
+    sim.set_protocols(wl.protocols)
+    sim.run_steps(4)
+    occ = sim.read_occupancy()
+    offs = np.concatenate([[0], np.cumsum([r * l for r, l in zip(wl.rails, wl.sites)])])
+    D = len(wl.rails)
+    for d in (0, 1, 77, 200, D - 1):
+        a, b = offs[d], offs[d + 1]
+        R, L = wl.rails[d], wl.sites[d]
+        assert np.array_equal(occ[a:b].reshape(R, L).sum(axis=1), occ0[a:b].reshape(R, L).sum(axis=1))
+        rails = [1] * d + [R]
+        sites = [2] * d + [L]
+        p_or = oracle.OracleParams(ph, rails, sites)
+        part = np.concatenate([np.zeros(2 * d, dtype=np.int8), occ0[a:b]])
+        oracle.run(p_or, [constant(0.0)] * d + [wl.protocols[d]], part, 0, 4, want_dec=False)
+        assert np.array_equal(occ[a:b], part[2 * d:]), d
