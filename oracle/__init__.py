@@ -63,6 +63,8 @@ def lib():
         L.orc_delta_energy_f64.restype = C.c_double
         L.orc_delta_energy_f32.argtypes = L.orc_delta_energy_f64.argtypes
         L.orc_delta_energy_f32.restype = C.c_float
+        L.orc_dense_potential.argtypes = [P(_Params), P(C.c_int8), P(C.c_double)]
+        L.orc_dense_potential.restype = None
         L.orc_hop_prob_f64.argtypes = [P(_Params), C.c_double, C.c_double]
         L.orc_hop_prob_f64.restype = C.c_double
         L.orc_hop_prob_f32.argtypes = [P(_Params), C.c_double, C.c_float]
@@ -145,6 +147,16 @@ def delta_energy(p: OracleParams, R: int, L: int, S: np.ndarray, r: int, o: int,
     S = np.ascontiguousarray(S, dtype=np.int8).reshape(-1)
     f = lib().orc_delta_energy_f32 if fp32 else lib().orc_delta_energy_f64
     return float(f(C.byref(p.s), R, L, _ptr(S, C.c_int8), r, o, t, V))
+
+
+def dense_potential(p: OracleParams, occ: np.ndarray) -> np.ndarray:
+    """phi at every site (binary64), devices concatenated, [rails*sites] each."""
+    o = np.ascontiguousarray(occ, dtype=np.int8).reshape(-1)
+    if o.size != p.n_sites:
+        raise ValueError("occupancy size mismatch")
+    phi = np.zeros(p.n_sites, dtype=np.float64)
+    lib().orc_dense_potential(C.byref(p.s), _ptr(o, C.c_int8), _ptr(phi, C.c_double))
+    return phi
 
 
 def hop_prob(p: OracleParams, ea: float, dE: float, fp32: bool = False) -> float:

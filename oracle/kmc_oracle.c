@@ -242,6 +242,37 @@ float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
     return e_app + e_coul;
 }
 
+/* Coulomb potential at every site, binary64: phi(r, s) = sum over the distinct
+ * rails r' within rail_range of r (r itself included) and sites j of
+ * occ(r', j) K(s - j, dist(r, r')), the site itself excluded (K(0,0) = 0).
+ * This is the field of the ions that the main text (section 3) adds to the
+ * bias; for a hop o -> t on rail r the Coulomb part of the energy change is
+ * phi(t) - K(1, 0) - phi(o), the K(1, 0) removing the moving ion's own
+ * contribution at its target.  occ and phi are [rails][sites] per device,
+ * devices concatenated. */
+void orc_dense_potential(const orc_params *P, const int8_t *occ, double *phi)
+{
+    for (int d = 0; d < P->n_devices; ++d) {
+        int R = P->rails[d], L = P->sites[d];
+        int64_t off = dev_offset(P, d);
+        const int8_t *od = occ + off;
+        double *pd = phi + off;
+        for (int r = 0; r < R; ++r) {
+            int rails[64], dists[64];
+            int nr = neighbour_rails(P, R, r, rails, dists);
+            for (int s = 0; s < L; ++s) {
+                double acc = 0.0;
+                for (int i = 0; i < nr; ++i) {
+                    const int8_t *row = od + (int64_t)rails[i] * L;
+                    for (int j = 0; j < L; ++j)
+                        if (row[j]) acc += orc_kernel(P, s - j, dists[i]);
+                }
+                pd[(int64_t)r * L + s] = acc;
+            }
+        }
+    }
+}
+
 /* hop probability p = min(nu0*dt*exp(-beta*(Ea + dE/2)), 1) */
 double orc_hop_prob_f64(const orc_params *P, double ea, double dE)
 {

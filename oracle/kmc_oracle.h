@@ -60,6 +60,7 @@ double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
                             int r, int o, int t, double V);
 float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
                            int r, int o, int t, double V);
+void orc_dense_potential(const orc_params *P, const int8_t *occ, double *phi);
 double orc_hop_prob_f64(const orc_params *P, double ea, double dE);
 float orc_hop_prob_f32(const orc_params *P, double ea, float dE);
 int orc_ions_per_rail(double filling, int L);

@@ -253,3 +253,42 @@ def test_dilute_drift_exact():
         se = disp[sel].std() / math.sqrt(sel.sum())
         assert abs(disp[sel].mean() - exact) < 4 * se, (parity, disp[sel].mean(), exact, se)
     assert disp.mean() < 0
+
+
+@pytest.mark.parametrize("R,L,m,cut,lam", [(6, 40, 4, 39, 0.0), (3, 24, 2, 10, 3.0), (9, 32, 4, 31, 0.0), (1, 16, 0, 15, 0.0)])
+def test_dense_potential(R, L, m, cut, lam):
+    """phi (binary64): (a) one ion alone makes phi = K at every other site and
+    0 at its own; (b) phi(t) - K(1,0) - phi(o) equals the Coulomb part of the
+    pinned energy change delta_energy - alpha V (t - o)/L for every candidate
+    of random states; (c) phi is additive over ions."""
+    ph = Physics(precision=FP64, coulomb_kappa_v=0.03, screening_sites=lam, cutoff_sites=cut, rail_range=m)
+    p = oracle.OracleParams(ph, [R], [L])
+    one = np.zeros(R * L, dtype=np.int8)
+    r0, s0 = R // 2, L // 3
+    one[r0 * L + s0] = 1
+    phi1 = oracle.dense_potential(p, one).reshape(R, L)
+    for r in range(R):
+        dr = min((r - r0) % R, (r0 - r) % R)
+        for s in range(L):
+            assert phi1[r, s] == oracle.kernel(p, s - s0, dr), (r, s)
+    rng = np.random.default_rng(R + L)
+    for trial in range(3):
+        occ = (rng.random(R * L) < 0.35).astype(np.int8)
+        phi = oracle.dense_potential(p, occ).reshape(R, L)
+        # additivity over ions
+        acc = np.zeros((R, L))
+        for i in np.flatnonzero(occ):
+            e = np.zeros(R * L, dtype=np.int8)
+            e[i] = 1
+            acc += oracle.dense_potential(p, e).reshape(R, L)
+        assert np.allclose(acc, phi, rtol=1e-12, atol=1e-15)
+        S = occ.reshape(R, L)
+        V = 0.37
+        k10 = oracle.kernel(p, 1, 0)
+        for r in range(R):
+            for s in range(L - 1):
+                if S[r, s] == S[r, s + 1]:
+                    continue
+                o, t = (s, s + 1) if S[r, s] else (s + 1, s)
+                e_coul = oracle.delta_energy(p, R, L, S, r, o, t, V) - ph.field_coupling * V * (t - o) / L
+                assert abs(phi[r, t] - k10 - phi[r, o] - e_coul) <= 1e-12 * (abs(phi[r, t]) + abs(phi[r, o]) + 1e-3)
