@@ -45,9 +45,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent"])
     ap.add_argument("--tile-sites", type=int, default=0)
-    ap.add_argument("--workload", default="large-device", choices=["large-device", "batch", "gradient"],
+    ap.add_argument("--workload", default="large-device", choices=["large-device", "batch", "gradient", "dense"],
                     help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
-                         "gradient: forward + score replay of 512 replicas x 256 x 512")
+                         "gradient: forward + score replay of 512 replicas x 256 x 512; "
+                         "dense: 64 replicas x 1024 x 512 with the MFMA long-range potential")
     return ap.parse_args()
 
 
@@ -102,6 +103,8 @@ def main():
         return bench_batch(args)
     if args.workload == "gradient":
         return bench_gradient(args)
+    if args.workload == "dense":
+        return bench_dense(args)
     import torch
     import paper_2511_09413_amd as kmc
     from workloads import c2_large_device
@@ -262,6 +265,49 @@ def bench_gradient(args):
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": None, "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps},
         "grad_mean_over_replicas": [float(x) for x in g.mean(axis=0)],
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+BF16_DENSE_PEAK_TFLOPS = 2500.0
+
+
+def bench_dense(args):
+    """64 replicas of 1024 x 512, unscreened 1/r over the whole rail and +-4
+    rails, 1 V, potential of every site on MFMA (BF16 hi/lo, FP32 accumulate),
+    binary32 decisions.  The dominant kernel is the potential; it is also timed
+    alone (the same kernel through kmc_dense_potential)."""
+    import torch
+    import paper_2511_09413_amd as kmc
+    from workloads import c4_dense
+    steps = args.steps if args.steps != 100_000 else 1000
+    wl = c4_dense(n_steps=1000)
+    sim = kmc.Simulator(wl.physics, wl.rails, wl.sites, device="cuda:0")
+    sim.fill_random(wl.filling)
+    sim.set_protocols(wl.protocols)
+    sim.run_steps(min(args.warmup, 20))
+    stream = torch.cuda.current_stream()
+    sec = _timed(lambda: sim.run_steps(steps), stream)
+    sim.read_current()
+    value = wl.n_sites * steps / sec
+    n_pot = 200
+    t_phi = _timed(lambda: [sim.dense_potential() for _ in range(n_pot)], stream) / n_pot
+    M, L, m = sum(wl.rails), wl.sites[0], wl.physics.rail_range
+    flops = 2 * 2 * M * L * (m + 1) * L          # hi and lo products, rails at +-dist folded
+    achieved = flops / t_phi / 1e12
+    out = {
+        "metric": "site-updates/s (dense long-range potential)", "value": value, "unit": "site-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 20), "ms_per_step": sec * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2+fp32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "replicas": len(wl.rails), "rails": wl.rails[0], "sites": L,
+                   "rail_range": m, "kernel": "kappa/d, whole rail"},
+        "potential_us": t_phi * 1e6,
+        "potential_share_of_step": 2 * t_phi / (sec / steps),
+        "roofline": {"bound": "mfma", "kernel": "dense_phi", "achieved": achieved, "peak": BF16_DENSE_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / BF16_DENSE_PEAK_TFLOPS, "traffic": None,
+                     "avg_launch_us": t_phi * 1e6, "flop_per_launch": flops},
     }
     print(json.dumps(out), flush=True)
     sim.close()

@@ -48,9 +48,11 @@ typedef enum {
 typedef enum {
     KMC_FP64 = 0,   /* binary64 energies, exponent and probabilities          */
     KMC_FP32 = 1,   /* binary32 energies/probabilities, tables from binary64  */
-    KMC_BF16X2 = 2  /* dense long-range potential on MFMA: BF16 hi+lo split of
-                       the kernel matrix, FP32 accumulation (needs cutoff_sites
-                       = sites-1, the unscreened kernel and equal shapes)      */
+    KMC_BF16X2 = 2  /* Coulomb term from the potential of every site computed
+                       as a matrix product on the MFMA units: kernel values
+                       split as BF16 hi + lo, FP32 accumulation; energies and
+                       probabilities binary32 (needs the same number of sites,
+                       at most 1024, on every device)                          */
 } kmc_precision;
 
 /* Physical and numerical parameters (paper SI Table S1 for geometry and
@@ -180,6 +182,16 @@ kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t
  * or nu0_hz <= 0; KMC_EUNSUPPORTED if step0 + n_steps exceeds 2^32 - 1. */
 kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
                             const double *weight_dev, double *grad_dev);
+
+/* Coulomb potential of the current state at every site, as used by the
+ * KMC_BF16X2 step: phi(r, s) = sum over the distinct rails r' within
+ * rail_range (r included) and sites j of occ(r', j) K(s - j, dist(r, r')),
+ * K(0, 0) = 0 (the ion field of main text section 3; the hop o -> t then has
+ * dE_coul = phi(t) - K(1, 0) - phi(o)).  K is split as BF16 hi + lo with
+ * |K - hi - lo| <= 2^-16 |K|, products accumulated in FP32.
+ *   phi_dev: device float [total sites], occupancy layout (written).
+ * KMC_EUNSUPPORTED unless the context was created with KMC_BF16X2. */
+kmc_status kmc_dense_potential(kmc_ctx *ctx, float *phi_dev);
 
 /* Launch strategy of kmc_run_steps.
  *   KMC_LAUNCH_HALF_STEP: one kernel launch per half-step; the state makes a

@@ -69,6 +69,7 @@ def lib():
         L.kmc_score_replay.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
         L.kmc_get_persistent_groups.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
+        L.kmc_dense_potential.argtypes = [vp, vp]
         L.kmc_last_error.restype = C.c_char_p
         L.kmc_destroy.argtypes = [vp]
         L.kmc_destroy.restype = None
@@ -76,7 +77,7 @@ def lib():
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
-                     "kmc_set_persistent_group_limit"):
+                     "kmc_set_persistent_group_limit", "kmc_dense_potential"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -269,6 +270,13 @@ class Simulator:
         grad = torch.empty((self.n_devices, 4), dtype=torch.float64, device=self.device)
         score_replay(self.ctx, occ0.data_ptr(), step0, w.shape[0], w.data_ptr(), grad.data_ptr())
         return grad
+
+    def dense_potential(self):
+        """Coulomb potential of the current state at every site (float32 device
+        tensor, occupancy layout); KMC_BF16X2 contexts only."""
+        phi = self.torch.empty(self.n_sites, dtype=self.torch.float32, device=self.device)
+        _check(lib().kmc_dense_potential(C.c_void_p(self.ctx), C.c_void_p(phi.data_ptr())))
+        return phi
 
     def read_occupancy(self) -> np.ndarray:
         return read_occupancy(self.ctx, self.n_sites)

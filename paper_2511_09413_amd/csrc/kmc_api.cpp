@@ -41,6 +41,9 @@ hipError_t launch_persistent(const PArgs &a, int block, size_t lds, bool fp64, h
 hipError_t persistent_capacity(int block, size_t lds, bool fp64, int *blocks_per_cu);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_dense_phi(const DenseArgs &a, hipStream_t st);
+hipError_t launch_dense_decide(const HopArgs &a, int pitch, hipStream_t st);
+hipError_t set_dense_lds_limit(size_t lds_bytes);
 }  // namespace kmc
 
 using namespace kmc;
@@ -63,12 +66,13 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, progress, pub, status,
-        rp_a, rp_b, score_log, dtab64, dtab32, total;
+        rp_a, rp_b, score_log, dtab64, dtab32, phi, ktiles, dtiles, ctiles, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int max_pitch;
     int64_t total_sites, total_pad, rails_total;
     int cut;     // interaction table cutoff actually stored
     int dpitch;  // entries per row of the window-difference tables
+    int dense_nb;  // dense potential: 32-site blocks per rail (0 when not used)
 };
 
 bool is_finite(double x) { return std::isfinite(x); }
@@ -99,8 +103,12 @@ kmc_status validate(const kmc_params *p) {
         return fail(KMC_EUNSUPPORTED, "rail_range must be in [0, 4]");
     if (p->precision != KMC_FP64 && p->precision != KMC_FP32 && p->precision != KMC_BF16X2)
         return fail(KMC_EINVAL, "unknown precision");
-    if (p->precision == KMC_BF16X2)
-        return fail(KMC_EUNSUPPORTED, "KMC_BF16X2 needs the dense-potential path");
+    if (p->precision == KMC_BF16X2) {
+        for (int d = 1; d < p->n_devices; ++d)
+            if (p->sites[d] != p->sites[0])
+                return fail(KMC_EUNSUPPORTED, "KMC_BF16X2 needs the same number of sites on every device");
+        if (p->sites[0] > kDenseMaxSites) return fail(KMC_EUNSUPPORTED, "KMC_BF16X2 supports up to 1024 sites");
+    }
     return KMC_OK;
 }
 
@@ -165,6 +173,16 @@ Layout layout_for(const kmc_params *p) {
     L.dpitch = (2 * L.cut + 2 + 15) / 16 * 16;
     L.dtab64 = take(sizeof(double) * 2 * (m + 1) * (size_t)L.dpitch);
     L.dtab32 = take(sizeof(float) * 2 * (m + 1) * (size_t)L.dpitch);
+    if (p->precision == KMC_BF16X2) {
+        // potential of every site (rows padded to a multiple of 128 sites), the
+        // distinct 32 x 32 Toeplitz blocks of the kernel as MFMA fragments, tiles
+        const int lp = (p->sites[0] + 127) / 128 * 128;
+        L.dense_nb = lp / 32;
+        L.phi = take(sizeof(float) * (size_t)rails * lp);
+        L.ktiles = take((size_t)16 * 256 * (m + 1) * (2 * L.dense_nb - 1));
+        L.dtiles = take(sizeof(Tile) * (size_t)rails);
+        L.ctiles = take(sizeof(Tile) * (size_t)rails);
+    }
     L.total = off;
     return L;
 }
@@ -192,6 +210,9 @@ struct kmc_ctx {
     hipStream_t stream = nullptr;
     bool poisoned = false;
     bool fp64 = false;
+    bool dense = false;                // KMC_BF16X2: Coulomb term from the MFMA potential
+    std::vector<Tile> dtiles;          // dense-potential tiles (<= kDenseRails rails)
+    std::vector<Tile> ctiles;          // dense decision tiles (whole rails, one 256-thread workgroup)
     int64_t n = 0;            // host mirror of the step counter
     int64_t steps_run = 0;    // steps since init (for the mean current)
     size_t hop_lds = 0;
@@ -206,6 +227,7 @@ struct kmc_ctx {
     bool p_ok = false;                 // persistent tiling fits co-resident on this GPU
     int mode = 0;                      // KMC_LAUNCH_AUTO / _HALF_STEP / _PERSISTENT
     uint64_t epoch = 0;
+    float k10 = 0.0f;                  // K(1, 0) rounded to binary32
 
     template <typename T>
     T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -352,7 +374,7 @@ void make_ptiles(kmc_ctx *c) {
 }
 
 bool use_persistent(const kmc_ctx *c) {
-    if (c->mode == 1) return false;
+    if (c->dense || c->mode == 1) return false;
     if (c->mode == 2) return c->p_ok;
     // automatic: persistent whenever the whole lattice fits co-resident in LDS
     return c->p_ok;
@@ -389,7 +411,29 @@ HopArgs hop_args(kmc_ctx *c) {
     a.kappa = c->p.coulomb_kappa_v;
     a.dtab = c->fp64 ? (const void *)c->at<double>(c->lay.dtab64) : (const void *)c->at<float>(c->lay.dtab32);
     a.dpitch = c->lay.dpitch;
+    if (c->dense) {
+        a.phi = c->at<float>(c->lay.phi);
+        a.phi_row = (int64_t)c->lay.dense_nb * 32;
+        a.k10 = c->k10;
+        a.dtiles = c->at<Tile>(c->lay.ctiles);
+        a.n_dtiles = (int32_t)c->ctiles.size();
+    }
     return a;
+}
+
+DenseArgs dense_args(kmc_ctx *c, const int8_t *occ, float *phi, int64_t phi_row) {
+    DenseArgs d{};
+    d.occ = occ;
+    d.devs = c->at<DevInfo>(c->lay.devs);
+    d.tiles = c->at<Tile>(c->lay.dtiles);
+    d.n_tiles = (int32_t)c->dtiles.size();
+    d.ktiles = c->ws + c->lay.ktiles;
+    d.nb = c->lay.dense_nb;
+    d.rail_range = c->p.rail_range;
+    d.phi = phi;
+    d.phi_row = phi_row;
+    d.sites = c->sites[0];
+    return d;
 }
 
 kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
@@ -452,7 +496,13 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
                 a.occ_out = c->nxt;
                 a.step_in_chunk = k;
                 a.h = h;
-                KMC_HIP(c, launch_hop(a, c->hop_lds, c->fp64, c->stream));
+                if (c->dense) {
+                    KMC_HIP(c, launch_dense_phi(dense_args(c, c->cur, c->at<float>(c->lay.phi), a.phi_row),
+                                                c->stream));
+                    KMC_HIP(c, launch_dense_decide(a, c->devs[0].pitch, c->stream));
+                } else {
+                    KMC_HIP(c, launch_hop(a, c->hop_lds, c->fp64, c->stream));
+                }
                 std::swap(c->cur, c->nxt);
             }
         }
@@ -528,7 +578,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     // rails of |K(0,dist)|, whatever the configuration.
     const int D = params->n_devices;
     c->devs.resize(D);
-    int64_t off = 0, off_pad = 0;
+    int64_t off = 0, off_pad = 0, rows_before = 0;
     for (int d = 0; d < D; ++d) {
         DevInfo &dv = c->devs[d];
         std::memset(&dv, 0, sizeof(dv));
@@ -538,6 +588,8 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
         dv.n_knots = 1;
         dv.off = off;
         dv.off_pad = off_pad;
+        dv.row0 = rows_before;
+        rows_before += dv.rails;
         dv.n_set = 0;
         dv.ea_min = params->ea_ev;
         neighbour_offsets(dv.rails, params->rail_range, dv);
@@ -583,6 +635,52 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
                 d32[at] = kt32 - ko32;
             }
 
+    // Dense potential (KMC_BF16X2): the distinct 32 x 32 blocks of
+    // T[(dist, j)][s] = K(s - j, dist), as MFMA B fragments, each value split
+    // into BF16 hi = RN(K) and lo = RN(K - hi).  Block (dist, delta) holds
+    // rows j = 32 (sb + delta) + kk and columns s = 32 sb + ss; lane l of
+    // k-step q carries kk = 16 q + 8 (l / 32) + e (e = 0..7), ss = l % 32.
+    c->dense = params->precision == KMC_BF16X2;
+    c->k10 = cut >= 1 ? k32[1] : 0.0f;
+    std::vector<uint16_t> kt_host;
+    if (c->dense) {
+        auto bf16_rne = [](float f) {
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            u += 0x7FFFu + ((u >> 16) & 1u);
+            return (uint16_t)(u >> 16);
+        };
+        auto bf16_val = [](uint16_t h) {
+            const uint32_t u = (uint32_t)h << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            return (double)f;
+        };
+        const int nb = lay.dense_nb, nd = 2 * nb - 1;
+        kt_host.assign((size_t)(m + 1) * nd * 256 * 8, 0);
+        for (int dd = 0; dd <= m; ++dd)
+            for (int di = 0; di < nd; ++di)
+                for (int q = 0; q < 2; ++q)
+                    for (int l = 0; l < 64; ++l)
+                        for (int e = 0; e < 8; ++e) {
+                            const int delta = di - (nb - 1);
+                            const int ds = -32 * delta + (l % 32) - 16 * q - 8 * (l / 32) - e;
+                            const double k = kernel64(params, ds, dd);
+                            const uint16_t hi = bf16_rne((float)k);
+                            const uint16_t lo = bf16_rne((float)(k - bf16_val(hi)));
+                            const size_t base = ((size_t)(dd * nd + di) * 2) * 2;
+                            kt_host[(((base + 0 * 2 + q) * 64) + l) * 8 + e] = hi;
+                            kt_host[(((base + 1 * 2 + q) * 64) + l) * 8 + e] = lo;
+                        }
+        const int per_wg = 256 / (c->devs[0].pitch / 8);  // rails of one decision workgroup
+        for (int d = 0; d < D; ++d) {
+            for (int r0 = 0; r0 < c->rails[d]; r0 += kDenseRails)
+                c->dtiles.push_back(Tile{d, r0, std::min(kDenseRails, c->rails[d] - r0), 0});
+            for (int r0 = 0; r0 < c->rails[d]; r0 += per_wg)
+                c->ctiles.push_back(Tile{d, r0, std::min(per_wg, c->rails[d] - r0), 0});
+        }
+    }
+
     std::vector<int32_t> rail_dev, rail_idx, n_ions(D, 0);
     rail_dev.reserve(lay.rails_total);
     rail_idx.reserve(lay.rails_total);
@@ -608,6 +706,12 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(h2d(lay.ktab32, k32.data(), sizeof(float) * k32.size()), "copy kernel table");
     chk(h2d(lay.dtab64, d64.data(), sizeof(double) * d64.size()), "copy window differences");
     chk(h2d(lay.dtab32, d32.data(), sizeof(float) * d32.size()), "copy window differences");
+    if (c->dense) {
+        chk(h2d(lay.ktiles, kt_host.data(), sizeof(uint16_t) * kt_host.size()), "copy kernel blocks");
+        chk(h2d(lay.dtiles, c->dtiles.data(), sizeof(Tile) * c->dtiles.size()), "copy dense tiles");
+        chk(h2d(lay.ctiles, c->ctiles.data(), sizeof(Tile) * c->ctiles.size()), "copy decision tiles");
+        chk(set_dense_lds_limit((size_t)(kDenseRails + 2 * m) * (lay.dense_nb * 32 + 8)), "LDS limit of the dense kernel");
+    }
     chk(h2d(lay.ctl, &ctl, sizeof(Ctl)), "copy ctl");
     chk(h2d(lay.rail_dev, rail_dev.data(), sizeof(int32_t) * rail_dev.size()), "copy rail table");
     chk(h2d(lay.rail_idx, rail_idx.data(), sizeof(int32_t) * rail_idx.size()), "copy rail table");
@@ -838,6 +942,7 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     if (c->p.coulomb_kappa_v == 0.0)
         return fail(KMC_EINVAL, "score replay needs coulomb_kappa_v != 0 (the kappa score is dE_coul/kappa)");
     if (!(c->p.nu0_hz > 0.0)) return fail(KMC_EINVAL, "score replay needs nu0_hz > 0");
+    if (c->dense) return fail(KMC_EUNSUPPORTED, "score replay runs the binary64/binary32 window paths only");
     const int D = c->p.n_devices;
     KMC_HIP(c, launch_zero_i64(reinterpret_cast<int64_t *>(grad_dev), 4 * (int64_t)D, c->stream));
     if (n_steps == 0) return KMC_OK;
@@ -859,6 +964,15 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
             std::swap(cur, nxt);
         }
     }
+    return KMC_OK;
+}
+
+kmc_status kmc_dense_potential(kmc_ctx *c, float *phi_dev) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (!phi_dev) return fail(KMC_EINVAL, "phi_dev is NULL");
+    if (!c->dense) return fail(KMC_EUNSUPPORTED, "the dense potential needs a KMC_BF16X2 context");
+    KMC_HIP(c, launch_dense_phi(dense_args(c, c->cur, phi_dev, c->sites[0]), c->stream));
     return KMC_OK;
 }
 

@@ -26,6 +26,7 @@ struct DevInfo {
     int64_t off;                         // unpadded offset (caller layout)
     int64_t off_pad;                     // padded offset (internal buffers)
     int64_t n_set;                       // step at which the protocol was installed
+    int64_t row0;                        // global index of the device's first rail
     double ea_min;                       // minimum barrier of the device, eV
     double ea_step;                      // barrier class width: class q covers
                                          // [ea_min + q*ea_step, ...), eV
@@ -82,13 +83,36 @@ struct HopArgs {
     struct LogBuf { int64_t *count; void *entries; int64_t cap; } log;
     int32_t step_in_chunk;
     int32_t h;
-    // score replay only (hop_half_step<..., true>)
+    // score replay only (hop_half_step<..., 1>)
     int64_t n_abs;             // step index of the launch
     double nu0, kappa;
     const void *dtab;          // [2][m+1][dpitch] window differences K(t-j) - K(o-j), path precision
     int32_t dpitch;            // entries per row, >= 2*cutoff + 2, multiple of 16
     const double *score_w;     // [D] weights of this step's decisions
     double *score_grad;        // [D][4] accumulators (Ea shift, nu0, kappa, alpha)
+    // dense-potential decisions only (dense_decide)
+    const float *phi;          // [total rails][phi_row] potential of the half-step's snapshot
+    int64_t phi_row;
+    float k10;                 // K(1, 0) in binary32
+    const Tile *dtiles;        // decision tiles: whole rails of one device per workgroup
+    int32_t n_dtiles;
+};
+
+// Dense potential (MFMA): every site's Coulomb potential of one state.
+constexpr int kDenseRails = 128;         // rails per workgroup tile of the dense kernel
+constexpr int kDenseMaxSites = 1024;     // sites per rail supported by the dense path
+
+struct DenseArgs {
+    const int8_t *occ;        // padded internal state (bit 0 = occupied)
+    const DevInfo *devs;
+    const Tile *tiles;        // rails [r0, r0 + nr) of device d, nr <= kDenseRails
+    int32_t n_tiles;
+    const void *ktiles;       // [m+1][2 nb - 1][hi, lo][q][64 lanes] 16-byte MFMA B fragments
+    int32_t nb;               // 32-site blocks per rail (multiple of 4)
+    int32_t rail_range;
+    float *phi;               // output rows
+    int64_t phi_row;          // floats per output row
+    int32_t sites;            // valid sites per row (columns >= sites are not written)
 };
 
 // Arguments of the persistent kernel (several steps per launch, each

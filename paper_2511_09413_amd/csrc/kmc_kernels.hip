@@ -69,8 +69,9 @@ __device__ __forceinline__ uint32_t window_bits(const uint16_t *rb, int p16, int
 //   rbits  [(nr + 2m) * pitch / 16] uint16 occupancy bits (score replay only)
 //   dtab   [2][m + 1][dpitch] Real window differences (score replay only)
 // ------------------------------------------------------------------------
-template <typename Real, int H, bool kScore>
+template <typename Real, int H, int kMode>
 __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
+    constexpr bool kScore = kMode == 1;  // score replay
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ HopShared sh;
 
@@ -252,13 +253,13 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
             }
         }
         __syncthreads();
-        if (!kScore && tid == 0 && sh.n_hop > 0) {
-            const int64_t k = n - a.ctl->tally_base;
-            const int64_t base = k * a.n_devices + tile.d;
-            atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
-            for (int q = 0; q < kDeciles; ++q)
-                if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);
-        }
+    }
+    if (!kScore && tid == 0 && sh.n_hop > 0) {
+        const int64_t k = n - a.ctl->tally_base;
+        const int64_t base = k * a.n_devices + tile.d;
+        atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
+        for (int q = 0; q < kDeciles; ++q)
+            if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);
     }
 
     // 5. apply the accepted hops that touch the lane's chunk, write it out
@@ -609,32 +610,32 @@ __global__ void copy_bytes(const uint4 *src, uint4 *dst, int64_t n16) {
 // ------------------------------------------------------------------------
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
-template <bool kScore>
+template <int kMode>
 static hipError_t launch_half_step(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
     const dim3 grid(a.n_tiles), block(kBlock);
     if (fp64) {
-        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<double, 0, kScore>), grid, block, lds_bytes, st, a);
-        else hipLaunchKernelGGL((hop_half_step<double, 1, kScore>), grid, block, lds_bytes, st, a);
+        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<double, 0, kMode>), grid, block, lds_bytes, st, a);
+        else hipLaunchKernelGGL((hop_half_step<double, 1, kMode>), grid, block, lds_bytes, st, a);
     } else {
-        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<float, 0, kScore>), grid, block, lds_bytes, st, a);
-        else hipLaunchKernelGGL((hop_half_step<float, 1, kScore>), grid, block, lds_bytes, st, a);
+        if (a.h == 0) hipLaunchKernelGGL((hop_half_step<float, 0, kMode>), grid, block, lds_bytes, st, a);
+        else hipLaunchKernelGGL((hop_half_step<float, 1, kMode>), grid, block, lds_bytes, st, a);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
-    return launch_half_step<false>(a, lds_bytes, fp64, st);
+    return launch_half_step<0>(a, lds_bytes, fp64, st);
 }
 
 hipError_t launch_score(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
-    return launch_half_step<true>(a, lds_bytes, fp64, st);
+    return launch_half_step<1>(a, lds_bytes, fp64, st);
 }
 
 hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes) {
-    const void *fns[8] = {(const void *)hop_half_step<double, 0, false>, (const void *)hop_half_step<double, 1, false>,
-                          (const void *)hop_half_step<float, 0, false>,  (const void *)hop_half_step<float, 1, false>,
-                          (const void *)hop_half_step<double, 0, true>,  (const void *)hop_half_step<double, 1, true>,
-                          (const void *)hop_half_step<float, 0, true>,   (const void *)hop_half_step<float, 1, true>};
+    const void *fns[8] = {(const void *)hop_half_step<double, 0, 0>, (const void *)hop_half_step<double, 1, 0>,
+                          (const void *)hop_half_step<float, 0, 0>,  (const void *)hop_half_step<float, 1, 0>,
+                          (const void *)hop_half_step<double, 0, 1>, (const void *)hop_half_step<double, 1, 1>,
+                          (const void *)hop_half_step<float, 0, 1>,  (const void *)hop_half_step<float, 1, 1>};
     for (int i = 0; i < 8; ++i) {
         const int bytes = (int)(i < 4 ? lds_bytes : score_lds_bytes);
         hipError_t e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
