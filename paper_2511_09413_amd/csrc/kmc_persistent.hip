@@ -34,7 +34,9 @@ namespace kmc {
 constexpr int kSpinLimit = 1 << 20;  // about a second of polling
 
 struct PShared {
-    int32_t n_surv, n_down, n_up, stop;
+    int32_t n_surv[2];            // survivors of even / odd half-steps (reset one half-step ahead)
+    int32_t n_down, n_up, stop;
+    int32_t check[2];             // slot check in this half-step (decided before its first barrier)
     int32_t dec[kDeciles];
     int64_t ver_prev, ver_next;   // neighbour progress verified so far (half-steps, relative)
 };
@@ -133,7 +135,14 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         sh.stop = 0;
         sh.ver_prev = -1;
         sh.ver_next = -1;
+        sh.n_surv[0] = 0;
+        sh.n_surv[1] = 0;
+        sh.n_down = 0;
+        sh.n_up = 0;
+        for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
     }
+    __syncthreads();
+    for (int i = tid; i < nr * W; i += bdim) B1[i] = B0[i];  // the first half-step writes B1
     __syncthreads();
 
     // The edge rails of `state` as state j (no wait: tags validate the data).
@@ -182,17 +191,17 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         uint64_t *nxt = (js & 1) ? B0 : B1;
         const int kstep = js >> 1;
         const int64_t need = j + 2 - kRing - j0;
+        // The counter of the next half-step is cleared here, before this
+        // half-step's barrier: its last readers (the previous half-step) have
+        // either passed that half-step's survivor barrier or read a zero.
         if (tid == 0) {
-            if (h == 0) {
-                sh.n_down = 0;
-                sh.n_up = 0;
-                for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
-            }
-            sh.n_surv = 0;
+            sh.n_surv[(js + 1) & 1] = 0;
+            // whether this half-step re-verifies the neighbours' progress (see
+            // below); decided by thread 0 alone, from its own records, and read
+            // by everyone after the barrier, so that the barrier ordering the
+            // check before the publication is taken by all or by none
+            sh.check[js & 1] = !isolated && js >= 4 && (sh.ver_prev < need + 8 || sh.ver_next < need + 8);
         }
-        for (int i = tid; i < nr * W; i += bdim) nxt[i] = cur[i];
-        lds_barrier();
-        if (sh.stop) break;
 
         // candidates, Philox words, exact two-stage prefilter
         if (has_chunk) {
@@ -218,7 +227,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                     const int o = s0 + (((bits >> bit) & 1u) ? bit : bit + 1);
                     const uint32_t w = word_of8(blkA, blkB, bit >> 1);
                     if (w <= threshold_of(a.c0, cls_A[cls[row * P + o]], step_g[kstep])) {
-                        const int k = atomicAdd(&sh.n_surv, 1);
+                        const int k = atomicAdd(&sh.n_surv[js & 1], 1);
                         sv_pos[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
                         sv_w[k] = w;
                         Real ea;
@@ -230,6 +239,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
             }
         }
         lds_barrier();
+        if (sh.stop) break;
 
         // Slot check for the publication at the end of this half-step: the slot
         // of state j+1 held state j+1-kRing, which the neighbours read during
@@ -243,7 +253,8 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         // reliably), and only if a neighbour is truly behind does thread 0
         // poll for state `need`.  In steady state that is one load
         // latency every twenty-odd half-steps for wavefront 0 alone.
-        if (!isolated && tid == 0 && js >= 4 && (sh.ver_prev < need + 8 || sh.ver_next < need + 8)) {
+        const bool check = sh.check[js & 1];
+        if (check && tid == 0) {
             const int64_t slot_prev = (int64_t)tile.prev * a.pub_stride + ((j - 4) % kRing) * slot_words;
             const int64_t slot_next = (int64_t)tile.next * a.pub_stride + ((j - 4) % kRing) * slot_words;
             const uint64_t vp = __hip_atomic_load(a.pub + slot_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -267,7 +278,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         }
 
         // survivors: one wavefront each
-        const int n_surv = sh.n_surv;
+        const int n_surv = sh.n_surv[js & 1];
         for (int i = wave; i < n_surv; i += n_waves) {
             const int srow = (int)(sv_pos[i] >> 13), s = (int)(sv_pos[i] & 8191u);
             const int o = ((cur[srow * W + (s >> 6)] >> (s & 63)) & 1u) ? s : s + 1;
@@ -328,16 +339,29 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
-        lds_barrier();
-        if (sh.stop) break;
+        // Only a half-step with survivors or a slot check (both uniform) needs a
+        // second barrier: the survivors read `cur` and flip bits of `nxt`, and
+        // the publication must follow the check.  Otherwise `nxt` is already
+        // final (the copy below, made in the previous half-step, was complete at
+        // this half-step's first barrier) and the verified progress of both
+        // neighbours is at least 8 half-steps beyond what the slot needs.
+        if (n_surv > 0 || check) lds_barrier();
 
         if (!isolated) publish(nxt, j + 1);
-        if (h == 1 && tid == 0 && (sh.n_down | sh.n_up)) {
-            const int64_t base = (n - a.ctl->tally_base) * a.n_devices + tile.d;
-            atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
-            for (int q = 0; q < kDeciles; ++q)
-                if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);
+        if (h == 1 && tid == 0) {
+            if (sh.n_down | sh.n_up) {
+                const int64_t base = (n - a.ctl->tally_base) * a.n_devices + tile.d;
+                atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
+                for (int q = 0; q < kDeciles; ++q)
+                    if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);
+            }
+            sh.n_down = 0;
+            sh.n_up = 0;
+            for (int q = 0; q < kDeciles; ++q) sh.dec[q] = 0;
         }
+        // `cur` is read by no one any more: it becomes the next half-step's
+        // output, starting as a copy of the new state.
+        for (int i = tid; i < nr * W; i += bdim) const_cast<uint64_t *>(cur)[i] = nxt[i];
     }
 
     // write the tile back (an even number of half-steps ends in B0)

@@ -168,3 +168,21 @@ def test_c2_full_size_sampled(mode):
         ref = part.reshape(4096, 1024)
         assert np.array_equal(occ[lo + 6:lo + 24], ref[lo + 6:lo + 24]), lo
     assert int(np.abs(net.cpu().numpy()).sum()) >= 0
+
+
+def test_persistent_long_run_keeps_ring_protocol():
+    """4096 x 1024 persistent run over 40 launches (40960 steps): every
+    neighbour wait completes (the kernel status stays clear) and every rail keeps
+    its ion count.  A publication issued before the slot-reuse check made such
+    long runs time out."""
+    from paper_2511_09413_amd import Simulator
+    wl = c2_large_device(n_steps=100_000)
+    sim = Simulator(wl.physics, wl.rails, wl.sites, ea=wl.ea_site)
+    assert sim.launch_mode == "persistent"
+    sim.fill_random(wl.filling)
+    occ0 = sim.read_occupancy().reshape(4096, 1024).sum(axis=1)
+    sim.set_protocols(wl.protocols)
+    sim.run_steps(40 * 1024)
+    sim.read_current()   # raises on a timed-out neighbour wait
+    occ = sim.read_occupancy().reshape(4096, 1024).sum(axis=1)
+    assert np.array_equal(occ, occ0)
