@@ -167,16 +167,22 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         if (last < 15) cand &= last < 0 ? 0u : ((2u << last) - 1u);
         cand_all = cand;
         const uint32_t thr0 = sh.wtab[0];  // the largest threshold (lowest class)
+        // stage 0: the smallest candidate word (non-candidates forced to all
+        // ones by their sign-extended bit) against the largest threshold
+        const uint32_t nc = ~cand;
+        auto masked = [&](uint32_t w, int bit) { return w | (uint32_t)__builtin_amdgcn_sbfe((int)nc, bit, 1); };
+        const uint32_t mA = min(min(masked(blkA.x, H), masked(blkA.y, H + 2)),
+                                min(masked(blkA.z, H + 4), masked(blkA.w, H + 6)));
+        const uint32_t mB = min(min(masked(blkB.x, H + 8), masked(blkB.y, H + 10)),
+                                min(masked(blkB.z, H + 12), masked(blkB.w, H + 14)));
         uint32_t sv = 0;
+        if (min(mA, mB) <= thr0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int bit = H + 2 * j;
-            if (((cand >> bit) & 1u) && word_of(blkA, j) <= thr0) sv |= 1u << bit;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int bit = 8 + H + 2 * j;
-            if (((cand >> bit) & 1u) && word_of(blkB, j) <= thr0) sv |= 1u << bit;
+            for (int j = 0; j < 4; ++j) {
+                const int bit = H + 2 * j;
+                if (((cand >> bit) & 1u) && word_of(blkA, j) <= thr0) sv |= 1u << bit;
+                if (((cand >> (bit + 8)) & 1u) && word_of(blkB, j) <= thr0) sv |= 1u << (bit + 8);
+            }
         }
         if (sv) {  // rare: compare with the threshold of the origin's class
             while (sv) {

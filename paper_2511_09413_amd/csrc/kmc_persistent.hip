@@ -214,12 +214,25 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
                 const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
                 const uint32_t thr0 = step_thr0[kstep];
+                // stage 0: the smallest word among the candidate bonds (the
+                // other words forced to all ones by their sign-extended
+                // non-candidate bit) against the largest threshold
+                const uint32_t nc = ~cand;
+                auto masked = [&](uint32_t w, int bit) {
+                    return w | (uint32_t)__builtin_amdgcn_sbfe((int)nc, bit, 1);
+                };
+                const uint32_t mA = min(min(masked(blkA.x, h), masked(blkA.y, h + 2)),
+                                        min(masked(blkA.z, h + 4), masked(blkA.w, h + 6)));
+                const uint32_t mB = min(min(masked(blkB.x, h + 8), masked(blkB.y, h + 10)),
+                                        min(masked(blkB.z, h + 12), masked(blkB.w, h + 14)));
                 uint32_t sv = 0;
+                if (min(mA, mB) <= thr0) {
 #pragma unroll
-                for (int jj = 0; jj < 4; ++jj) {
-                    const int bit = h + 2 * jj;
-                    if (((cand >> bit) & 1u) && word_of(blkA, jj) <= thr0) sv |= 1u << bit;
-                    if (((cand >> (bit + 8)) & 1u) && word_of(blkB, jj) <= thr0) sv |= 1u << (bit + 8);
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int bit = h + 2 * jj;
+                        if (((cand >> bit) & 1u) && word_of(blkA, jj) <= thr0) sv |= 1u << bit;
+                        if (((cand >> (bit + 8)) & 1u) && word_of(blkB, jj) <= thr0) sv |= 1u << (bit + 8);
+                    }
                 }
                 while (sv) {  // rare: the threshold of the origin's barrier class
                     const int bit = __builtin_ctz(sv);
