@@ -150,11 +150,27 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     // tracks a wavefront's loads and stores, so a wavefront that later waits
     // for a load (thread 0's progress probes) must not have stores in flight.
     const int pub_first = bdim - ((slot_words + 63) / 64) * 64;
+    // word i of a slot: 32 bits of edge rail i / W32 (the first m rails, then
+    // the last m); when the last wavefronts have a lane per word, each lane's
+    // word is fixed for the launch
+    const int pub_i = tid - (pub_first > 0 ? pub_first : 0);
+    const bool pub_one = pub_first >= 0;
+    int pub_w = 0, pub_sh = 0;
+    if (pub_one && pub_i >= 0 && pub_i < slot_words) {
+        const int b = pub_i / W32, q = pub_i - b * W32;
+        pub_w = (b < m ? b : nr - 2 * m + b) * W + (q >> 1);
+        pub_sh = 32 * (q & 1);
+    }
     auto publish = [&](const uint64_t *state, int64_t j) {
         uint64_t *slot = a.pub + (int64_t)ti * a.pub_stride + (int64_t)(j % kRing) * slot_words;
         const uint64_t tag = (uint64_t)pub_tag(epoch, j - j0) << 32;
-        for (int i = tid - (pub_first > 0 ? pub_first : 0); i >= 0 && i < slot_words;
-             i += (pub_first > 0 ? slot_words : bdim)) {
+        if (pub_one) {
+            if (pub_i >= 0 && pub_i < slot_words)
+                __hip_atomic_store(slot + pub_i, tag | (uint32_t)(state[pub_w] >> pub_sh), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        for (int i = tid; i < slot_words; i += bdim) {
             const int b = i / W32, q = i - b * W32;
             const int rrow = b < m ? b : nr - 2 * m + b;
             const uint32_t data = (uint32_t)(state[rrow * W + (q >> 1)] >> (32 * (q & 1)));
@@ -209,24 +225,22 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
             uint32_t bits = (uint32_t)(word >> sb) & 0xFFFFu;
             if (h && nx_exists) bits |= (uint32_t)((nx_here ? (word >> (sb + 16)) : cur[wi + 1]) & 1u) << 16;
             const uint32_t cand = (bits ^ (bits >> 1)) & (h ? 0xAAAAu : 0x5555u) & valid;
-            if (cand) {
+            {
+                // the key enters each half-step opaquely, so that the compiler
+                // derives the round keys on the scalar unit here instead of
+                // keeping twenty of them live (and spilled) across the loop
+                uint32_t k0 = a.key0, k1 = a.key1;
+                asm volatile("" : "+s"(k0), "+s"(k1));
                 const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
-                const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, a.key0, a.key1);
-                const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, a.key0, a.key1);
+                const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, k0, k1);
+                const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, k0, k1);
                 const uint32_t thr0 = step_thr0[kstep];
-                // stage 0: the smallest word among the candidate bonds (the
-                // other words forced to all ones by their sign-extended
-                // non-candidate bit) against the largest threshold
-                const uint32_t nc = ~cand;
-                auto masked = [&](uint32_t w, int bit) {
-                    return w | (uint32_t)__builtin_amdgcn_sbfe((int)nc, bit, 1);
-                };
-                const uint32_t mA = min(min(masked(blkA.x, h), masked(blkA.y, h + 2)),
-                                        min(masked(blkA.z, h + 4), masked(blkA.w, h + 6)));
-                const uint32_t mB = min(min(masked(blkB.x, h + 8), masked(blkB.y, h + 10)),
-                                        min(masked(blkB.z, h + 12), masked(blkB.w, h + 14)));
+                // stage 0: the smallest of the eight words against the largest
+                // threshold; only then the candidate bonds' words one by one
+                const uint32_t mn = min(min(min(blkA.x, blkA.y), min(blkA.z, blkA.w)),
+                                        min(min(blkB.x, blkB.y), min(blkB.z, blkB.w)));
                 uint32_t sv = 0;
-                if (min(mA, mB) <= thr0) {
+                if (mn <= thr0) {
 #pragma unroll
                     for (int jj = 0; jj < 4; ++jj) {
                         const int bit = h + 2 * jj;
