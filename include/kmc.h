@@ -226,6 +226,18 @@ kmc_status kmc_set_persistent_group_limit(kmc_ctx *ctx, int32_t max_tiles);
  * for the work already enqueued.  Trajectories do not depend on it. */
 kmc_status kmc_set_tile_sites(kmc_ctx *ctx, int32_t sites);
 
+/* Pick the launch strategy and tile size by timing trial runs of
+ * trial_steps steps (1..65536) for each candidate (persistent with several
+ * tile sizes when it fits, half-step launches with several tile sizes).  The
+ * state, step counter, tallies and log are restored after every trial and at
+ * the end, so tuning changes no trajectory; the fastest configuration stays
+ * selected.  Outputs (each may be NULL): the chosen tile size (0 = default),
+ * strategy (kmc_launch_mode) and its time per step in microseconds.
+ * Synchronises; KMC_EUNSUPPORTED if the trials would take the step counter
+ * past 2^32. */
+kmc_status kmc_autotune(kmc_ctx *ctx, int32_t trial_steps, int32_t *tile_sites, int32_t *mode,
+                        double *us_per_step);
+
 /* Current step counter. */
 kmc_status kmc_get_step(kmc_ctx *ctx, int64_t *step);
 

@@ -70,6 +70,7 @@ def lib():
         L.kmc_get_persistent_groups.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
         L.kmc_dense_potential.argtypes = [vp, vp]
+        L.kmc_autotune.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)]
         L.kmc_last_error.restype = C.c_char_p
         L.kmc_destroy.argtypes = [vp]
         L.kmc_destroy.restype = None
@@ -77,7 +78,8 @@ def lib():
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
-                     "kmc_set_persistent_group_limit", "kmc_dense_potential"):
+                     "kmc_set_persistent_group_limit", "kmc_dense_potential",
+                     "kmc_autotune"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -286,6 +288,42 @@ class Simulator:
 
     def read_threshold_log(self, cap: int = 65536):
         return read_threshold_log(self.ctx, cap)
+
+    def autotune(self, trial_steps: int = 256, cache: Optional[str] = None) -> dict:
+        """Select the fastest launch strategy and tile size (kmc_autotune; the
+        state is restored, no trajectory changes).  With `cache` (a JSON file),
+        a configuration measured before for the same shapes, physics and GPU is
+        applied without trials, and new results are added to the file."""
+        import json
+        key = self._tune_key()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if key in table:
+                hit = table[key]
+                set_tile_sites(self.ctx, int(hit["tile_sites"]))
+                set_launch_mode(self.ctx, hit["mode"])
+                return dict(hit, cached=True)
+        t, m, us = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
+        _check(lib().kmc_autotune(C.c_void_p(self.ctx), trial_steps, C.byref(t), C.byref(m), C.byref(us)))
+        out = {"tile_sites": int(t.value), "mode": {1: "half_step", 2: "persistent"}.get(int(m.value), "auto"),
+               "us_per_step": float(us.value), "trial_steps": trial_steps}
+        if cache:
+            table[key] = out
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return dict(out, cached=False)
+
+    def _tune_key(self) -> str:
+        import hashlib
+        ph = self.physics
+        gpu = self.torch.cuda.get_device_name(self.device)
+        desc = repr((self.rails, self.sites, ph.precision, ph.rail_range, ph.cutoff_sites, ph.screening_sites,
+                     gpu, self.ea is not None))
+        return hashlib.sha1(desc.encode()).hexdigest()
 
     def set_group_limit(self, max_tiles: int) -> None:
         """At most max_tiles workgroup tiles per persistent launch (0 = what fits)."""

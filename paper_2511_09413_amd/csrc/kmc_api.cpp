@@ -923,6 +923,117 @@ kmc_status kmc_set_tile_sites(kmc_ctx *c, int32_t sites) {
     return retile(c);
 }
 
+namespace {
+// Everything a trial run changes, saved so that tuning leaves no trace.
+struct Saved {
+    Ctl ctl;
+    std::vector<int64_t> net_total, dec_run;
+    int64_t log_count = 0;
+    int64_t n = 0, steps_run = 0;
+};
+
+kmc_status save_state(kmc_ctx *c, Saved &sv) {
+    const int D = c->p.n_devices;
+    sv.net_total.resize(D);
+    sv.dec_run.resize((size_t)D * kDeciles);
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.rp_a, c->cur, (size_t)c->lay.total_pad, hipMemcpyDeviceToDevice,
+                              c->stream));
+    KMC_HIP(c, hipMemcpyAsync(&sv.ctl, c->ws + c->lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+    KMC_HIP(c, hipMemcpyAsync(sv.net_total.data(), c->ws + c->lay.net_total, sizeof(int64_t) * D,
+                              hipMemcpyDeviceToHost, c->stream));
+    KMC_HIP(c, hipMemcpyAsync(sv.dec_run.data(), c->ws + c->lay.dec_run, sizeof(int64_t) * D * kDeciles,
+                              hipMemcpyDeviceToHost, c->stream));
+    KMC_HIP(c, hipMemcpyAsync(&sv.log_count, c->ws + c->lay.log_count, sizeof(int64_t), hipMemcpyDeviceToHost,
+                              c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));
+    sv.n = c->n;
+    sv.steps_run = c->steps_run;
+    return KMC_OK;
+}
+
+kmc_status restore_state(kmc_ctx *c, const Saved &sv) {
+    const int D = c->p.n_devices;
+    KMC_HIP(c, hipMemcpyAsync(c->cur, c->ws + c->lay.rp_a, (size_t)c->lay.total_pad, hipMemcpyDeviceToDevice,
+                              c->stream));
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.ctl, &sv.ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.net_total, sv.net_total.data(), sizeof(int64_t) * D,
+                              hipMemcpyHostToDevice, c->stream));
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.dec_run, sv.dec_run.data(), sizeof(int64_t) * D * kDeciles,
+                              hipMemcpyHostToDevice, c->stream));
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.log_count, &sv.log_count, sizeof(int64_t), hipMemcpyHostToDevice,
+                              c->stream));
+    KMC_HIP(c, launch_zero_i32(c->at<int32_t>(c->lay.status), 4, c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));  // the host copies above are locals of the caller
+    c->n = sv.n;
+    c->steps_run = sv.steps_run;
+    return KMC_OK;
+}
+}  // namespace
+
+kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, int32_t *mode, double *us_per_step) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (trial_steps < 1 || trial_steps > 65536) return fail(KMC_EINVAL, "trial_steps must be in [1, 65536]");
+    if (c->n + 2 * (int64_t)trial_steps > (int64_t)0xffffffffLL)
+        return fail(KMC_EUNSUPPORTED, "step counter too close to 2^32 for the trials");
+    Saved sv;
+    s = save_state(c, sv);
+    if (s != KMC_OK) return s;
+    const int old_tile = c->tile_sites, old_mode = c->mode;
+    struct Cand { int mode, tile; };
+    std::vector<Cand> cands;
+    if (!c->dense)
+        for (int t : {0, 4096, 8192, 12288, 16384}) cands.push_back({KMC_LAUNCH_PERSISTENT, t});
+    for (int t : {0, 1024, 2048, 8192}) cands.push_back({KMC_LAUNCH_HALF_STEP, t});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    KMC_HIP(c, hipEventCreate(&e0));
+    KMC_HIP(c, hipEventCreate(&e1));
+    double best = 1e300;
+    Cand pick{old_mode, old_tile};
+    for (const Cand &cd : cands) {
+        c->tile_sites = cd.tile;
+        s = retile(c);
+        if (s != KMC_OK) break;
+        if (cd.mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) continue;
+        c->mode = cd.mode;
+        float ms = 0.0f;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run pays one-time costs
+            s = restore_state(c, sv);
+            if (s != KMC_OK) break;
+            KMC_HIP(c, launch_begin_call(c->at<Ctl>(c->lay.ctl), nullptr, nullptr, c->stream));
+            KMC_HIP(c, hipEventRecord(e0, c->stream));
+            s = enqueue_steps(c, trial_steps);
+            if (s != KMC_OK) break;
+            KMC_HIP(c, hipEventRecord(e1, c->stream));
+            KMC_HIP(c, hipEventSynchronize(e1));
+            KMC_HIP(c, hipEventElapsedTime(&ms, e0, e1));
+            int32_t st = 0;
+            KMC_HIP(c, hipMemcpy(&st, c->ws + c->lay.status, sizeof(int32_t), hipMemcpyDeviceToHost));
+            ok = st == 0;  // a configuration whose neighbour waits timed out is not a candidate
+        }
+        if (s != KMC_OK) break;
+        const double us = 1e3 * ms / trial_steps;
+        if (ok && us < best) {
+            best = us;
+            pick = cd;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != KMC_OK) return s;
+    c->tile_sites = pick.tile;
+    s = retile(c);
+    if (s != KMC_OK) return s;
+    c->mode = (pick.mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) ? KMC_LAUNCH_AUTO : pick.mode;
+    s = restore_state(c, sv);
+    if (s != KMC_OK) return s;
+    if (tile_sites) *tile_sites = pick.tile;
+    if (mode) *mode = pick.mode;
+    if (us_per_step) *us_per_step = best;
+    return KMC_OK;
+}
+
 kmc_status kmc_set_persistent_group_limit(kmc_ctx *c, int32_t max_tiles) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;

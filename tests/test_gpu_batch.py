@@ -94,3 +94,31 @@ def test_c3_full_batch_sampled():
         part = np.concatenate([np.zeros(2 * d, dtype=np.int8), occ0[a:b]])
         oracle.run(p_or, [constant(0.0)] * d + [wl.protocols[d]], part, 0, 4, want_dec=False)
         assert np.array_equal(occ[a:b], part[2 * d:]), d
+
+
+def test_autotune_leaves_trajectory_and_caches(tmp_path):
+    """kmc_autotune times the candidate configurations but restores the state,
+    step counter and tallies: afterwards the run equals that of an untuned
+    context step for step; a second context with the same shapes takes the
+    configuration from the JSON cache without trials."""
+    import torch
+    from paper_2511_09413_amd import Simulator
+    ph = Physics(precision=FP32, seed=21, ea_ev=0.15)
+    protos = _protocols(len(RAILS))
+    runs = []
+    cache = str(tmp_path / "tune.json")
+    for tune in (False, True, True):
+        sim = Simulator(ph, RAILS, SITES)
+        sim.fill_random(FILL)
+        sim.set_protocols(protos)
+        sim.run_steps(50)
+        info = sim.autotune(trial_steps=64, cache=cache) if tune else None
+        assert sim.step == 50
+        net, dec = sim.run_steps(300, tallies=True)
+        runs.append((net.cpu(), dec.cpu(), sim.read_occupancy(), sim.read_current()[1], info))
+        sim.close()
+    for r in runs[1:]:
+        assert torch.equal(r[0], runs[0][0]) and torch.equal(r[1], runs[0][1])
+        assert np.array_equal(r[2], runs[0][2]) and np.array_equal(r[3], runs[0][3])
+    assert runs[1][4]["cached"] is False and runs[1][4]["us_per_step"] > 0
+    assert runs[2][4]["cached"] is True and runs[2][4]["mode"] == runs[1][4]["mode"]
