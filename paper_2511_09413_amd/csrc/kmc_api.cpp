@@ -59,6 +59,7 @@ kmc_status fail(kmc_status s, const std::string &msg) {
 
 constexpr int64_t kLogCap = 65536;
 constexpr int64_t kMaxPTiles = 2048;
+constexpr int kPTileSites = 8192;  // default padded sites per persistent tile
 constexpr double kElementaryCharge = 1.602176634e-19;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -155,13 +156,22 @@ Layout layout_for(const kmc_params *p) {
     L.rail_idx = take(sizeof(int32_t) * (size_t)rails);
     L.n_ions = take(sizeof(int32_t) * D);
     // persistent kernel: tiles, progress counters (one cache line each) and the
-    // edge-rail publication rings, capped at 64 MiB
+    // edge-rail publications (a slot per state of a launch), capped at 2 GiB by
+    // limiting the tiles of one launch
     int max_pitch = 0;
     for (int d = 0; d < D; ++d) max_pitch = std::max(max_pitch, (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites);
     L.max_pitch = max_pitch;
-    L.pub_stride = (int64_t)kRing * 2 * std::max(m, 1) * ((max_pitch + 31) / 32);
-    const int64_t pub_cap = ((int64_t)64 << 20) / (8 * L.pub_stride);
-    L.max_ptiles = std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap);
+    L.pub_stride = (int64_t)kPubSlots * 2 * std::max(m, 1) * ((max_pitch + 31) / 32);
+    // tiles of one launch: at most twice the default tiling's tile count (room
+    // for the autotuner's smaller tiles) or 64, and at most 1 GiB of publications
+    int64_t default_tiles = 0;
+    for (int d = 0; d < D; ++d) {
+        const int pitch = (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites;
+        default_tiles += std::max(1, p->rails[d] / std::max(std::max(m, 1), kPTileSites / pitch));
+    }
+    const int64_t pub_cap = std::max<int64_t>(1, ((int64_t)1 << 30) / (8 * L.pub_stride));
+    L.max_ptiles = std::min<int64_t>(std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap),
+                                     std::max<int64_t>(2 * default_tiles, 64));
     L.ptiles = take(sizeof(PTile) * (size_t)rails);  // every tile is at least one rail
     L.progress = take(sizeof(uint64_t) * 8 * (size_t)L.max_ptiles);
     L.pub = take(sizeof(uint64_t) * (size_t)(L.pub_stride * L.max_ptiles));
@@ -306,7 +316,7 @@ void make_tiles(kmc_ctx *c) {
 void make_ptiles(kmc_ctx *c) {
     c->ptiles.clear();
     const int m = std::max(c->p.rail_range, 1);
-    const int target = c->tile_sites > 0 ? c->tile_sites : 8192;
+    const int target = c->tile_sites > 0 ? c->tile_sites : kPTileSites;
     int max_chunks = 0;
     size_t lds = 0;
     const size_t real = c->fp64 ? sizeof(double) : sizeof(float);

@@ -49,7 +49,7 @@ struct PTile {
     int32_t d, r0, nr, prev, next, pad_;
 };
 
-constexpr int kRing = 32;                // publication slots per tile
+constexpr int kPubSlots = 2 * kTallySteps + 1;  // publication slots per tile: one per state of a launch
 constexpr int kPMaxBlock = 1024;         // threads per workgroup, persistent kernel
 
 // Step bookkeeping in device memory (lets a captured graph be replayed).
@@ -136,8 +136,8 @@ struct PArgs {
     int32_t n_devices;
     HopArgs::LogBuf log;
     uint64_t *progress;        // [n_tiles * 8]: (epoch << 40) | half-steps completed
-    uint64_t *pub;             // edge-rail publications, pub_stride words per tile
-    int64_t pub_stride;        // kRing * 2m * max_pitch / 8
+    uint64_t *pub;             // edge-rail publications, pub_stride words per tile, one slot per state
+    int64_t pub_stride;        // kPubSlots * 2m * ceil(max_pitch / 32) words per tile
     int32_t max_pitch;
     uint64_t epoch;
     int32_t n_steps;

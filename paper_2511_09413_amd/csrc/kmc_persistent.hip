@@ -9,19 +9,19 @@
 //
 // Only the tile's first and last rail_range rails cross workgroups: the
 // Coulomb windows of the neighbouring tiles reach into them.  After every
-// half-step the workgroup writes those rails into a ring of kRing slots in
-// global memory as 64-bit words, 32 occupancy bits plus a 32-bit tag naming
-// the state (launch epoch, half-step).  Data and tag travel in one store, so
-// a writer never waits for its stores; a reader that needs a neighbour's rail
-// (a survivor whose window crosses the tile edge, which is rare) polls the
-// words it needs until their tags name the state it wants.  Before a slot is
-// overwritten, the writer checks, with one load issued a half-step ahead, that
-// both neighbours have published the state that proves they finished reading
-// it.  There is no grid-wide barrier.  Every wait is bounded: on time-out the
-// kernel raises a status flag, all workgroups leave their loops and the host
-// reports the error.  Cross-workgroup words are accessed only with relaxed
-// agent-scope atomics, which gfx950 executes as coherent (sc1) loads and
-// stores.
+// half-step the workgroup writes those rails into its own slot for that state
+// (a slot per state of the launch, never reused within it) as 64-bit words:
+// 32 occupancy bits plus a 32-bit tag naming the state (launch epoch,
+// half-step).  Data and tag travel in one store, so a writer never waits; a
+// reader that needs a neighbour's rail (a survivor whose window crosses the
+// tile edge, which is rare) polls the words it needs until their tags name the
+// state it wants.  Nothing else couples the workgroups: there is no grid-wide
+// barrier and no slot reuse to guard, so a workgroup waits only when one of its
+// survivors needs a neighbour's state that is not published yet.  Every wait
+// is bounded: on time-out the kernel raises a status flag, all workgroups leave
+// their loops and the host reports the error.  Cross-workgroup words are
+// accessed only with relaxed agent-scope atomics, which gfx950 executes as
+// coherent (sc1) loads and stores.
 //
 // Per bond the work is that of hop_half_step: Philox4x32-10 draw, candidate
 // test, exact two-stage prefilter, survivor energy (wavefront-cooperative
@@ -36,9 +36,7 @@ constexpr int kSpinLimit = 1 << 20;  // about a second of polling
 struct PShared {
     int32_t n_surv[2];            // survivors of even / odd half-steps (reset one half-step ahead)
     int32_t n_down, n_up, stop;
-    int32_t check[2];             // slot check in this half-step (decided before its first barrier)
     int32_t dec[kDeciles];
-    int64_t ver_prev, ver_next;   // neighbour progress verified so far (half-steps, relative)
 };
 
 __device__ __forceinline__ uint32_t pub_tag(uint64_t epoch, int64_t j_rel) {
@@ -133,8 +131,6 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     }
     if (tid == 0) {
         sh.stop = 0;
-        sh.ver_prev = -1;
-        sh.ver_next = -1;
         sh.n_surv[0] = 0;
         sh.n_surv[1] = 0;
         sh.n_down = 0;
@@ -162,7 +158,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         pub_sh = 32 * (q & 1);
     }
     auto publish = [&](const uint64_t *state, int64_t j) {
-        uint64_t *slot = a.pub + (int64_t)ti * a.pub_stride + (int64_t)(j % kRing) * slot_words;
+        uint64_t *slot = a.pub + (int64_t)ti * a.pub_stride + (j - j0) * slot_words;
         const uint64_t tag = (uint64_t)pub_tag(epoch, j - j0) << 32;
         if (pub_one) {
             if (pub_i >= 0 && pub_i < slot_words)
@@ -178,14 +174,14 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         }
     };
     // Wait until word `i` of tile t's slot for state j carries state j's tag
-    // (or a later one when `at_least`) and store it in *out; false on time-out.
-    auto fetch = [&](int t, int64_t j, int i, bool at_least, uint64_t *out) -> bool {
-        const uint64_t *w = a.pub + (int64_t)t * a.pub_stride + (int64_t)(j % kRing) * slot_words + i;
+    // and store it in *out; false on time-out.
+    auto fetch = [&](int t, int64_t j, int i, uint64_t *out) -> bool {
+        const uint64_t *w = a.pub + (int64_t)t * a.pub_stride + (j - j0) * slot_words + i;
         const uint32_t want = pub_tag(epoch, j - j0);
         for (int spins = 0;; ++spins) {
             const uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t tag = (uint32_t)(v >> 32);
-            if (tag == want || (at_least && (tag >> 12) == (want >> 12) && tag > want)) {
+            if (tag == want) {
                 *out = v;
                 return true;
             }
@@ -206,18 +202,10 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         const uint64_t *cur = (js & 1) ? B1 : B0;
         uint64_t *nxt = (js & 1) ? B0 : B1;
         const int kstep = js >> 1;
-        const int64_t need = j + 2 - kRing - j0;
         // The counter of the next half-step is cleared here, before this
         // half-step's barrier: its last readers (the previous half-step) have
         // either passed that half-step's survivor barrier or read a zero.
-        if (tid == 0) {
-            sh.n_surv[(js + 1) & 1] = 0;
-            // whether this half-step re-verifies the neighbours' progress (see
-            // below); decided by thread 0 alone, from its own records, and read
-            // by everyone after the barrier, so that the barrier ordering the
-            // check before the publication is taken by all or by none
-            sh.check[js & 1] = !isolated && js >= 4 && (sh.ver_prev < need + 8 || sh.ver_next < need + 8);
-        }
+        if (tid == 0) sh.n_surv[(js + 1) & 1] = 0;
 
         // candidates, Philox words, exact two-stage prefilter
         if (has_chunk) {
@@ -268,42 +256,6 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         lds_barrier();
         if (sh.stop) break;
 
-        // Slot check for the publication at the end of this half-step: the slot
-        // of state j+1 held state j+1-kRing, which the neighbours read during
-        // their half-step j+1-kRing; they finished it once they published
-        // state j+2-kRing (`need`, relative to the launch).  Thread 0 keeps the
-        // latest published state it has seen of each neighbour and refreshes
-        // it only when it comes within 8 half-steps of the need: both
-        // neighbours' slots of state j-4 are loaded together (their tags name
-        // the state they hold; a store takes about a half-step to become
-        // visible, so a state published a few half-steps ago is read back
-        // reliably), and only if a neighbour is truly behind does thread 0
-        // poll for state `need`.  In steady state that is one load
-        // latency every twenty-odd half-steps for wavefront 0 alone.
-        const bool check = sh.check[js & 1];
-        if (check && tid == 0) {
-            const int64_t slot_prev = (int64_t)tile.prev * a.pub_stride + ((j - 4) % kRing) * slot_words;
-            const int64_t slot_next = (int64_t)tile.next * a.pub_stride + ((j - 4) % kRing) * slot_words;
-            const uint64_t vp = __hip_atomic_load(a.pub + slot_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint64_t vn = __hip_atomic_load(a.pub + slot_next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t epoch_bits = pub_tag(epoch, 0) >> 12;
-            const uint32_t tp = (uint32_t)(vp >> 32), tn = (uint32_t)(vn >> 32);
-            if ((tp >> 12) == epoch_bits) sh.ver_prev = max(sh.ver_prev, (int64_t)(tp & 0xFFFu));
-            if ((tn >> 12) == epoch_bits) sh.ver_next = max(sh.ver_next, (int64_t)(tn & 0xFFFu));
-            if (tile.next == tile.prev) sh.ver_next = sh.ver_prev = max(sh.ver_prev, sh.ver_next);
-            bool ok = true;
-            uint64_t v = 0;
-            if (need > 0 && sh.ver_prev < need) {
-                ok = fetch(tile.prev, j0 + need, 0, true, &v);
-                if (ok) sh.ver_prev = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
-            }
-            if (ok && need > 0 && sh.ver_next < need) {
-                ok = fetch(tile.next, j0 + need, 0, true, &v);
-                if (ok) sh.ver_next = (int64_t)((uint32_t)(v >> 32) & 0xFFFu);
-            }
-            if (!ok) sh.stop = 1;
-        }
-
         // survivors: one wavefront each
         const int n_surv = sh.n_surv[js & 1];
         for (int i = wave; i < n_surv; i += n_waves) {
@@ -329,7 +281,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                         bit = (uint32_t)(cur[rho * W + (jj >> 6)] >> (jj & 63)) & 1u;
                     } else {
                         uint64_t v = 0;
-                        if (!fetch(nb, j, band * W32 + (jj >> 5), false, &v)) {
+                        if (!fetch(nb, j, band * W32 + (jj >> 5), &v)) {
                             ok = false;
                             break;
                         }
@@ -366,13 +318,11 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 }
             }
         }
-        // Only a half-step with survivors or a slot check (both uniform) needs a
-        // second barrier: the survivors read `cur` and flip bits of `nxt`, and
-        // the publication must follow the check.  Otherwise `nxt` is already
-        // final (the copy below, made in the previous half-step, was complete at
-        // this half-step's first barrier) and the verified progress of both
-        // neighbours is at least 8 half-steps beyond what the slot needs.
-        if (n_surv > 0 || check) lds_barrier();
+        // Only a half-step with survivors (uniform) needs a second barrier: the
+        // survivors read `cur` and flip bits of `nxt`.  Otherwise `nxt` is
+        // already final (the copy below, made in the previous half-step, was
+        // complete at this half-step's first barrier).
+        if (n_surv > 0) lds_barrier();
 
         if (!isolated) publish(nxt, j + 1);
         if (h == 1 && tid == 0) {

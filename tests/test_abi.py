@@ -53,4 +53,4 @@ def test_validation_errors_without_gpu():
 def test_workspace_scales_with_lattice():
     a = _status(Physics(), [64], [128])[1]
     b = _status(Physics(), [4096], [1024])[1]
-    assert b > 2 * 4096 * 1024 > a
+    assert b > 2 * 4096 * 1024 and 16 * a < b
