@@ -59,7 +59,8 @@ kmc_status fail(kmc_status s, const std::string &msg) {
 
 constexpr int64_t kLogCap = 65536;
 constexpr int64_t kMaxPTiles = 2048;
-constexpr int kPTileSites = 8192;  // default padded sites per persistent tile
+constexpr int kPTileSites = 4096;  // default padded sites per persistent tile
+constexpr int kStepWin = 128;      // per-step table window of the persistent kernel
 constexpr double kElementaryCharge = 1.602176634e-19;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -156,20 +157,19 @@ Layout layout_for(const kmc_params *p) {
     L.rail_idx = take(sizeof(int32_t) * (size_t)rails);
     L.n_ions = take(sizeof(int32_t) * D);
     // persistent kernel: tiles, progress counters (one cache line each) and the
-    // edge-rail publications (a slot per state of a launch), capped at 2 GiB by
-    // limiting the tiles of one launch
+    // edge-rail publications (a slot per state of a launch)
     int max_pitch = 0;
     for (int d = 0; d < D; ++d) max_pitch = std::max(max_pitch, (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites);
     L.max_pitch = max_pitch;
     L.pub_stride = (int64_t)kPubSlots * 2 * std::max(m, 1) * ((max_pitch + 31) / 32);
     // tiles of one launch: at most twice the default tiling's tile count (room
-    // for the autotuner's smaller tiles) or 64, and at most 1 GiB of publications
+    // for the autotuner's smaller tiles) or 64, and at most 1.25 GiB of publications
     int64_t default_tiles = 0;
     for (int d = 0; d < D; ++d) {
         const int pitch = (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites;
         default_tiles += std::max(1, p->rails[d] / std::max(std::max(m, 1), kPTileSites / pitch));
     }
-    const int64_t pub_cap = std::max<int64_t>(1, ((int64_t)1 << 30) / (8 * L.pub_stride));
+    const int64_t pub_cap = std::max<int64_t>(1, ((int64_t)5 << 28) / (8 * L.pub_stride));
     L.max_ptiles = std::min<int64_t>(std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap),
                                      std::max<int64_t>(2 * default_tiles, 64));
     L.ptiles = take(sizeof(PTile) * (size_t)rails);  // every tile is at least one rail
@@ -336,12 +336,13 @@ void make_ptiles(kmc_ctx *c) {
             c->ptiles.push_back(PTile{d, r0, nr, prev, next, 0});
             r0 += nr;
             max_chunks = std::max(max_chunks, nr * dv.pitch / kChunkSites);
-            // occupancy bits (two buffers), barrier classes, survivor lists, kernel table
+            // occupancy bits (two buffers), barrier classes, survivor positions, kernel
+            // table, a window of per-step tables
             const size_t words = (size_t)nr * ((dv.pitch + 63) / 64);
             const size_t cap = (size_t)nr * dv.pitch / 2;
             lds = std::max(lds, 2 * words * sizeof(uint64_t) + (size_t)nr * dv.pitch +
-                                    (2 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + ((kt + 7) & ~(size_t)7) +
-                                    (size_t)kTallySteps * (2 * sizeof(double) + sizeof(uint32_t)));
+                                    (cap + (cap & 1)) * sizeof(uint32_t) + ((kt + 7) & ~(size_t)7) +
+                                    (size_t)kStepWin * (2 * sizeof(double) + sizeof(uint32_t)));
         }
     }
     c->p_block = std::min(kPMaxBlock, (max_chunks + 63) / 64 * 64);

@@ -32,6 +32,7 @@
 namespace kmc {
 
 constexpr int kSpinLimit = 1 << 20;  // about a second of polling
+constexpr int kStepWin = 128;        // steps of the per-step tables held in LDS
 
 struct PShared {
     int32_t n_surv[2];            // survivors of even / odd half-steps (reset one half-step ahead)
@@ -75,19 +76,18 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     uint64_t *B0 = reinterpret_cast<uint64_t *>(smem);
     uint64_t *B1 = B0 + nr * W;
     unsigned char *cls = reinterpret_cast<unsigned char *>(B1 + nr * W);
-    uint32_t *sv_pos = reinterpret_cast<uint32_t *>(cls + nr * P);
-    uint32_t *sv_w = sv_pos + cap;
-    Real *sv_ea = reinterpret_cast<Real *>(sv_w + cap + (cap & 1));
-    Real *kt_lds = sv_ea + cap;
+    uint32_t *sv_pos = reinterpret_cast<uint32_t *>(cls + nr * P);  // survivors: row << 13 | bond
+    Real *kt_lds = reinterpret_cast<Real *>(sv_pos + cap + (cap & 1));
     const int kt_stride = a.cutoff + 1;
     const int n_kt = (m + 1) * kt_stride;
     const bool kt_in_lds = n_kt <= kLdsTableMax;
-    // per-step tables of the launch: bias V, g = exp(beta (|alpha V|/L + coul_bound)/2)
-    // and the stage-0 threshold
+    // per-step tables, a window of kStepWin steps refreshed half a window
+    // ahead: bias V, g = exp(beta (|alpha V|/L + coul_bound)/2) and the
+    // stage-0 threshold of step k at index k % kStepWin
     double *step_V = reinterpret_cast<double *>(
         reinterpret_cast<unsigned char *>(kt_lds) + (kt_in_lds ? ((n_kt * (int)sizeof(Real) + 7) & ~7) : 0));
-    double *step_g = step_V + a.n_steps;
-    uint32_t *step_thr0 = reinterpret_cast<uint32_t *>(step_g + a.n_steps);
+    double *step_g = step_V + kStepWin;
+    uint32_t *step_thr0 = reinterpret_cast<uint32_t *>(step_g + kStepWin);
     const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
                                                             : reinterpret_cast<const Real *>(a.ktab32);
     const Real *kt = kt_in_lds ? kt_lds : kt_glob;
@@ -121,14 +121,17 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     if (kt_in_lds)
         for (int i = tid; i < n_kt; i += bdim) kt_lds[i] = kt_glob[i];
     for (int q = tid; q < kClasses; q += bdim) cls_A[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
-    for (int k = tid; k < a.n_steps; k += bdim) {
-        const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots,
-                                          dv.n_knots, (double)((j0 >> 1) + k - dv.n_set) * a.dt);
-        const double g = exp(0.5 * a.beta * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
-        step_V[k] = V;
-        step_g[k] = g;
-        step_thr0[k] = threshold_of(a.c0, exp(-a.beta * dv.ea_min), g);
-    }
+    auto fill_steps = [&](int k_lo, int k_hi) {  // table entries of steps [k_lo, k_hi)
+        for (int k = k_lo + tid; k < k_hi && k < a.n_steps; k += bdim) {
+            const double V = protocol_voltage(a.knot_t + tile.d * kMaxKnots, a.knot_v + tile.d * kMaxKnots,
+                                              dv.n_knots, (double)((j0 >> 1) + k - dv.n_set) * a.dt);
+            const double g = exp(0.5 * a.beta * (fabs(a.alpha * V) / (double)L + dv.coul_bound));
+            step_V[k % kStepWin] = V;
+            step_g[k % kStepWin] = g;
+            step_thr0[k % kStepWin] = threshold_of(a.c0, exp(-a.beta * dv.ea_min), g);
+        }
+    };
+    fill_steps(0, kStepWin);
     if (tid == 0) {
         sh.stop = 0;
         sh.n_surv[0] = 0;
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                 const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
                 const uint4 blkA = philox4x32_10((uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, k0, k1);
                 const uint4 blkB = philox4x32_10((uint32_t)(s0 >> 3) + 1u, rail, (uint32_t)n, ctr3, k0, k1);
-                const uint32_t thr0 = step_thr0[kstep];
+                const uint32_t thr0 = step_thr0[kstep % kStepWin];
                 // stage 0: the smallest of the eight words against the largest
                 // threshold; only then the candidate bonds' words one by one
                 const uint32_t mn = min(min(min(blkA.x, blkA.y), min(blkA.z, blkA.w)),
@@ -241,20 +244,16 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                     sv &= sv - 1;
                     const int o = s0 + (((bits >> bit) & 1u) ? bit : bit + 1);
                     const uint32_t w = word_of8(blkA, blkB, bit >> 1);
-                    if (w <= threshold_of(a.c0, cls_A[cls[row * P + o]], step_g[kstep])) {
+                    if (w <= threshold_of(a.c0, cls_A[cls[row * P + o]], step_g[kstep % kStepWin])) {
                         const int k = atomicAdd(&sh.n_surv[js & 1], 1);
                         sv_pos[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
-                        sv_w[k] = w;
-                        Real ea;
-                        if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)rail * L + o];
-                        else ea = (Real)a.ea_scalar;
-                        sv_ea[k] = ea;
                     }
                 }
             }
         }
         lds_barrier();
         if (sh.stop) break;
+        if (js > 0 && (js % kStepWin) == 0) fill_steps(kstep + kStepWin / 2, kstep + kStepWin);
 
         // survivors: one wavefront each
         const int n_surv = sh.n_surv[js & 1];
@@ -302,9 +301,16 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
 #pragma unroll
             for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
             if (lane == 0) {
-                const Real e_app = ((alpha_r * (Real)step_V[kstep]) * (Real)(t - o)) / (Real)L;
+                const Real e_app = ((alpha_r * (Real)step_V[kstep % kStepWin]) * (Real)(t - o)) / (Real)L;
                 const int srail = tile.r0 + srow;
-                if (decide_hop<Real>(e_app + part, sv_ea[i], sv_w[i], beta_r, c0_r, a.log, tile.d, h, n, srail, s)) {
+                // the survivor's word and barrier again (rare: cheaper than
+                // keeping them for every possible survivor)
+                const uint4 blk = philox4x32_10((uint32_t)(s >> 3), (uint32_t)srail, (uint32_t)n,
+                                                ((uint32_t)tile.d << 4) | (uint32_t)h, a.key0, a.key1);
+                const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)srail * L + o]
+                                     : (Real)a.ea_scalar;
+                if (decide_hop<Real>(e_app + part, ea, word_of(blk, (s >> 1) & 3), beta_r, c0_r, a.log, tile.d, h, n,
+                                     srail, s)) {
                     atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + (s >> 6)]), 1ull << (s & 63));
                     atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + ((s + 1) >> 6)]),
                               1ull << ((s + 1) & 63));
