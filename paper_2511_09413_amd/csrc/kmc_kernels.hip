@@ -51,8 +51,10 @@ struct HopShared {
 // j0 + k), zero outside the row.  rbits holds each row as 16-bit words.
 __device__ __forceinline__ uint32_t window_bits(const uint16_t *rb, int p16, int j0) {
     const int w = j0 >> 4, sh = j0 & 15;
-    const uint32_t lo = (w >= 0 && w < p16) ? rb[w] : 0u;
-    const uint32_t hi = (w + 1 >= 0 && w + 1 < p16) ? rb[w + 1] : 0u;
+    // clamped reads and selects instead of guarded loads (no branches)
+    const int wl = min(max(w, 0), p16 - 1), wh = min(max(w + 1, 0), p16 - 1);
+    const uint32_t lo = (w >= 0 && w < p16) ? (uint32_t)rb[wl] : 0u;
+    const uint32_t hi = (w + 1 >= 0 && w + 1 < p16) ? (uint32_t)rb[wh] : 0u;
     return ((hi << 16 | lo) >> sh) & 0xFFFFu;
 }
 
@@ -312,15 +314,44 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         if (dt_in_lds)
             for (int i = tid; i < n_dt; i += kBlock) dt_lds[i] = reinterpret_cast<const Real *>(a.dtab)[i];
         __syncthreads();
-        const Real *dtab = dt_in_lds ? dt_lds : reinterpret_cast<const Real *>(a.dtab);
         const int n_cand = sh.n_cand;
         const int wn = 2 * a.cutoff + 2;   // window length
+        const int n_full = wn >> 4;        // full 16-site blocks, then wn % 16 single sites
         const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
         const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
         const double W = a.score_w[tile.d];
         const double beta = a.beta, V = sh.V;
         const double g_ea = -beta, g_nu = 1.0 / a.nu0;
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        // Sum of occ_j D(j - s) over a 16-site block: every entry is loaded and
+        // masked with its sign-extended occupancy bit (an empty site adds +0).
+        auto block_sum = [&](Real acc, const Real *d, uint32_t wb) {
+            Real v[16];
+            if constexpr (std::is_same<Real, float>::value) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float4 f = reinterpret_cast<const float4 *>(d)[q];
+                    v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    acc += __int_as_float(__float_as_int(v[q]) & __builtin_amdgcn_sbfe((int)wb, q, 1));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const double2 f = reinterpret_cast<const double2 *>(d)[q];
+                    v[2 * q] = f.x; v[2 * q + 1] = f.y;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {  // both 32-bit halves masked explicitly
+                    const unsigned long long b64 = (unsigned long long)__double_as_longlong(v[q]);
+                    const uint32_t mk = (uint32_t)__builtin_amdgcn_sbfe((int)wb, q, 1);
+                    const uint32_t lo = (uint32_t)b64 & mk, hi = (uint32_t)(b64 >> 32) & mk;
+                    acc += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+                }
+            }
+            return acc;
+        };
         for (int i = tid; i < n_cand; i += kBlock) {
             const uint32_t e = clist[i];
             const int crow = (int)(e >> 14), s = (int)(e & 4095u);
@@ -328,20 +359,29 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
             const uint32_t y = (e >> 13) & 1u;
             const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
             const int j0 = s - a.cutoff;
+            // the up-move table serves both directions: the down move's terms
+            // are the exact negatives, so is its ordered sum (symmetric rounding)
             Real ec = (Real)0;
             for (int k = 0; k < dv.n_nbr; ++k) {
-                const Real *drow = dtab + (dir * (m + 1) + dv.nbr_dist[k]) * a.dpitch;
                 const uint16_t *rb = rbits + (m + crow + dv.nbr_off[k]) * p16;
-                for (int x0 = 0; x0 < wn; x0 += 16) {
-                    const uint32_t wb = window_bits(rb, p16, j0 + x0);
-                    if (x0 + 16 <= wn) {
-#pragma unroll
-                        for (int q = 0; q < 16; ++q) ec += ((wb >> q) & 1u) ? drow[x0 + q] : (Real)0;
-                    } else {
-                        for (int q = 0; q < wn - x0; ++q) ec += ((wb >> q) & 1u) ? drow[x0 + q] : (Real)0;
+                const int row_at = dv.nbr_dist[k] * a.dpitch;
+                const Real *dr = dt_in_lds ? dt_lds + row_at : reinterpret_cast<const Real *>(a.dtab) + row_at;
+                if (dt_in_lds) {
+                    for (int b = 0; b < n_full; ++b)
+                        ec = block_sum(ec, dt_lds + row_at + 16 * b, window_bits(rb, p16, j0 + 16 * b));
+                } else {
+                    for (int b = 0; b < n_full; ++b)
+                        ec = block_sum(ec, dr + 16 * b, window_bits(rb, p16, j0 + 16 * b));
+                }
+                if (16 * n_full < wn) {  // the last wn % 16 sites, in order
+                    const uint32_t wb = window_bits(rb, p16, j0 + 16 * n_full);
+                    for (int q = 0; q < wn - 16 * n_full; ++q) {
+                        const Real d = dr[16 * n_full + q];
+                        ec += ((wb >> q) & 1u) ? d : (Real)0;
                     }
                 }
             }
+            if (dir) ec = -ec;
             const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
             const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[rail_at + o] : (Real)a.ea_scalar;
             const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
