@@ -321,7 +321,10 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
         const double W = a.score_w[tile.d];
         const double beta = a.beta, V = sh.V;
-        const double g_ea = -beta, g_nu = 1.0 / a.nu0;
+        // weights of the four log-derivatives, folded once per workgroup:
+        // W g = W (-beta), W / nu0, W (-beta / (2 kappa)) dE_coul, W (-beta V / (2 L)) (t - o)
+        const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
+        const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
         // Sum of occ_j D(j - s) over a 16-site block: every entry is loaded and
         // masked with its sign-extended occupancy bit (an empty site adds +0).
@@ -391,12 +394,10 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
             if (p < (Real)1) {
                 const double pd = (double)p;
                 const double ratio = ((double)y - pd) / (1.0 - pd);
-                const double g_k = -0.5 * beta * (double)ec / a.kappa;
-                const double g_a = -0.5 * beta * V * (double)(t - o) / (double)L;
-                g0 += W * g_ea * ratio;
-                g1 += W * g_nu * ratio;
-                g2 += W * g_k * ratio;
-                g3 += W * g_a * ratio;
+                g0 += w_ea * ratio;
+                g1 += w_nu * ratio;
+                g2 += (w_k * (double)ec) * ratio;
+                g3 += (t > o ? w_a : -w_a) * ratio;
             }
         }
 #pragma unroll
