@@ -250,7 +250,18 @@ def bench_gradient(args):
     t_rep = _timed(lambda: grads.append(sim.score_replay(occ0, 0, W)), stream)
     g = grads[0].cpu().numpy()
     value = wl.n_sites * steps / (t_fwd + t_rep)
-    achieved = OPS_PER_PHILOX_BLOCK * philox_blocks_per_step(wl.rails, wl.sites) * steps / t_rep / 1e12
+    # replay work: the Philox stream plus, for every candidate bond, a masked
+    # add per window site (2 lane-operations) over the distinct rails in range;
+    # candidates per bond 2 f (1 - f) for the fixed ion count f L per rail
+    ph = wl.physics
+    wn = 2 * ph.cutoff_sites + 2
+    window_ops = 0.0
+    for R, L, f in zip(wl.rails, wl.sites, wl.filling):
+        fr = round(f * L) / L
+        n_nbr = min(2 * ph.rail_range + 1, R)
+        window_ops += R * (L - 1) * 2 * fr * (1 - fr) * n_nbr * wn * 2
+    replay_ops = OPS_PER_PHILOX_BLOCK * philox_blocks_per_step(wl.rails, wl.sites) + window_ops
+    achieved = replay_ops * steps / t_rep / 1e12
     out = {
         "metric": "gradient site-updates/s (forward + score replay)", "value": value, "unit": "site-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": (t_fwd + t_rep) * 1e3 / steps,
@@ -262,6 +273,7 @@ def bench_gradient(args):
         "replay_site_updates_per_s": wl.n_sites * steps / t_rep,
         "replay_over_forward_time": t_rep / t_fwd,
         "roofline": {"bound": "alu", "kernel": "hop_half_step<float,h,score>", "achieved": achieved,
+                     "ops": "Philox + 2 per window site of every candidate (expected candidate count)",
                      "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": None, "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps},
         "grad_mean_over_replicas": [float(x) for x in g.mean(axis=0)],

@@ -201,19 +201,33 @@ kmc_status kmc_dense_potential(kmc_ctx *ctx, float *phi_dev);
  *     only its edge rails with its two neighbouring tiles.  Needs every single
  *     device's tiling co-resident on the GPU; larger batches of devices run as
  *     several launches per chunk, one per group of whole devices.
- *   KMC_LAUNCH_AUTO (default): persistent when it fits, else half-step.
- * Both give bit-identical trajectories. */
-typedef enum { KMC_LAUNCH_AUTO = 0, KMC_LAUNCH_HALF_STEP = 1, KMC_LAUNCH_PERSISTENT = 2 } kmc_launch_mode;
+ *   KMC_LAUNCH_WAVE: persistent like KMC_LAUNCH_PERSISTENT, but every tile is
+ *     one wavefront that keeps its rails' occupancy in registers (16 or 32
+ *     sites per lane, so rails of up to 2048 padded sites), so a half-step has
+ *     no workgroup barrier; neighbouring tiles exchange edge rails only after
+ *     half-steps that changed them.  Needs every device's rails to fit 64
+ *     lanes (at least max(rail_range, 1) rails per tile unless the device is
+ *     one tile) and every single device's tiling co-resident.
+ *   KMC_LAUNCH_AUTO (default): WAVE when it fits, else PERSISTENT when it
+ *     fits, else HALF_STEP.
+ * All give bit-identical trajectories. */
+typedef enum {
+    KMC_LAUNCH_AUTO = 0,
+    KMC_LAUNCH_HALF_STEP = 1,
+    KMC_LAUNCH_PERSISTENT = 2,
+    KMC_LAUNCH_WAVE = 3
+} kmc_launch_mode;
 
-/* Select the launch strategy; KMC_EUNSUPPORTED if PERSISTENT does not fit. */
+/* Select the launch strategy; KMC_EUNSUPPORTED if PERSISTENT or WAVE does not
+ * fit. */
 kmc_status kmc_set_launch_mode(kmc_ctx *ctx, int32_t mode);
 
-/* The strategy kmc_run_steps will use now (HALF_STEP or PERSISTENT). */
+/* The strategy kmc_run_steps will use now (HALF_STEP, PERSISTENT or WAVE). */
 kmc_status kmc_get_launch_mode(kmc_ctx *ctx, int32_t *mode);
 
-/* Number of persistent launches per 1024-step chunk: the devices are split
- * into groups of whole devices whose tiles are co-resident on the GPU
- * (0 when the persistent strategy does not fit). */
+/* Number of launches per 1024-step chunk of the strategy in use (PERSISTENT
+ * or WAVE): the devices are split into groups of whole devices whose tiles
+ * are co-resident on the GPU (0 for HALF_STEP). */
 kmc_status kmc_get_persistent_groups(kmc_ctx *ctx, int32_t *groups);
 
 /* Cap the number of workgroup tiles of one persistent launch (0 = as many as
@@ -222,13 +236,16 @@ kmc_status kmc_get_persistent_groups(kmc_ctx *ctx, int32_t *groups);
 kmc_status kmc_set_persistent_group_limit(kmc_ctx *ctx, int32_t max_tiles);
 
 /* Target number of (padded) sites per workgroup tile, 0 = built-in default,
- * else in [16, 65536]; tiles are whole rails.  Used by the autotuner.  Waits
- * for the work already enqueued.  Trajectories do not depend on it. */
+ * else in [16, 65536]; tiles are whole rails.  For KMC_LAUNCH_WAVE, 1024 and
+ * 2048 select 16 and 32 sites per lane (other values: 16 when every rail has
+ * at most 1024 padded sites, else 32).  Used by the autotuner.  Waits for the
+ * work already enqueued.  Trajectories do not depend on it. */
 kmc_status kmc_set_tile_sites(kmc_ctx *ctx, int32_t sites);
 
 /* Pick the launch strategy and tile size by timing trial runs of
- * trial_steps steps (1..65536) for each candidate (persistent with several
- * tile sizes when it fits, half-step launches with several tile sizes).  The
+ * trial_steps steps (1..65536) for each candidate (wave tiles of 16 and 32
+ * sites per lane and persistent with several tile sizes when they fit,
+ * half-step launches with several tile sizes).  The
  * state, step counter, tallies and log are restored after every trial and at
  * the end, so tuning changes no trajectory; the fastest configuration stays
  * selected.  Outputs (each may be NULL): the chosen tile size (0 = default),

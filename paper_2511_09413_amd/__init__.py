@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_build", "libkmc.so")
 
 KMC_OK, KMC_EINVAL, KMC_EUNSUPPORTED, KMC_EHIP, KMC_ESTATE, KMC_ETOOSMALL = 0, -1, -2, -3, -4, -5
-LAUNCH_MODES = {"auto": 0, "half_step": 1, "persistent": 2}
+LAUNCH_MODES = {"auto": 0, "half_step": 1, "persistent": 2, "wave": 3}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
                       ("s", np.int32), ("u", np.float64), ("p", np.float64)])
@@ -307,7 +307,7 @@ class Simulator:
                 return dict(hit, cached=True)
         t, m, us = C.c_int32(0), C.c_int32(0), C.c_double(0.0)
         _check(lib().kmc_autotune(C.c_void_p(self.ctx), trial_steps, C.byref(t), C.byref(m), C.byref(us)))
-        out = {"tile_sites": int(t.value), "mode": {1: "half_step", 2: "persistent"}.get(int(m.value), "auto"),
+        out = {"tile_sites": int(t.value), "mode": {1: "half_step", 2: "persistent", 3: "wave"}.get(int(m.value), "auto"),
                "us_per_step": float(us.value), "trial_steps": trial_steps}
         if cache:
             table[key] = out

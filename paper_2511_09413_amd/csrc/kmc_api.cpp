@@ -40,6 +40,10 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 hipError_t launch_persistent(const PArgs &a, int block, size_t lds, bool fp64, hipStream_t st);
 hipError_t persistent_capacity(int block, size_t lds, bool fp64, int *blocks_per_cu);
 hipError_t launch_zero_i64(int64_t *p, int64_t n, hipStream_t st);
+hipError_t launch_wave(const PArgs &a, int spl, size_t lds, bool fp64, hipStream_t st);
+hipError_t wave_capacity(int spl, size_t lds, bool fp64, int *blocks_per_cu);
+size_t wave_lds_bytes(int spl, int n_kt, bool fp64);
+int wave_band_words(int spl);
 hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_dense_phi(const DenseArgs &a, hipStream_t st);
 hipError_t launch_dense_decide(const HopArgs &a, int pitch, hipStream_t st);
@@ -61,6 +65,7 @@ constexpr int64_t kLogCap = 65536;
 constexpr int64_t kMaxPTiles = 2048;
 constexpr int kPTileSites = 4096;  // default padded sites per persistent tile
 constexpr int kStepWin = 128;      // per-step table window of the persistent kernel
+constexpr int64_t kMaxWaveTiles = 8192;  // wave kernel: tiles per launch (publication memory)
 constexpr double kElementaryCharge = 1.602176634e-19;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -70,12 +75,17 @@ struct Layout {
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, progress, pub, status,
         rp_a, rp_b, score_log, dtab64, dtab32, phi, ktiles, dtiles, ctiles, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
+    int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
+    size_t wtiles;                    // wave tiling (PTile array)
     int max_pitch;
     int64_t total_sites, total_pad, rails_total;
     int cut;     // interaction table cutoff actually stored
     int dpitch;  // entries per row of the window-difference tables
     int dense_nb;  // dense potential: 32-site blocks per rail (0 when not used)
 };
+
+// 64-bit words of the publication region (shared by the two persistent kernels)
+int64_t pub_words(const Layout &L) { return std::max(L.pub_stride * L.max_ptiles, L.wpub_stride * L.max_wtiles); }
 
 bool is_finite(double x) { return std::isfinite(x); }
 
@@ -112,6 +122,16 @@ kmc_status validate(const kmc_params *p) {
         if (p->sites[0] > kDenseMaxSites) return fail(KMC_EUNSUPPORTED, "KMC_BF16X2 supports up to 1024 sites");
     }
     return KMC_OK;
+}
+
+// Wave-kernel geometry of a device: lanes per rail and the most rails one
+// wavefront holds (0: the rails do not fit).
+struct WaveGeom {
+    int lpr, nr_max;
+};
+WaveGeom wave_geom(int pitch, int spl) {
+    const int lpr = (pitch + spl - 1) / spl;
+    return WaveGeom{lpr, 64 / lpr};
 }
 
 Layout layout_for(const kmc_params *p) {
@@ -174,7 +194,30 @@ Layout layout_for(const kmc_params *p) {
                                      std::max<int64_t>(2 * default_tiles, 64));
     L.ptiles = take(sizeof(PTile) * (size_t)rails);  // every tile is at least one rail
     L.progress = take(sizeof(uint64_t) * 8 * (size_t)L.max_ptiles);
-    L.pub = take(sizeof(uint64_t) * (size_t)(L.pub_stride * L.max_ptiles));
+    // wave kernel: per tile one word per state of a launch plus a ring of
+    // edge-rail snapshots; tiles of one launch bounded by kMaxWaveTiles
+    {
+        int64_t tiles = 0, slot = 1;
+        for (int spl : {16, 32}) {
+            int64_t t = 0;
+            for (int d = 0; d < D; ++d) {
+                const int pitch = (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites;
+                const WaveGeom g = wave_geom(pitch, spl);
+                if (g.nr_max < 1) {
+                    t = 0;
+                    break;
+                }
+                t += (p->rails[d] + g.nr_max - 1) / g.nr_max;
+                slot = std::max<int64_t>(slot, (int64_t)std::min(g.nr_max, 2 * std::max(m, 1)) * ((pitch + 31) / 32));
+            }
+            tiles = std::max(tiles, t);
+        }
+        L.max_wtiles = std::min<int64_t>(std::max<int64_t>(tiles, 1), kMaxWaveTiles);
+        L.wpub_stride = kPubSlots + (int64_t)kSnapSlots * slot;
+    }
+    L.pub = take(sizeof(uint64_t) *
+                 (size_t)std::max(L.pub_stride * L.max_ptiles, L.wpub_stride * L.max_wtiles));
+    L.wtiles = take(sizeof(PTile) * (size_t)rails);  // every wave tile is at least one rail
     L.status = take(sizeof(int32_t) * 4);
     // score replay: its own pair of state planes and a discarded event count
     L.rp_a = take((size_t)pad);
@@ -235,6 +278,11 @@ struct kmc_ctx {
     int p_block = 0;
     size_t p_lds = 0;
     bool p_ok = false;                 // persistent tiling fits co-resident on this GPU
+    std::vector<PTile> wtiles;         // wave tiling (prev/next relative to the tile's group)
+    std::vector<std::pair<int, int>> wgroups;
+    int w_spl = 0;                     // sites per lane of the wave tiling
+    size_t w_lds = 0;
+    bool w_ok = false;                 // wave tiling fits co-resident on this GPU
     int mode = 0;                      // KMC_LAUNCH_AUTO / _HALF_STEP / _PERSISTENT
     uint64_t epoch = 0;
     float k10 = 0.0f;                  // K(1, 0) rounded to binary32
@@ -384,12 +432,85 @@ void make_ptiles(kmc_ctx *c) {
     c->p_ok = true;
 }
 
-bool use_persistent(const kmc_ctx *c) {
-    if (c->dense || c->mode == 1) return false;
-    if (c->mode == 2) return c->p_ok;
-    // automatic: persistent whenever the whole lattice fits co-resident in LDS
-    return c->p_ok;
+// Wave tiling: every device cut into n_t >= 1 tiles of consecutive rails that
+// fit one wavefront (rails x lanes per rail <= 64), sizes within one rail of
+// each other and at least max(rail_range, 1) rails unless the device is a
+// single tile.  Sites per lane: 16 when every rail fits 64 lanes that way,
+// else 32; tile_sites 1024 or 2048 asks for 16 or 32.
+void make_wtiles(kmc_ctx *c) {
+    c->wtiles.clear();
+    c->wgroups.clear();
+    c->w_ok = false;
+    if (c->dense) return;
+    const int m = c->p.rail_range, mm = std::max(m, 1);
+    int max_pitch = 0;
+    for (const DevInfo &dv : c->devs) max_pitch = std::max(max_pitch, dv.pitch);
+    int spl = max_pitch <= 1024 ? 16 : 32;
+    if (c->tile_sites == 1024) spl = 16;
+    if (c->tile_sites == 2048) spl = 32;
+    c->w_spl = spl;
+    for (int d = 0; d < c->p.n_devices; ++d) {
+        const DevInfo &dv = c->devs[d];
+        const WaveGeom g = wave_geom(dv.pitch, spl);
+        if (g.nr_max < 1) return;
+        const int n_t = (dv.rails + g.nr_max - 1) / g.nr_max;
+        if (n_t > 1 && dv.rails / n_t < mm) return;
+        const int w32 = (dv.pitch + 31) / 32;
+        if (n_t > 1 && 2 * m * w32 > wave_band_words(spl)) return;
+        const int first = (int)c->wtiles.size();
+        const int base = dv.rails / n_t, extra = dv.rails % n_t;
+        int r0 = 0;
+        for (int i = 0; i < n_t; ++i) {
+            const int nr = base + (i < extra ? 1 : 0);
+            if (kPubSlots + (int64_t)kSnapSlots * std::min(nr, 2 * m) * w32 > c->lay.wpub_stride) return;
+            const int prev = first + (i + n_t - 1) % n_t, next = first + (i + 1) % n_t;
+            c->wtiles.push_back(PTile{d, r0, nr, prev, next, 0});
+            r0 += nr;
+        }
+    }
+    const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
+    c->w_lds = wave_lds_bytes(spl, (int)n_kt, c->fp64);
+    int per_cu = 0, dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
+    if (wave_capacity(spl, c->w_lds, c->fp64, &per_cu) != hipSuccess) return;
+    // groups of whole devices, each co-resident (and within the publication memory)
+    int64_t cap = std::min<int64_t>((int64_t)per_cu * prop.multiProcessorCount * kWaveTilesPerWG, c->lay.max_wtiles);
+    if (c->group_limit > 0) cap = std::min<int64_t>(cap, c->group_limit);
+    if (cap < 1) return;
+    int first = 0, count = 0;
+    for (int i = 0; i < (int)c->wtiles.size();) {
+        const int d = c->wtiles[i].d;
+        int n_d = 0;
+        while (i + n_d < (int)c->wtiles.size() && c->wtiles[i + n_d].d == d) ++n_d;
+        if (n_d > cap) return;
+        if (count + n_d > cap) {
+            c->wgroups.emplace_back(first, count);
+            first = i;
+            count = 0;
+        }
+        count += n_d;
+        i += n_d;
+    }
+    if (count > 0) c->wgroups.emplace_back(first, count);
+    for (const auto &g : c->wgroups)
+        for (int i = g.first; i < g.first + g.second; ++i) {
+            c->wtiles[i].prev -= g.first;
+            c->wtiles[i].next -= g.first;
+        }
+    c->w_ok = true;
 }
+
+// The strategy a run uses: KMC_LAUNCH_WAVE, _PERSISTENT or _HALF_STEP.
+int launch_kind(const kmc_ctx *c) {
+    if (c->dense || c->mode == KMC_LAUNCH_HALF_STEP) return KMC_LAUNCH_HALF_STEP;
+    if (c->mode == KMC_LAUNCH_WAVE) return c->w_ok ? KMC_LAUNCH_WAVE : KMC_LAUNCH_HALF_STEP;
+    if (c->mode == KMC_LAUNCH_PERSISTENT) return c->p_ok ? KMC_LAUNCH_PERSISTENT : KMC_LAUNCH_HALF_STEP;
+    // automatic: a persistent kernel whenever one fits co-resident
+    if (c->w_ok) return KMC_LAUNCH_WAVE;
+    return c->p_ok ? KMC_LAUNCH_PERSISTENT : KMC_LAUNCH_HALF_STEP;
+}
+
 
 HopArgs hop_args(kmc_ctx *c) {
     const int D = c->p.n_devices;
@@ -450,7 +571,9 @@ DenseArgs dense_args(kmc_ctx *c, const int8_t *occ, float *phi, int64_t phi_row)
 kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
     const int D = c->p.n_devices;
     HopArgs a = hop_args(c);
-    const bool persistent = use_persistent(c);
+    const int kind = launch_kind(c);
+    const bool wave = kind == KMC_LAUNCH_WAVE;
+    const bool persistent = wave || kind == KMC_LAUNCH_PERSISTENT;
     PArgs pa{};
     if (persistent) {
         pa.occ = c->cur;
@@ -478,7 +601,7 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.log = a.log;
         pa.progress = c->at<uint64_t>(c->lay.progress);
         pa.pub = c->at<uint64_t>(c->lay.pub);
-        pa.pub_stride = c->lay.pub_stride;
+        pa.pub_stride = wave ? c->lay.wpub_stride : c->lay.pub_stride;
         pa.max_pitch = c->lay.max_pitch;
         pa.status = c->at<int32_t>(c->lay.status);
     }
@@ -486,19 +609,20 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
     while (done < n_steps) {
         const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
         if (persistent) {
-            for (const auto &g : c->pgroups) {
+            for (const auto &g : wave ? c->wgroups : c->pgroups) {
                 // publication tags carry the low 20 bits of the epoch: at every
                 // wrap the ring is cleared so that no stale word can match a new tag
                 if ((++c->epoch & 0xFFFFFu) == 0) {
-                    KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.pub), c->lay.pub_stride * c->lay.max_ptiles,
+                    KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.pub), pub_words(c->lay),
                                                c->stream));
                     ++c->epoch;
                 }
-                pa.tiles = c->at<PTile>(c->lay.ptiles) + g.first;
+                pa.tiles = c->at<PTile>(wave ? c->lay.wtiles : c->lay.ptiles) + g.first;
                 pa.n_tiles = g.second;
                 pa.epoch = c->epoch;
                 pa.n_steps = chunk;
-                KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
+                if (wave) KMC_HIP(c, launch_wave(pa, c->w_spl, c->w_lds, c->fp64, c->stream));
+                else KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
             }
         }
         for (int k = 0; k < chunk && !persistent; ++k) {
@@ -652,6 +776,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     // rows j = 32 (sb + delta) + kk and columns s = 32 sb + ss; lane l of
     // k-step q carries kk = 16 q + 8 (l / 32) + e (e = 0..7), ss = l % 32.
     c->dense = params->precision == KMC_BF16X2;
+    make_wtiles(c);
     c->k10 = cut >= 1 ? k32[1] : 0.0f;
     std::vector<uint16_t> kt_host;
     if (c->dense) {
@@ -713,6 +838,8 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(h2d(lay.devs, c->devs.data(), sizeof(DevInfo) * D), "copy device table");
     chk(h2d(lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size()), "copy tiles");
     chk(h2d(lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size()), "copy persistent tiles");
+    if (!c->wtiles.empty())
+        chk(h2d(lay.wtiles, c->wtiles.data(), sizeof(PTile) * c->wtiles.size()), "copy wave tiles");
     chk(h2d(lay.ktab64, k64.data(), sizeof(double) * k64.size()), "copy kernel table");
     chk(h2d(lay.ktab32, k32.data(), sizeof(float) * k32.size()), "copy kernel table");
     chk(h2d(lay.dtab64, d64.data(), sizeof(double) * d64.size()), "copy window differences");
@@ -733,7 +860,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i64(c->at<int64_t>(lay.net_total), D, st), "zero totals");
     chk(launch_zero_i64(c->at<int64_t>(lay.log_count), 1, st), "zero log");
     chk(launch_zero_i64(c->at<int64_t>(lay.progress), 8 * lay.max_ptiles, st), "zero progress counters");
-    chk(launch_zero_i64(c->at<int64_t>(lay.pub), lay.pub_stride * lay.max_ptiles, st), "zero publication ring");
+    chk(launch_zero_i64(c->at<int64_t>(lay.pub), pub_words(lay), st), "zero publication ring");
     chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
     chk(set_hop_lds_limit(c->hop_lds, c->score_lds), "LDS limit of the hop kernel");
     {
@@ -884,9 +1011,11 @@ kmc_status kmc_get_step(kmc_ctx *c, int64_t *step) {
 kmc_status kmc_set_launch_mode(kmc_ctx *c, int32_t mode) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;
-    if (mode < KMC_LAUNCH_AUTO || mode > KMC_LAUNCH_PERSISTENT) return fail(KMC_EINVAL, "unknown launch mode");
+    if (mode < KMC_LAUNCH_AUTO || mode > KMC_LAUNCH_WAVE) return fail(KMC_EINVAL, "unknown launch mode");
     if (mode == KMC_LAUNCH_PERSISTENT && !c->p_ok)
         return fail(KMC_EUNSUPPORTED, "the persistent tiling does not fit co-resident on this GPU");
+    if (mode == KMC_LAUNCH_WAVE && !c->w_ok)
+        return fail(KMC_EUNSUPPORTED, "the wave tiling does not fit co-resident on this GPU");
     c->mode = mode;
     return KMC_OK;
 }
@@ -894,14 +1023,16 @@ kmc_status kmc_set_launch_mode(kmc_ctx *c, int32_t mode) {
 kmc_status kmc_get_launch_mode(kmc_ctx *c, int32_t *mode) {
     if (!c) return fail(KMC_EINVAL, "context is NULL");
     if (!mode) return fail(KMC_EINVAL, "mode is NULL");
-    *mode = use_persistent(c) ? KMC_LAUNCH_PERSISTENT : KMC_LAUNCH_HALF_STEP;
+    *mode = launch_kind(c);
     return KMC_OK;
 }
 
 kmc_status kmc_get_persistent_groups(kmc_ctx *c, int32_t *groups) {
     if (!c) return fail(KMC_EINVAL, "context is NULL");
     if (!groups) return fail(KMC_EINVAL, "groups is NULL");
-    *groups = c->p_ok ? (int32_t)c->pgroups.size() : 0;
+    const int kind = launch_kind(c);
+    *groups = kind == KMC_LAUNCH_WAVE ? (int32_t)c->wgroups.size()
+                                      : (kind == KMC_LAUNCH_PERSISTENT ? (int32_t)c->pgroups.size() : 0);
     return KMC_OK;
 }
 
@@ -913,12 +1044,17 @@ kmc_status retile(kmc_ctx *c) {
     KMC_HIP(c, hipStreamSynchronize(c->stream));  // launches in flight use the old tiles
     make_tiles(c);
     make_ptiles(c);
+    make_wtiles(c);
     KMC_HIP(c, hipMemcpy(c->ws + c->lay.tiles, c->tiles.data(), sizeof(Tile) * c->tiles.size(),
                          hipMemcpyHostToDevice));
     KMC_HIP(c, hipMemcpy(c->ws + c->lay.ptiles, c->ptiles.data(), sizeof(PTile) * c->ptiles.size(),
                          hipMemcpyHostToDevice));
+    if (!c->wtiles.empty())
+        KMC_HIP(c, hipMemcpy(c->ws + c->lay.wtiles, c->wtiles.data(), sizeof(PTile) * c->wtiles.size(),
+                             hipMemcpyHostToDevice));
     KMC_HIP(c, set_hop_lds_limit(c->hop_lds, c->score_lds));
     if (c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) c->mode = KMC_LAUNCH_AUTO;
+    if (c->mode == KMC_LAUNCH_WAVE && !c->w_ok) c->mode = KMC_LAUNCH_AUTO;
     return KMC_OK;
 }
 }  // namespace
@@ -993,8 +1129,10 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
     const int old_tile = c->tile_sites, old_mode = c->mode;
     struct Cand { int mode, tile; };
     std::vector<Cand> cands;
-    if (!c->dense)
+    if (!c->dense) {
+        for (int t : {1024, 2048}) cands.push_back({KMC_LAUNCH_WAVE, t});
         for (int t : {0, 4096, 8192, 12288, 16384}) cands.push_back({KMC_LAUNCH_PERSISTENT, t});
+    }
     for (int t : {0, 1024, 2048, 8192}) cands.push_back({KMC_LAUNCH_HALF_STEP, t});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     KMC_HIP(c, hipEventCreate(&e0));
@@ -1006,6 +1144,7 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
         s = retile(c);
         if (s != KMC_OK) break;
         if (cd.mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) continue;
+        if (cd.mode == KMC_LAUNCH_WAVE && !c->w_ok) continue;
         c->mode = cd.mode;
         float ms = 0.0f;
         bool ok = true;
@@ -1036,7 +1175,9 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
     c->tile_sites = pick.tile;
     s = retile(c);
     if (s != KMC_OK) return s;
-    c->mode = (pick.mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) ? KMC_LAUNCH_AUTO : pick.mode;
+    c->mode = pick.mode;
+    if ((c->mode == KMC_LAUNCH_PERSISTENT && !c->p_ok) || (c->mode == KMC_LAUNCH_WAVE && !c->w_ok))
+        c->mode = KMC_LAUNCH_AUTO;
     s = restore_state(c, sv);
     if (s != KMC_OK) return s;
     if (tile_sites) *tile_sites = pick.tile;

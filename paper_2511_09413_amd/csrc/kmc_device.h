@@ -143,4 +143,12 @@ __device__ inline uint32_t class_threshold(double c0, double beta, double alpha,
     return pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
 }
 
+// Inclusive threshold of a Philox word for a class with static factor
+// A = exp(-beta ea_lb), widened like class_threshold; g = exp(beta (|alpha V|/L
+// + coul_bound) / 2) carries the step's field and the Coulomb bound.
+__device__ __forceinline__ uint32_t threshold_of(double c0, double A, double g) {
+    const double pb = c0 * A * g * (1.0 + 1e-3) + 2e-6;
+    return pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
+}
+
 }  // namespace kmc

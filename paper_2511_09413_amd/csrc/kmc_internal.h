@@ -51,6 +51,8 @@ struct PTile {
 
 constexpr int kPubSlots = 2 * kTallySteps + 1;  // publication slots per tile: one per state of a launch
 constexpr int kPMaxBlock = 1024;         // threads per workgroup, persistent kernel
+constexpr int kWaveTilesPerWG = 4;       // wave kernel: tiles (one wavefront each) per workgroup
+constexpr int kSnapSlots = 64;           // wave kernel: edge-row snapshots per tile in a ring
 
 // Step bookkeeping in device memory (lets a captured graph be replayed).
 struct Ctl {

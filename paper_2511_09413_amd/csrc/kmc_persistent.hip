@@ -44,13 +44,6 @@ __device__ __forceinline__ uint32_t pub_tag(uint64_t epoch, int64_t j_rel) {
     return ((uint32_t)(epoch & 0xFFFFFu) << 12) | (uint32_t)j_rel;
 }
 
-// Inclusive threshold of a Philox word for a class with static factor
-// A = exp(-beta ea_lb) (see class_threshold), widened like class_threshold.
-__device__ __forceinline__ uint32_t threshold_of(double c0, double A, double g) {
-    const double pb = c0 * A * g * (1.0 + 1e-3) + 2e-6;
-    return pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
-}
-
 template <typename Real>
 __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];

@@ -1,0 +1,479 @@
+// Persistent hop-step kernel with one wavefront per tile.
+//
+// A tile is whole rails of one device that fit one wavefront: each lane owns
+// SPL (16 or 32) consecutive sites of a rail for the whole launch and keeps
+// their occupancy as bits in a register.  A half-step therefore needs neither
+// an LDS round trip nor a workgroup barrier: the bit past a lane's last site
+// comes from the next lane by a cross-lane move, the Philox words, the
+// candidate test and the exact prefilter stay in registers, and a wavefront
+// vote finds the rare half-steps with prefilter survivors.  Only those build
+// an LDS copy of the tile's bits (the Jacobi snapshot) and, when a survivor's
+// Coulomb window may cross the tile edge, fetch the neighbouring tiles' edge
+// rails.  The workgroup is only a container for kWaveTilesPerWG independent
+// tiles; its one barrier precedes the loop.
+//
+// Cross-tile data.  After every half-step a tile stores one 64-bit word for
+// the new state into its per-state array: a tag naming the state (launch
+// epoch, half-step) and which snapshot holds that state's edge rails.  Only a
+// half-step that changed an edge rail stores a new snapshot (64-bit words:
+// 32 occupancy bits plus the tag of the snapshot's state) into a ring of
+// kSnapSlots slots.  A snapshot serves every state from its own up to the next
+// snapshot's; before a tile reuses a slot it waits until both neighbouring
+// tiles have published the state at which the slot's snapshot stops serving,
+// after which no neighbour can still ask for it.  A reader polls the state
+// word, then the snapshot words, until their tags name what it wants.  Every
+// wait is for a state no later than the waiter's own, so the tile furthest
+// behind never waits; every wait is also bounded: on time-out the kernel raises
+// the status flag, all tiles leave their loops and the host reports the error.
+//
+// Per bond the work is that of hop_half_step: Philox4x32-10 draw, candidate
+// test, exact two-stage prefilter, survivor energy (wavefront-cooperative
+// window sum in the same order as the other kernels), Arrhenius probability
+// and accept test.
+#include <type_traits>
+
+#include "kmc_device.h"
+#include "kmc_internal.h"
+
+namespace kmc {
+
+namespace {
+
+constexpr int kWaveSpin = 1 << 20;   // polls before a wait is declared hung
+constexpr int kWaveWin = 64;         // per-step table entries: one per lane
+
+// A tile's LDS: per-device and per-step tables and the rare-path buffers.
+template <int SPL>
+struct WaveLds {
+    static constexpr int kBand = 4 * SPL + 16;  // 32-bit words of neighbour rails
+    double cls_a[kClasses];              // exp(-beta (ea_min + q ea_step)) of the tile's device
+    double step_v[kWaveWin];             // bias of the steps of the current window
+    double step_g[kWaveWin];             // exp(beta (|alpha V| / L + coul_bound) / 2)
+    uint32_t snap[64];                   // each lane's bits at the start of a survivor half-step
+    uint32_t band[kBand];                // neighbour rails: prev tile's last m, next tile's first m
+    int16_t snap_state[kSnapSlots];      // launch-relative state of each ring slot's snapshot
+    unsigned char cls[64 * SPL];         // barrier class of every site, rows at the device pitch
+};
+static_assert(sizeof(WaveLds<16>) % 16 == 0 && sizeof(WaveLds<32>) % 16 == 0, "LDS tiles stay 16-byte aligned");
+static_assert(offsetof(WaveLds<16>, cls) % 16 == 0 && offsetof(WaveLds<32>, cls) % 16 == 0,
+              "class rows are written as 16-byte vectors");
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_tag(uint64_t epoch, int64_t j_rel) {
+    return ((uint32_t)(epoch & 0xFFFFFu) << 12) | (uint32_t)j_rel;
+}
+
+// Poll a published word until its tag is `want` (stored in *out); false on
+// time-out (raising the status flag) or once another tile has raised it.
+__device__ __forceinline__ bool poll_tag(const uint64_t *p, uint32_t want, int32_t *status, uint64_t *out) {
+    for (int spins = 0;; ++spins) {
+        const uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(v >> 32) == want) {
+            *out = v;
+            return true;
+        }
+        if (spins > kWaveSpin) {
+            __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// Uniform values used only on rare paths enter those paths through these, so
+// the compiler derives what it needs there instead of hoisting it out of the
+// loop into registers held for the whole launch.
+__device__ __forceinline__ int opaque(int v) {
+    v = __builtin_amdgcn_readfirstlane(v);
+    asm volatile("" : "+s"(v));
+    return v;
+}
+__device__ __forceinline__ int64_t opaque(int64_t v) {
+    const uint64_t u = (uint64_t)v;
+    return (int64_t)(((uint64_t)(uint32_t)opaque((int)(u >> 32)) << 32) | (uint32_t)opaque((int)(uint32_t)u));
+}
+__device__ __forceinline__ double opaque(double v) { return __longlong_as_double(opaque((int64_t)__double_as_longlong(v))); }
+
+// The lane's Philox words live in registers: every access below uses a
+// compile-time index (template recursion), never a runtime one, so the words
+// are never placed in scratch memory.
+template <int K, int N>
+__device__ __forceinline__ void draw_words(uint32_t (&wd)[N], uint32_t blk0, uint32_t rail, uint32_t n, uint32_t c3,
+                                           uint32_t k0, uint32_t k1) {
+    if constexpr (K < N / 4) {
+        const uint4 x = philox4x32_10(blk0 + (uint32_t)K, rail, n, c3, k0, k1);
+        wd[4 * K + 0] = x.x;
+        wd[4 * K + 1] = x.y;
+        wd[4 * K + 2] = x.z;
+        wd[4 * K + 3] = x.w;
+        draw_words<K + 1>(wd, blk0, rail, n, c3, k0, k1);
+    }
+}
+template <int K, int N>
+__device__ __forceinline__ uint32_t min_word(const uint32_t (&wd)[N]) {
+    if constexpr (K == N - 1) return wd[K];
+    else return min(wd[K], min_word<K + 1>(wd));
+}
+// word i (runtime index): a select chain
+template <int K, int N>
+__device__ __forceinline__ uint32_t pick_word(const uint32_t (&wd)[N], int i) {
+    if constexpr (K == N - 1) return wd[K];
+    else return i == K ? wd[K] : pick_word<K + 1>(wd, i);
+}
+
+}  // namespace
+
+template <typename Real, int SPL>
+__global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int kW = SPL / 2;          // Philox words per lane and half-step (SPL / 8 blocks):
+                                         // word b / 2 belongs to the bond at site s0 + b
+    constexpr uint32_t kAll = SPL == 32 ? 0xFFFFFFFFu : 0xFFFFu;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile data in scalar registers
+
+    // the kernel table K(dist, ds), shared by the workgroup's tiles
+    const int m = a.rail_range;
+    const int kt_stride = a.cutoff + 1;
+    const int n_kt = (m + 1) * kt_stride;
+    const bool kt_in_lds = n_kt <= kLdsTableMax;
+    const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
+                                                            : reinterpret_cast<const Real *>(a.ktab32);
+    Real *kt_lds = reinterpret_cast<Real *>(smem);
+    if (kt_in_lds)
+        for (int i = threadIdx.x; i < n_kt; i += blockDim.x) kt_lds[i] = kt_glob[i];
+    __syncthreads();
+    const Real *kt = kt_in_lds ? kt_lds : kt_glob;
+    const size_t kt_bytes = kt_in_lds ? (((size_t)n_kt * sizeof(Real) + 15) & ~(size_t)15) : 0;
+    WaveLds<SPL> &w = reinterpret_cast<WaveLds<SPL> *>(smem + kt_bytes)[wave];
+
+    const int n_groups = (a.n_tiles + kWaveTilesPerWG - 1) / kWaveTilesPerWG;
+    const int ti = tile_of_block(blockIdx.x, n_groups) * kWaveTilesPerWG + wave;
+    if (ti >= a.n_tiles) return;  // no barrier follows
+
+    const PTile tile = a.tiles[ti];
+    const DevInfo &dv = a.devs[tile.d];
+    const int R = dv.rails, L = dv.sites, P = dv.pitch;
+    const int lpr = (P + SPL - 1) / SPL;  // lanes per rail
+    const int nr = tile.nr;
+    const int W32 = (P + 31) / 32;        // 32-bit words of a published rail
+    const bool single = tile.prev == ti && tile.next == ti;
+    const bool isolated = single || m == 0;  // no rail of another tile is ever read
+    const int e = nr < 2 * m ? nr : 2 * m;   // edge rails: the first min(m, nr) and the last m
+    const uint64_t epoch = a.epoch;
+    const int64_t j0 = 2 * a.ctl->n_base;
+    const int64_t tally_base = a.ctl->tally_base;
+    uint64_t *own = a.pub + (int64_t)ti * a.pub_stride;  // kPubSlots state words, then the ring
+
+    // the lane's sites, fixed for the launch
+    const bool has = lane < nr * lpr;
+    const int row = has ? lane / lpr : 0;
+    const int s0 = has ? (lane - row * lpr) * SPL : 0;
+    const uint32_t rail = (uint32_t)(tile.r0 + row);
+    const int last = L - 2 - s0;  // the bond at s0 + b lies inside the rail iff b <= last
+    const uint32_t valid = (!has || last < 0) ? 0u : (last >= SPL - 1 ? kAll : ((2u << last) - 1u));
+
+    // load the tile: occupancy bits to registers, barrier classes to LDS
+    int8_t *gstate = a.occ + dv.off_pad + (int64_t)tile.r0 * P;
+    uint32_t bits = 0;
+    if (has) {
+#pragma unroll
+        for (int c = 0; c < SPL / 16; ++c) {
+            if (c == 0 || s0 + 16 * c < P) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(gstate + row * P + s0 + 16 * c);
+                bits |= occ_bits(v) << (16 * c);
+                *reinterpret_cast<uint4 *>(w.cls + row * P + s0 + 16 * c) =
+                    make_uint4((v.x >> 1) & 0x7F7F7F7Fu, (v.y >> 1) & 0x7F7F7F7Fu, (v.z >> 1) & 0x7F7F7F7Fu,
+                               (v.w >> 1) & 0x7F7F7F7Fu);
+            }
+        }
+    }
+    for (int q = lane; q < kClasses; q += 64) w.cls_a[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
+    wave_sync();
+
+    // Per-step tables of the window [kb, kb + 64): lane k holds step kb + k's
+    // stage-0 threshold in a register, the bias and g go to LDS.
+    uint32_t thr_lane = 0;
+    auto refresh = [&](int kb) {
+        const int d = opaque(tile.d);
+        const int64_t k = opaque((j0 >> 1) - dv.n_set + kb) + lane;
+        const double beta = opaque(a.beta), alpha = opaque(a.alpha);
+        const double V = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
+                                          (double)k * opaque(a.dt));
+        const double g = exp(0.5 * beta * (fabs(alpha * V) / (double)opaque(L) + dv.coul_bound));
+        w.step_v[lane] = V;
+        w.step_g[lane] = g;
+        thr_lane = threshold_of(opaque(a.c0), w.cls_a[0], g);
+        wave_sync();
+    };
+
+    // 32 bits [32 q, 32 q + 32) of tile row r, gathered from the owning lanes;
+    // every lane takes part in the cross-lane reads
+    auto row_word = [&](int r, int q) -> uint32_t {
+        if (SPL == 32) return __shfl(bits, r * lpr + q, 64);
+        const uint32_t lo = __shfl(bits, r * lpr + 2 * q, 64);
+        const uint32_t hi = __shfl(bits, r * lpr + (2 * q + 1 < lpr ? 2 * q + 1 : 2 * q), 64);
+        return lo | (2 * q + 1 < lpr ? hi << 16 : 0u);
+    };
+    // snapshot of the edge rails as state jrel into ring slot `slot`
+    auto write_snapshot = [&](int slot, int64_t jrel) {
+        const int w32 = opaque(W32), mm = opaque(m), ee = opaque(e), nrr = opaque(nr);
+        uint64_t *dst = own + kPubSlots + (int64_t)slot * (ee * w32);
+        const uint64_t tag = (uint64_t)wave_tag(epoch, jrel) << 32;
+        for (int sr = 0; sr < ee; ++sr)
+            for (int q0 = 0; q0 < w32; q0 += 64) {
+                const int q = q0 + lane < w32 ? q0 + lane : w32 - 1;
+                const uint32_t word = row_word(sr < mm ? sr : sr + (nrr - ee), q);
+                if (q0 + lane < w32)
+                    __hip_atomic_store(dst + sr * w32 + q, tag | word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+    };
+    // Neighbour rails of state jrel into w.band: entry idx * W32 + q holds rail
+    // offset idx - m (idx < m, from the previous tile) or nr + idx - m (from the
+    // next tile).  Uniform result.
+    auto fetch_bands = [&](int64_t jrel) -> bool {
+        const int w32 = opaque(W32), mm = opaque(m);
+        bool ok = true;
+        for (int idx = 0; idx < 2 * mm; ++idx) {
+            const int T = idx < mm ? tile.prev : tile.next;
+            const int nrT = a.tiles[T].nr;
+            const int eT = nrT < 2 * mm ? nrT : 2 * mm;
+            const int rr = idx < mm ? nrT - mm + idx : idx - mm;  // rail of tile T
+            const int sr = rr < mm ? rr : rr - (nrT - eT);        // its row in T's snapshots
+            const uint64_t *base = a.pub + (int64_t)T * a.pub_stride;
+            for (int q = lane; q < w32; q += 64) {
+                uint64_t st = 0, v = 0;
+                if (ok) ok = poll_tag(base + jrel, wave_tag(epoch, jrel), a.status, &st);
+                if (ok) {
+                    const int slot = (int)((uint32_t)st >> 12);
+                    const int64_t snap_rel = (int64_t)(st & 0xFFFu);
+                    ok = poll_tag(base + kPubSlots + (int64_t)slot * (eT * w32) + sr * w32 + q,
+                                  wave_tag(epoch, snap_rel), a.status, &v);
+                }
+                w.band[idx * w32 + q] = (uint32_t)v;
+            }
+        }
+        return __ballot(!ok) == 0;
+    };
+
+
+    int snap_count = 0, snap_slot = 0;
+    int64_t snap_rel = 0;
+    if (!isolated) {
+        write_snapshot(0, 0);
+        if (lane == 0) {
+            w.snap_state[0] = 0;
+            __hip_atomic_store(own, (uint64_t)wave_tag(epoch, 0) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    for (int js = 0; js < 2 * a.n_steps; ++js) {
+        const int64_t j = j0 + js;
+        const int64_t n = j >> 1;
+        const int h = js & 1;  // j0 is even
+        const int kstep = js >> 1;
+        const int kw = kstep & (kWaveWin - 1);
+        if (h == 0 && kw == 0) refresh(kstep);
+
+        // candidates: bonds of parity h whose two sites differ
+        const uint32_t nb = __shfl_down(bits, 1, 64);
+        const uint32_t cand = (bits ^ ((bits >> 1) | ((nb & 1u) << (SPL - 1)))) & (h ? 0xAAAAAAAAu : 0x55555555u) & valid;
+
+        // Philox words; the key enters each half-step opaquely, so that the
+        // round keys are derived on the scalar unit instead of being kept live
+        uint32_t k0 = a.key0, k1 = a.key1;
+        asm volatile("" : "+s"(k0), "+s"(k1));
+        const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
+        uint32_t wd[kW];
+        draw_words<0>(wd, (uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, k0, k1);
+        // stage 0: the smallest word against the lowest class's threshold;
+        // stage 1 (rare): each candidate's word against its origin's class
+        const uint32_t thr0 = (uint32_t)__builtin_amdgcn_readlane((int)thr_lane, kw);
+        const uint32_t mn = min_word<0>(wd);
+        uint32_t sv = 0;
+        if (mn <= thr0 && cand != 0u) {
+            uint32_t c = cand;
+            while (c) {
+                const int b = __builtin_ctz(c);
+                c &= c - 1;
+                const uint32_t x = pick_word<0>(wd, b >> 1);
+                if (x <= thr0) {
+                    const int o = s0 + (((bits >> b) & 1u) ? b : b + 1);
+                    if (x <= threshold_of(a.c0, w.cls_a[w.cls[row * P + o]], w.step_g[kw])) sv |= 1u << b;
+                }
+            }
+        }
+
+        // survivors (rare): one at a time over the whole wavefront
+        bool edge_changed = false;
+        const uint64_t any = __ballot(sv != 0u);
+        if (any) {
+            const int cut = opaque(a.cutoff), Lq = opaque(L), lprq = opaque(lpr), nrq = opaque(nr), mq = opaque(m);
+            const int w32 = opaque(W32);
+            auto bit_at = [&](int r, int site) -> uint32_t {
+                return (w.snap[r * lprq + site / SPL] >> (site % SPL)) & 1u;
+            };
+            w.snap[lane] = bits;
+            bool ok = true;
+            if (!isolated) ok = fetch_bands(js);
+            wave_sync();
+            if (!ok) break;
+            uint32_t fl = 0;
+            uint64_t rest = any;
+            while (rest) {
+                const int l = __builtin_ctzll(rest);
+                rest &= rest - 1;
+                uint32_t svl = (uint32_t)__builtin_amdgcn_readlane((int)sv, l);
+                const int lrow = __builtin_amdgcn_readlane(row, l);
+                const int ls0 = __builtin_amdgcn_readlane(s0, l);
+                while (svl) {
+                    const int b = __builtin_ctz(svl);
+                    svl &= svl - 1;
+                    const int s = ls0 + b;
+                    const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)pick_word<0>(wd, b >> 1), l);
+                    const int o = bit_at(lrow, s) ? s : s + 1;
+                    const int t = (o == s) ? s + 1 : s;
+                    int lo = s - cut, hi = s + 1 + cut;
+                    lo = lo < 0 ? 0 : lo;
+                    hi = hi > Lq - 1 ? Lq - 1 : hi;
+                    Real part = (Real)0;
+                    const int n_nbr = dv.n_nbr;
+                    for (int k = 0; k < n_nbr; ++k) {
+                        const int off = dv.nbr_off[k];
+                        const Real *ktr = kt + dv.nbr_dist[k] * (cut + 1);
+                        int rho = lrow + off, band = -1;
+                        if (single) {
+                            const int Rq = opaque(R);
+                            while (rho < 0) rho += Rq;
+                            while (rho >= Rq) rho -= Rq;
+                        } else if (rho < 0) {
+                            band = rho + mq;
+                        } else if (rho >= nrq) {
+                            band = mq + rho - nrq;
+                        }
+                        for (int jj = lo + lane; jj <= hi; jj += 64) {
+                            uint32_t bit = band < 0 ? bit_at(rho, jj) : (w.band[band * w32 + (jj >> 5)] >> (jj & 31)) & 1u;
+                            if (off == 0 && (jj == o || jj == t)) bit = 0;
+                            const int dt_ = t - jj < 0 ? jj - t : t - jj;
+                            const int do_ = o - jj < 0 ? jj - o : o - jj;
+                            const Real kt_v = dt_ > cut ? (Real)0 : ktr[dt_];
+                            const Real ko_v = do_ > cut ? (Real)0 : ktr[do_];
+                            part += bit ? (kt_v - ko_v) : (Real)0;
+                        }
+                    }
+#pragma unroll
+                    for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
+                    int acc = 0;
+                    if (lane == 0) {
+                        const Real alpha_r = (Real)opaque(a.alpha), beta_r = (Real)opaque(a.beta);
+                        const Real c0_r = (Real)opaque(a.c0);
+                        const Real e_app = ((alpha_r * (Real)w.step_v[kw]) * (Real)(t - o)) / (Real)Lq;
+                        const int srail = tile.r0 + lrow;
+                        const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)srail * Lq + o]
+                                             : (Real)a.ea_scalar;
+                        acc = decide_hop<Real>(e_app + part, ea, word, beta_r, c0_r, a.log, tile.d, h, n, srail, s);
+                        if (acc) {
+                            const int64_t base = (n - tally_base) * a.n_devices + tile.d;
+                            atomicAdd(&a.tally_net[base], t < o ? 1 : -1);
+                            const int qo = (10 * o) / Lq, qt = (10 * t) / Lq;
+                            if (qo != qt) {
+                                atomicAdd(&a.tally_dec[base * kDeciles + qo], -1);
+                                atomicAdd(&a.tally_dec[base * kDeciles + qt], 1);
+                            }
+                        }
+                    }
+                    acc = __builtin_amdgcn_readfirstlane(acc);
+                    if (acc) {
+                        if (lane == lrow * lprq + s / SPL) fl ^= 1u << (s % SPL);
+                        if (lane == lrow * lprq + (s + 1) / SPL) fl ^= 1u << ((s + 1) % SPL);
+                        if (lrow < mq || lrow >= nrq - mq) edge_changed = true;
+                    }
+                }
+            }
+            bits ^= fl;
+        }
+
+        // publish the new state js + 1
+        if (!isolated) {
+            const int64_t jn = js + 1;
+            if (edge_changed) {
+                ++snap_count;
+                const int slot = snap_count % kSnapSlots;
+                if (snap_count >= kSnapSlots) {
+                    // the slot's snapshot serves states before the next snapshot's
+                    const int64_t need = w.snap_state[(slot + 1) % kSnapSlots];
+                    bool ok = true;
+                    if (lane < 2) {
+                        const int T = lane == 0 ? tile.prev : tile.next;
+                        uint64_t v = 0;
+                        ok = poll_tag(a.pub + (int64_t)T * a.pub_stride + need, wave_tag(epoch, need), a.status, &v);
+                    }
+                    if (__ballot(!ok)) break;
+                }
+                write_snapshot(slot, jn);
+                if (lane == 0) w.snap_state[slot] = (int16_t)jn;
+                snap_slot = slot;
+                snap_rel = jn;
+            }
+            if (lane == 0)
+                __hip_atomic_store(own + jn,
+                                   ((uint64_t)wave_tag(epoch, jn) << 32) | ((uint32_t)snap_slot << 12) |
+                                       (uint32_t)snap_rel,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+
+    // write the tile back
+    if (has) {
+#pragma unroll
+        for (int c = 0; c < SPL / 16; ++c) {
+            if (c == 0 || s0 + 16 * c < P) {
+                const uint32_t b16 = (bits >> (16 * c)) & 0xFFFFu;
+                const uint4 cv = *reinterpret_cast<const uint4 *>(w.cls + row * P + s0 + 16 * c);
+                uint4 v;
+                v.x = (((b16 >> 0) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.x << 1);
+                v.y = (((b16 >> 4) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.y << 1);
+                v.z = (((b16 >> 8) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.z << 1);
+                v.w = (((b16 >> 12) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.w << 1);
+                *reinterpret_cast<uint4 *>(gstate + (int64_t)row * P + s0 + 16 * c) = v;
+            }
+        }
+    }
+}
+
+namespace {
+const void *wave_fn(int spl, bool fp64) {
+    if (spl == 32) return fp64 ? (const void *)hop_wave<double, 32> : (const void *)hop_wave<float, 32>;
+    return fp64 ? (const void *)hop_wave<double, 16> : (const void *)hop_wave<float, 16>;
+}
+}  // namespace
+
+size_t wave_lds_bytes(int spl, int n_kt, bool fp64) {
+    const size_t kt = n_kt <= kLdsTableMax ? ((size_t)n_kt * (fp64 ? sizeof(double) : sizeof(float)) + 15) & ~(size_t)15 : 0;
+    return kt + kWaveTilesPerWG * (spl == 32 ? sizeof(WaveLds<32>) : sizeof(WaveLds<16>));
+}
+
+int wave_band_words(int spl) { return spl == 32 ? WaveLds<32>::kBand : WaveLds<16>::kBand; }
+
+hipError_t launch_wave(const PArgs &a, int spl, size_t lds, bool fp64, hipStream_t st) {
+    PArgs args = a;
+    void *kargs[] = {&args};
+    const int groups = (a.n_tiles + kWaveTilesPerWG - 1) / kWaveTilesPerWG;
+    return hipLaunchCooperativeKernel(wave_fn(spl, fp64), dim3(groups), dim3(64 * kWaveTilesPerWG), kargs,
+                                      (unsigned)lds, st);
+}
+
+hipError_t wave_capacity(int spl, size_t lds, bool fp64, int *blocks_per_cu) {
+    const void *fn = wave_fn(spl, fp64);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, 64 * kWaveTilesPerWG, lds);
+}
+
+}  // namespace kmc

@@ -23,9 +23,10 @@ def _protocols(n):
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("limit,tile_sites", [(3, 512), (5, 512), (0, 0)])
-def test_grouped_persistent_batch_matches_oracle(precision, limit, tile_sites):
-    """12 devices of different shapes, fillings and protocols; the persistent
+@pytest.mark.parametrize("mode,limit,tile_sites", [("persistent", 3, 512), ("persistent", 5, 512),
+                                                   ("persistent", 0, 0), ("wave", 3, 0), ("wave", 0, 2048)])
+def test_grouped_persistent_batch_matches_oracle(precision, mode, limit, tile_sites):
+    """12 devices of different shapes, fillings and protocols; a persistent
     strategy split into groups of at most `limit` tiles (several launches per
     chunk) follows the oracle step by step."""
     from paper_2511_09413_amd import Simulator
@@ -34,7 +35,7 @@ def test_grouped_persistent_batch_matches_oracle(precision, limit, tile_sites):
     sim = Simulator(ph, RAILS, SITES, tile_sites=tile_sites)
     if limit:
         sim.set_group_limit(limit)
-    sim.set_launch_mode("persistent")
+    sim.set_launch_mode(mode)
     if limit:
         assert sim.n_groups > 1
     p_or = oracle.OracleParams(ph, RAILS, SITES)
@@ -46,15 +47,17 @@ def test_grouped_persistent_batch_matches_oracle(precision, limit, tile_sites):
 
 
 def test_batch_strategies_agree():
-    """Half-step launches, one persistent group and many small groups give the
-    same per-step tallies and final state."""
+    """Half-step launches, one persistent group and many small groups, and the
+    wave strategy (one group, many groups, 32 sites per lane) give the same
+    per-step tallies and final state."""
     import torch
     from paper_2511_09413_amd import Simulator
     ph = Physics(precision=FP32, seed=5, ea_ev=0.15)
     protos = _protocols(len(RAILS))
     outs = []
-    for mode, limit in (("half_step", 0), ("persistent", 0), ("persistent", 3)):
-        sim = Simulator(ph, RAILS, SITES, tile_sites=512)
+    for mode, limit, tile in (("half_step", 0, 512), ("persistent", 0, 512), ("persistent", 3, 512),
+                              ("wave", 0, 0), ("wave", 3, 0), ("wave", 0, 2048)):
+        sim = Simulator(ph, RAILS, SITES, tile_sites=tile)
         sim.set_group_limit(limit)
         sim.set_launch_mode(mode)
         sim.fill_random(FILL)
@@ -67,16 +70,18 @@ def test_batch_strategies_agree():
         assert np.array_equal(o[2], outs[0][2])
 
 
-def test_c3_full_batch_sampled():
-    """The 256-device batch (1.4e8 sites) in the automatic strategy: after 4
-    steps, sampled devices equal the oracle's run of that device alone (the
+@pytest.mark.parametrize("mode", ["persistent", "wave"])
+def test_c3_full_batch_sampled(mode):
+    """The 256-device batch (1.4e8 sites) in both persistent strategies: after
+    4 steps, sampled devices equal the oracle's run of that device alone (the
     devices before it shrunk to 1 x 2 empty sites so its random stream index is
     unchanged), and every rail keeps its ion count."""
     from paper_2511_09413_amd import Simulator
     wl = c3_batched(n_steps=100_000)
     ph = wl.physics.replace(ea_ev=0.2)   # more hops per step than at 0.3 eV
     sim = Simulator(ph, wl.rails, wl.sites)
-    assert sim.launch_mode == "persistent" and sim.n_groups > 1
+    sim.set_launch_mode(mode)
+    assert sim.launch_mode == mode and sim.n_groups > 1
     sim.fill_random(wl.filling)
     occ0 = sim.read_occupancy()
     sim.set_protocols(wl.protocols)

@@ -13,7 +13,7 @@ pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
 
-MODES = [("half_step", 0), ("persistent", 0), ("persistent", 512)]
+MODES = [("half_step", 0), ("persistent", 0), ("persistent", 512), ("wave", 0), ("wave", 2048)]
 
 
 def _sim(physics, rails, sites, occ=None, ea=None, mode="auto", tile_sites=0):
@@ -146,7 +146,7 @@ def test_near_threshold_log_matches_oracle():
 
 
 # ------------------------------------------------------------- full size
-@pytest.mark.parametrize("mode", ["half_step", "persistent"])
+@pytest.mark.parametrize("mode", ["half_step", "persistent", "wave"])
 def test_c2_full_size_sampled(mode):
     """4096 x 1024, FP32, per-site barriers, in the benchmark's launch
     configuration: after 3 steps, rails [lo+6, hi-6) of several windows equal the
@@ -170,15 +170,17 @@ def test_c2_full_size_sampled(mode):
     assert int(np.abs(net.cpu().numpy()).sum()) >= 0
 
 
-def test_persistent_long_run_keeps_ring_protocol():
-    """4096 x 1024 persistent run over 40 launches (40960 steps): every
-    neighbour wait completes (the kernel status stays clear) and every rail keeps
-    its ion count.  A publication issued before the slot-reuse check made such
-    long runs time out."""
+@pytest.mark.parametrize("mode", ["persistent", "wave"])
+def test_persistent_long_run_keeps_ring_protocol(mode):
+    """4096 x 1024 run of a persistent strategy over 40 launches (40960
+    steps): every neighbour wait completes (the kernel status stays clear) and
+    every rail keeps its ion count.  A publication issued before the slot-reuse
+    check made such long runs time out."""
     from paper_2511_09413_amd import Simulator
     wl = c2_large_device(n_steps=100_000)
     sim = Simulator(wl.physics, wl.rails, wl.sites, ea=wl.ea_site)
-    assert sim.launch_mode == "persistent"
+    sim.set_launch_mode(mode)
+    assert sim.launch_mode == mode
     sim.fill_random(wl.filling)
     occ0 = sim.read_occupancy().reshape(4096, 1024).sum(axis=1)
     sim.set_protocols(wl.protocols)
@@ -186,3 +188,18 @@ def test_persistent_long_run_keeps_ring_protocol():
     sim.read_current()   # raises on a timed-out neighbour wait
     occ = sim.read_occupancy().reshape(4096, 1024).sum(axis=1)
     assert np.array_equal(occ, occ0)
+
+
+@pytest.mark.parametrize("tile", [0, 2048])
+def test_wave_snapshot_ring_wraps_under_many_hops(tile):
+    """One- and two-rail wave tiles at a barrier low enough that nearly every
+    half-step changes an edge rail: the snapshot ring wraps many times per
+    launch (its slot reuse waits for both neighbours), over more than one
+    launch, and the trajectory still follows the oracle step by step."""
+    ph = Physics(precision=FP64, seed=31, ea_ev=0.06, coulomb_kappa_v=0.03)
+    rails, sites = [6, 3], [1000, 500]
+    from workloads import Workload
+    wl = Workload("wave_ring", ph, rails, sites, [0.3, 0.4], [triangle(1.0, 400e-12), constant(0.5)], 0)
+    st, sim = _run_parity(wl, 1100, 550, mode="wave", tile_sites=tile)
+    assert sim.launch_mode == "wave"
+    assert st["hops"] > 2000

@@ -49,7 +49,7 @@ def _forward_and_replay(ph, rails, sites, filling, protocols, n_steps, weights_s
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
-@pytest.mark.parametrize("mode,tile", [("half_step", 0), ("persistent", 0), ("half_step", 512)])
+@pytest.mark.parametrize("mode,tile", [("half_step", 0), ("persistent", 0), ("half_step", 512), ("wave", 0)])
 def test_replay_matches_oracle_ragged(precision, mode, tile):
     """Two devices of different shapes, validation barrier (many hops), a bias
     sweep: the GPU replay's four sums per device equal the oracle's."""
