@@ -196,6 +196,24 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     }
     for (int q = lane; q < kClasses; q += 64) w.cls_a[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
     wave_sync();
+    // the next lane's first site (the far end of the lane's last bond);
+    // refreshed only after half-steps that moved ions
+    uint32_t nbit = __shfl_down(bits, 1, 64) & 1u;
+
+    // Stage-0 scale of the lane: every origin of its bonds (sites s0 ..
+    // s0 + SPL) has a class >= q_lo, so every exact threshold is at most
+    // rho (thr0 + 1) + 2^32 2e-6 with rho = A(q_lo) / A(0); r_lane = ceil(rho
+    // 2^32), and the per-step bound is min(thr0, mulhi(thr0, r_lane) + 8600)
+    // (the margin covers the widening term, both ceilings and binary64
+    // rounding).
+    uint32_t r_lane = 0;
+    if (has && last >= 0) {
+        int q_lo = kClasses;
+        const int s_hi = s0 + SPL < L - 1 ? s0 + SPL : L - 1;
+        for (int x = s0; x <= s_hi; ++x) q_lo = min(q_lo, (int)w.cls[row * P + x]);
+        const double rho = w.cls_a[q_lo] / w.cls_a[0];
+        r_lane = q_lo == 0 ? 0xFFFFFFFFu : (uint32_t)fmin(ceil(rho * 4294967296.0), 4294967295.0);
+    }
 
     // Per-step tables of the window [kb, kb + 64): lane k holds step kb + k's
     // stage-0 threshold in a register, the bias and g go to LDS.
@@ -282,8 +300,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         if (h == 0 && kw == 0) refresh(kstep);
 
         // candidates: bonds of parity h whose two sites differ
-        const uint32_t nb = __shfl_down(bits, 1, 64);
-        const uint32_t cand = (bits ^ ((bits >> 1) | ((nb & 1u) << (SPL - 1)))) & (h ? 0xAAAAAAAAu : 0x55555555u) & valid;
+        const uint32_t cand = (bits ^ ((bits >> 1) | (nbit << (SPL - 1)))) & (h ? 0xAAAAAAAAu : 0x55555555u) & valid;
 
         // Philox words; the key enters each half-step opaquely, so that the
         // round keys are derived on the scalar unit instead of being kept live
@@ -292,18 +309,22 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
         uint32_t wd[kW];
         draw_words<0>(wd, (uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, k0, k1);
-        // stage 0: the smallest word against the lowest class's threshold;
-        // stage 1 (rare): each candidate's word against its origin's class
+        // stage 0: the smallest word against the bound of the lane's lowest
+        // class; stage 1 (rare): each candidate's word against its origin's
+        // exact class threshold
         const uint32_t thr0 = (uint32_t)__builtin_amdgcn_readlane((int)thr_lane, kw);
+        uint32_t t_lane = __umulhi(thr0, r_lane);
+        t_lane = t_lane < 0xFFFF0000u ? t_lane + 8600u : 0xFFFFFFFFu;
+        t_lane = min(thr0, t_lane);
         const uint32_t mn = min_word<0>(wd);
         uint32_t sv = 0;
-        if (mn <= thr0 && cand != 0u) {
+        if (mn <= t_lane && cand != 0u) {
             uint32_t c = cand;
             while (c) {
                 const int b = __builtin_ctz(c);
                 c &= c - 1;
                 const uint32_t x = pick_word<0>(wd, b >> 1);
-                if (x <= thr0) {
+                if (x <= t_lane) {
                     const int o = s0 + (((bits >> b) & 1u) ? b : b + 1);
                     if (x <= threshold_of(a.c0, w.cls_a[w.cls[row * P + o]], w.step_g[kw])) sv |= 1u << b;
                 }
@@ -397,6 +418,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                 }
             }
             bits ^= fl;
+            nbit = __shfl_down(bits, 1, 64) & 1u;
         }
 
         // publish the new state js + 1
