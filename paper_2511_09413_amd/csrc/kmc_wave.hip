@@ -42,10 +42,26 @@ namespace {
 constexpr int kWaveSpin = 1 << 20;   // polls before a wait is declared hung
 constexpr int kWaveWin = 64;         // per-step table entries: one per lane
 
-// A tile's LDS: per-device and per-step tables and the rare-path buffers.
+// Values of a tile that only the rare paths need.  They live in LDS and are
+// read again where needed, so that they do not hold scalar registers across
+// the loop (which would push the loop's own values into spill code).
+struct WaveGeo {
+    int32_t R, L, P, lpr, nr, m, W32, e, r0, d, prev, next, ti, single, isolated, cutoff;
+    int32_t n_nbr, n_knots;
+    int8_t nbr_off[2 * kMaxRailRange + 1];
+    int8_t nbr_dist[2 * kMaxRailRange + 1];
+    int8_t pad_[6];
+    int64_t dv_off, off_pad, n_set, n_base, tally_base;
+    double coul_bound;
+};
+static_assert(sizeof(WaveGeo) % 16 == 0, "LDS tiles stay 16-byte aligned");
+
+// A tile's LDS: its rare-path values, per-device and per-step tables and the
+// rare-path buffers.
 template <int SPL>
 struct WaveLds {
     static constexpr int kBand = 4 * SPL + 16;  // 32-bit words of neighbour rails
+    WaveGeo geo;
     double cls_a[kClasses];              // exp(-beta (ea_min + q ea_step)) of the tile's device
     double step_v[kWaveWin];             // bias of the steps of the current window
     double step_g[kWaveWin];             // exp(beta (|alpha V| / L + coul_bound) / 2)
@@ -64,9 +80,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t wave_tag(uint64_t epoch, int64_t j_rel) {
-    return ((uint32_t)(epoch & 0xFFFFFu) << 12) | (uint32_t)j_rel;
-}
 
 // Poll a published word until its tag is `want` (stored in *out); false on
 // time-out (raising the status flag) or once another tile has raised it.
@@ -86,19 +99,27 @@ __device__ __forceinline__ bool poll_tag(const uint64_t *p, uint32_t want, int32
     }
 }
 
-// Uniform values used only on rare paths enter those paths through these, so
-// the compiler derives what it needs there instead of hoisting it out of the
-// loop into registers held for the whole launch.
-__device__ __forceinline__ int opaque(int v) {
-    v = __builtin_amdgcn_readfirstlane(v);
-    asm volatile("" : "+s"(v));
-    return v;
+// The kernel arguments, read again from the argument segment where a rare
+// path needs them (scalar loads); the opaque pointer keeps the compiler from
+// hoisting those loads out of the loop.
+typedef const __attribute__((address_space(4))) PArgs *KArgs;
+__device__ __forceinline__ KArgs kargs() {
+    KArgs p = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return p;
 }
-__device__ __forceinline__ int64_t opaque(int64_t v) {
-    const uint64_t u = (uint64_t)v;
-    return (int64_t)(((uint64_t)(uint32_t)opaque((int)(u >> 32)) << 32) | (uint32_t)opaque((int)(uint32_t)u));
+// An LDS object made opaque in the same way (its loads stay LDS loads).
+template <typename T>
+__device__ __forceinline__ T *lds_opaque(T *p) {
+    __attribute__((address_space(3))) T *q = (__attribute__((address_space(3))) T *)p;
+    asm volatile("" : "+s"(q));
+    return (T *)q;
 }
-__device__ __forceinline__ double opaque(double v) { return __longlong_as_double(opaque((int64_t)__double_as_longlong(v))); }
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t rfl(int64_t v) {
+    return (int64_t)(((uint64_t)(uint32_t)rfl((int)((uint64_t)v >> 32)) << 32) | (uint32_t)rfl((int)(uint32_t)v));
+}
+__device__ __forceinline__ double rfl(double v) { return __longlong_as_double(rfl((int64_t)__double_as_longlong(v))); }
 
 // The lane's Philox words live in registers: every access below uses a
 // compile-time index (template recursion), never a runtime one, so the words
@@ -139,162 +160,205 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile data in scalar registers
 
     // the kernel table K(dist, ds), shared by the workgroup's tiles
-    const int m = a.rail_range;
-    const int kt_stride = a.cutoff + 1;
-    const int n_kt = (m + 1) * kt_stride;
-    const bool kt_in_lds = n_kt <= kLdsTableMax;
-    const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
-                                                            : reinterpret_cast<const Real *>(a.ktab32);
-    Real *kt_lds = reinterpret_cast<Real *>(smem);
-    if (kt_in_lds)
-        for (int i = threadIdx.x; i < n_kt; i += blockDim.x) kt_lds[i] = kt_glob[i];
+    {
+        const int n_kt = (a.rail_range + 1) * (a.cutoff + 1);
+        if (n_kt <= kLdsTableMax) {
+            const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
+                                                                    : reinterpret_cast<const Real *>(a.ktab32);
+            for (int i = threadIdx.x; i < n_kt; i += blockDim.x) reinterpret_cast<Real *>(smem)[i] = kt_glob[i];
+        }
+    }
     __syncthreads();
-    const Real *kt = kt_in_lds ? kt_lds : kt_glob;
-    const size_t kt_bytes = kt_in_lds ? (((size_t)n_kt * sizeof(Real) + 15) & ~(size_t)15) : 0;
-    WaveLds<SPL> &w = reinterpret_cast<WaveLds<SPL> *>(smem + kt_bytes)[wave];
+    // the tile's LDS (after the kernel table when that is in LDS)
+    auto lds_of = [&](KArgs ka) -> WaveLds<SPL> & {
+        const int n_kt = (ka->rail_range + 1) * (ka->cutoff + 1);
+        const size_t kt_bytes = n_kt <= kLdsTableMax ? (((size_t)n_kt * sizeof(Real) + 15) & ~(size_t)15) : 0;
+        return reinterpret_cast<WaveLds<SPL> *>(smem + kt_bytes)[wave];
+    };
+    WaveLds<SPL> &w = lds_of(kargs());
 
     const int n_groups = (a.n_tiles + kWaveTilesPerWG - 1) / kWaveTilesPerWG;
     const int ti = tile_of_block(blockIdx.x, n_groups) * kWaveTilesPerWG + wave;
     if (ti >= a.n_tiles) return;  // no barrier follows
 
-    const PTile tile = a.tiles[ti];
-    const DevInfo &dv = a.devs[tile.d];
-    const int R = dv.rails, L = dv.sites, P = dv.pitch;
-    const int lpr = (P + SPL - 1) / SPL;  // lanes per rail
-    const int nr = tile.nr;
-    const int W32 = (P + 31) / 32;        // 32-bit words of a published rail
-    const bool single = tile.prev == ti && tile.next == ti;
-    const bool isolated = single || m == 0;  // no rail of another tile is ever read
-    const int e = nr < 2 * m ? nr : 2 * m;   // edge rails: the first min(m, nr) and the last m
-    const uint64_t epoch = a.epoch;
-    const int64_t j0 = 2 * a.ctl->n_base;
-    const int64_t tally_base = a.ctl->tally_base;
-    uint64_t *own = a.pub + (int64_t)ti * a.pub_stride;  // kPubSlots state words, then the ring
+    // ------------------------------------------------------------ set-up
+    // Values the loop itself needs stay in registers; the rest goes to w.geo.
+    uint32_t bits = 0, valid = 0, rail = 0, r_lane = 0, nbit = 0;
+    int s0 = 0, cls_base = 0, d = 0;
+    bool isolated = true;
+    uint64_t *own = nullptr;
+    {
+        const PTile tile = a.tiles[ti];
+        const DevInfo &dv = a.devs[tile.d];
+        const int R = dv.rails, L = dv.sites, P = dv.pitch, m = a.rail_range;
+        const int lpr = (P + SPL - 1) / SPL;  // lanes per rail
+        const int nr = tile.nr;
+        const bool single = tile.prev == ti && tile.next == ti;
+        isolated = single || m == 0;  // no rail of another tile is ever read
+        d = tile.d;
+        own = a.pub + (int64_t)ti * a.pub_stride;  // kPubSlots state words, then the ring
+        if (lane == 0) {
+            WaveGeo &g = w.geo;
+            g.R = R;
+            g.L = L;
+            g.P = P;
+            g.lpr = lpr;
+            g.nr = nr;
+            g.m = m;
+            g.W32 = (P + 31) / 32;              // 32-bit words of a published rail
+            g.e = nr < 2 * m ? nr : 2 * m;      // edge rails: the first min(m, nr) and the last m
+            g.r0 = tile.r0;
+            g.d = tile.d;
+            g.prev = tile.prev;
+            g.next = tile.next;
+            g.ti = ti;
+            g.single = single;
+            g.isolated = isolated;
+            g.cutoff = a.cutoff;
+            g.n_nbr = dv.n_nbr;
+            g.n_knots = dv.n_knots;
+            for (int k = 0; k < 2 * kMaxRailRange + 1; ++k) {
+                g.nbr_off[k] = dv.nbr_off[k];
+                g.nbr_dist[k] = dv.nbr_dist[k];
+            }
+            g.dv_off = dv.off;
+            g.off_pad = dv.off_pad;
+            g.n_set = dv.n_set;
+            g.n_base = a.ctl->n_base;
+            g.tally_base = a.ctl->tally_base;
+            g.coul_bound = dv.coul_bound;
+        }
+        // the lane's sites, fixed for the launch
+        const bool has = lane < nr * lpr;
+        const int row = has ? lane / lpr : 0;
+        s0 = has ? (lane - row * lpr) * SPL : 0;
+        cls_base = row * P;
+        rail = (uint32_t)(tile.r0 + row);
+        const int last = L - 2 - s0;  // the bond at s0 + b lies inside the rail iff b <= last
+        valid = (!has || last < 0) ? 0u : (last >= SPL - 1 ? kAll : ((2u << last) - 1u));
 
-    // the lane's sites, fixed for the launch
-    const bool has = lane < nr * lpr;
-    const int row = has ? lane / lpr : 0;
-    const int s0 = has ? (lane - row * lpr) * SPL : 0;
-    const uint32_t rail = (uint32_t)(tile.r0 + row);
-    const int last = L - 2 - s0;  // the bond at s0 + b lies inside the rail iff b <= last
-    const uint32_t valid = (!has || last < 0) ? 0u : (last >= SPL - 1 ? kAll : ((2u << last) - 1u));
-
-    // load the tile: occupancy bits to registers, barrier classes to LDS
-    int8_t *gstate = a.occ + dv.off_pad + (int64_t)tile.r0 * P;
-    uint32_t bits = 0;
-    if (has) {
+        // load the tile: occupancy bits to registers, barrier classes to LDS
+        const int8_t *gstate = a.occ + dv.off_pad + (int64_t)tile.r0 * P;
+        if (has) {
 #pragma unroll
-        for (int c = 0; c < SPL / 16; ++c) {
-            if (c == 0 || s0 + 16 * c < P) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(gstate + row * P + s0 + 16 * c);
-                bits |= occ_bits(v) << (16 * c);
-                *reinterpret_cast<uint4 *>(w.cls + row * P + s0 + 16 * c) =
-                    make_uint4((v.x >> 1) & 0x7F7F7F7Fu, (v.y >> 1) & 0x7F7F7F7Fu, (v.z >> 1) & 0x7F7F7F7Fu,
-                               (v.w >> 1) & 0x7F7F7F7Fu);
+            for (int c = 0; c < SPL / 16; ++c) {
+                if (c == 0 || s0 + 16 * c < P) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(gstate + row * P + s0 + 16 * c);
+                    bits |= occ_bits(v) << (16 * c);
+                    *reinterpret_cast<uint4 *>(w.cls + row * P + s0 + 16 * c) =
+                        make_uint4((v.x >> 1) & 0x7F7F7F7Fu, (v.y >> 1) & 0x7F7F7F7Fu, (v.z >> 1) & 0x7F7F7F7Fu,
+                                   (v.w >> 1) & 0x7F7F7F7Fu);
+                }
             }
         }
-    }
-    for (int q = lane; q < kClasses; q += 64) w.cls_a[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
-    wave_sync();
-    // the next lane's first site (the far end of the lane's last bond);
-    // refreshed only after half-steps that moved ions
-    uint32_t nbit = __shfl_down(bits, 1, 64) & 1u;
+        for (int q = lane; q < kClasses; q += 64) w.cls_a[q] = exp(-a.beta * (dv.ea_min + (double)q * dv.ea_step));
+        wave_sync();
+        // the next lane's first site (the far end of the lane's last bond);
+        // refreshed only after half-steps that moved ions
+        nbit = __shfl_down(bits, 1, 64) & 1u;
 
-    // Stage-0 scale of the lane: every origin of its bonds (sites s0 ..
-    // s0 + SPL) has a class >= q_lo, so every exact threshold is at most
-    // rho (thr0 + 1) + 2^32 2e-6 with rho = A(q_lo) / A(0); r_lane = ceil(rho
-    // 2^32), and the per-step bound is min(thr0, mulhi(thr0, r_lane) + 8600)
-    // (the margin covers the widening term, both ceilings and binary64
-    // rounding).
-    uint32_t r_lane = 0;
-    if (has && last >= 0) {
-        int q_lo = kClasses;
-        const int s_hi = s0 + SPL < L - 1 ? s0 + SPL : L - 1;
-        for (int x = s0; x <= s_hi; ++x) q_lo = min(q_lo, (int)w.cls[row * P + x]);
-        const double rho = w.cls_a[q_lo] / w.cls_a[0];
-        r_lane = q_lo == 0 ? 0xFFFFFFFFu : (uint32_t)fmin(ceil(rho * 4294967296.0), 4294967295.0);
+        // Stage-0 scale of the lane: every origin of its bonds (sites s0 ..
+        // s0 + SPL) has a class >= q_lo, so every exact threshold is at most
+        // rho (thr0 + 1) + 2^32 2e-6 with rho = A(q_lo) / A(0); r_lane =
+        // ceil(rho 2^32), and the per-step bound is min(thr0, mulhi(thr0,
+        // r_lane) + 8600) (the margin covers the widening term, both
+        // ceilings and binary64 rounding).
+        if (has && last >= 0) {
+            int q_lo = kClasses;
+            const int s_hi = s0 + SPL < L - 1 ? s0 + SPL : L - 1;
+            for (int x = s0; x <= s_hi; ++x) q_lo = min(q_lo, (int)w.cls[row * P + x]);
+            const double rho = w.cls_a[q_lo] / w.cls_a[0];
+            r_lane = q_lo == 0 ? 0xFFFFFFFFu : (uint32_t)fmin(ceil(rho * 4294967296.0), 4294967295.0);
+        }
     }
+    const uint32_t tag_hi = (uint32_t)(a.epoch & 0xFFFFFu) << 12;  // state tag = tag_hi | launch-relative state
+    const uint32_t n0 = (uint32_t)a.ctl->n_base;                   // Philox step word of the first step
 
     // Per-step tables of the window [kb, kb + 64): lane k holds step kb + k's
     // stage-0 threshold in a register, the bias and g go to LDS.
     uint32_t thr_lane = 0;
     auto refresh = [&](int kb) {
-        const int d = opaque(tile.d);
-        const int64_t k = opaque((j0 >> 1) - dv.n_set + kb) + lane;
-        const double beta = opaque(a.beta), alpha = opaque(a.alpha);
-        const double V = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
-                                          (double)k * opaque(a.dt));
-        const double g = exp(0.5 * beta * (fabs(alpha * V) / (double)opaque(L) + dv.coul_bound));
-        w.step_v[lane] = V;
-        w.step_g[lane] = g;
-        thr_lane = threshold_of(opaque(a.c0), w.cls_a[0], g);
+        const KArgs ka = kargs();
+        WaveLds<SPL> &wr = *lds_opaque(&w);
+        const WaveGeo &g = wr.geo;
+        const int dd = rfl(g.d);
+        const int64_t k = rfl(g.n_base) - rfl(g.n_set) + kb + lane;
+        const double V = protocol_voltage(ka->knot_t + dd * kMaxKnots, ka->knot_v + dd * kMaxKnots, rfl(g.n_knots),
+                                          (double)k * ka->dt);
+        const double gg = exp(0.5 * ka->beta * (fabs(ka->alpha * V) / (double)rfl(g.L) + rfl(g.coul_bound)));
+        wr.step_v[lane] = V;
+        wr.step_g[lane] = gg;
+        thr_lane = threshold_of(ka->c0, wr.cls_a[0], gg);
         wave_sync();
     };
 
     // 32 bits [32 q, 32 q + 32) of tile row r, gathered from the owning lanes;
     // every lane takes part in the cross-lane reads
-    auto row_word = [&](int r, int q) -> uint32_t {
+    auto row_word = [&](int lpr, int r, int q) -> uint32_t {
         if (SPL == 32) return __shfl(bits, r * lpr + q, 64);
         const uint32_t lo = __shfl(bits, r * lpr + 2 * q, 64);
         const uint32_t hi = __shfl(bits, r * lpr + (2 * q + 1 < lpr ? 2 * q + 1 : 2 * q), 64);
         return lo | (2 * q + 1 < lpr ? hi << 16 : 0u);
     };
     // snapshot of the edge rails as state jrel into ring slot `slot`
-    auto write_snapshot = [&](int slot, int64_t jrel) {
-        const int w32 = opaque(W32), mm = opaque(m), ee = opaque(e), nrr = opaque(nr);
+    auto write_snapshot = [&](const WaveGeo &g, int slot, int64_t jrel) {
+        const int w32 = rfl(g.W32), mm = rfl(g.m), ee = rfl(g.e), nrr = rfl(g.nr), lpr = rfl(g.lpr);
         uint64_t *dst = own + kPubSlots + (int64_t)slot * (ee * w32);
-        const uint64_t tag = (uint64_t)wave_tag(epoch, jrel) << 32;
+        const uint64_t tag = (uint64_t)(tag_hi | (uint32_t)jrel) << 32;
         for (int sr = 0; sr < ee; ++sr)
             for (int q0 = 0; q0 < w32; q0 += 64) {
                 const int q = q0 + lane < w32 ? q0 + lane : w32 - 1;
-                const uint32_t word = row_word(sr < mm ? sr : sr + (nrr - ee), q);
+                const uint32_t word = row_word(lpr, sr < mm ? sr : sr + (nrr - ee), q);
                 if (q0 + lane < w32)
                     __hip_atomic_store(dst + sr * w32 + q, tag | word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
     };
-    // Neighbour rails of state jrel into w.band: entry idx * W32 + q holds rail
-    // offset idx - m (idx < m, from the previous tile) or nr + idx - m (from the
-    // next tile).  Uniform result.
-    auto fetch_bands = [&](int64_t jrel) -> bool {
-        const int w32 = opaque(W32), mm = opaque(m);
+    // Neighbour rails of state jrel into band: entry idx * W32 + q holds rail
+    // offset idx - m (idx < m, from the previous tile) or nr + idx - m (from
+    // the next tile).  Uniform result.
+    auto fetch_bands = [&](KArgs ka, WaveLds<SPL> &wr, int64_t jrel) -> bool {
+        const WaveGeo &g = wr.geo;
+        const int w32 = rfl(g.W32), mm = rfl(g.m), prev = rfl(g.prev), next = rfl(g.next);
+        const PTile *tiles = ka->tiles;
+        uint64_t *pub = ka->pub;
+        const int64_t stride = ka->pub_stride;
+        int32_t *status = ka->status;
         bool ok = true;
         for (int idx = 0; idx < 2 * mm; ++idx) {
-            const int T = idx < mm ? tile.prev : tile.next;
-            const int nrT = a.tiles[T].nr;
+            const int T = idx < mm ? prev : next;
+            const int nrT = tiles[T].nr;
             const int eT = nrT < 2 * mm ? nrT : 2 * mm;
             const int rr = idx < mm ? nrT - mm + idx : idx - mm;  // rail of tile T
             const int sr = rr < mm ? rr : rr - (nrT - eT);        // its row in T's snapshots
-            const uint64_t *base = a.pub + (int64_t)T * a.pub_stride;
+            const uint64_t *base = pub + (int64_t)T * stride;
             for (int q = lane; q < w32; q += 64) {
                 uint64_t st = 0, v = 0;
-                if (ok) ok = poll_tag(base + jrel, wave_tag(epoch, jrel), a.status, &st);
+                if (ok) ok = poll_tag(base + jrel, tag_hi | (uint32_t)jrel, status, &st);
                 if (ok) {
                     const int slot = (int)((uint32_t)st >> 12);
-                    const int64_t snap_rel = (int64_t)(st & 0xFFFu);
-                    ok = poll_tag(base + kPubSlots + (int64_t)slot * (eT * w32) + sr * w32 + q,
-                                  wave_tag(epoch, snap_rel), a.status, &v);
+                    const uint32_t snap_rel = (uint32_t)st & 0xFFFu;
+                    ok = poll_tag(base + kPubSlots + (int64_t)slot * (eT * w32) + sr * w32 + q, tag_hi | snap_rel,
+                                  status, &v);
                 }
-                w.band[idx * w32 + q] = (uint32_t)v;
+                wr.band[idx * w32 + q] = (uint32_t)v;
             }
         }
         return __ballot(!ok) == 0;
     };
 
-
-    int snap_count = 0, snap_slot = 0;
-    int64_t snap_rel = 0;
+    int snap_count = 0;
+    uint32_t snap_word = 0;  // ring slot << 12 | launch-relative state of the latest snapshot
     if (!isolated) {
-        write_snapshot(0, 0);
+        write_snapshot(w.geo, 0, 0);
         if (lane == 0) {
             w.snap_state[0] = 0;
-            __hip_atomic_store(own, (uint64_t)wave_tag(epoch, 0) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(own, (uint64_t)tag_hi << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
+    const uint32_t key0 = a.key0, key1 = a.key1;
     for (int js = 0; js < 2 * a.n_steps; ++js) {
-        const int64_t j = j0 + js;
-        const int64_t n = j >> 1;
-        const int h = js & 1;  // j0 is even
+        const int h = js & 1;  // the first state of a launch is even
         const int kstep = js >> 1;
         const int kw = kstep & (kWaveWin - 1);
         if (h == 0 && kw == 0) refresh(kstep);
@@ -304,11 +368,11 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
 
         // Philox words; the key enters each half-step opaquely, so that the
         // round keys are derived on the scalar unit instead of being kept live
-        uint32_t k0 = a.key0, k1 = a.key1;
+        uint32_t k0 = key0, k1 = key1;
         asm volatile("" : "+s"(k0), "+s"(k1));
-        const uint32_t ctr3 = ((uint32_t)tile.d << 4) | (uint32_t)h;
+        const uint32_t ctr3 = ((uint32_t)d << 4) | (uint32_t)h;
         uint32_t wd[kW];
-        draw_words<0>(wd, (uint32_t)(s0 >> 3), rail, (uint32_t)n, ctr3, k0, k1);
+        draw_words<0>(wd, (uint32_t)(s0 >> 3), rail, n0 + (uint32_t)kstep, ctr3, k0, k1);
         // stage 0: the smallest word against the bound of the lane's lowest
         // class; stage 1 (rare): each candidate's word against its origin's
         // exact class threshold
@@ -319,6 +383,9 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         const uint32_t mn = min_word<0>(wd);
         uint32_t sv = 0;
         if (mn <= t_lane && cand != 0u) {
+            const double c0 = kargs()->c0;
+            WaveLds<SPL> &wr = *lds_opaque(&w);
+            const double g_step = wr.step_g[kw];
             uint32_t c = cand;
             while (c) {
                 const int b = __builtin_ctz(c);
@@ -326,7 +393,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                 const uint32_t x = pick_word<0>(wd, b >> 1);
                 if (x <= t_lane) {
                     const int o = s0 + (((bits >> b) & 1u) ? b : b + 1);
-                    if (x <= threshold_of(a.c0, w.cls_a[w.cls[row * P + o]], w.step_g[kw])) sv |= 1u << b;
+                    if (x <= threshold_of(c0, wr.cls_a[wr.cls[cls_base + o]], g_step)) sv |= 1u << b;
                 }
             }
         }
@@ -335,14 +402,24 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         bool edge_changed = false;
         const uint64_t any = __ballot(sv != 0u);
         if (any) {
-            const int cut = opaque(a.cutoff), Lq = opaque(L), lprq = opaque(lpr), nrq = opaque(nr), mq = opaque(m);
-            const int w32 = opaque(W32);
+            const KArgs ka = kargs();
+            WaveLds<SPL> &wr = *lds_opaque(&w);
+            const WaveGeo &g = wr.geo;
+            const int cut = rfl(g.cutoff), Lq = rfl(g.L), lprq = rfl(g.lpr), nrq = rfl(g.nr), mq = rfl(g.m);
+            const int w32 = rfl(g.W32), Rq = rfl(g.R), n_nbr = rfl(g.n_nbr), r0 = rfl(g.r0), dd = rfl(g.d);
+            const bool single = rfl(g.single) != 0;
+            const int64_t n = rfl(g.n_base) + kstep;
+            const int n_kt = (ka->rail_range + 1) * (cut + 1);
+            const Real *kt = n_kt <= kLdsTableMax ? reinterpret_cast<const Real *>(smem)
+                                                  : (std::is_same<Real, double>::value
+                                                         ? reinterpret_cast<const Real *>(ka->ktab64)
+                                                         : reinterpret_cast<const Real *>(ka->ktab32));
             auto bit_at = [&](int r, int site) -> uint32_t {
-                return (w.snap[r * lprq + site / SPL] >> (site % SPL)) & 1u;
+                return (wr.snap[r * lprq + site / SPL] >> (site % SPL)) & 1u;
             };
-            w.snap[lane] = bits;
+            wr.snap[lane] = bits;
             bool ok = true;
-            if (!isolated) ok = fetch_bands(js);
+            if (!isolated) ok = fetch_bands(ka, wr, js);
             wave_sync();
             if (!ok) break;
             uint32_t fl = 0;
@@ -351,8 +428,8 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                 const int l = __builtin_ctzll(rest);
                 rest &= rest - 1;
                 uint32_t svl = (uint32_t)__builtin_amdgcn_readlane((int)sv, l);
-                const int lrow = __builtin_amdgcn_readlane(row, l);
                 const int ls0 = __builtin_amdgcn_readlane(s0, l);
+                const int lrow = __builtin_amdgcn_readlane(cls_base, l) / rfl(g.P);
                 while (svl) {
                     const int b = __builtin_ctz(svl);
                     svl &= svl - 1;
@@ -364,13 +441,11 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                     lo = lo < 0 ? 0 : lo;
                     hi = hi > Lq - 1 ? Lq - 1 : hi;
                     Real part = (Real)0;
-                    const int n_nbr = dv.n_nbr;
                     for (int k = 0; k < n_nbr; ++k) {
-                        const int off = dv.nbr_off[k];
-                        const Real *ktr = kt + dv.nbr_dist[k] * (cut + 1);
+                        const int off = rfl((int)g.nbr_off[k]);
+                        const Real *ktr = kt + rfl((int)g.nbr_dist[k]) * (cut + 1);
                         int rho = lrow + off, band = -1;
                         if (single) {
-                            const int Rq = opaque(R);
                             while (rho < 0) rho += Rq;
                             while (rho >= Rq) rho -= Rq;
                         } else if (rho < 0) {
@@ -379,7 +454,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                             band = mq + rho - nrq;
                         }
                         for (int jj = lo + lane; jj <= hi; jj += 64) {
-                            uint32_t bit = band < 0 ? bit_at(rho, jj) : (w.band[band * w32 + (jj >> 5)] >> (jj & 31)) & 1u;
+                            uint32_t bit = band < 0 ? bit_at(rho, jj) : (wr.band[band * w32 + (jj >> 5)] >> (jj & 31)) & 1u;
                             if (off == 0 && (jj == o || jj == t)) bit = 0;
                             const int dt_ = t - jj < 0 ? jj - t : t - jj;
                             const int do_ = o - jj < 0 ? jj - o : o - jj;
@@ -392,20 +467,23 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                     for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
                     int acc = 0;
                     if (lane == 0) {
-                        const Real alpha_r = (Real)opaque(a.alpha), beta_r = (Real)opaque(a.beta);
-                        const Real c0_r = (Real)opaque(a.c0);
-                        const Real e_app = ((alpha_r * (Real)w.step_v[kw]) * (Real)(t - o)) / (Real)Lq;
-                        const int srail = tile.r0 + lrow;
-                        const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)srail * Lq + o]
-                                             : (Real)a.ea_scalar;
-                        acc = decide_hop<Real>(e_app + part, ea, word, beta_r, c0_r, a.log, tile.d, h, n, srail, s);
+                        const Real alpha_r = (Real)ka->alpha, beta_r = (Real)ka->beta, c0_r = (Real)ka->c0;
+                        const Real e_app = ((alpha_r * (Real)wr.step_v[kw]) * (Real)(t - o)) / (Real)Lq;
+                        const int srail = r0 + lrow;
+                        const Real ea = ka->ea ? reinterpret_cast<const Real *>(ka->ea)[rfl(g.dv_off) + (int64_t)srail * Lq + o]
+                                               : (Real)ka->ea_scalar;
+                        HopArgs::LogBuf log;
+                        log.count = ka->log.count;
+                        log.entries = ka->log.entries;
+                        log.cap = ka->log.cap;
+                        acc = decide_hop<Real>(e_app + part, ea, word, beta_r, c0_r, log, dd, h, n, srail, s);
                         if (acc) {
-                            const int64_t base = (n - tally_base) * a.n_devices + tile.d;
-                            atomicAdd(&a.tally_net[base], t < o ? 1 : -1);
+                            const int64_t base = (n - rfl(g.tally_base)) * ka->n_devices + dd;
+                            atomicAdd(&ka->tally_net[base], t < o ? 1 : -1);
                             const int qo = (10 * o) / Lq, qt = (10 * t) / Lq;
                             if (qo != qt) {
-                                atomicAdd(&a.tally_dec[base * kDeciles + qo], -1);
-                                atomicAdd(&a.tally_dec[base * kDeciles + qt], 1);
+                                atomicAdd(&ka->tally_dec[base * kDeciles + qo], -1);
+                                atomicAdd(&ka->tally_dec[base * kDeciles + qt], 1);
                             }
                         }
                     }
@@ -423,47 +501,52 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
 
         // publish the new state js + 1
         if (!isolated) {
-            const int64_t jn = js + 1;
+            const uint32_t jn = (uint32_t)js + 1u;
             if (edge_changed) {
+                const KArgs ka = kargs();
+                WaveLds<SPL> &wr = *lds_opaque(&w);
                 ++snap_count;
                 const int slot = snap_count % kSnapSlots;
                 if (snap_count >= kSnapSlots) {
                     // the slot's snapshot serves states before the next snapshot's
-                    const int64_t need = w.snap_state[(slot + 1) % kSnapSlots];
+                    const uint32_t need = (uint32_t)wr.snap_state[(slot + 1) % kSnapSlots];
                     bool ok = true;
                     if (lane < 2) {
-                        const int T = lane == 0 ? tile.prev : tile.next;
+                        const int T = lane == 0 ? rfl(wr.geo.prev) : rfl(wr.geo.next);
                         uint64_t v = 0;
-                        ok = poll_tag(a.pub + (int64_t)T * a.pub_stride + need, wave_tag(epoch, need), a.status, &v);
+                        ok = poll_tag(ka->pub + (int64_t)T * ka->pub_stride + need, tag_hi | need, ka->status, &v);
                     }
                     if (__ballot(!ok)) break;
                 }
-                write_snapshot(slot, jn);
-                if (lane == 0) w.snap_state[slot] = (int16_t)jn;
-                snap_slot = slot;
-                snap_rel = jn;
+                write_snapshot(wr.geo, slot, jn);
+                if (lane == 0) wr.snap_state[slot] = (int16_t)jn;
+                snap_word = ((uint32_t)slot << 12) | jn;
             }
             if (lane == 0)
-                __hip_atomic_store(own + jn,
-                                   ((uint64_t)wave_tag(epoch, jn) << 32) | ((uint32_t)snap_slot << 12) |
-                                       (uint32_t)snap_rel,
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(own + jn, ((uint64_t)(tag_hi | jn) << 32) | snap_word, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 
     // write the tile back
-    if (has) {
+    {
+        const KArgs ka = kargs();
+        const WaveGeo &g = lds_opaque(&w)->geo;
+        const int P = rfl(g.P);
+        int8_t *gstate = ka->occ + rfl(g.off_pad) + (int64_t)rfl(g.r0) * P;
+        if (lane < rfl(g.nr) * rfl(g.lpr)) {
 #pragma unroll
-        for (int c = 0; c < SPL / 16; ++c) {
-            if (c == 0 || s0 + 16 * c < P) {
-                const uint32_t b16 = (bits >> (16 * c)) & 0xFFFFu;
-                const uint4 cv = *reinterpret_cast<const uint4 *>(w.cls + row * P + s0 + 16 * c);
-                uint4 v;
-                v.x = (((b16 >> 0) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.x << 1);
-                v.y = (((b16 >> 4) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.y << 1);
-                v.z = (((b16 >> 8) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.z << 1);
-                v.w = (((b16 >> 12) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.w << 1);
-                *reinterpret_cast<uint4 *>(gstate + (int64_t)row * P + s0 + 16 * c) = v;
+            for (int c = 0; c < SPL / 16; ++c) {
+                if (c == 0 || s0 + 16 * c < P) {
+                    const uint32_t b16 = (bits >> (16 * c)) & 0xFFFFu;
+                    const uint4 cv = *reinterpret_cast<const uint4 *>(w.cls + cls_base + s0 + 16 * c);
+                    uint4 v;
+                    v.x = (((b16 >> 0) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.x << 1);
+                    v.y = (((b16 >> 4) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.y << 1);
+                    v.z = (((b16 >> 8) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.z << 1);
+                    v.w = (((b16 >> 12) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.w << 1);
+                    *reinterpret_cast<uint4 *>(gstate + cls_base + s0 + 16 * c) = v;
+                }
             }
         }
     }
