@@ -31,11 +31,6 @@ OPS_PER_PHILOX_BLOCK = 40
 # algorithmic bytes per site-update of the method (occupancy 1 B and the
 # binary32 barrier 4 B per half-step pass)
 BYTES_PER_SITE_UPDATE = 10.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hop_persistent_c2_traffic.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2511_09413_amd", "csrc", f)
-                  for f in ("kmc_persistent.hip", "kmc_device.h", "kmc_internal.h")]
-
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2_048)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent"])
+    ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent", "wave"])
     ap.add_argument("--tile-sites", type=int, default=0)
     ap.add_argument("--workload", default="large-device", choices=["large-device", "batch", "gradient", "dense"],
                     help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
@@ -52,20 +47,32 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_sha1() -> str:
+# counter summaries of the persistent kernels and the sources they were taken from
+TRAFFIC = {
+    "hop_persistent": ("hop_persistent_c2_traffic.md", "kmc_persistent.hip"),
+    "hop_wave": ("hop_wave_c2_traffic.md", "kmc_wave.hip"),
+}
+
+
+def kernel_sha1(kernel: str) -> str:
     h = hashlib.sha1()
-    for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+    for f in (TRAFFIC[kernel][1], "kmc_device.h", "kmc_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2511_09413_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the hop kernel from the counter profile summary
-    (its json block), or None when there is none."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a persistent hop kernel from its counter profile
+    summary (the json block), or None when there is none or when the kernel's
+    sources changed since the counters were taken."""
+    if kernel not in TRAFFIC:
         return None
-    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_FILE).read(), re.S)
-    return json.loads(m.group(1)) if m else None
+    path = os.path.join(ROOT, "profiles", TRAFFIC[kernel][0])
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    t = json.loads(m.group(1)) if m else None
+    return t if t is not None and t.get("kernel_sha1") == kernel_sha1(kernel) else None
 
 
 def philox_blocks_per_step(rails, sites) -> int:
@@ -130,22 +137,19 @@ def main():
     cur, tot, t_sim = sim.read_current()   # also checks the kernel status
     mode = sim.launch_mode
 
-    # dominant kernel: hop_persistent (one launch per 1024 steps) or
-    # hop_half_step (one launch per half-step)
-    if mode == "persistent":
+    # dominant kernel: hop_wave or hop_persistent (one launch per 1024 steps)
+    # or hop_half_step (one launch per half-step)
+    if mode in ("persistent", "wave"):
         launches = (args.steps + 1023) // 1024
-        kernel = "hop_persistent"
+        kernel = "hop_wave" if mode == "wave" else "hop_persistent"
     else:
         launches = 2 * args.steps
         kernel = "hop_half_step"
     per_launch_s = sec / launches
     blocks_per_launch = philox_blocks_per_step(wl.rails, wl.sites) * args.steps / launches
     achieved = OPS_PER_PHILOX_BLOCK * blocks_per_launch / per_launch_s / 1e12
-    traffic = None
-    if mode == "persistent":
-        t = measured_traffic()
-        if t is not None and t.get("kernel_sha1") == kernel_sha1():
-            traffic = t["hbm_bytes_per_launch"]
+    t = measured_traffic(kernel)
+    traffic = t["hbm_bytes_per_launch"] if t is not None else None
     out = {
         "metric": "site-updates/s (4096x1024 rails)",
         "value": value,
@@ -207,7 +211,7 @@ def bench_batch(args):
     mode = sim.launch_mode
     value = wl.n_sites * steps / sec
     chunks = (steps + 1023) // 1024
-    launches = chunks * sim.n_groups if mode == "persistent" else 2 * steps
+    launches = chunks * sim.n_groups if mode in ("persistent", "wave") else 2 * steps
     per_launch_s = sec / launches
     achieved = OPS_PER_PHILOX_BLOCK * philox_blocks_per_step(wl.rails, wl.sites) * steps / sec / 1e12
     out = {
@@ -217,7 +221,8 @@ def bench_batch(args):
         "config": {"workload": wl.name, "devices": len(wl.rails), "sites_total": wl.n_sites,
                    "launch_mode": mode, "groups": sim.n_groups},
         "effective_hbm_gbs": BYTES_PER_SITE_UPDATE / 5 * 2 * value / 1e9,
-        "roofline": {"bound": "alu", "kernel": "hop_persistent" if mode == "persistent" else "hop_half_step",
+        "roofline": {"bound": "alu",
+                     "kernel": {"persistent": "hop_persistent", "wave": "hop_wave"}.get(mode, "hop_half_step"),
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                      "avg_launch_us": per_launch_s * 1e6, "launches": launches},
