@@ -227,8 +227,25 @@ def bench_batch(args):
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                      "avg_launch_us": per_launch_s * 1e6, "launches": launches},
     }
-    print(json.dumps(out), flush=True)
     sim.close()
+    # the same devices run one by one, each alone in its own context (every
+    # 8th device), for the batched-versus-plain comparison
+    sample = list(range(0, len(wl.rails), 8))
+    k_one, t_one, sites_one = 1024, 0.0, 0
+    for d in sample:
+        one = kmc.Simulator(wl.physics, [wl.rails[d]], [wl.sites[d]], device="cuda:0")
+        one.fill_random([wl.filling[d]])
+        one.set_protocols([wl.protocols[d]])
+        one.run_steps(128)
+        t_one += _timed(lambda: one.run_steps(k_one), stream)
+        one.read_current()
+        sites_one += wl.rails[d] * wl.sites[d]
+        one.close()
+    out["one_by_one_site_updates_per_s"] = sites_one * k_one / t_one
+    out["batched_over_one_by_one"] = value / out["one_by_one_site_updates_per_s"]
+    out["one_by_one_sample"] = (f"{len(sample)} devices (every 8th, {sites_one} sites), each alone for {k_one} "
+                                f"steps after 128 warm-up steps, automatic launch mode")
+    print(json.dumps(out), flush=True)
 
 
 def bench_gradient(args):
@@ -326,8 +343,22 @@ def bench_dense(args):
                      "unit": "TFLOP/s", "frac": achieved / BF16_DENSE_PEAK_TFLOPS, "traffic": None,
                      "avg_launch_us": t_phi * 1e6, "flop_per_launch": flops},
     }
-    print(json.dumps(out), flush=True)
     sim.close()
+    # the same lattice and physics as the plain binary32 step (per-candidate
+    # window sums behind the exact prefilter, no potential), a few steps
+    from workloads import FP32
+    plain = kmc.Simulator(wl.physics.replace(precision=FP32), wl.rails, wl.sites, device="cuda:0")
+    plain.fill_random(wl.filling)
+    plain.set_protocols(wl.protocols)
+    plain.run_steps(2)
+    k_plain = 20
+    t_plain = _timed(lambda: plain.run_steps(k_plain), stream)
+    plain.read_current()
+    out["plain_fp32_site_updates_per_s"] = wl.n_sites * k_plain / t_plain
+    out["dense_over_plain_fp32"] = value / out["plain_fp32_site_updates_per_s"]
+    out["plain_fp32_launch_mode"] = plain.launch_mode
+    plain.close()
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -237,8 +237,8 @@ kmc_status kmc_set_persistent_group_limit(kmc_ctx *ctx, int32_t max_tiles);
 
 /* Target number of (padded) sites per workgroup tile, 0 = built-in default,
  * else in [16, 65536]; tiles are whole rails.  For KMC_LAUNCH_WAVE, 1024 and
- * 2048 select 16 and 32 sites per lane (other values: 16 when every rail has
- * at most 1024 padded sites, else 32).  Used by the autotuner.  Waits for the
+ * 2048 select 16 and 32 sites per lane (other values: 16 when that tiling
+ * exists, else 32).  Used by the autotuner.  Waits for the
  * work already enqueued.  Trajectories do not depend on it. */
 kmc_status kmc_set_tile_sites(kmc_ctx *ctx, int32_t sites);
 

@@ -435,39 +435,51 @@ void make_ptiles(kmc_ctx *c) {
 // Wave tiling: every device cut into n_t >= 1 tiles of consecutive rails that
 // fit one wavefront (rails x lanes per rail <= 64), sizes within one rail of
 // each other and at least max(rail_range, 1) rails unless the device is a
-// single tile.  Sites per lane: 16 when every rail fits 64 lanes that way,
-// else 32; tile_sites 1024 or 2048 asks for 16 or 32.
-void make_wtiles(kmc_ctx *c) {
+// single tile.  Sites per lane: 16 when that tiling exists, else 32;
+// tile_sites 1024 or 2048 asks for 16 or 32.  False if the tiling with spl
+// sites per lane does not exist.
+bool wave_tiles_for(kmc_ctx *c, int spl) {
     c->wtiles.clear();
-    c->wgroups.clear();
-    c->w_ok = false;
-    if (c->dense) return;
     const int m = c->p.rail_range, mm = std::max(m, 1);
-    int max_pitch = 0;
-    for (const DevInfo &dv : c->devs) max_pitch = std::max(max_pitch, dv.pitch);
-    int spl = max_pitch <= 1024 ? 16 : 32;
-    if (c->tile_sites == 1024) spl = 16;
-    if (c->tile_sites == 2048) spl = 32;
-    c->w_spl = spl;
     for (int d = 0; d < c->p.n_devices; ++d) {
         const DevInfo &dv = c->devs[d];
         const WaveGeom g = wave_geom(dv.pitch, spl);
-        if (g.nr_max < 1) return;
+        if (g.nr_max < 1) return false;
         const int n_t = (dv.rails + g.nr_max - 1) / g.nr_max;
-        if (n_t > 1 && dv.rails / n_t < mm) return;
+        if (n_t > 1 && dv.rails / n_t < mm) return false;
         const int w32 = (dv.pitch + 31) / 32;
-        if (n_t > 1 && 2 * m * w32 > wave_band_words(spl)) return;
+        if (n_t > 1 && 2 * m * w32 > wave_band_words(spl)) return false;
         const int first = (int)c->wtiles.size();
         const int base = dv.rails / n_t, extra = dv.rails % n_t;
         int r0 = 0;
         for (int i = 0; i < n_t; ++i) {
             const int nr = base + (i < extra ? 1 : 0);
-            if (kPubSlots + (int64_t)kSnapSlots * std::min(nr, 2 * m) * w32 > c->lay.wpub_stride) return;
+            if (kPubSlots + (int64_t)kSnapSlots * std::min(nr, 2 * m) * w32 > c->lay.wpub_stride) return false;
             const int prev = first + (i + n_t - 1) % n_t, next = first + (i + 1) % n_t;
             c->wtiles.push_back(PTile{d, r0, nr, prev, next, 0});
             r0 += nr;
         }
     }
+    return true;
+}
+
+void make_wtiles(kmc_ctx *c) {
+    c->wtiles.clear();
+    c->wgroups.clear();
+    c->w_ok = false;
+    if (c->dense) return;
+    int spl = 0;
+    if (c->tile_sites == 1024 || c->tile_sites == 2048) {
+        spl = c->tile_sites / 64;
+        if (!wave_tiles_for(c, spl)) return;
+    } else if (wave_tiles_for(c, 16)) {
+        spl = 16;
+    } else if (wave_tiles_for(c, 32)) {
+        spl = 32;
+    } else {
+        return;
+    }
+    c->w_spl = spl;
     const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
     c->w_lds = wave_lds_bytes(spl, (int)n_kt, c->fp64);
     int per_cu = 0, dev = 0;

@@ -92,7 +92,8 @@ def test_ragged_multi_device_with_barrier_field(precision, mode, tile):
 @pytest.mark.parametrize("mode,tile", MODES)
 @pytest.mark.parametrize("R,L,m,cut,lam", [
     (1, 64, 1, 16, 4.0), (2, 50, 1, 16, 4.0), (3, 40, 2, 8, 4.0), (17, 96, 0, 16, 4.0),
-    (12, 64, 4, 63, 0.0), (5, 33, 3, 5, 2.0), (40, 48, 2, 16, 4.0), (24, 160, 4, 30, 0.0)])
+    (12, 64, 4, 63, 0.0), (5, 33, 3, 5, 2.0), (40, 48, 2, 16, 4.0), (24, 160, 4, 30, 0.0),
+    (16, 500, 4, 40, 0.0)])
 def test_interaction_variants(R, L, m, cut, lam, mode, tile):
     ph = Physics(precision=FP64, seed=5, ea_ev=0.12, coulomb_kappa_v=0.04, screening_sites=lam,
                  cutoff_sites=cut, rail_range=m)
