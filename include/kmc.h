@@ -230,8 +230,11 @@ kmc_status kmc_get_launch_mode(kmc_ctx *ctx, int32_t *mode);
  * are co-resident on the GPU (0 for HALF_STEP). */
 kmc_status kmc_get_persistent_groups(kmc_ctx *ctx, int32_t *groups);
 
-/* Cap the number of workgroup tiles of one persistent launch (0 = as many as
- * are co-resident), for example to leave room for other work on the GPU.
+/* Cap the number of tiles of one persistent launch (0 = as many as are
+ * co-resident): workgroups of KMC_LAUNCH_PERSISTENT, wavefronts of
+ * KMC_LAUNCH_WAVE.  For example to leave room for other work on the GPU.  A
+ * strategy under which one device no longer fits a launch becomes
+ * unavailable, and a mode that selected it falls back to KMC_LAUNCH_AUTO.
  * Waits for the work already enqueued.  Trajectories do not depend on it. */
 kmc_status kmc_set_persistent_group_limit(kmc_ctx *ctx, int32_t max_tiles);
 
