@@ -40,10 +40,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent", "wave"])
     ap.add_argument("--tile-sites", type=int, default=0)
-    ap.add_argument("--workload", default="large-device", choices=["large-device", "batch", "gradient", "dense"],
+    ap.add_argument("--workload", default="large-device",
+                    choices=["large-device", "batch", "gradient", "dense", "small-fp64"],
                     help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
                          "gradient: forward + score replay of 512 replicas x 256 x 512; "
-                         "dense: 64 replicas x 1024 x 512 with the MFMA long-range potential")
+                         "dense: 64 replicas x 1024 x 512 with the MFMA long-range potential; "
+                         "small-fp64: 64 x 128 in binary64 (latency)")
     return ap.parse_args()
 
 
@@ -112,6 +114,8 @@ def main():
         return bench_gradient(args)
     if args.workload == "dense":
         return bench_dense(args)
+    if args.workload == "small-fp64":
+        return bench_small(args)
     import torch
     import paper_2511_09413_amd as kmc
     from workloads import c2_large_device
@@ -246,6 +250,35 @@ def bench_batch(args):
     out["one_by_one_sample"] = (f"{len(sample)} devices (every 8th, {sites_one} sites), each alone for {k_one} "
                                 f"steps after 128 warm-up steps, automatic launch mode")
     print(json.dumps(out), flush=True)
+
+
+def bench_small(args):
+    """64 x 128 in binary64, 20% filling, 0.5 V: a lattice far too small to
+    fill the GPU, so the step time is the latency of the step."""
+    import torch
+    import paper_2511_09413_amd as kmc
+    from workloads import c1_plain_fp64
+    steps = args.steps if args.steps != 100_000 else 10_000
+    wl = c1_plain_fp64(n_steps=10_000)
+    sim = kmc.Simulator(wl.physics, wl.rails, wl.sites, device="cuda:0", mode=args.mode,
+                        tile_sites=args.tile_sites)
+    sim.fill_random(wl.filling)
+    sim.set_protocols(wl.protocols)
+    sim.run_steps(min(args.warmup, 1024))
+    stream = torch.cuda.current_stream()
+    sec = _timed(lambda: sim.run_steps(steps), stream)
+    sim.read_current()
+    value = wl.n_sites * steps / sec
+    out = {
+        "metric": "us per step (64x128, binary64)", "value": sec * 1e6 / steps, "unit": "us/step", "n_gpus": 1,
+        "steps": steps, "warmup": min(args.warmup, 1024), "ms_per_step": sec * 1e3 / steps,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "fp64", "data": "synthetic",
+        "config": {"workload": wl.name, "rails": 64, "sites": 128, "launch_mode": sim.launch_mode,
+                   "groups": sim.n_groups},
+        "site_updates_per_s": value,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
 
 
 def bench_gradient(args):
