@@ -2,15 +2,17 @@
 //
 // A tile is whole rails of one device that fit one wavefront: each lane owns
 // SPL (16 or 32) consecutive sites of a rail for the whole launch and keeps
-// their occupancy as bits in a register.  A half-step therefore needs neither
-// an LDS round trip nor a workgroup barrier: the bit past a lane's last site
-// comes from the next lane by a cross-lane move, the Philox words, the
-// candidate test and the exact prefilter stay in registers, and a wavefront
-// vote finds the rare half-steps with prefilter survivors.  Only those build
-// an LDS copy of the tile's bits (the Jacobi snapshot) and, when a survivor's
-// Coulomb window may cross the tile edge, fetch the neighbouring tiles' edge
-// rails.  The workgroup is only a container for kWaveTilesPerWG independent
-// tiles; its one barrier precedes the loop.
+// their occupancy as bits in a register, with the next lane's first bit (the
+// far end of its last bond) beside them, refreshed by a cross-lane move only
+// after half-steps that moved ions.  A half-step therefore needs neither an
+// LDS round trip nor a workgroup barrier: the Philox words, the candidate test
+// and the exact prefilter (against a per-lane bound from the lowest barrier
+// class of the lane's sites) stay in registers, and a wavefront vote finds the
+// rare half-steps with prefilter survivors.  Only those build an LDS copy of
+// the tile's bits (the Jacobi snapshot) and, when a survivor's Coulomb window
+// may cross the tile edge, fetch the neighbouring tiles' edge rails.  The
+// workgroup is only a container for kWaveTilesPerWG independent tiles; its one
+// barrier precedes the loop.
 //
 // Cross-tile data.  After every half-step a tile stores one 64-bit word for
 // the new state into its per-state array: a tag naming the state (launch
@@ -261,8 +263,8 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         // s0 + SPL) has a class >= q_lo, so every exact threshold is at most
         // rho (thr0 + 1) + 2^32 2e-6 with rho = A(q_lo) / A(0); r_lane =
         // ceil(rho 2^32), and the per-step bound is min(thr0, mulhi(thr0,
-        // r_lane) + 8600) (the margin covers the widening term, both
-        // ceilings and binary64 rounding).
+        // r_lane) + 8600), the addition saturating (the margin covers the
+        // widening term, both ceilings and binary64 rounding).
         if (has && last >= 0) {
             int q_lo = kClasses;
             const int s_hi = s0 + SPL < L - 1 ? s0 + SPL : L - 1;
@@ -377,9 +379,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         // class; stage 1 (rare): each candidate's word against its origin's
         // exact class threshold
         const uint32_t thr0 = (uint32_t)__builtin_amdgcn_readlane((int)thr_lane, kw);
-        uint32_t t_lane = __umulhi(thr0, r_lane);
-        t_lane = t_lane < 0xFFFF0000u ? t_lane + 8600u : 0xFFFFFFFFu;
-        t_lane = min(thr0, t_lane);
+        const uint32_t t_lane = min(thr0, __builtin_elementwise_add_sat(__umulhi(thr0, r_lane), 8600u));
         const uint32_t mn = min_word<0>(wd);
         uint32_t sv = 0;
         if (mn <= t_lane && cand != 0u) {
