@@ -208,6 +208,9 @@ def bench_batch(args):
                         tile_sites=args.tile_sites)
     sim.fill_random(wl.filling)
     sim.set_protocols(wl.protocols)
+    # the autotuner picks strategy and tile size (trials restore the state)
+    # unless a mode or tile size was asked for
+    tuned = sim.autotune(trial_steps=256) if args.mode == "auto" and args.tile_sites == 0 else None
     sim.run_steps(args.warmup)
     stream = torch.cuda.current_stream()
     sec = _timed(lambda: sim.run_steps(steps), stream)
@@ -223,7 +226,8 @@ def bench_batch(args):
         "steps": steps, "warmup": args.warmup, "ms_per_step": sec * 1e3 / steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": wl.name, "devices": len(wl.rails), "sites_total": wl.n_sites,
-                   "launch_mode": mode, "groups": sim.n_groups},
+                   "launch_mode": mode, "groups": sim.n_groups,
+                   "autotuned": None if tuned is None else {k: tuned[k] for k in ("tile_sites", "mode", "us_per_step")}},
         "effective_hbm_gbs": BYTES_PER_SITE_UPDATE / 5 * 2 * value / 1e9,
         "roofline": {"bound": "alu",
                      "kernel": {"persistent": "hop_persistent", "wave": "hop_wave"}.get(mode, "hop_half_step"),
