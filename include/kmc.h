@@ -238,6 +238,14 @@ kmc_status kmc_get_persistent_groups(kmc_ctx *ctx, int32_t *groups);
  * Waits for the work already enqueued.  Trajectories do not depend on it. */
 kmc_status kmc_set_persistent_group_limit(kmc_ctx *ctx, int32_t max_tiles);
 
+/* Polls before a neighbour wait of a persistent strategy is declared hung
+ * (default 2^20, about a second); 0 makes every wait fail at once.  A wait
+ * declared hung stops the launch cleanly: every tile leaves its loop, the
+ * kernel ends, and the next read_* call returns KMC_EHIP and poisons the
+ * context (the state is invalid).  For tests of that path and for callers
+ * that prefer a shorter bound.  Takes effect for launches enqueued after it. */
+kmc_status kmc_set_wait_limit(kmc_ctx *ctx, int32_t polls);
+
 /* Target number of (padded) sites per workgroup tile, 0 = built-in default,
  * else in [16, 65536]; tiles are whole rails.  For KMC_LAUNCH_WAVE, 1024 and
  * 2048 select 16 and 32 sites per lane (other values: 16 when that tiling

@@ -69,6 +69,7 @@ def lib():
         L.kmc_score_replay.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
         L.kmc_get_persistent_groups.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
+        L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
         L.kmc_dense_potential.argtypes = [vp, vp]
         L.kmc_autotune.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)]
         L.kmc_last_error.restype = C.c_char_p
@@ -78,7 +79,7 @@ def lib():
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
-                     "kmc_set_persistent_group_limit", "kmc_dense_potential",
+                     "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential",
                      "kmc_autotune"):
             getattr(L, name).restype = C.c_int
         _LIB = L
@@ -324,6 +325,11 @@ class Simulator:
         desc = repr((self.rails, self.sites, ph.precision, ph.rail_range, ph.cutoff_sites, ph.screening_sites,
                      gpu, self.ea is not None))
         return hashlib.sha1(desc.encode()).hexdigest()
+
+    def set_wait_limit(self, polls: int) -> None:
+        """Polls before a persistent kernel's neighbour wait is declared hung
+        (kmc_set_wait_limit; 0: every wait fails at once)."""
+        _check(lib().kmc_set_wait_limit(C.c_void_p(self.ctx), polls))
 
     def set_group_limit(self, max_tiles: int) -> None:
         """At most max_tiles workgroup tiles per persistent launch (0 = what fits)."""

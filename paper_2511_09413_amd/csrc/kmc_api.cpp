@@ -273,6 +273,7 @@ struct kmc_ctx {
     int8_t *cur = nullptr, *nxt = nullptr;
     int tile_sites = 0;                // target padded sites per tile (0 = default)
     int group_limit = 0;               // max tiles per persistent launch (0 = what fits)
+    int spin_limit = 1 << 20;          // polls before a neighbour wait is declared hung
     std::vector<PTile> ptiles;         // persistent tiling (prev/next relative to the tile's group)
     std::vector<std::pair<int, int>> pgroups;  // (first tile, tiles): devices run together in one launch
     int p_block = 0;
@@ -616,6 +617,7 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.pub_stride = wave ? c->lay.wpub_stride : c->lay.pub_stride;
         pa.max_pitch = c->lay.max_pitch;
         pa.status = c->at<int32_t>(c->lay.status);
+        pa.spin_limit = c->spin_limit;
     }
     int64_t done = 0;
     while (done < n_steps) {
@@ -1195,6 +1197,14 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
     if (tile_sites) *tile_sites = pick.tile;
     if (mode) *mode = pick.mode;
     if (us_per_step) *us_per_step = best;
+    return KMC_OK;
+}
+
+kmc_status kmc_set_wait_limit(kmc_ctx *c, int32_t polls) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (polls < 0) return fail(KMC_EINVAL, "polls must be >= 0");
+    c->spin_limit = polls;
     return KMC_OK;
 }
 

@@ -145,6 +145,7 @@ struct PArgs {
     int32_t n_steps;
     int32_t max_nr;            // largest tile (LDS sizing)
     int32_t *status;           // nonzero: a neighbour wait timed out
+    int32_t spin_limit;        // polls before a neighbour wait is declared hung (0: at once)
 };
 
 }  // namespace kmc

@@ -31,7 +31,6 @@
 
 namespace kmc {
 
-constexpr int kSpinLimit = 1 << 20;  // about a second of polling
 constexpr int kStepWin = 128;        // steps of the per-step tables held in LDS
 
 struct PShared {
@@ -175,15 +174,15 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         const uint64_t *w = a.pub + (int64_t)t * a.pub_stride + (j - j0) * slot_words + i;
         const uint32_t want = pub_tag(epoch, j - j0);
         for (int spins = 0;; ++spins) {
+            if (spins >= a.spin_limit) {  // declared hung (at once for a limit of 0)
+                __hip_atomic_store(a.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
             const uint64_t v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t tag = (uint32_t)(v >> 32);
             if (tag == want) {
                 *out = v;
                 return true;
-            }
-            if (spins > kSpinLimit) {
-                __hip_atomic_store(a.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                return false;
             }
             if (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
             __builtin_amdgcn_s_sleep(2);

@@ -41,7 +41,6 @@ namespace kmc {
 
 namespace {
 
-constexpr int kWaveSpin = 1 << 20;   // polls before a wait is declared hung
 constexpr int kWaveWin = 64;         // per-step table entries: one per lane
 
 // Values of a tile that only the rare paths need.  They live in LDS and are
@@ -83,18 +82,19 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 
-// Poll a published word until its tag is `want` (stored in *out); false on
-// time-out (raising the status flag) or once another tile has raised it.
-__device__ __forceinline__ bool poll_tag(const uint64_t *p, uint32_t want, int32_t *status, uint64_t *out) {
+// Poll a published word until its tag is `want` (stored in *out); false after
+// `limit` polls (raising the status flag; at once for a limit of 0) or once
+// another tile has raised it.
+__device__ __forceinline__ bool poll_tag(const uint64_t *p, uint32_t want, int32_t *status, int limit, uint64_t *out) {
     for (int spins = 0;; ++spins) {
+        if (spins >= limit) {
+            __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
         const uint64_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if ((uint32_t)(v >> 32) == want) {
             *out = v;
             return true;
-        }
-        if (spins > kWaveSpin) {
-            __hip_atomic_store(status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
         }
         if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
         __builtin_amdgcn_s_sleep(2);
@@ -325,6 +325,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         uint64_t *pub = ka->pub;
         const int64_t stride = ka->pub_stride;
         int32_t *status = ka->status;
+        const int limit = ka->spin_limit;
         bool ok = true;
         for (int idx = 0; idx < 2 * mm; ++idx) {
             const int T = idx < mm ? prev : next;
@@ -335,12 +336,12 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             const uint64_t *base = pub + (int64_t)T * stride;
             for (int q = lane; q < w32; q += 64) {
                 uint64_t st = 0, v = 0;
-                if (ok) ok = poll_tag(base + jrel, tag_hi | (uint32_t)jrel, status, &st);
+                if (ok) ok = poll_tag(base + jrel, tag_hi | (uint32_t)jrel, status, limit, &st);
                 if (ok) {
                     const int slot = (int)((uint32_t)st >> 12);
                     const uint32_t snap_rel = (uint32_t)st & 0xFFFu;
                     ok = poll_tag(base + kPubSlots + (int64_t)slot * (eT * w32) + sr * w32 + q, tag_hi | snap_rel,
-                                  status, &v);
+                                  status, limit, &v);
                 }
                 wr.band[idx * w32 + q] = (uint32_t)v;
             }
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                     if (lane < 2) {
                         const int T = lane == 0 ? rfl(wr.geo.prev) : rfl(wr.geo.next);
                         uint64_t v = 0;
-                        ok = poll_tag(ka->pub + (int64_t)T * ka->pub_stride + need, tag_hi | need, ka->status, &v);
+                        ok = poll_tag(ka->pub + (int64_t)T * ka->pub_stride + need, tag_hi | need, ka->status, ka->spin_limit, &v);
                     }
                     if (__ballot(!ok)) break;
                 }

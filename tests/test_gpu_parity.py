@@ -204,3 +204,27 @@ def test_wave_snapshot_ring_wraps_under_many_hops(tile):
     st, sim = _run_parity(wl, 1100, 550, mode="wave", tile_sites=tile)
     assert sim.launch_mode == "wave"
     assert st["hops"] > 2000
+
+
+@pytest.mark.parametrize("mode,tile", [("persistent", 512), ("wave", 0)])
+def test_neighbour_wait_failure_is_reported(mode, tile):
+    """A neighbour wait declared hung (the wait limit set to 0 from the host, so
+    every wait fails at once) ends the launch cleanly and the next read reports
+    it; a new context then runs normally and follows the oracle."""
+    from paper_2511_09413_amd import KMC_EHIP, KmcError
+    wl = c1_plain_fp64()
+    ph = wl.physics.replace(ea_ev=0.15)   # many hops: survivors at tile edges in every step
+    sim = _sim(ph, wl.rails, wl.sites, mode=mode, tile_sites=tile)
+    assert sim.launch_mode == mode
+    p_or = oracle.OracleParams(ph, wl.rails, wl.sites)
+    occ0 = oracle.fill(p_or, wl.filling)
+    sim.load_occupancy(occ0)
+    sim.set_protocols(wl.protocols)
+    sim.set_wait_limit(0)
+    sim.run_steps(50)
+    with pytest.raises(KmcError) as err:
+        sim.read_current()
+    assert err.value.status == KMC_EHIP and "timed out" in str(err.value)
+    sim.close()
+    st, _ = _run_parity(wl, 40, 40, occ0=occ0, phys=ph, mode=mode, tile_sites=tile)
+    assert st["steps"] == 40
