@@ -72,7 +72,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
-        net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, progress, pub, status,
+        net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
         rp_a, rp_b, score_log, dtab64, dtab32, phi, ktiles, dtiles, ctiles, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
@@ -176,8 +176,7 @@ Layout layout_for(const kmc_params *p) {
     L.rail_dev = take(sizeof(int32_t) * (size_t)rails);
     L.rail_idx = take(sizeof(int32_t) * (size_t)rails);
     L.n_ions = take(sizeof(int32_t) * D);
-    // persistent kernel: tiles, progress counters (one cache line each) and the
-    // edge-rail publications (a slot per state of a launch)
+    // persistent kernels: tiles and the edge-rail publications
     int max_pitch = 0;
     for (int d = 0; d < D; ++d) max_pitch = std::max(max_pitch, (p->sites[d] + kChunkSites - 1) / kChunkSites * kChunkSites);
     L.max_pitch = max_pitch;
@@ -193,7 +192,6 @@ Layout layout_for(const kmc_params *p) {
     L.max_ptiles = std::min<int64_t>(std::min<int64_t>(std::min<int64_t>(kMaxPTiles, rails), pub_cap),
                                      std::max<int64_t>(2 * default_tiles, 64));
     L.ptiles = take(sizeof(PTile) * (size_t)rails);  // every tile is at least one rail
-    L.progress = take(sizeof(uint64_t) * 8 * (size_t)L.max_ptiles);
     // wave kernel: per tile one word per state of a launch plus a ring of
     // edge-rail snapshots; tiles of one launch bounded by kMaxWaveTiles
     {
@@ -612,7 +610,6 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.tally_dec = a.tally_dec;
         pa.n_devices = D;
         pa.log = a.log;
-        pa.progress = c->at<uint64_t>(c->lay.progress);
         pa.pub = c->at<uint64_t>(c->lay.pub);
         pa.pub_stride = wave ? c->lay.wpub_stride : c->lay.pub_stride;
         pa.max_pitch = c->lay.max_pitch;
@@ -873,7 +870,6 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i32(c->at<int32_t>(lay.tally_dec), (int64_t)kTallySteps * D * kDeciles, st), "zero tallies");
     chk(launch_zero_i64(c->at<int64_t>(lay.net_total), D, st), "zero totals");
     chk(launch_zero_i64(c->at<int64_t>(lay.log_count), 1, st), "zero log");
-    chk(launch_zero_i64(c->at<int64_t>(lay.progress), 8 * lay.max_ptiles, st), "zero progress counters");
     chk(launch_zero_i64(c->at<int64_t>(lay.pub), pub_words(lay), st), "zero publication ring");
     chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
     chk(set_hop_lds_limit(c->hop_lds, c->score_lds), "LDS limit of the hop kernel");

@@ -137,7 +137,6 @@ struct PArgs {
     int32_t *tally_dec;
     int32_t n_devices;
     HopArgs::LogBuf log;
-    uint64_t *progress;        // [n_tiles * 8]: (epoch << 40) | half-steps completed
     uint64_t *pub;             // edge-rail publications, pub_stride words per tile, one slot per state
     int64_t pub_stride;        // kPubSlots * 2m * ceil(max_pitch / 32) words per tile
     int32_t max_pitch;

@@ -138,8 +138,8 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
 
     // The edge rails of `state` as state j (no wait: tags validate the data).
     // The stores are issued by the last wavefronts: on gfx950 one counter
-    // tracks a wavefront's loads and stores, so a wavefront that later waits
-    // for a load (thread 0's progress probes) must not have stores in flight.
+    // tracks a wavefront's loads and stores, so the first wavefronts, which
+    // load the per-step tables, never wait for publication stores.
     const int pub_first = bdim - ((slot_words + 63) / 64) * 64;
     // word i of a slot: 32 bits of edge rail i / W32 (the first m rails, then
     // the last m); when the last wavefronts have a lane per word, each lane's
