@@ -612,7 +612,6 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.log = a.log;
         pa.pub = c->at<uint64_t>(c->lay.pub);
         pa.pub_stride = wave ? c->lay.wpub_stride : c->lay.pub_stride;
-        pa.max_pitch = c->lay.max_pitch;
         pa.status = c->at<int32_t>(c->lay.status);
         pa.spin_limit = c->spin_limit;
     }

@@ -137,12 +137,11 @@ struct PArgs {
     int32_t *tally_dec;
     int32_t n_devices;
     HopArgs::LogBuf log;
-    uint64_t *pub;             // edge-rail publications, pub_stride words per tile, one slot per state
-    int64_t pub_stride;        // kPubSlots * 2m * ceil(max_pitch / 32) words per tile
-    int32_t max_pitch;
+    uint64_t *pub;             // edge-rail publications, pub_stride words per tile
+    int64_t pub_stride;        // block tiles: a slot per state; wave tiles: a word per state, then
+                               // the snapshot ring
     uint64_t epoch;
     int32_t n_steps;
-    int32_t max_nr;            // largest tile (LDS sizing)
     int32_t *status;           // nonzero: a neighbour wait timed out
     int32_t spin_limit;        // polls before a neighbour wait is declared hung (0: at once)
 };
