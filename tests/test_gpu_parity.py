@@ -228,3 +228,39 @@ def test_neighbour_wait_failure_is_reported(mode, tile):
     sim.close()
     st, _ = _run_parity(wl, 40, 40, occ0=occ0, phys=ph, mode=mode, tile_sites=tile)
     assert st["steps"] == 40
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_wave_random_geometries(seed):
+    """Seeded random lattices for the wave strategy: rail counts 1..40, sites
+    2..2016 (pitches that are and are not multiples of 32), rail ranges 0..4,
+    cutoffs 0..40, screened and unscreened, both precisions, 16 or 32 sites per
+    lane; 60 steps in lockstep with the oracle.  Geometries the wave tiling
+    cannot hold are skipped."""
+    from paper_2511_09413_amd import KmcError, KMC_EUNSUPPORTED
+    g = np.random.default_rng(1000 + seed)
+    n_dev = int(g.integers(1, 4))
+    m = int(g.integers(0, 5))
+    l_max = 32 * (64 // max(m, 1)) - 32     # rails of this length fit the tiling at 32 sites per lane
+    rails = [int(g.integers(1, 41)) for _ in range(n_dev)]
+    sites = [int(g.integers(2, l_max + 1)) for _ in range(n_dev)]
+    cut = int(g.integers(0, 41))
+    lam = float(g.choice([0.0, 2.0, 4.0]))
+    precision = FP64 if seed % 2 == 0 else FP32
+    tile = [0, 2048][seed % 3 == 0]
+    ph = Physics(precision=precision, seed=seed, ea_ev=0.13, coulomb_kappa_v=0.04, screening_sites=lam,
+                 cutoff_sites=cut, rail_range=m)
+    fill = [float(g.uniform(0.05, 0.6)) for _ in range(n_dev)]
+    protos = [triangle(2.0, 120e-12), constant(-0.8), step_then_relax(1.5, 30e-12)][:n_dev]
+    try:
+        sim = _sim(ph, rails, sites, mode="wave", tile_sites=tile)
+    except KmcError as e:
+        if e.status != KMC_EUNSUPPORTED:
+            raise
+        pytest.skip(f"the wave tiling does not hold {rails} x {sites} with rail range {m}")
+    p_or = oracle.OracleParams(ph, rails, sites)
+    occ0 = oracle.fill(p_or, fill)
+    sim.load_occupancy(occ0)
+    sim.set_protocols(protos)
+    st = lockstep(sim, p_or, protos, occ0, 60, 30)
+    assert sim.launch_mode == "wave" and st["steps"] == 60
