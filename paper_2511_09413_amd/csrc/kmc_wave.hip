@@ -123,19 +123,92 @@ __device__ __forceinline__ int64_t rfl(int64_t v) {
 }
 __device__ __forceinline__ double rfl(double v) { return __longlong_as_double(rfl((int64_t)__double_as_longlong(v))); }
 
-// The lane's Philox words live in registers: every access below uses a
-// compile-time index (template recursion), never a runtime one, so the words
-// are never placed in scratch memory.
-template <int K, int N>
-__device__ __forceinline__ void draw_words(uint32_t (&wd)[N], uint32_t blk0, uint32_t rail, uint32_t n, uint32_t c3,
-                                           uint32_t k0, uint32_t k1) {
-    if constexpr (K < N / 4) {
-        const uint4 x = philox4x32_10(blk0 + (uint32_t)K, rail, n, c3, k0, k1);
-        wd[4 * K + 0] = x.x;
-        wd[4 * K + 1] = x.y;
-        wd[4 * K + 2] = x.z;
-        wd[4 * K + 3] = x.w;
-        draw_words<K + 1>(wd, blk0, rail, n, c3, k0, k1);
+// Philox4x32-10 of the hop words, counter (blk, rail, n, c3), key (k0, k1),
+// with its first rounds split by how often their inputs change: blk and rail
+// are fixed per lane, c3 = d << 4 | h takes one value per half-step parity, n
+// one value per step.  Round i uses the keys k0 + i W0 and k1 + i W1.
+//   PhLane (once per launch): what depends on blk and c3 only, for both
+//     parities: round 0's product M0 blk and round 1's product M1 x2.
+//   PhStep (once per step, shared by both half-steps): round 0's product
+//     M1 n, round 1's product M0 x0 and round 2's product M1 x2 (x2 after
+//     round 1 does not depend on the parity).
+//   ph_words (each half-step): the rest of rounds 1 and 2, then rounds 3 to 9.
+// The words equal philox4x32_10(blk, rail, n, c3, k0, k1).  Every array index
+// below is a compile-time constant (template recursion), so the values stay
+// in registers.
+constexpr uint32_t kPhM0 = 0xD2511F53u, kPhM1 = 0xCD9E8D57u, kPhW0 = 0x9E3779B9u, kPhW1 = 0xBB67AE85u;
+
+template <int NB>
+struct PhLane {
+    uint32_t p[2][NB];  // [h][block] hi(M1 x2) ^ (k0 + W0), x2 = hi(M0 blk) ^ c3 ^ k1 after round 0
+    uint32_t q[2][NB];  // [h][block] lo(M1 x2): word x1 after round 1
+    uint32_t r[NB];     // lo(M0 blk) ^ (k1 + W1)
+};
+template <int NB>
+struct PhStep {
+    uint32_t lo_b0;      // lo(M1 n): word x1 after round 0
+    uint32_t lo_a1;      // lo(M0 x0) of round 1: word x3 after round 1
+    uint32_t hi_b2[NB];  // M1 x2 of round 2, per block
+    uint32_t lo_b2[NB];
+};
+
+template <int K, int NB>
+__device__ __forceinline__ void ph_lane_init(PhLane<NB> &pl, uint32_t blk0, uint32_t c3, uint32_t k0, uint32_t k1) {
+    if constexpr (K < NB) {
+        const uint64_t a0 = (uint64_t)kPhM0 * (blk0 + (uint32_t)K);
+        const uint64_t b_even = (uint64_t)kPhM1 * ((uint32_t)(a0 >> 32) ^ c3 ^ k1);
+        const uint64_t b_odd = (uint64_t)kPhM1 * ((uint32_t)(a0 >> 32) ^ (c3 | 1u) ^ k1);
+        pl.p[0][K] = (uint32_t)(b_even >> 32) ^ (k0 + kPhW0);
+        pl.q[0][K] = (uint32_t)b_even;
+        pl.p[1][K] = (uint32_t)(b_odd >> 32) ^ (k0 + kPhW0);
+        pl.q[1][K] = (uint32_t)b_odd;
+        pl.r[K] = (uint32_t)a0 ^ (k1 + kPhW1);
+        ph_lane_init<K + 1>(pl, blk0, c3, k0, k1);
+    }
+}
+template <int K, int NB>
+__device__ __forceinline__ void ph_step_blocks(PhStep<NB> &ps, const PhLane<NB> &pl, uint32_t hi_a1) {
+    if constexpr (K < NB) {
+        const uint64_t b2 = (uint64_t)kPhM1 * (hi_a1 ^ pl.r[K]);
+        ps.hi_b2[K] = (uint32_t)(b2 >> 32);
+        ps.lo_b2[K] = (uint32_t)b2;
+        ph_step_blocks<K + 1>(ps, pl, hi_a1);
+    }
+}
+template <int NB>
+__device__ __forceinline__ void ph_step(PhStep<NB> &ps, const PhLane<NB> &pl, uint32_t rail, uint32_t n,
+                                        uint32_t k0) {
+    const uint64_t b0 = (uint64_t)kPhM1 * n;
+    const uint64_t a1 = (uint64_t)kPhM0 * ((uint32_t)(b0 >> 32) ^ k0 ^ rail);
+    ps.lo_b0 = (uint32_t)b0;
+    ps.lo_a1 = (uint32_t)a1;
+    ph_step_blocks<0>(ps, pl, (uint32_t)(a1 >> 32));
+}
+template <int H, int K, int N, int NB>
+__device__ __forceinline__ void ph_words(uint32_t (&wd)[N], const PhLane<NB> &pl, const PhStep<NB> &ps, uint32_t k0,
+                                         uint32_t k1) {
+    if constexpr (K < NB) {
+        const uint64_t a2 = (uint64_t)kPhM0 * (pl.p[H][K] ^ ps.lo_b0);
+        uint32_t x0 = xor3(ps.hi_b2[K], pl.q[H][K], k0 + 2u * kPhW0);
+        uint32_t x1 = ps.lo_b2[K];
+        uint32_t x2 = xor3((uint32_t)(a2 >> 32), ps.lo_a1, k1 + 2u * kPhW1);
+        uint32_t x3 = (uint32_t)a2;
+#pragma unroll
+        for (int round = 3; round < 10; ++round) {
+            const uint64_t m0 = (uint64_t)kPhM0 * x0;
+            const uint64_t m1 = (uint64_t)kPhM1 * x2;
+            const uint32_t y0 = xor3((uint32_t)(m1 >> 32), x1, k0 + (uint32_t)round * kPhW0);
+            const uint32_t y2 = xor3((uint32_t)(m0 >> 32), x3, k1 + (uint32_t)round * kPhW1);
+            x1 = (uint32_t)m1;
+            x3 = (uint32_t)m0;
+            x0 = y0;
+            x2 = y2;
+        }
+        wd[4 * K + 0] = x0;
+        wd[4 * K + 1] = x1;
+        wd[4 * K + 2] = x2;
+        wd[4 * K + 3] = x3;
+        ph_words<H, K + 1>(wd, pl, ps, k0, k1);
     }
 }
 template <int K, int N>
@@ -157,6 +230,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int kW = SPL / 2;          // Philox words per lane and half-step (SPL / 8 blocks):
                                          // word b / 2 belongs to the bond at site s0 + b
+    constexpr int kNB = SPL / 8;         // Philox blocks per lane and half-step
     constexpr uint32_t kAll = SPL == 32 ? 0xFFFFFFFFu : 0xFFFFu;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile data in scalar registers
@@ -273,8 +347,10 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             r_lane = q_lo == 0 ? 0xFFFFFFFFu : (uint32_t)fmin(ceil(rho * 4294967296.0), 4294967295.0);
         }
     }
+    PhLane<kNB> phl;
+    ph_lane_init<0>(phl, (uint32_t)(s0 >> 3), (uint32_t)d << 4, a.key0, a.key1);
     const uint32_t tag_hi = (uint32_t)(a.epoch & 0xFFFFFu) << 12;  // state tag = tag_hi | launch-relative state
-    const uint32_t n0 = (uint32_t)a.ctl->n_base;                   // Philox step word of the first step
+    const uint32_t n0 = (uint32_t)rfl((int)(uint32_t)a.ctl->n_base);  // Philox step word of the first step
 
     // Per-step tables of the window [kb, kb + 64): lane k holds step kb + k's
     // stage-0 threshold in a register, the bias and g go to LDS.
@@ -360,11 +436,13 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     }
 
     const uint32_t key0 = a.key0, key1 = a.key1;
-    for (int js = 0; js < 2 * a.n_steps; ++js) {
-        const int h = js & 1;  // the first state of a launch is even
-        const int kstep = js >> 1;
+    // One half-step of parity h (a compile-time constant): state js = 2 kstep
+    // + h to js + 1 (the first state of a launch is even).  False when a wait
+    // for a neighbour failed.
+    auto half_step = [&](auto h_c, const int kstep, const PhStep<kNB> &ps) -> bool {
+        constexpr int h = decltype(h_c)::value;
+        const int js = 2 * kstep + h;
         const int kw = kstep & (kWaveWin - 1);
-        if (h == 0 && kw == 0) refresh(kstep);
 
         // candidates: bonds of parity h whose two sites differ
         const uint32_t cand = (bits ^ ((bits >> 1) | (nbit << (SPL - 1)))) & (h ? 0xAAAAAAAAu : 0x55555555u) & valid;
@@ -373,9 +451,8 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         // round keys are derived on the scalar unit instead of being kept live
         uint32_t k0 = key0, k1 = key1;
         asm volatile("" : "+s"(k0), "+s"(k1));
-        const uint32_t ctr3 = ((uint32_t)d << 4) | (uint32_t)h;
         uint32_t wd[kW];
-        draw_words<0>(wd, (uint32_t)(s0 >> 3), rail, n0 + (uint32_t)kstep, ctr3, k0, k1);
+        ph_words<h, 0>(wd, phl, ps, k0, k1);
         // stage 0: the smallest word against the bound of the lane's lowest
         // class; stage 1 (rare): each candidate's word against its origin's
         // exact class threshold
@@ -422,7 +499,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             bool ok = true;
             if (!isolated) ok = fetch_bands(ka, wr, js);
             wave_sync();
-            if (!ok) break;
+            if (!ok) return false;
             uint32_t fl = 0;
             uint64_t rest = any;
             while (rest) {
@@ -517,7 +594,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                         uint64_t v = 0;
                         ok = poll_tag(ka->pub + (int64_t)T * ka->pub_stride + need, tag_hi | need, ka->status, ka->spin_limit, &v);
                     }
-                    if (__ballot(!ok)) break;
+                    if (__ballot(!ok)) return false;
                 }
                 write_snapshot(wr.geo, slot, jn);
                 if (lane == 0) wr.snap_state[slot] = (int16_t)jn;
@@ -527,6 +604,16 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                 __hip_atomic_store(own + jn, ((uint64_t)(tag_hi | jn) << 32) | snap_word, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         }
+        return true;
+    };
+    for (int kstep = 0; kstep < a.n_steps; ++kstep) {
+        if ((kstep & (kWaveWin - 1)) == 0) refresh(kstep);
+        uint32_t k0 = key0;
+        asm volatile("" : "+s"(k0));
+        PhStep<kNB> ps;
+        ph_step(ps, phl, rail, n0 + (uint32_t)kstep, k0);
+        if (!half_step(std::integral_constant<int, 0>{}, kstep, ps)) break;
+        if (!half_step(std::integral_constant<int, 1>{}, kstep, ps)) break;
     }
 
     // write the tile back
