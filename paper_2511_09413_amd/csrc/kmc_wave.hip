@@ -134,8 +134,8 @@ __device__ __forceinline__ double rfl(double v) { return __longlong_as_double(rf
 //     round 1 does not depend on the parity).
 //   ph_words (each half-step): the rest of rounds 1 and 2, then rounds 3 to 9.
 // The words equal philox4x32_10(blk, rail, n, c3, k0, k1).  Every array index
-// below is a compile-time constant (template recursion), so the values stay
-// in registers.
+// below is a compile-time constant (template recursion or fully unrolled
+// loops), so the values stay in registers.
 constexpr uint32_t kPhM0 = 0xD2511F53u, kPhM1 = 0xCD9E8D57u, kPhW0 = 0x9E3779B9u, kPhW1 = 0xBB67AE85u;
 
 template <int NB>
@@ -184,31 +184,45 @@ __device__ __forceinline__ void ph_step(PhStep<NB> &ps, const PhLane<NB> &pl, ui
     ps.lo_a1 = (uint32_t)a1;
     ph_step_blocks<0>(ps, pl, (uint32_t)(a1 >> 32));
 }
-template <int H, int K, int N, int NB>
+template <int H, int N, int NB>
 __device__ __forceinline__ void ph_words(uint32_t (&wd)[N], const PhLane<NB> &pl, const PhStep<NB> &ps, uint32_t k0,
                                          uint32_t k1) {
-    if constexpr (K < NB) {
-        const uint64_t a2 = (uint64_t)kPhM0 * (pl.p[H][K] ^ ps.lo_b0);
-        uint32_t x0 = xor3(ps.hi_b2[K], pl.q[H][K], k0 + 2u * kPhW0);
-        uint32_t x1 = ps.lo_b2[K];
-        uint32_t x2 = xor3((uint32_t)(a2 >> 32), ps.lo_a1, k1 + 2u * kPhW1);
-        uint32_t x3 = (uint32_t)a2;
+    // all blocks advance round by round; each round key is derived just before
+    // its round (the empty asm keeps the compiler from deriving them all at
+    // once and holding them in scalar registers)
+    uint32_t x0[NB], x1[NB], x2[NB], x3[NB];
+    uint32_t kr0 = k0 + 2u * kPhW0, kr1 = k1 + 2u * kPhW1;
 #pragma unroll
-        for (int round = 3; round < 10; ++round) {
-            const uint64_t m0 = (uint64_t)kPhM0 * x0;
-            const uint64_t m1 = (uint64_t)kPhM1 * x2;
-            const uint32_t y0 = xor3((uint32_t)(m1 >> 32), x1, k0 + (uint32_t)round * kPhW0);
-            const uint32_t y2 = xor3((uint32_t)(m0 >> 32), x3, k1 + (uint32_t)round * kPhW1);
-            x1 = (uint32_t)m1;
-            x3 = (uint32_t)m0;
-            x0 = y0;
-            x2 = y2;
+    for (int K = 0; K < NB; ++K) {
+        const uint64_t a2 = (uint64_t)kPhM0 * (pl.p[H][K] ^ ps.lo_b0);
+        x0[K] = xor3(ps.hi_b2[K], pl.q[H][K], kr0);
+        x1[K] = ps.lo_b2[K];
+        x2[K] = xor3((uint32_t)(a2 >> 32), ps.lo_a1, kr1);
+        x3[K] = (uint32_t)a2;
+    }
+#pragma unroll
+    for (int round = 3; round < 10; ++round) {
+        kr0 += kPhW0;
+        kr1 += kPhW1;
+        asm volatile("" : "+s"(kr0), "+s"(kr1));
+#pragma unroll
+        for (int K = 0; K < NB; ++K) {
+            const uint64_t m0 = (uint64_t)kPhM0 * x0[K];
+            const uint64_t m1 = (uint64_t)kPhM1 * x2[K];
+            const uint32_t y0 = xor3((uint32_t)(m1 >> 32), x1[K], kr0);
+            const uint32_t y2 = xor3((uint32_t)(m0 >> 32), x3[K], kr1);
+            x1[K] = (uint32_t)m1;
+            x3[K] = (uint32_t)m0;
+            x0[K] = y0;
+            x2[K] = y2;
         }
-        wd[4 * K + 0] = x0;
-        wd[4 * K + 1] = x1;
-        wd[4 * K + 2] = x2;
-        wd[4 * K + 3] = x3;
-        ph_words<H, K + 1>(wd, pl, ps, k0, k1);
+    }
+#pragma unroll
+    for (int K = 0; K < NB; ++K) {
+        wd[4 * K + 0] = x0[K];
+        wd[4 * K + 1] = x1[K];
+        wd[4 * K + 2] = x2[K];
+        wd[4 * K + 3] = x3[K];
     }
 }
 template <int K, int N>
@@ -260,6 +274,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     // ------------------------------------------------------------ set-up
     // Values the loop itself needs stay in registers; the rest goes to w.geo.
     uint32_t bits = 0, valid = 0, rail = 0, r_lane = 0, nbit = 0;
+    uint32_t bx = 0;  // 16 sites per lane: bits | nbit << 16
     int s0 = 0, cls_base = 0, d = 0;
     bool isolated = true;
     uint64_t *own = nullptr;
@@ -332,13 +347,14 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         // the next lane's first site (the far end of the lane's last bond);
         // refreshed only after half-steps that moved ions
         nbit = __shfl_down(bits, 1, 64) & 1u;
+        bx = bits | (nbit << 16);
 
         // Stage-0 scale of the lane: every origin of its bonds (sites s0 ..
         // s0 + SPL) has a class >= q_lo, so every exact threshold is at most
         // rho (thr0 + 1) + 2^32 2e-6 with rho = A(q_lo) / A(0); r_lane =
-        // ceil(rho 2^32), and the per-step bound is min(thr0, mulhi(thr0,
-        // r_lane) + 8600), the addition saturating (the margin covers the
-        // widening term, both ceilings and binary64 rounding).
+        // ceil(rho 2^32), and the per-step bound is mulhi(thr0, r_lane) +
+        // 8600, the addition saturating (the margin covers the widening term,
+        // both ceilings and binary64 rounding).
         if (has && last >= 0) {
             int q_lo = kClasses;
             const int s_hi = s0 + SPL < L - 1 ? s0 + SPL : L - 1;
@@ -349,8 +365,12 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     }
     PhLane<kNB> phl;
     ph_lane_init<0>(phl, (uint32_t)(s0 >> 3), (uint32_t)d << 4, a.key0, a.key1);
+    // the candidate bonds of each parity that lie inside the rail
+    const uint32_t valid_e = valid & 0x55555555u, valid_o = valid & 0xAAAAAAAAu;
+    // the tile's publication words are written by one lane: keeping their base
+    // in a vector register frees two scalar registers for the whole loop
+    asm volatile("" : "+v"(own));
     const uint32_t tag_hi = (uint32_t)(a.epoch & 0xFFFFFu) << 12;  // state tag = tag_hi | launch-relative state
-    const uint32_t n0 = (uint32_t)rfl((int)(uint32_t)a.ctl->n_base);  // Philox step word of the first step
 
     // Per-step tables of the window [kb, kb + 64): lane k holds step kb + k's
     // stage-0 threshold in a register, the bias and g go to LDS.
@@ -435,7 +455,16 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         }
     }
 
-    const uint32_t key0 = a.key0, key1 = a.key1;
+    // The publication of each new state: lane 0 of a tile with neighbours
+    // writes word j of the tile's slots with tag tag_hi | j.  The address, the
+    // tag and the snapshot count live in vector registers (they change every
+    // half-step or only on a rare path), which keeps the scalar registers for
+    // the loop's own values.
+    const bool pub_lane = lane == 0 && !isolated;
+    uint64_t *pub_at = own;
+    uint32_t tag_j = tag_hi;
+    asm volatile("" : "+v"(tag_j), "+v"(snap_count));
+
     // One half-step of parity h (a compile-time constant): state js = 2 kstep
     // + h to js + 1 (the first state of a launch is even).  False when a wait
     // for a neighbour failed.
@@ -445,19 +474,22 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         const int kw = kstep & (kWaveWin - 1);
 
         // candidates: bonds of parity h whose two sites differ
-        const uint32_t cand = (bits ^ ((bits >> 1) | (nbit << (SPL - 1)))) & (h ? 0xAAAAAAAAu : 0x55555555u) & valid;
+        // (the site after bond b: bit b + 1, or the next lane's first site)
+        const uint32_t after = SPL == 32 ? __builtin_amdgcn_alignbit(nbit, bits, 1) : bx >> 1;
+        const uint32_t cand = (bits ^ after) & (h ? valid_o : valid_e);
 
-        // Philox words; the key enters each half-step opaquely, so that the
-        // round keys are derived on the scalar unit instead of being kept live
-        uint32_t k0 = key0, k1 = key1;
-        asm volatile("" : "+s"(k0), "+s"(k1));
+        // Philox words (the key is read from the kernel arguments each
+        // half-step, a scalar load, rather than held in scalar registers)
         uint32_t wd[kW];
-        ph_words<h, 0>(wd, phl, ps, k0, k1);
+        {
+            const KArgs ka = kargs();
+            ph_words<h>(wd, phl, ps, ka->key0, ka->key1);
+        }
         // stage 0: the smallest word against the bound of the lane's lowest
         // class; stage 1 (rare): each candidate's word against its origin's
         // exact class threshold
         const uint32_t thr0 = (uint32_t)__builtin_amdgcn_readlane((int)thr_lane, kw);
-        const uint32_t t_lane = min(thr0, __builtin_elementwise_add_sat(__umulhi(thr0, r_lane), 8600u));
+        const uint32_t t_lane = __builtin_elementwise_add_sat(__umulhi(thr0, r_lane), 8600u);
         const uint32_t mn = min_word<0>(wd);
         uint32_t sv = 0;
         if (mn <= t_lane && cand != 0u) {
@@ -575,43 +607,46 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             }
             bits ^= fl;
             nbit = __shfl_down(bits, 1, 64) & 1u;
+            bx = bits | (nbit << 16);
         }
 
         // publish the new state js + 1
-        if (!isolated) {
+        ++pub_at;
+        ++tag_j;
+        if (edge_changed && !isolated) {
             const uint32_t jn = (uint32_t)js + 1u;
-            if (edge_changed) {
-                const KArgs ka = kargs();
-                WaveLds<SPL> &wr = *lds_opaque(&w);
-                ++snap_count;
-                const int slot = snap_count % kSnapSlots;
-                if (snap_count >= kSnapSlots) {
-                    // the slot's snapshot serves states before the next snapshot's
-                    const uint32_t need = (uint32_t)wr.snap_state[(slot + 1) % kSnapSlots];
-                    bool ok = true;
-                    if (lane < 2) {
-                        const int T = lane == 0 ? rfl(wr.geo.prev) : rfl(wr.geo.next);
-                        uint64_t v = 0;
-                        ok = poll_tag(ka->pub + (int64_t)T * ka->pub_stride + need, tag_hi | need, ka->status, ka->spin_limit, &v);
-                    }
-                    if (__ballot(!ok)) return false;
+            const KArgs ka = kargs();
+            WaveLds<SPL> &wr = *lds_opaque(&w);
+            const int sc = rfl(snap_count) + 1;
+            snap_count = sc;
+            const int slot = sc % kSnapSlots;
+            if (sc >= kSnapSlots) {
+                // the slot's snapshot serves states before the next snapshot's
+                const uint32_t need = (uint32_t)wr.snap_state[(slot + 1) % kSnapSlots];
+                bool ok = true;
+                if (lane < 2) {
+                    const int T = lane == 0 ? rfl(wr.geo.prev) : rfl(wr.geo.next);
+                    uint64_t v = 0;
+                    ok = poll_tag(ka->pub + (int64_t)T * ka->pub_stride + need, tag_hi | need, ka->status, ka->spin_limit, &v);
                 }
-                write_snapshot(wr.geo, slot, jn);
-                if (lane == 0) wr.snap_state[slot] = (int16_t)jn;
-                snap_word = ((uint32_t)slot << 12) | jn;
+                if (__ballot(!ok)) return false;
             }
-            if (lane == 0)
-                __hip_atomic_store(own + jn, ((uint64_t)(tag_hi | jn) << 32) | snap_word, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            write_snapshot(wr.geo, slot, jn);
+            if (lane == 0) wr.snap_state[slot] = (int16_t)jn;
+            snap_word = ((uint32_t)slot << 12) | jn;
         }
+        if (pub_lane)
+            __hip_atomic_store(pub_at, ((uint64_t)tag_j << 32) | snap_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     };
     for (int kstep = 0; kstep < a.n_steps; ++kstep) {
         if ((kstep & (kWaveWin - 1)) == 0) refresh(kstep);
-        uint32_t k0 = key0;
-        asm volatile("" : "+s"(k0));
         PhStep<kNB> ps;
-        ph_step(ps, phl, rail, n0 + (uint32_t)kstep, k0);
+        {
+            const KArgs ka = kargs();
+            const uint32_t n_first = (uint32_t)((const __attribute__((address_space(4))) Ctl *)ka->ctl)->n_base;
+            ph_step(ps, phl, rail, n_first + (uint32_t)kstep, ka->key0);
+        }
         if (!half_step(std::integral_constant<int, 0>{}, kstep, ps)) break;
         if (!half_step(std::integral_constant<int, 1>{}, kstep, ps)) break;
     }
