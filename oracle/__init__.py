@@ -35,7 +35,9 @@ class _Protocol(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("shuffle_seed", C.c_uint64), ("rail_lo", C.c_int), ("rail_hi", C.c_int),
                 ("score_w", C.POINTER(C.c_double)), ("score_grad", C.POINTER(C.c_double)),
-                ("score_mag", C.POINTER(C.c_double)), ("score_sens", C.POINTER(C.c_double))]
+                ("score_mag", C.POINTER(C.c_double)), ("score_sens", C.POINTER(C.c_double)),
+                ("score_sens_arg", C.POINTER(C.c_double)), ("score_sens_b", C.POINTER(C.c_double)),
+                ("score_hops", C.POINTER(C.c_int64)), ("score_coul64", C.c_int)]
 
 
 LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
@@ -219,12 +221,16 @@ def run(p: OracleParams, protocols, occ: np.ndarray, n0: int, n_steps: int,
 
 
 def score_replay(p: OracleParams, protocols, occ0: np.ndarray, n0: int, weights: np.ndarray,
-                 n_set: Optional[Sequence[int]] = None) -> Dict[str, np.ndarray]:
+                 n_set: Optional[Sequence[int]] = None, coul64: bool = False) -> Dict[str, np.ndarray]:
     """Replay the steps [n0, n0 + len(weights)) from occ0 (not modified) and sum,
     per device, the score-function terms of every hop decision weighted by
     weights[k][d] (k = step - n0).  Returns grad, mag (sum of |term|) and sens
     (sum of |W g| p/(1-p)^2), each [D][4] over theta = (Ea shift, nu0, kappa,
-    alpha), and the replayed final occupancy."""
+    alpha), and the replayed final occupancy.  Also returned, as scales for
+    the tolerance of a replay that sums the Coulomb part in another order:
+    sens_arg and sens_b [D][4] (see orc_run_opts) and hops [D], the accepted
+    hops.  coul64: in the binary32 path the score terms take the Coulomb part
+    summed in binary64 and rounded once to binary32 (decisions unchanged)."""
     D = len(p.rails)
     w = np.ascontiguousarray(weights, dtype=np.float64)
     n_steps = w.shape[0]
@@ -235,8 +241,12 @@ def score_replay(p: OracleParams, protocols, occ0: np.ndarray, n0: int, weights:
     grad = np.zeros((D, 4))
     mag = np.zeros((D, 4))
     sens = np.zeros((D, 4))
+    sens_arg = np.zeros((D, 4))
+    sens_b = np.zeros((D, 4))
+    hops = np.zeros(D, dtype=np.int64)
     opts = _Opts(0, 0, 0, _ptr(w, C.c_double), _ptr(grad, C.c_double), _ptr(mag, C.c_double),
-                 _ptr(sens, C.c_double))
+                 _ptr(sens, C.c_double), _ptr(sens_arg, C.c_double), _ptr(sens_b, C.c_double),
+                 _ptr(hops, C.c_int64), 1 if coul64 else 0)
     n_log = C.c_int64(0)
     rc = lib().orc_run(C.byref(p.s), prot.arr, _ptr(occ, C.c_int8), n0, n_steps, None, None, None,
                        None, 0, C.byref(n_log), C.byref(opts))
@@ -244,4 +254,5 @@ def score_replay(p: OracleParams, protocols, occ0: np.ndarray, n0: int, weights:
         raise ValueError("score replay needs kappa != 0 and nu0 > 0")
     if rc != 0:
         raise ValueError("oracle rejected the run (step counter out of range)")
-    return {"grad": grad, "mag": mag, "sens": sens, "occ": occ}
+    return {"grad": grad, "mag": mag, "sens": sens, "sens_arg": sens_arg, "sens_b": sens_b, "hops": hops,
+            "occ": occ}

@@ -177,7 +177,7 @@ static double device_voltage(const orc_protocol *pr, int d, int64_t n, double dt
  * the neighbour order, sites in increasing order). */
 static void delta_energy_parts_f64(const orc_params *P, int R, int L, const int8_t *S,
                                    int r, int o, int t, double V, double *e_app_out,
-                                   double *e_coul_out)
+                                   double *e_coul_out, double *a_abs_out)
 {
     double e_app = ((P->alpha * V) * (double)(t - o)) / (double)L;
     int rails[64], dists[64];
@@ -186,22 +186,24 @@ static void delta_energy_parts_f64(const orc_params *P, int R, int L, const int8
     int hi = (o > t ? o : t) + P->cutoff;
     if (lo < 0) lo = 0;
     if (hi > L - 1) hi = L - 1;
-    double e_coul = 0.0;
+    double e_coul = 0.0, a_abs = 0.0;
     for (int i = 0; i < nr; ++i) {
         const int8_t *row = S + (int64_t)rails[i] * L;
         for (int j = lo; j <= hi; ++j) {
             if (rails[i] == r && (j == o || j == t)) continue;
             if (!row[j]) continue;
             e_coul += orc_kernel(P, t - j, dists[i]) - orc_kernel(P, o - j, dists[i]);
+            a_abs += fabs(orc_kernel(P, t - j, dists[i])) + fabs(orc_kernel(P, o - j, dists[i]));
         }
     }
     *e_app_out = e_app;
     *e_coul_out = e_coul;
+    if (a_abs_out) *a_abs_out = a_abs;
 }
 
 static void delta_energy_parts_f32(const orc_params *P, int R, int L, const int8_t *S,
                                    int r, int o, int t, double V, float *e_app_out,
-                                   float *e_coul_out)
+                                   float *e_coul_out, double *a_abs_out)
 {
     float a = (float)P->alpha, v = (float)V;
     float e_app = ((a * v) * (float)(t - o)) / (float)L;
@@ -212,6 +214,7 @@ static void delta_energy_parts_f32(const orc_params *P, int R, int L, const int8
     if (lo < 0) lo = 0;
     if (hi > L - 1) hi = L - 1;
     float e_coul = 0.0f;
+    double a_abs = 0.0;
     for (int i = 0; i < nr; ++i) {
         const int8_t *row = S + (int64_t)rails[i] * L;
         for (int j = lo; j <= hi; ++j) {
@@ -220,17 +223,19 @@ static void delta_energy_parts_f32(const orc_params *P, int R, int L, const int8
             float kt = (float)orc_kernel(P, t - j, dists[i]);
             float ko = (float)orc_kernel(P, o - j, dists[i]);
             e_coul += kt - ko;
+            a_abs += fabs(orc_kernel(P, t - j, dists[i])) + fabs(orc_kernel(P, o - j, dists[i]));
         }
     }
     *e_app_out = e_app;
     *e_coul_out = e_coul;
+    if (a_abs_out) *a_abs_out = a_abs;
 }
 
 double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
                             int r, int o, int t, double V)
 {
     double e_app, e_coul;
-    delta_energy_parts_f64(P, R, L, S, r, o, t, V, &e_app, &e_coul);
+    delta_energy_parts_f64(P, R, L, S, r, o, t, V, &e_app, &e_coul, NULL);
     return e_app + e_coul;
 }
 
@@ -238,7 +243,7 @@ float orc_delta_energy_f32(const orc_params *P, int R, int L, const int8_t *S,
                            int r, int o, int t, double V)
 {
     float e_app, e_coul;
-    delta_energy_parts_f32(P, R, L, S, r, o, t, V, &e_app, &e_coul);
+    delta_energy_parts_f32(P, R, L, S, r, o, t, V, &e_app, &e_coul, NULL);
     return e_app + e_coul;
 }
 
@@ -368,7 +373,8 @@ static void permutation(int64_t m, uint64_t seed, int64_t *perm)
  * sensitivity of the term to a relative change of p (its derivative in p
  * times p). */
 static void add_score(const orc_params *P, const orc_run_opts *opts, int64_t k, int d,
-                      int accept, double p, double e_coul, double V, int o, int t, int L)
+                      int accept, double p, double e_coul, double V, int o, int t, int L,
+                      double ea, double dE, double a_abs)
 {
     if (!(p < 1.0)) return;
     const int D = P->n_devices;
@@ -377,11 +383,19 @@ static void add_score(const orc_params *P, const orc_run_opts *opts, int64_t k, 
     const double g[4] = {-beta, 1.0 / P->nu0, -0.5 * beta * e_coul / P->kappa,
                          -0.5 * beta * V * (double)(t - o) / (double)L};
     const double ratio = ((double)accept - p) / (1.0 - p);
+    const double b = a_abs + fabs(dE) + fabs(e_coul) + 2.0 * fabs(orc_kernel(P, 1, 0));
     for (int q = 0; q < 4; ++q) {
         const double term = W * g[q] * ratio;
+        const double base = fabs(W * g[q]) * p / ((1.0 - p) * (1.0 - p));
         opts->score_grad[d * 4 + q] += term;
         if (opts->score_mag) opts->score_mag[d * 4 + q] += fabs(term);
-        if (opts->score_sens) opts->score_sens[d * 4 + q] += fabs(W * g[q]) * p / ((1.0 - p) * (1.0 - p));
+        if (opts->score_sens) opts->score_sens[d * 4 + q] += base;
+        if (opts->score_sens_arg) opts->score_sens_arg[d * 4 + q] += base * fabs(beta * (ea + 0.5 * dE));
+        if (opts->score_sens_b) {
+            double scale = base * 0.5 * beta;
+            if (q == 2) scale += fabs(W * 0.5 * beta / P->kappa) * fabs(ratio);
+            opts->score_sens_b[d * 4 + q] += scale * b;
+        }
     }
 }
 
@@ -440,32 +454,42 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                     uint32_t w = orc_hop_word(P->seed, d, n, r, s);
                     int accept;
                     double u_log, p_log;
-                    double p_score, e_coul_score;
+                    double p_score, e_coul_score, de_score, a_abs = 0.0;
                     if (P->fp32) {
                         float e_app, e_coul;
-                        delta_energy_parts_f32(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul);
+                        delta_energy_parts_f32(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul, &a_abs);
                         float dE = e_app + e_coul;
                         float p = orc_hop_prob_f32(P, ea, dE);
                         float u = ldexpf((float)w, -32);
                         accept = u < p;
                         u_log = u; p_log = p;
-                        p_score = p; e_coul_score = e_coul;
+                        p_score = p; e_coul_score = e_coul; de_score = dE;
                         if (fabsf(u - p) < 1e-6f)
                             log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
+                        if (opts && opts->score_grad && opts->score_coul64) {
+                            double e_app64, e_coul64;
+                            delta_energy_parts_f64(P, R, L, Sd, r, o, t, V[d], &e_app64, &e_coul64, &a_abs);
+                            float dE_s = e_app + (float)e_coul64;
+                            p_score = orc_hop_prob_f32(P, ea, dE_s);
+                            e_coul_score = e_coul64;
+                            de_score = dE_s;
+                        }
                     } else {
                         double e_app, e_coul;
-                        delta_energy_parts_f64(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul);
+                        delta_energy_parts_f64(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul, &a_abs);
                         double dE = e_app + e_coul;
                         double p = orc_hop_prob_f64(P, ea, dE);
                         double u = ldexp((double)w, -32);
                         accept = u < p;
                         u_log = u; p_log = p;
-                        p_score = p; e_coul_score = e_coul;
+                        p_score = p; e_coul_score = e_coul; de_score = dE;
                         if (fabs(u - p) < 1e-6)
                             log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
                     }
                     if (opts && opts->score_grad)
-                        add_score(P, opts, k, d, accept, p_score, e_coul_score, V[d], o, t, L);
+                        add_score(P, opts, k, d, accept, p_score, e_coul_score, V[d], o, t, L,
+                                  ea, de_score, a_abs);
+                    if (accept && opts && opts->score_hops) ++opts->score_hops[d];
                     if (accept) {
                         Od[(int64_t)r * L + o] = 0;
                         Od[(int64_t)r * L + t] = 1;

@@ -49,6 +49,23 @@ typedef struct {
     double *score_grad;
     double *score_mag;
     double *score_sens;
+    /* Tolerance diagnostics for a replay whose Coulomb part is summed in
+     * another order (all optional, NULL: not accumulated).  Per decision with
+     * p < 1 and base_q = |W g_q| p/(1-p)^2:
+     *   score_sens_arg [D][4]: base_q |beta (Ea + dE/2)|, the scale of a
+     *     rounding difference in the exponent's argument;
+     *   score_sens_b [D][4]: (base_q beta/2 + [q = kappa] |W beta/(2 kappa)|
+     *     |(y - p)/(1 - p)|) B with B = A + |dE| + |e_coul| + 2 |K(1, 0)| and A
+     *     the sum over the occupied window sites of |K(t - j)| + |K(o - j)|
+     *     (binary64), the scale of a difference in the summed Coulomb part;
+     *   score_hops [D]: accepted hops. */
+    double *score_sens_arg;
+    double *score_sens_b;
+    int64_t *score_hops;
+    /* nonzero: in the binary32 path the score terms use the Coulomb part
+     * summed in binary64 and rounded once to binary32 (the decisions still
+     * use the binary32 sum) */
+    int score_coul64;
 } orc_run_opts;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -45,6 +45,8 @@ hipError_t wave_capacity(int spl, size_t lds, bool fp64, int *blocks_per_cu);
 size_t wave_lds_bytes(int spl, int n_kt, bool fp64);
 int wave_band_words(int spl);
 hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st);
+hipError_t launch_replay_phi_full(const PhiArgs &a, hipStream_t st);
+hipError_t launch_replay_phi_update(const PhiArgs &a, hipStream_t st);
 hipError_t launch_dense_phi(const DenseArgs &a, hipStream_t st);
 hipError_t launch_dense_decide(const HopArgs &a, int pitch, hipStream_t st);
 hipError_t set_dense_lds_limit(size_t lds_bytes);
@@ -73,14 +75,14 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
-        rp_a, rp_b, score_log, dtab64, dtab32, phi, ktiles, dtiles, ctiles, total;
+        rp_a, rp_b, score_log, rphi, hops, hop_ctl, phi, ktiles, dtiles, ctiles, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
     size_t wtiles;                    // wave tiling (PTile array)
     int max_pitch;
     int64_t total_sites, total_pad, rails_total;
     int cut;     // interaction table cutoff actually stored
-    int dpitch;  // entries per row of the window-difference tables
+    int64_t hop_cap;  // score replay: entries of the accepted-hop list
     int dense_nb;  // dense potential: 32-site blocks per rail (0 when not used)
 };
 
@@ -217,13 +219,18 @@ Layout layout_for(const kmc_params *p) {
                  (size_t)std::max(L.pub_stride * L.max_ptiles, L.wpub_stride * L.max_wtiles));
     L.wtiles = take(sizeof(PTile) * (size_t)rails);  // every wave tile is at least one rail
     L.status = take(sizeof(int32_t) * 4);
-    // score replay: its own pair of state planes and a discarded event count
+    // score replay: its own pair of state planes, a discarded event count, the
+    // binary64 Coulomb potential of every site and the list of a half-step's
+    // accepted hops (a longer list falls back to recomputing the potential)
     L.rp_a = take((size_t)pad);
     L.rp_b = take((size_t)pad);
     L.score_log = take(sizeof(int64_t));
-    L.dpitch = (2 * L.cut + 2 + 15) / 16 * 16;
-    L.dtab64 = take(sizeof(double) * 2 * (m + 1) * (size_t)L.dpitch);
-    L.dtab32 = take(sizeof(float) * 2 * (m + 1) * (size_t)L.dpitch);
+    L.hop_cap = std::min<int64_t>(std::max<int64_t>(L.total_sites / 64, 4096), (int64_t)1 << 24);
+    if (p->precision != KMC_BF16X2) {
+        L.rphi = take(sizeof(double) * (size_t)L.total_sites);
+        L.hops = take(sizeof(uint4) * (size_t)L.hop_cap);
+        L.hop_ctl = take(sizeof(int64_t) * 2);
+    }
     if (p->precision == KMC_BF16X2) {
         // potential of every site (rows padded to a multiple of 128 sites), the
         // distinct 32 x 32 Toeplitz blocks of the kernel as MFMA fragments, tiles
@@ -285,6 +292,7 @@ struct kmc_ctx {
     int mode = 0;                      // KMC_LAUNCH_AUTO / _HALF_STEP / _PERSISTENT
     uint64_t epoch = 0;
     float k10 = 0.0f;                  // K(1, 0) rounded to binary32
+    double k01 = 0.0;                  // K(1, 0) in binary64 (score replay)
 
     template <typename T>
     T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -349,9 +357,7 @@ void make_tiles(kmc_ctx *c) {
         const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
         const size_t base = rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt;
         lds = std::max(lds, base);
-        const size_t n_dt = (size_t)2 * (c->p.rail_range + 1) * c->lay.dpitch;
-        const size_t dt = n_dt <= (size_t)kLdsTableMax ? n_dt * real : 0;
-        score_lds = std::max(score_lds, align_up(base + rows / kChunkSites * sizeof(uint16_t), 16) + dt);
+        score_lds = std::max(score_lds, base);
     }
     c->hop_lds = lds;
     c->score_lds = score_lds;
@@ -552,8 +558,13 @@ HopArgs hop_args(kmc_ctx *c) {
     a.log.cap = kLogCap;
     a.nu0 = c->p.nu0_hz;
     a.kappa = c->p.coulomb_kappa_v;
-    a.dtab = c->fp64 ? (const void *)c->at<double>(c->lay.dtab64) : (const void *)c->at<float>(c->lay.dtab32);
-    a.dpitch = c->lay.dpitch;
+    if (!c->dense) {
+        a.rphi = c->at<double>(c->lay.rphi);
+        a.hops = c->at<uint4>(c->lay.hops);
+        a.hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
+        a.hop_cap = c->lay.hop_cap;
+        a.k01 = c->k01;
+    }
     if (c->dense) {
         a.phi = c->at<float>(c->lay.phi);
         a.phi_row = (int64_t)c->lay.dense_nb * 32;
@@ -758,28 +769,6 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
             k32[(size_t)dr * (cut + 1) + ds] = (float)k64[(size_t)dr * (cut + 1) + ds];
         }
 
-    // Window differences for the score replay: row (dir, dist), entry x is
-    // site j = s - cut + x of the rail at that distance, for the bond (s, s+1)
-    // with the ion moving up (dir 0: o = s, t = s+1) or down (dir 1); the
-    // moving ion's own two sites are zero on its own rail.  Each precision's
-    // entry is the difference of that precision's two table values.
-    const int dp = lay.dpitch;
-    std::vector<double> d64((size_t)2 * (m + 1) * dp, 0.0);
-    std::vector<float> d32(d64.size(), 0.0f);
-    for (int dir = 0; dir < 2; ++dir)
-        for (int dist = 0; dist <= m; ++dist)
-            for (int x = 0; x <= 2 * cut + 1; ++x) {
-                const int jr = x - cut, orl = dir ? 1 : 0, trl = dir ? 0 : 1;
-                if (dist == 0 && (jr == 0 || jr == 1)) continue;
-                const int dt = std::abs(trl - jr), dO = std::abs(orl - jr);
-                const size_t at = ((size_t)dir * (m + 1) + dist) * dp + x;
-                const size_t row = (size_t)dist * (cut + 1);
-                const double kt64 = dt <= cut ? k64[row + dt] : 0.0, ko64 = dO <= cut ? k64[row + dO] : 0.0;
-                const float kt32 = dt <= cut ? k32[row + dt] : 0.0f, ko32 = dO <= cut ? k32[row + dO] : 0.0f;
-                d64[at] = kt64 - ko64;
-                d32[at] = kt32 - ko32;
-            }
-
     // Dense potential (KMC_BF16X2): the distinct 32 x 32 blocks of
     // T[(dist, j)][s] = K(s - j, dist), as MFMA B fragments, each value split
     // into BF16 hi = RN(K) and lo = RN(K - hi).  Block (dist, delta) holds
@@ -788,6 +777,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     c->dense = params->precision == KMC_BF16X2;
     make_wtiles(c);
     c->k10 = cut >= 1 ? k32[1] : 0.0f;
+    c->k01 = cut >= 1 ? k64[1] : 0.0;
     std::vector<uint16_t> kt_host;
     if (c->dense) {
         auto bf16_rne = [](float f) {
@@ -852,8 +842,6 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
         chk(h2d(lay.wtiles, c->wtiles.data(), sizeof(PTile) * c->wtiles.size()), "copy wave tiles");
     chk(h2d(lay.ktab64, k64.data(), sizeof(double) * k64.size()), "copy kernel table");
     chk(h2d(lay.ktab32, k32.data(), sizeof(float) * k32.size()), "copy kernel table");
-    chk(h2d(lay.dtab64, d64.data(), sizeof(double) * d64.size()), "copy window differences");
-    chk(h2d(lay.dtab32, d32.data(), sizeof(float) * d32.size()), "copy window differences");
     if (c->dense) {
         chk(h2d(lay.ktiles, kt_host.data(), sizeof(uint16_t) * kt_host.size()), "copy kernel blocks");
         chk(h2d(lay.dtiles, c->dtiles.data(), sizeof(Tile) * c->dtiles.size()), "copy dense tiles");
@@ -1233,6 +1221,20 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     a.log.count = c->at<int64_t>(c->lay.score_log);
     a.log.cap = 0;
     a.score_grad = grad_dev;
+    // the Coulomb potential of the starting state, then per half-step the
+    // replay (which lists its accepted hops) and the potential's update
+    PhiArgs pa{};
+    pa.occ = cur;
+    pa.devs = c->at<DevInfo>(c->lay.devs);
+    pa.n_devices = D;
+    pa.ktab64 = c->at<double>(c->lay.ktab64);
+    pa.cutoff = c->lay.cut;
+    pa.phi = c->at<double>(c->lay.rphi);
+    pa.hops = c->at<uint4>(c->lay.hops);
+    pa.hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
+    pa.hop_cap = c->lay.hop_cap;
+    KMC_HIP(c, launch_zero_i64(pa.hop_ctl, 2, c->stream));
+    KMC_HIP(c, launch_replay_phi_full(pa, c->stream));
     for (int64_t k = 0; k < n_steps; ++k) {
         a.n_abs = step0 + k;
         a.score_w = weight_dev + k * D;
@@ -1241,6 +1243,8 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
             a.occ_out = nxt;
             a.h = h;
             KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
+            pa.occ = nxt;  // the new state, for a full recomputation after an overflow
+            KMC_HIP(c, launch_replay_phi_update(pa, c->stream));
             std::swap(cur, nxt);
         }
     }

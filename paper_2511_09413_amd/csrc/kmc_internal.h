@@ -88,8 +88,11 @@ struct HopArgs {
     // score replay only (hop_half_step<..., 1>)
     int64_t n_abs;             // step index of the launch
     double nu0, kappa;
-    const void *dtab;          // [2][m+1][dpitch] window differences K(t-j) - K(o-j), path precision
-    int32_t dpitch;            // entries per row, >= 2*cutoff + 2, multiple of 16
+    const double *rphi;        // Coulomb potential of the half-step's state, binary64, unpadded
+    double k01;                // K(1, 0) in binary64 (0 when the cutoff is 0)
+    uint4 *hops;               // accepted hops of the half-step (device, rail, s, dir), hop_cap entries
+    int64_t *hop_ctl;          // [0] entries appended, [1] workgroups done (replay_phi_update)
+    int64_t hop_cap;
     const double *score_w;     // [D] weights of this step's decisions
     double *score_grad;        // [D][4] accumulators (Ea shift, nu0, kappa, alpha)
     // dense-potential decisions only (dense_decide)
@@ -98,6 +101,20 @@ struct HopArgs {
     float k10;                 // K(1, 0) in binary32
     const Tile *dtiles;        // decision tiles: whole rails of one device per workgroup
     int32_t n_dtiles;
+};
+
+// Coulomb potential of the score replay (binary64) and its update by the
+// accepted hops of a half-step.
+struct PhiArgs {
+    const int8_t *occ;         // padded state (bit 0 = occupied): read by full recomputations
+    const DevInfo *devs;
+    int32_t n_devices;
+    const double *ktab64;      // [(m+1)][(c+1)] kernel table
+    int32_t cutoff;
+    double *phi;               // unpadded [device offset + r L + s]
+    const uint4 *hops;         // (device, rail, s, dir): dir 0 moves the ion at s up
+    int64_t *hop_ctl;          // [0] entries, [1] workgroups done; cleared by replay_phi_update
+    int64_t hop_cap;
 };
 
 // Dense potential (MFMA): every site's Coulomb potential of one state.

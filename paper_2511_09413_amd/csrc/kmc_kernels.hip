@@ -26,10 +26,12 @@
 // With kScore the same kernel replays a half-step for the score-function
 // gradient: the decisions are taken exactly as above (so the replay follows the
 // forward trajectory), and in addition every candidate bond gets its hop
-// probability from a lane-serial Coulomb sum over the occupied sites of the
-// window (rails in neighbour order, sites ascending) and contributes
-// W g (y - p)/(1 - p) to the device's four accumulators, g being the
-// log-derivative of p in (Ea shift, nu0, kappa, alpha).
+// probability from the Coulomb potential phi of the half-step's state (binary64,
+// kept up to date by replay_phi_update: dE_coul = phi(t) - K(1, 0) - phi(o),
+// rounded once to the path precision) and contributes W g (y - p)/(1 - p) to
+// the device's four accumulators, g being the log-derivative of p in (Ea shift,
+// nu0, kappa, alpha).  The accepted hops go to a global list for the potential
+// update.
 #include <math.h>
 
 #include <type_traits>
@@ -47,17 +49,6 @@ struct HopShared {
     uint32_t wtab[kClasses];  // inclusive Philox-word thresholds per barrier class
 };
 
-// Sixteen occupancy bits of sites j0 .. j0+15 of a tile row (bit k = site
-// j0 + k), zero outside the row.  rbits holds each row as 16-bit words.
-__device__ __forceinline__ uint32_t window_bits(const uint16_t *rb, int p16, int j0) {
-    const int w = j0 >> 4, sh = j0 & 15;
-    // clamped reads and selects instead of guarded loads (no branches)
-    const int wl = min(max(w, 0), p16 - 1), wh = min(max(w + 1, 0), p16 - 1);
-    const uint32_t lo = (w >= 0 && w < p16) ? (uint32_t)rb[wl] : 0u;
-    const uint32_t hi = (w + 1 >= 0 && w + 1 < p16) ? (uint32_t)rb[wh] : 0u;
-    return ((hi << 16 | lo) >> sh) & 0xFFFFu;
-}
-
 // ------------------------------------------------------------------------
 // The half-step kernel.  H = bond parity.  State bytes: bit 0 = occupied,
 // bits 1..7 = barrier class of the site (a lower bound of its barrier used only
@@ -68,8 +59,6 @@ __device__ __forceinline__ uint32_t window_bits(const uint16_t *rb, int p16, int
 //   hops   [cap] uint32 (row << 13 | s)
 //   survea [cap] Real (barrier of the survivor's origin)
 //   ktab   [(m + 1) * (cutoff + 1)] Real, when small enough
-//   rbits  [(nr + 2m) * pitch / 16] uint16 occupancy bits (score replay only)
-//   dtab   [2][m + 1][dpitch] Real window differences (score replay only)
 // ------------------------------------------------------------------------
 template <typename Real, int H, int kMode>
 __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
@@ -95,7 +84,6 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     const int kt_stride = a.cutoff + 1;
     const int n_kt = (m + 1) * kt_stride;
     const bool kt_in_lds = n_kt <= kLdsTableMax;
-    uint16_t *rbits = reinterpret_cast<uint16_t *>(kt_lds + (kt_in_lds ? n_kt : 0));
     const Real *kt_glob = std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
                                                             : reinterpret_cast<const Real *>(a.ktab32);
     const int tid = threadIdx.x;
@@ -155,10 +143,6 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         *reinterpret_cast<uint4 *>(rows + halo_lds_row(i) * pitch + (i - (i / p16) * p16) * kChunkSites) =
             *reinterpret_cast<const uint4 *>(halo_src(i));
     __syncthreads();
-    if constexpr (kScore) {
-        for (int i = tid; i < n_rows * p16; i += kBlock)
-            rbits[i] = (uint16_t)occ_bits(*reinterpret_cast<const uint4 *>(rows + i * kChunkSites));
-    }
 
     // 3. candidates and the exact two-stage prefilter
     uint32_t bits = 0, cand_all = 0;
@@ -289,12 +273,18 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     // 6. score replay: every candidate's term W g (y - p)/(1 - p), binary64.
     //    The candidates of the tile are listed in LDS (the survivor list is free
     //    now) and shared round-robin by all lanes.  The Coulomb part of dE is
-    //    the sum over the window sites j = s - cutoff .. s + 1 + cutoff, rail by
-    //    rail in neighbour order and j ascending, of occ_j D(j - s), with D the
-    //    precomputed difference K(t - j) - K(o - j) in the path precision (zero
-    //    at the moving ion's two sites): the same terms in the same order as a
-    //    serial sum over the occupied sites, the empty ones adding an exact 0.
+    //    phi(t) - K(1, 0) - phi(o) from the potential of the half-step's state,
+    //    in binary64, rounded once to the path precision for p.  The half-step's
+    //    accepted hops are appended to the global list (device, rail, site,
+    //    direction) that replay_phi_update applies before the next half-step.
     if constexpr (kScore) {
+        const int n_hop = sh.n_hop;
+        for (int i = tid; i < n_hop; i += kBlock) {
+            const int hr = (int)(hops[i] >> 13), hs = (int)(hops[i] & 8191u);
+            const uint32_t dir = (rows[(m + hr) * pitch + hs] & 1) ? 0u : 1u;  // 0: the ion at hs moves up
+            const int64_t k = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl), 1ull);
+            if (k < a.hop_cap) a.hops[k] = make_uint4((uint32_t)tile.d, (uint32_t)(tile.r0 + hr), (uint32_t)hs, dir);
+        }
         uint32_t *clist = surv;
         if (has_chunk) {
             uint32_t cm = cand_all;
@@ -307,16 +297,8 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                 clist[k] = ((uint32_t)row << 14) | (y << 13) | (dir << 12) | (uint32_t)(s0 + bit);
             }
         }
-        const size_t dt_at = (reinterpret_cast<unsigned char *>(rbits + n_rows * p16) - smem + 15) & ~(size_t)15;
-        Real *dt_lds = reinterpret_cast<Real *>(smem + dt_at);
-        const int n_dt = 2 * (m + 1) * a.dpitch;
-        const bool dt_in_lds = n_dt <= kLdsTableMax;
-        if (dt_in_lds)
-            for (int i = tid; i < n_dt; i += kBlock) dt_lds[i] = reinterpret_cast<const Real *>(a.dtab)[i];
         __syncthreads();
         const int n_cand = sh.n_cand;
-        const int wn = 2 * a.cutoff + 2;   // window length
-        const int n_full = wn >> 4;        // full 16-site blocks, then wn % 16 single sites
         const Real alpha_r = (Real)a.alpha, V_r = (Real)sh.V;
         const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0;
         const double W = a.score_w[tile.d];
@@ -326,66 +308,15 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
         const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-        // Sum of occ_j D(j - s) over a 16-site block: every entry is loaded and
-        // masked with its sign-extended occupancy bit (an empty site adds +0).
-        auto block_sum = [&](Real acc, const Real *d, uint32_t wb) {
-            Real v[16];
-            if constexpr (std::is_same<Real, float>::value) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const float4 f = reinterpret_cast<const float4 *>(d)[q];
-                    v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
-                }
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    acc += __int_as_float(__float_as_int(v[q]) & __builtin_amdgcn_sbfe((int)wb, q, 1));
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const double2 f = reinterpret_cast<const double2 *>(d)[q];
-                    v[2 * q] = f.x; v[2 * q + 1] = f.y;
-                }
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {  // both 32-bit halves masked explicitly
-                    const unsigned long long b64 = (unsigned long long)__double_as_longlong(v[q]);
-                    const uint32_t mk = (uint32_t)__builtin_amdgcn_sbfe((int)wb, q, 1);
-                    const uint32_t lo = (uint32_t)b64 & mk, hi = (uint32_t)(b64 >> 32) & mk;
-                    acc += __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-                }
-            }
-            return acc;
-        };
         for (int i = tid; i < n_cand; i += kBlock) {
             const uint32_t e = clist[i];
             const int crow = (int)(e >> 14), s = (int)(e & 4095u);
             const int dir = (int)((e >> 12) & 1u);
             const uint32_t y = (e >> 13) & 1u;
             const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
-            const int j0 = s - a.cutoff;
-            // the up-move table serves both directions: the down move's terms
-            // are the exact negatives, so is its ordered sum (symmetric rounding)
-            Real ec = (Real)0;
-            for (int k = 0; k < dv.n_nbr; ++k) {
-                const uint16_t *rb = rbits + (m + crow + dv.nbr_off[k]) * p16;
-                const int row_at = dv.nbr_dist[k] * a.dpitch;
-                const Real *dr = dt_in_lds ? dt_lds + row_at : reinterpret_cast<const Real *>(a.dtab) + row_at;
-                if (dt_in_lds) {
-                    for (int b = 0; b < n_full; ++b)
-                        ec = block_sum(ec, dt_lds + row_at + 16 * b, window_bits(rb, p16, j0 + 16 * b));
-                } else {
-                    for (int b = 0; b < n_full; ++b)
-                        ec = block_sum(ec, dr + 16 * b, window_bits(rb, p16, j0 + 16 * b));
-                }
-                if (16 * n_full < wn) {  // the last wn % 16 sites, in order
-                    const uint32_t wb = window_bits(rb, p16, j0 + 16 * n_full);
-                    for (int q = 0; q < wn - 16 * n_full; ++q) {
-                        const Real d = dr[16 * n_full + q];
-                        ec += ((wb >> q) & 1u) ? d : (Real)0;
-                    }
-                }
-            }
-            if (dir) ec = -ec;
             const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
+            const double ec64 = a.rphi[rail_at + t] - a.k01 - a.rphi[rail_at + o];
+            const Real ec = (Real)ec64;
             const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[rail_at + o] : (Real)a.ea_scalar;
             const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
             const Real dE = e_app + ec;
@@ -396,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                 const double ratio = ((double)y - pd) / (1.0 - pd);
                 g0 += w_ea * ratio;
                 g1 += w_nu * ratio;
-                g2 += (w_k * (double)ec) * ratio;
+                g2 += (w_k * ec64) * ratio;
                 g3 += (t > o ? w_a : -w_a) * ratio;
             }
         }
@@ -657,6 +588,89 @@ __global__ void copy_bytes(const uint4 *src, uint4 *dst, int64_t n16) {
 // ------------------------------------------------------------------------
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// ------------------------------------------------------------------------
+// Coulomb potential of the score replay, binary64 (main text section 3: the
+// field of the ions; SI Eq. S1 takes its difference between target and
+// origin).  phi(r, s) = sum over the distinct neighbour rails r + off (offsets
+// and minimal-image distances of the device, off = 0 included) and the sites j
+// with |s - j| <= cutoff of occ(r + off, j) K(|s - j|, dist), the site itself
+// excluded.  phi is unpadded: [device offset + r L + s].
+// ------------------------------------------------------------------------
+__device__ double replay_phi_site(const PhiArgs &a, const DevInfo &dv, int r, int s) {
+    const int R = dv.rails, L = dv.sites, cut = a.cutoff;
+    const int lo = s - cut < 0 ? 0 : s - cut, hi = s + cut > L - 1 ? L - 1 : s + cut;
+    double acc = 0.0;
+    for (int k = 0; k < dv.n_nbr; ++k) {
+        const int off = dv.nbr_off[k];
+        int rr = (r + off) % R;
+        rr = rr < 0 ? rr + R : rr;
+        const int8_t *row = a.occ + dv.off_pad + (int64_t)rr * dv.pitch;
+        const double *kr = a.ktab64 + dv.nbr_dist[k] * (cut + 1);
+        for (int j = lo; j <= hi; ++j) {
+            if (off == 0 && j == s) continue;
+            if (row[j] & 1) acc += kr[j < s ? s - j : j - s];
+        }
+    }
+    return acc;
+}
+
+// every site of every device from the state a.occ
+__device__ void replay_phi_all(const PhiArgs &a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int d = 0; d < a.n_devices; ++d) {
+        const DevInfo &dv = a.devs[d];
+        const int64_t n = (int64_t)dv.rails * dv.sites;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+            a.phi[dv.off + i] = replay_phi_site(a, dv, (int)(i / dv.sites), (int)(i % dv.sites));
+    }
+}
+
+__global__ __launch_bounds__(256) void replay_phi_full(PhiArgs a) { replay_phi_all(a); }
+
+// Applies the half-step's accepted hops (device, rail, s, dir; dir 0: o = s,
+// t = s + 1, dir 1: o = s + 1, t = s) to phi: every site within the cutoff of the
+// origin loses the ion's term, every site within the cutoff of the target
+// gains it (binary64 atomic adds; the hops of one half-step touch disjoint
+// bonds).  A list that overflowed (count > capacity) is replaced by a full
+// recomputation from the new state.  The last workgroup to finish clears the
+// count for the next half-step.
+__global__ __launch_bounds__(256) void replay_phi_update(PhiArgs a) {
+    const int64_t cnt = __hip_atomic_load(a.hop_ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (cnt > a.hop_cap) {
+        replay_phi_all(a);
+    } else {
+        const int cut = a.cutoff, w = 2 * cut + 1;
+        for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+            const uint4 e = a.hops[i];
+            const int d = (int)e.x, r = (int)e.y, s = (int)e.z;
+            const int o = e.w ? s + 1 : s, t = e.w ? s : s + 1;
+            const DevInfo &dv = a.devs[d];
+            const int R = dv.rails, L = dv.sites;
+            const int n_pairs = dv.n_nbr * 2 * w;
+            for (int q = threadIdx.x; q < n_pairs; q += blockDim.x) {
+                const int k = q / (2 * w), rem = q - k * 2 * w, side = rem / w;
+                const int c = side ? t : o;  // side 0: the origin loses the ion, side 1: the target gains it
+                const int j = c - cut + (rem - side * w);
+                const int off = dv.nbr_off[k];
+                if (j < 0 || j >= L || (off == 0 && j == c)) continue;
+                int rr = (r + off) % R;
+                rr = rr < 0 ? rr + R : rr;
+                const double kv = a.ktab64[dv.nbr_dist[k] * (cut + 1) + (j < c ? c - j : j - c)];
+                unsafeAtomicAdd(&a.phi[dv.off + (int64_t)rr * L + j], side ? kv : -kv);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long done = atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl + 1), 1ull);
+        if (done == gridDim.x - 1) {
+            __hip_atomic_store(a.hop_ctl, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.hop_ctl + 1, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int kMode>
 static hipError_t launch_half_step(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st) {
     const dim3 grid(a.n_tiles), block(kBlock);
@@ -766,6 +780,18 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st) {
 hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st) {
     const int64_t n16 = (int64_t)(bytes / 16);
     hipLaunchKernelGGL(copy_bytes, dim3(2048), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16);
+    return hipGetLastError();
+}
+
+constexpr int kPhiGrid = 2048;  // workgroups of the potential kernels
+
+hipError_t launch_replay_phi_full(const PhiArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(replay_phi_full, dim3(kPhiGrid), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_replay_phi_update(const PhiArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(replay_phi_update, dim3(kPhiGrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

@@ -1,15 +1,25 @@
 """Score-function replay on the GPU (kmc_score_replay) against the oracle's
 replay on the same seeds, and the autograd bridge (needs an MI355X).
 
-Tolerance.  Both sides take the same decisions and sum the same terms
-W g (y - p)/(1 - p) in binary64, in different orders.  The Coulomb part of
-the energy is summed in the same order on both sides, so p differs only
-through the exponential (device libm vs glibc, a few units in the last place
-of the path's precision, eps).  A relative change dp/p = eps moves a term by
-|W g| p/(1 - p)^2 eps, so
-    |grad_gpu - grad_oracle| <= 4 eps sens + 1e-9 mag
-with sens = sum |W g| p/(1-p)^2 and mag = sum |term| from the oracle; the
-second part covers the binary64 summation order."""
+Tolerance.  Both sides take the same decisions (the replay decides as the
+forward does) and sum the terms W g (y - p)/(1 - p) in binary64, in different
+orders.  The score terms take the Coulomb part of dE in binary64 rounded once
+to the path precision: the GPU as phi(t) - K(1, 0) - phi(o) from a potential
+kept up to date hop by hop, the oracle (coul64) as the window sum.  The two
+binary64 values differ by at most (n + 2 H + 8) eps64 B, with n the window's
+terms, H the device's accepted hops (each changes a site's potential at most
+twice) and B = A + |dE| + |dE_coul| + 2 K(1, 0), A the window's sum of
+|K(t - j)| + |K(o - j)| over occupied sites.  After the rounding to the path
+precision (eps) the Coulomb parts are equal or one unit apart, so dE differs
+by at most eps B, the exponent's argument by (beta/2) eps B plus the two
+roundings of its evaluation (2 eps |arg|), and the exponential by a few units
+(device libm vs glibc).  A relative change dp/p = x moves a term by
+|W g| p/(1 - p)^2 x (and the kappa term also through dE_coul itself), so
+    |grad_gpu - grad_oracle| <= 4 eps sens + 2 eps sens_arg
+                                + (eps + (n + 2 H + 8) eps64) sens_b + 1e-9 mag
+with sens = sum |W g| p/(1-p)^2, sens_arg the same weighted by |arg|,
+sens_b the dE-scale sum of the oracle (orc_run_opts) and mag = sum |term|;
+the last part covers the binary64 summation order."""
 import math
 
 import numpy as np
@@ -25,8 +35,11 @@ pytestmark = [pytest.mark.gpu,
 EPS = {FP64: 2.0 ** -52, FP32: 2.0 ** -23}
 
 
-def _tolerance(ref, precision):
-    return 4 * EPS[precision] * ref["sens"] + 1e-9 * ref["mag"]
+def _tolerance(ref, ph):
+    eps = EPS[ph.precision]
+    n_terms = (2 * ph.rail_range + 1) * (2 * ph.cutoff_sites + 2)
+    c_b = eps + (n_terms + 2 * ref["hops"][:, None] + 8) * EPS[FP64]
+    return 4 * eps * ref["sens"] + 2 * eps * ref["sens_arg"] + c_b * ref["sens_b"] + 1e-9 * ref["mag"]
 
 
 def _forward_and_replay(ph, rails, sites, filling, protocols, n_steps, weights_seed, ea=None, mode="auto",
@@ -44,7 +57,7 @@ def _forward_and_replay(ph, rails, sites, filling, protocols, n_steps, weights_s
     grad = sim.score_replay(occ0, 0, torch.from_numpy(W)).cpu().numpy()
     p_or = oracle.OracleParams(ph, rails, sites, ea)
     fwd = oracle.run(p_or, protocols, occ0_h.copy(), 0, n_steps, want_dec=False)
-    ref = oracle.score_replay(p_or, protocols, occ0_h, 0, W)
+    ref = oracle.score_replay(p_or, protocols, occ0_h, 0, W, coul64=True)
     return sim, grad, ref, net_g.cpu().numpy(), fwd
 
 
@@ -60,7 +73,7 @@ def test_replay_matches_oracle_ragged(precision, mode, tile):
                                                      tile_sites=tile)
     assert np.array_equal(net_g, fwd["net"])      # forward trajectory identical to the oracle's
     assert np.abs(fwd["net"]).sum() > 100
-    tol = _tolerance(ref, precision)
+    tol = _tolerance(ref, ph)
     assert np.all(np.abs(grad - ref["grad"]) <= tol), (grad, ref["grad"], tol)
     assert np.all(ref["mag"] > 0)
 
@@ -72,7 +85,19 @@ def test_replay_with_barrier_field_and_wide_interaction():
     ea = np.random.default_rng(3).normal(0.15, 0.02, size=R * L)
     sim, grad, ref, net_g, fwd = _forward_and_replay(ph, [R], [L], [0.3], [constant(0.6)], 120, 9, ea=ea)
     assert np.array_equal(net_g, fwd["net"])
-    assert np.all(np.abs(grad - ref["grad"]) <= _tolerance(ref, FP64))
+    assert np.all(np.abs(grad - ref["grad"]) <= _tolerance(ref, ph))
+
+
+def test_replay_many_hops_per_half_step():
+    """A barrier low enough that about half the candidates hop: each half-step
+    accepts more hops than the list holds (4096 for this lattice), so the
+    potential is recomputed from the new state after every half-step."""
+    ph = Physics(precision=FP64, seed=21, ea_ev=0.02)
+    R, L = 64, 1024
+    sim, grad, ref, net_g, fwd = _forward_and_replay(ph, [R], [L], [0.3], [triangle(0.5, 40e-12)], 8, 4)
+    assert np.array_equal(net_g, fwd["net"])
+    assert ref["hops"][0] > 8 * 2 * 4096
+    assert np.all(np.abs(grad - ref["grad"]) <= _tolerance(ref, ph)), (grad, ref["grad"], _tolerance(ref, ph))
 
 
 def test_replay_leaves_the_context_alone():
@@ -131,8 +156,8 @@ def test_autograd_backward_equals_oracle_estimator():
     assert np.allclose(f.detach().cpu().numpy(), fo, rtol=0, atol=0)
     base = (fo.sum(axis=1, keepdims=True) - fo) / (D - 1)
     W = np.cumsum((w.numpy()[:, None] * (fo - base))[::-1], axis=0)[::-1]
-    ref = oracle.score_replay(p_or, protos, occ0, 0, W)
-    tol = _tolerance(ref, FP64).sum(axis=0)
+    ref = oracle.score_replay(p_or, protos, occ0, 0, W, coul64=True)
+    tol = _tolerance(ref, ph).sum(axis=0)
     assert np.all(np.abs(g_gpu - ref["grad"].sum(axis=0)) <= tol), (g_gpu, ref["grad"].sum(axis=0), tol)
 
 
@@ -161,6 +186,6 @@ def test_c5_full_size_sampled():
         occ = np.concatenate([np.zeros(2 * d, dtype=np.int8), occ0_h[d]])
         Wd = np.zeros((30, d + 1))
         Wd[:, d] = W[:, d]
-        ref = oracle.score_replay(p_or, [wl.protocols[d]] * (d + 1), occ, 0, Wd)
-        tol = _tolerance(ref, FP32)[d]
+        ref = oracle.score_replay(p_or, [wl.protocols[d]] * (d + 1), occ, 0, Wd, coul64=True)
+        tol = _tolerance(ref, ph)[d]
         assert np.all(np.abs(grad[d] - ref["grad"][d]) <= tol), (d, grad[d], ref["grad"][d], tol)
