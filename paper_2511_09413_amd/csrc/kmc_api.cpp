@@ -1231,9 +1231,9 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     pa.cutoff = c->lay.cut;
     pa.phi = c->at<double>(c->lay.rphi);
     pa.hops = c->at<uint4>(c->lay.hops);
-    pa.hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
     pa.hop_cap = c->lay.hop_cap;
-    KMC_HIP(c, launch_zero_i64(pa.hop_ctl, 2, c->stream));
+    int64_t *hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
+    KMC_HIP(c, launch_zero_i64(hop_ctl, 2, c->stream));
     KMC_HIP(c, launch_replay_phi_full(pa, c->stream));
     for (int64_t k = 0; k < n_steps; ++k) {
         a.n_abs = step0 + k;
@@ -1244,6 +1244,7 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
             a.h = h;
             KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
             pa.occ = nxt;  // the new state, for a full recomputation after an overflow
+            pa.hop_count = hop_ctl + h;
             KMC_HIP(c, launch_replay_phi_update(pa, c->stream));
             std::swap(cur, nxt);
         }

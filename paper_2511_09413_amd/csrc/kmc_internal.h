@@ -91,7 +91,7 @@ struct HopArgs {
     const double *rphi;        // Coulomb potential of the half-step's state, binary64, unpadded
     double k01;                // K(1, 0) in binary64 (0 when the cutoff is 0)
     uint4 *hops;               // accepted hops of the half-step (device, rail, s, dir), hop_cap entries
-    int64_t *hop_ctl;          // [0] entries appended, [1] workgroups done (replay_phi_update)
+    int64_t *hop_ctl;          // [h] entries appended by the half-steps of parity h
     int64_t hop_cap;
     const double *score_w;     // [D] weights of this step's decisions
     double *score_grad;        // [D][4] accumulators (Ea shift, nu0, kappa, alpha)
@@ -113,7 +113,7 @@ struct PhiArgs {
     int32_t cutoff;
     double *phi;               // unpadded [device offset + r L + s]
     const uint4 *hops;         // (device, rail, s, dir): dir 0 moves the ion at s up
-    int64_t *hop_ctl;          // [0] entries, [1] workgroups done; cleared by replay_phi_update
+    const int64_t *hop_count;  // entries appended by the half-step (may exceed hop_cap)
     int64_t hop_cap;
 };
 

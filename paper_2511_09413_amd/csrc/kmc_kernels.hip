@@ -278,11 +278,15 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     //    accepted hops are appended to the global list (device, rail, site,
     //    direction) that replay_phi_update applies before the next half-step.
     if constexpr (kScore) {
+        // the count of the previous half-step's list (the other parity) was
+        // consumed by its update kernel: clear it for the next half-step
+        if (blockIdx.x == 0 && tid == 0)
+            __hip_atomic_store(a.hop_ctl + (1 - H), (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int n_hop = sh.n_hop;
         for (int i = tid; i < n_hop; i += kBlock) {
             const int hr = (int)(hops[i] >> 13), hs = (int)(hops[i] & 8191u);
             const uint32_t dir = (rows[(m + hr) * pitch + hs] & 1) ? 0u : 1u;  // 0: the ion at hs moves up
-            const int64_t k = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl), 1ull);
+            const int64_t k = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl + H), 1ull);
             if (k < a.hop_cap) a.hops[k] = make_uint4((uint32_t)tile.d, (uint32_t)(tile.r0 + hr), (uint32_t)hs, dir);
         }
         uint32_t *clist = surv;
@@ -632,10 +636,10 @@ __global__ __launch_bounds__(256) void replay_phi_full(PhiArgs a) { replay_phi_a
 // origin loses the ion's term, every site within the cutoff of the target
 // gains it (binary64 atomic adds; the hops of one half-step touch disjoint
 // bonds).  A list that overflowed (count > capacity) is replaced by a full
-// recomputation from the new state.  The last workgroup to finish clears the
-// count for the next half-step.
+// recomputation from the new state.  The count is cleared by the replay kernel
+// of the next half-step (which appends to the other parity's count).
 __global__ __launch_bounds__(256) void replay_phi_update(PhiArgs a) {
-    const int64_t cnt = __hip_atomic_load(a.hop_ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t cnt = __hip_atomic_load(a.hop_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cnt > a.hop_cap) {
         replay_phi_all(a);
     } else {
@@ -658,15 +662,6 @@ __global__ __launch_bounds__(256) void replay_phi_update(PhiArgs a) {
                 const double kv = a.ktab64[dv.nbr_dist[k] * (cut + 1) + (j < c ? c - j : j - c)];
                 unsafeAtomicAdd(&a.phi[dv.off + (int64_t)rr * L + j], side ? kv : -kv);
             }
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long done = atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl + 1), 1ull);
-        if (done == gridDim.x - 1) {
-            __hip_atomic_store(a.hop_ctl, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(a.hop_ctl + 1, (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
