@@ -125,3 +125,34 @@ def test_crn_fd_harness_matches_exact_derivative():
     se = per.std(axis=1) / math.sqrt(D)
     for q in range(4):
         assert abs(mean[q] - exact[q]) < 4.5 * se[q] + 1e-3 * abs(exact[q]), (THETA[q], mean[q], exact[q], se[q])
+
+
+def test_coul64_option_and_tolerance_scales():
+    """The coul64 option gives the score terms the binary64 Coulomb sum rounded
+    once to binary32.  The binary64 path is unchanged by it; the binary32 path
+    keeps its decisions (final state, accepted hops) and its gradient moves by
+    no more than a change of each Coulomb part by the binary32 sum's error
+    bound ((n + 1) eps A, n window terms) plus one rounding, with the resulting
+    roundings of the exponent's argument, allow: 2 eps sens_arg + (n + 3) eps
+    sens_b.  The accepted-hop count has the parity and at least the size of the
+    net hop count."""
+    protos = [triangle(1.0, 60e-12), constant(-0.4)]
+    for precision in (FP64, FP32):
+        ph = _physics(precision=precision, ea_ev=0.15, seed=5)
+        p = oracle.OracleParams(ph, [6, 3], [40, 23])
+        occ = oracle.fill(p, [0.3, 0.45])
+        W = np.random.default_rng(2).normal(size=(40, 2))
+        a = oracle.score_replay(p, protos, occ, 0, W)
+        b = oracle.score_replay(p, protos, occ, 0, W, coul64=True)
+        assert np.array_equal(a["occ"], b["occ"]) and np.array_equal(a["hops"], b["hops"])
+        fwd = oracle.run(p, protos, occ.copy(), 0, 40, want_dec=False)
+        net = fwd["net"].sum(axis=0)
+        assert np.all(a["hops"] >= np.abs(net)) and np.all((a["hops"] - net) % 2 == 0)
+        assert np.all(b["sens_b"] > 0) and np.all(b["sens_arg"] > b["sens"])
+        if precision == FP64:
+            assert np.array_equal(a["grad"], b["grad"])
+        else:
+            eps, n = 2.0 ** -23, (2 * ph.rail_range + 1) * (2 * ph.cutoff_sites + 2)
+            diff = np.abs(a["grad"] - b["grad"])
+            assert np.any(diff > 0)
+            assert np.all(diff <= 2 * eps * b["sens_arg"] + (n + 3) * eps * b["sens_b"])
