@@ -354,8 +354,7 @@ void make_tiles(kmc_ctx *c) {
         const size_t cap = (size_t)t.nr * dv.pitch / 2;
         const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
         const size_t kt = n_kt <= (size_t)kLdsTableMax ? n_kt * (c->fp64 ? sizeof(double) : sizeof(float)) : 0;
-        const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
-        const size_t base = rows + (3 * cap + (cap & 1)) * sizeof(uint32_t) + cap * real + kt;
+        const size_t base = rows + (cap + (cap & 1)) * sizeof(uint32_t) + kt;
         lds = std::max(lds, base);
         score_lds = std::max(score_lds, base);
     }

@@ -55,10 +55,10 @@ struct HopShared {
 // by the prefilter).  One lane per 16-site chunk (a tile has at most kBlock
 // chunks).  Dynamic LDS layout:
 //   rows   [(nr + 2m) * pitch] bytes : tile rails and halo rails (snapshot)
-//   surv   [cap] uint32 (row << 13 | s), survw [cap] uint32 (Philox word)
-//   hops   [cap] uint32 (row << 13 | s)
-//   survea [cap] Real (barrier of the survivor's origin)
+//   surv   [cap] uint32 (row << 13 | s; bit 31 set once the hop is accepted)
 //   ktab   [(m + 1) * (cutoff + 1)] Real, when small enough
+// The survivors' Philox words and barriers are read again where they are
+// needed (a rare path), which keeps the LDS per workgroup small.
 // ------------------------------------------------------------------------
 template <typename Real, int H, int kMode>
 __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
@@ -77,10 +77,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     const int cap = tile.nr * pitch / 2;
     unsigned char *rows = smem;
     uint32_t *surv = reinterpret_cast<uint32_t *>(smem + n_rows * pitch);
-    uint32_t *survw = surv + cap;
-    uint32_t *hops = survw + cap;
-    Real *surv_ea = reinterpret_cast<Real *>(hops + cap + (cap & 1));
-    Real *kt_lds = surv_ea + cap;
+    Real *kt_lds = reinterpret_cast<Real *>(surv + cap + (cap & 1));
     const int kt_stride = a.cutoff + 1;
     const int n_kt = (m + 1) * kt_stride;
     const bool kt_in_lds = n_kt <= kLdsTableMax;
@@ -178,14 +175,8 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                 const uint32_t obyte = ob < kChunkSites ? (word_of(v, ob >> 2) >> (8 * (ob & 3))) & 0xFFu : nxt;
                 const uint32_t w = word_of8(blkA, blkB, bit >> 1);
                 if (w <= sh.wtab[obyte >> 1]) {
-                    const int s = s0 + bit;
                     const int k = atomicAdd(&sh.n_surv, 1);
-                    surv[k] = ((uint32_t)row << 13) | (uint32_t)s;
-                    survw[k] = w;
-                    Real ea;
-                    if (a.ea) ea = reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)(tile.r0 + row) * L + s0 + ob];
-                    else ea = (Real)a.ea_scalar;
-                    surv_ea[k] = ea;
+                    surv[k] = ((uint32_t)row << 13) | (uint32_t)(s0 + bit);
                 }
             }
         }
@@ -229,11 +220,15 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                 const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
                 const Real dE = e_app + part;
                 const int srail = tile.r0 + srow;
-                const bool accept = decide_hop<Real>(dE, surv_ea[i], survw[i], beta_r, c0_r, a.log, tile.d, H, n,
-                                                     srail, s);
+                // the survivor's word and its origin's barrier, read again
+                const uint4 blk = philox4x32_10((uint32_t)(s >> 3), (uint32_t)srail, (uint32_t)n, ctr3, a.key0, a.key1);
+                const uint32_t word = word_of(blk, (s >> 1) & 3);
+                const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)srail * L + o]
+                                     : (Real)a.ea_scalar;
+                const bool accept = decide_hop<Real>(dE, ea, word, beta_r, c0_r, a.log, tile.d, H, n, srail, s);
                 if (accept) {
-                    const int k = atomicAdd(&sh.n_hop, 1);
-                    hops[k] = ((uint32_t)srow << 13) | (uint32_t)s;
+                    atomicAdd(&sh.n_hop, 1);
+                    surv[i] |= 1u << 31;
                     if (t < o) atomicAdd(&sh.n_down, 1);
                     else atomicAdd(&sh.n_up, 1);
                     const int qo = (10 * o) / L, qt = (10 * t) / L;
@@ -257,15 +252,18 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     // 5. apply the accepted hops that touch the lane's chunk, write it out
     uint32_t acc = 0;  // accepted bonds starting in the chunk
     if (has_chunk) {
-        const int n_hop = sh.n_hop;
-        for (int k = 0; k < n_hop; ++k) {
-            const int hr = (int)(hops[k] >> 13), hs = (int)(hops[k] & 8191u);
-            if (hr != row) continue;
-            if (hs >= s0 && hs < s0 + kChunkSites) {
-                flip_byte(v, hs - s0);
-                acc |= 1u << (hs - s0);
+        if (sh.n_hop > 0) {
+            for (int k = 0; k < n_surv; ++k) {
+                const uint32_t e = surv[k];
+                if (!(e >> 31)) continue;
+                const int hr = (int)((e >> 13) & 0x3FFFFu), hs = (int)(e & 8191u);
+                if (hr != row) continue;
+                if (hs >= s0 && hs < s0 + kChunkSites) {
+                    flip_byte(v, hs - s0);
+                    acc |= 1u << (hs - s0);
+                }
+                if (hs + 1 >= s0 && hs + 1 < s0 + kChunkSites) flip_byte(v, hs + 1 - s0);
             }
-            if (hs + 1 >= s0 && hs + 1 < s0 + kChunkSites) flip_byte(v, hs + 1 - s0);
         }
         *reinterpret_cast<uint4 *>(a.occ_out + dv.off_pad + (int64_t)(tile.r0 + row) * pitch + s0) = v;
     }
@@ -282,13 +280,15 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         // consumed by its update kernel: clear it for the next half-step
         if (blockIdx.x == 0 && tid == 0)
             __hip_atomic_store(a.hop_ctl + (1 - H), (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int n_hop = sh.n_hop;
-        for (int i = tid; i < n_hop; i += kBlock) {
-            const int hr = (int)(hops[i] >> 13), hs = (int)(hops[i] & 8191u);
+        for (int i = tid; i < n_surv; i += kBlock) {
+            const uint32_t e = surv[i];
+            if (!(e >> 31)) continue;
+            const int hr = (int)((e >> 13) & 0x3FFFFu), hs = (int)(e & 8191u);
             const uint32_t dir = (rows[(m + hr) * pitch + hs] & 1) ? 0u : 1u;  // 0: the ion at hs moves up
             const int64_t k = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl + H), 1ull);
             if (k < a.hop_cap) a.hops[k] = make_uint4((uint32_t)tile.d, (uint32_t)(tile.r0 + hr), (uint32_t)hs, dir);
         }
+        __syncthreads();  // the survivor list becomes the candidate list
         uint32_t *clist = surv;
         if (has_chunk) {
             uint32_t cm = cand_all;
