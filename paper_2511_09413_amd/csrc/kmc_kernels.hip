@@ -290,15 +290,26 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         }
         __syncthreads();  // the survivor list becomes the candidate list
         uint32_t *clist = surv;
-        if (has_chunk) {
-            uint32_t cm = cand_all;
+        {
+            // slots of the lane's candidates: a prefix sum over the wavefront
+            // and one LDS atomic per wavefront
+            const int nc = has_chunk ? __builtin_popcount(cand_all) : 0;
+            int pre = nc;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int t = __shfl_up(pre, d, 64);
+                if (lane >= d) pre += t;
+            }
+            int base = 0;
+            if (lane == 63) base = atomicAdd(&sh.n_cand, pre);
+            int k = __shfl(base, 63, 64) + pre - nc;
+            uint32_t cm = has_chunk ? cand_all : 0u;
             while (cm) {
                 const int bit = __builtin_ctz(cm);
                 cm &= cm - 1;
                 const uint32_t dir = ((bits >> bit) & 1u) ? 0u : 1u;  // 0: ion at s moves up
                 const uint32_t y = (acc >> bit) & 1u;
-                const int k = atomicAdd(&sh.n_cand, 1);
-                clist[k] = ((uint32_t)row << 14) | (y << 13) | (dir << 12) | (uint32_t)(s0 + bit);
+                clist[k++] = ((uint32_t)row << 14) | (y << 13) | (dir << 12) | (uint32_t)(s0 + bit);
             }
         }
         __syncthreads();
@@ -312,27 +323,51 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
         const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-        for (int i = tid; i < n_cand; i += kBlock) {
-            const uint32_t e = clist[i];
-            const int crow = (int)(e >> 14), s = (int)(e & 4095u);
-            const int dir = (int)((e >> 12) & 1u);
-            const uint32_t y = (e >> 13) & 1u;
-            const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
-            const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
-            const double ec64 = a.rphi[rail_at + t] - a.k01 - a.rphi[rail_at + o];
-            const Real ec = (Real)ec64;
-            const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[rail_at + o] : (Real)a.ea_scalar;
-            const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
-            const Real dE = e_app + ec;
-            Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
-            p = p < (Real)1 ? p : (Real)1;
-            if (p < (Real)1) {
-                const double pd = (double)p;
-                const double ratio = ((double)y - pd) / (1.0 - pd);
-                g0 += w_ea * ratio;
-                g1 += w_nu * ratio;
-                g2 += (w_k * ec64) * ratio;
-                g3 += (t > o ? w_a : -w_a) * ratio;
+        // four candidates per lane and pass: their loads are issued together
+        constexpr int kBatch = 4;
+        for (int i0 = tid; i0 < n_cand; i0 += kBatch * kBlock) {
+            double pt[kBatch], po[kBatch];
+            Real ea_b[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int i = i0 + u * kBlock;
+                pt[u] = 0.0;
+                po[u] = 0.0;
+                ea_b[u] = (Real)a.ea_scalar;
+                if (i < n_cand) {
+                    const uint32_t e = clist[i];
+                    const int crow = (int)(e >> 14), s = (int)(e & 4095u);
+                    const int dir = (int)((e >> 12) & 1u);
+                    const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
+                    const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
+                    pt[u] = a.rphi[rail_at + t];
+                    po[u] = a.rphi[rail_at + o];
+                    if (a.ea) ea_b[u] = reinterpret_cast<const Real *>(a.ea)[rail_at + o];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int i = i0 + u * kBlock;
+                if (i >= n_cand) break;
+                const uint32_t e = clist[i];
+                const int s = (int)(e & 4095u);
+                const int dir = (int)((e >> 12) & 1u);
+                const uint32_t y = (e >> 13) & 1u;
+                const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
+                const double ec64 = pt[u] - a.k01 - po[u];
+                const Real ec = (Real)ec64;
+                const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+                const Real dE = e_app + ec;
+                Real p = c0_r * exp_r<Real>(-beta_r * (ea_b[u] + (Real)0.5 * dE));
+                p = p < (Real)1 ? p : (Real)1;
+                if (p < (Real)1) {
+                    const double pd = (double)p;
+                    const double ratio = ((double)y - pd) / (1.0 - pd);
+                    g0 += w_ea * ratio;
+                    g1 += w_nu * ratio;
+                    g2 += (w_k * ec64) * ratio;
+                    g3 += (t > o ? w_a : -w_a) * ratio;
+                }
             }
         }
 #pragma unroll
