@@ -26,9 +26,10 @@
 // With kScore the same kernel replays a half-step for the score-function
 // gradient: the decisions are taken exactly as above (so the replay follows the
 // forward trajectory), and in addition every candidate bond gets its hop
-// probability from the Coulomb potential phi of the half-step's state (binary64,
-// kept up to date by replay_phi_update: dE_coul = phi(t) - K(1, 0) - phi(o),
-// rounded once to the path precision) and contributes W g (y - p)/(1 - p) to
+// probability from the Coulomb potential phi of the half-step's state (binary64
+// differences across each bond, kept up to date by replay_del_update: dE_coul
+// = phi(t) - K(1, 0) - phi(o), rounded once to the path precision) and
+// contributes W g (y - p)/(1 - p) to
 // the device's four accumulators, g being the log-derivative of p in (Ea shift,
 // nu0, kappa, alpha).  The accepted hops go to a global list for the potential
 // update.
@@ -271,10 +272,11 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
     // 6. score replay: every candidate's term W g (y - p)/(1 - p), binary64.
     //    The candidates of the tile are listed in LDS (the survivor list is free
     //    now) and shared round-robin by all lanes.  The Coulomb part of dE is
-    //    phi(t) - K(1, 0) - phi(o) from the potential of the half-step's state,
-    //    in binary64, rounded once to the path precision for p.  The half-step's
-    //    accepted hops are appended to the global list (device, rail, site,
-    //    direction) that replay_phi_update applies before the next half-step.
+    //    phi(t) - K(1, 0) - phi(o) from the potential differences of the
+    //    half-step's state (+-del - K(1, 0)), in binary64, rounded once to the
+    //    path precision for p.  The half-step's accepted hops are appended to
+    //    the global list (device, rail, site, direction) that replay_del_update
+    //    applies before the next half-step.
     if constexpr (kScore) {
         // the count of the previous half-step's list (the other parity) was
         // consumed by its update kernel: clear it for the next half-step
@@ -325,24 +327,24 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
         // four candidates per lane and pass: their loads are issued together
         constexpr int kBatch = 4;
+        const int64_t odd_at = (L + 1) / 2;  // start of the odd bonds in a rail's run
         for (int i0 = tid; i0 < n_cand; i0 += kBatch * kBlock) {
-            double pt[kBatch], po[kBatch];
+            double dl[kBatch];
             Real ea_b[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const int i = i0 + u * kBlock;
-                pt[u] = 0.0;
-                po[u] = 0.0;
+                dl[u] = 0.0;
                 ea_b[u] = (Real)a.ea_scalar;
                 if (i < n_cand) {
                     const uint32_t e = clist[i];
                     const int crow = (int)(e >> 14), s = (int)(e & 4095u);
-                    const int dir = (int)((e >> 12) & 1u);
-                    const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
                     const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
-                    pt[u] = a.rphi[rail_at + t];
-                    po[u] = a.rphi[rail_at + o];
-                    if (a.ea) ea_b[u] = reinterpret_cast<const Real *>(a.ea)[rail_at + o];
+                    dl[u] = a.rdel[rail_at + (H ? odd_at : 0) + (s >> 1)];
+                    if (a.ea) {
+                        const int o = ((e >> 12) & 1u) ? s + 1 : s;
+                        ea_b[u] = reinterpret_cast<const Real *>(a.ea)[rail_at + o];
+                    }
                 }
             }
 #pragma unroll
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                 const int dir = (int)((e >> 12) & 1u);
                 const uint32_t y = (e >> 13) & 1u;
                 const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
-                const double ec64 = pt[u] - a.k01 - po[u];
+                const double ec64 = (dir ? -dl[u] : dl[u]) - a.k01;
                 const Real ec = (Real)ec64;
                 const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
                 const Real dE = e_app + ec;
@@ -633,8 +635,15 @@ static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + b
 // origin).  phi(r, s) = sum over the distinct neighbour rails r + off (offsets
 // and minimal-image distances of the device, off = 0 included) and the sites j
 // with |s - j| <= cutoff of occ(r + off, j) K(|s - j|, dist), the site itself
-// excluded.  phi is unpadded: [device offset + r L + s].
+// excluded.  The replay needs it only as the difference across each bond,
+// del(r, s) = phi(r, s + 1) - phi(r, s), s <= L - 2 (dE_coul = del - K(1, 0)
+// for a hop up, -del - K(1, 0) for a hop down).  del is stored split by bond
+// parity, so that a half-step reads one contiguous run per rail.
 // ------------------------------------------------------------------------
+__device__ __forceinline__ int64_t del_index(const DevInfo &dv, int r, int s) {
+    return dv.off + (int64_t)r * dv.sites + ((s & 1) ? (dv.sites + 1) / 2 : 0) + (s >> 1);
+}
+
 __device__ double replay_phi_site(const PhiArgs &a, const DevInfo &dv, int r, int s) {
     const int R = dv.rails, L = dv.sites, cut = a.cutoff;
     const int lo = s - cut < 0 ? 0 : s - cut, hi = s + cut > L - 1 ? L - 1 : s + cut;
@@ -653,50 +662,61 @@ __device__ double replay_phi_site(const PhiArgs &a, const DevInfo &dv, int r, in
     return acc;
 }
 
-// every site of every device from the state a.occ
-__device__ void replay_phi_all(const PhiArgs &a) {
+// every bond of every device from the state a.occ
+__device__ void replay_del_all(const PhiArgs &a) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int d = 0; d < a.n_devices; ++d) {
         const DevInfo &dv = a.devs[d];
-        const int64_t n = (int64_t)dv.rails * dv.sites;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-            a.phi[dv.off + i] = replay_phi_site(a, dv, (int)(i / dv.sites), (int)(i % dv.sites));
+        const int nb = dv.sites - 1;
+        const int64_t n = (int64_t)dv.rails * nb;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const int r = (int)(i / nb), s = (int)(i - (int64_t)r * nb);
+            a.del[del_index(dv, r, s)] = replay_phi_site(a, dv, r, s + 1) - replay_phi_site(a, dv, r, s);
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void replay_phi_full(PhiArgs a) { replay_phi_all(a); }
+__global__ __launch_bounds__(256) void replay_del_full(PhiArgs a) { replay_del_all(a); }
 
 // Applies the half-step's accepted hops (device, rail, s, dir; dir 0: o = s,
-// t = s + 1, dir 1: o = s + 1, t = s) to phi: every site within the cutoff of the
-// origin loses the ion's term, every site within the cutoff of the target
-// gains it (binary64 atomic adds; the hops of one half-step touch disjoint
-// bonds).  A list that overflowed (count > capacity) is replaced by a full
-// recomputation from the new state.  The count is cleared by the replay kernel
-// of the next half-step (which appends to the other parity's count).
-__global__ __launch_bounds__(256) void replay_phi_update(PhiArgs a) {
+// t = s + 1, dir 1: o = s + 1, t = s) to del: the ion's term leaves every site
+// within the cutoff of the origin and enters every site within the cutoff of
+// the target, which changes del on the bonds j = s - cutoff - 1 .. s + 1 +
+// cutoff of each neighbour rail by dphi(j + 1) - dphi(j) (binary64 atomic adds;
+// the hops of one half-step touch disjoint bonds).  A list that overflowed
+// (count > capacity) is replaced by a full recomputation from the new state.
+// The count is cleared by the replay kernel of the next half-step (which
+// appends to the other parity's count).
+__global__ __launch_bounds__(256) void replay_del_update(PhiArgs a) {
     const int64_t cnt = __hip_atomic_load(a.hop_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cnt > a.hop_cap) {
-        replay_phi_all(a);
-    } else {
-        const int cut = a.cutoff, w = 2 * cut + 1;
-        for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-            const uint4 e = a.hops[i];
-            const int d = (int)e.x, r = (int)e.y, s = (int)e.z;
-            const int o = e.w ? s + 1 : s, t = e.w ? s : s + 1;
-            const DevInfo &dv = a.devs[d];
-            const int R = dv.rails, L = dv.sites;
-            const int n_pairs = dv.n_nbr * 2 * w;
-            for (int q = threadIdx.x; q < n_pairs; q += blockDim.x) {
-                const int k = q / (2 * w), rem = q - k * 2 * w, side = rem / w;
-                const int c = side ? t : o;  // side 0: the origin loses the ion, side 1: the target gains it
-                const int j = c - cut + (rem - side * w);
-                const int off = dv.nbr_off[k];
-                if (j < 0 || j >= L || (off == 0 && j == c)) continue;
-                int rr = (r + off) % R;
-                rr = rr < 0 ? rr + R : rr;
-                const double kv = a.ktab64[dv.nbr_dist[k] * (cut + 1) + (j < c ? c - j : j - c)];
-                unsafeAtomicAdd(&a.phi[dv.off + (int64_t)rr * L + j], side ? kv : -kv);
-            }
+        replay_del_all(a);
+        return;
+    }
+    const int cut = a.cutoff, w = 2 * cut + 3;  // bonds per rail whose del changes
+    for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const uint4 e = a.hops[i];
+        const int d = (int)e.x, r = (int)e.y, s = (int)e.z;
+        const int o = e.w ? s + 1 : s, t = e.w ? s : s + 1;
+        const DevInfo &dv = a.devs[d];
+        const int R = dv.rails, L = dv.sites;
+        for (int q = threadIdx.x; q < dv.n_nbr * w; q += blockDim.x) {
+            const int k = q / w, j = s - cut - 1 + (q - k * w);
+            if (j < 0 || j > L - 2) continue;
+            const int off = dv.nbr_off[k];
+            const double *kr = a.ktab64 + dv.nbr_dist[k] * (cut + 1);
+            // change of phi at site x of this rail: + K(x - t) - K(x - o), no self terms
+            auto dphi = [&](int x) {
+                const int dt = x < t ? t - x : x - t, dO = x < o ? o - x : x - o;
+                const double kt = (dt > cut || (off == 0 && x == t)) ? 0.0 : kr[dt];
+                const double ko = (dO > cut || (off == 0 && x == o)) ? 0.0 : kr[dO];
+                return kt - ko;
+            };
+            const double dd = dphi(j + 1) - dphi(j);
+            if (dd == 0.0) continue;
+            int rr = (r + off) % R;
+            rr = rr < 0 ? rr + R : rr;
+            unsafeAtomicAdd(&a.del[del_index(dv, rr, j)], dd);
         }
     }
 }
@@ -815,13 +835,13 @@ hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream
 
 constexpr int kPhiGrid = 2048;  // workgroups of the potential kernels
 
-hipError_t launch_replay_phi_full(const PhiArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(replay_phi_full, dim3(kPhiGrid), dim3(256), 0, st, a);
+hipError_t launch_replay_del_full(const PhiArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(replay_del_full, dim3(kPhiGrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_replay_phi_update(const PhiArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(replay_phi_update, dim3(kPhiGrid), dim3(256), 0, st, a);
+hipError_t launch_replay_del_update(const PhiArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(replay_del_update, dim3(kPhiGrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
