@@ -94,7 +94,7 @@ typedef struct {
 
 /* Bytes of device workspace kmc_init_device needs for these parameters
  * (apart from the dense precision, this includes 8 bytes per site for the
- * score replay's Coulomb potential). */
+ * score replay's Coulomb potential differences). */
 kmc_status kmc_workspace_bytes(const kmc_params *params, size_t *bytes);
 
 /* Create a context (paper SI S2.2 "initialization": geometry, filling and
@@ -179,12 +179,13 @@ kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t
  * from the same state and steps (the Philox stream is a function of the step
  * index).  The context's own state, step counter and tallies are not touched.
  * The hop probability of every candidate is evaluated in full: the Coulomb
- * part of dE comes from the binary64 potential of every site (the window sum
- * of the interaction kernel, built from occ0 and updated after each half-step
- * by the accepted hops) as phi(t) - K(1, 0) - phi(o), rounded once to the
- * path's precision; the rest of dE and p are evaluated in the path's
+ * part of dE is phi(t) - K(1, 0) - phi(o), phi being the window sum of the
+ * interaction kernel over the occupied sites.  It comes from binary64
+ * differences phi(s + 1) - phi(s) kept for every bond (built from occ0 and
+ * updated after each half-step by the accepted hops) and is rounded once to
+ * the path's precision; the rest of dE and p are evaluated in the path's
  * precision, and the terms are summed in binary64 (sum order not fixed).  The
- * potential and the hop list live in the workspace.
+ * differences and the hop list live in the workspace.
  * Errors: KMC_EINVAL for NULL pointers, negative indices, coulomb_kappa_v == 0
  * or nu0_hz <= 0; KMC_EUNSUPPORTED if step0 + n_steps exceeds 2^32 - 1. */
 kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
