@@ -1,6 +1,10 @@
-// HIP kernels of the rail-KMC hop step for gfx950 (MI355X).
+// HIP kernels of the rail-KMC hop step for gfx950 (MI355X): the half-step
+// kernel (the general path for lattices that are not kept co-resident, and
+// the score replay), the replay's Coulomb-potential differences, and the
+// set-up and bookkeeping kernels.  The persistent kernels are in
+// kmc_persistent.hip and kmc_wave.hip.
 //
-// The hot kernel is hop_half_step: one launch decides every bond of one parity
+// hop_half_step: one launch decides every bond of one parity
 // (a half-step of the pair checkerboard) for every device, reading the state
 // at the start of the half-step from one buffer and writing the new state to
 // the other.  One workgroup owns whole rails of one device ("tile"), one lane
