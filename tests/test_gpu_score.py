@@ -100,6 +100,23 @@ def test_replay_many_hops_per_half_step():
     assert np.all(np.abs(grad - ref["grad"]) <= _tolerance(ref, ph)), (grad, ref["grad"], _tolerance(ref, ph))
 
 
+@pytest.mark.parametrize("rails,sites,m,cut,precision", [
+    ([1, 2, 3], [40, 33, 57], 2, 16, FP64),   # rings shorter than the rail range: duplicate offsets
+    ([4, 2], [19, 64], 1, 0, FP32),           # cutoff 0: no Coulomb term, K(1, 0) = 0
+    ([6], [24], 2, 30, FP32),                 # window longer than the rail
+])
+def test_replay_edge_geometries(rails, sites, m, cut, precision):
+    """Replay of small rings, cutoff 0 and windows longer than the rail, with a
+    barrier low enough that the potential differences see many updates."""
+    ph = Physics(precision=precision, seed=31, ea_ev=0.08, rail_range=m, cutoff_sites=cut)
+    protos = [triangle(1.0, 80e-12), constant(0.5), step_then_relax(-1.0, 30e-12)][:len(rails)]
+    sim, grad, ref, net_g, fwd = _forward_and_replay(ph, rails, sites, [0.4] * len(rails), protos, 80, 6)
+    assert np.array_equal(net_g, fwd["net"])
+    assert np.all(ref["hops"] > 20)
+    tol = _tolerance(ref, ph)
+    assert np.all(np.abs(grad - ref["grad"]) <= tol), (grad, ref["grad"], tol)
+
+
 def test_replay_leaves_the_context_alone():
     """Replaying does not change the state, the step counter or the tallies:
     continuing afterwards gives the same trajectory as a context that never
