@@ -455,12 +455,12 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         }
     }
 
-    // The publication of each new state: lane 0 of a tile with neighbours
-    // writes word j of the tile's slots with tag tag_hi | j.  The address, the
-    // tag and the snapshot count live in vector registers (they change every
-    // half-step or only on a rare path), which keeps the scalar registers for
-    // the loop's own values.
-    const bool pub_lane = lane == 0 && !isolated;
+    // The publication of each new state: lane 0 writes word j of the tile's
+    // slots with tag tag_hi | j (an isolated tile writes its words too; no
+    // tile reads them, and the store needs no tile-dependent condition).  The
+    // address, the tag and the snapshot count live in vector registers (they
+    // change every half-step or only on a rare path), which keeps the scalar
+    // registers for the loop's own values.
     uint64_t *pub_at = own;
     uint32_t tag_j = tag_hi;
     asm volatile("" : "+v"(tag_j), "+v"(snap_count));
@@ -470,7 +470,13 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     // for a neighbour failed.
     auto half_step = [&](auto h_c, const int kstep, const PhStep<kNB> &ps) -> bool {
         constexpr int h = decltype(h_c)::value;
-        const int js = 2 * kstep + h;
+        // the state index, needed only on rare paths: derived there from an
+        // opaque copy of the step, so that no register holds it across the step
+        auto js_now = [&]() -> int {
+            int k = kstep;
+            asm volatile("" : "+s"(k));
+            return 2 * k + h;
+        };
         const int kw = kstep & (kWaveWin - 1);
 
         // candidates: bonds of parity h whose two sites differ
@@ -529,7 +535,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             };
             wr.snap[lane] = bits;
             bool ok = true;
-            if (!isolated) ok = fetch_bands(ka, wr, js);
+            if (!isolated) ok = fetch_bands(ka, wr, js_now());
             wave_sync();
             if (!ok) return false;
             uint32_t fl = 0;
@@ -614,7 +620,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         ++pub_at;
         ++tag_j;
         if (edge_changed && !isolated) {
-            const uint32_t jn = (uint32_t)js + 1u;
+            const uint32_t jn = (uint32_t)js_now() + 1u;
             const KArgs ka = kargs();
             WaveLds<SPL> &wr = *lds_opaque(&w);
             const int sc = rfl(snap_count) + 1;
@@ -635,7 +641,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             if (lane == 0) wr.snap_state[slot] = (int16_t)jn;
             snap_word = ((uint32_t)slot << 12) | jn;
         }
-        if (pub_lane)
+        if (lane == 0)
             __hip_atomic_store(pub_at, ((uint64_t)tag_j << 32) | snap_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     };
