@@ -1228,6 +1228,7 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     pa.n_devices = D;
     pa.ktab64 = c->at<double>(c->lay.ktab64);
     pa.cutoff = c->lay.cut;
+    pa.rail_range = c->p.rail_range;
     pa.del = c->at<double>(c->lay.rdel);
     pa.hops = c->at<uint4>(c->lay.hops);
     pa.hop_cap = c->lay.hop_cap;

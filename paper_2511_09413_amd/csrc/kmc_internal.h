@@ -111,7 +111,7 @@ struct PhiArgs {
     const DevInfo *devs;
     int32_t n_devices;
     const double *ktab64;      // [(m+1)][(c+1)] kernel table
-    int32_t cutoff;
+    int32_t cutoff, rail_range;
     double *del;               // [device offset + r L + (s odd ? (L + 1) / 2 : 0) + s / 2]
     const uint4 *hops;         // (device, rail, s, dir): dir 0 moves the ion at s up
     const int64_t *hop_count;  // entries appended by the half-step (may exceed hop_cap)

@@ -405,13 +405,25 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
 // Caller layout -> padded internal layout: bit 0 = occupied (any nonzero
 // byte), bits 1..7 = barrier class floor((Ea - ea_min)/ea_step) clamped to
 // [0, 127] (0 without a barrier field); padding bytes cleared.
+// The device holding element i of the padded (or unpadded) layout: the last
+// device whose offset is <= i (offsets ascend), by bisection.
+__device__ __forceinline__ int device_of(const DevInfo *devs, int n_dev, int64_t i, bool padded) {
+    int lo = 0, hi = n_dev - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int64_t at = padded ? devs[mid].off_pad : devs[mid].off;
+        if (at <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <typename Real>
 __global__ void import_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
                                  int64_t total_pad, const Real *ea) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total_pad) return;
-    int d = 0;
-    while (d + 1 < n_dev && devs[d + 1].off_pad <= i) ++d;
+    const int d = device_of(devs, n_dev, i, true);
     const DevInfo &dv = devs[d];
     const int64_t loc = i - dv.off_pad;
     const int r = (int)(loc / dv.pitch), s = (int)(loc - (int64_t)r * dv.pitch);
@@ -432,8 +444,7 @@ __global__ void export_occupancy(const int8_t *src, int8_t *dst, const DevInfo *
                                  int64_t total) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    int d = 0;
-    while (d + 1 < n_dev && devs[d + 1].off <= i) ++d;
+    const int d = device_of(devs, n_dev, i, false);
     const DevInfo &dv = devs[d];
     const int64_t loc = i - dv.off;
     const int r = (int)(loc / dv.sites), s = (int)(loc - (int64_t)r * dv.sites);
@@ -680,7 +691,65 @@ __device__ void replay_del_all(const PhiArgs &a) {
     }
 }
 
-__global__ __launch_bounds__(256) void replay_del_full(PhiArgs a) { replay_del_all(a); }
+// The starting differences, one workgroup per run of up to 256 bonds of one
+// rail: the occupancy of the run's window on every neighbour rail is staged
+// in LDS (zero outside the rail), and each lane sums its bond's terms over the
+// window in one pass, occ(j) D(dist, j - s + cut) with D the table of
+// K(|s + 1 - j|, dist) - K(|s - j|, dist) (the distance-0 row, the bond's own
+// rail, without the self terms).  Windows wider than kDelMaxCut fall back to
+// replay_del_all.
+constexpr int kDelRun = 256;
+constexpr int kDelMaxCut = 512;
+
+__global__ __launch_bounds__(kDelRun) void replay_del_full(PhiArgs a) {
+    const int cut = a.cutoff;
+    if (cut > kDelMaxCut) {
+        replay_del_all(a);
+        return;
+    }
+    __shared__ uint8_t win[2 * kMaxRailRange + 1][kDelRun + 2 * kDelMaxCut + 2];
+    __shared__ double dtab[(kMaxRailRange + 1) * (2 * kDelMaxCut + 2)];
+    const int wn = 2 * cut + 2;               // window of a bond: sites s - cut .. s + 1 + cut
+    const int width = kDelRun + 2 * cut + 2;  // window of the run: sites b0 - cut .. b0 + kDelRun + cut + 1
+    for (int i = threadIdx.x; i < (a.rail_range + 1) * wn; i += kDelRun) {
+        const int dist = i / wn, x = i - dist * wn;
+        const int dt = x - cut - 1 < 0 ? cut + 1 - x : x - cut - 1, dO = x - cut < 0 ? cut - x : x - cut;
+        const double *kr = a.ktab64 + dist * (cut + 1);
+        const double kt = (dt > cut || (dist == 0 && dt == 0)) ? 0.0 : kr[dt];
+        const double ko = (dO > cut || (dist == 0 && dO == 0)) ? 0.0 : kr[dO];
+        dtab[i] = kt - ko;
+    }
+    for (int d = 0; d < a.n_devices; ++d) {
+        const DevInfo &dv = a.devs[d];
+        const int R = dv.rails, L = dv.sites, nb = L - 1;
+        const int runs = (nb + kDelRun - 1) / kDelRun;
+        const int64_t units = (int64_t)R * runs;
+        for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+            const int r = (int)(u / runs), b0 = (int)(u - (int64_t)r * runs) * kDelRun;
+            __syncthreads();  // the table is written; the previous unit's window is no longer read
+            for (int k = 0; k < dv.n_nbr; ++k) {
+                int rr = (r + dv.nbr_off[k]) % R;
+                rr = rr < 0 ? rr + R : rr;
+                const int8_t *row = a.occ + dv.off_pad + (int64_t)rr * dv.pitch;
+                for (int x = threadIdx.x; x < width; x += kDelRun) {
+                    const int j = b0 - cut + x;
+                    win[k][x] = (j >= 0 && j < L) ? (uint8_t)(row[j] & 1) : (uint8_t)0;
+                }
+            }
+            __syncthreads();
+            const int s = b0 + (int)threadIdx.x;
+            if (s < nb) {
+                double acc = 0.0;
+                for (int k = 0; k < dv.n_nbr; ++k) {
+                    const double *dr = dtab + dv.nbr_dist[k] * wn;
+                    const uint8_t *w = win[k] + (int)threadIdx.x;  // w[x] is site s - cut + x
+                    for (int x = 0; x < wn; ++x) acc = fma((double)w[x], dr[x], acc);
+                }
+                a.del[del_index(dv, r, s)] = acc;
+            }
+        }
+    }
+}
 
 // Applies the half-step's accepted hops (device, rail, s, dir; dir 0: o = s,
 // t = s + 1, dir 1: o = s + 1, t = s) to del: the ion's term leaves every site
@@ -840,7 +909,7 @@ hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream
 constexpr int kPhiGrid = 2048;  // workgroups of the potential kernels
 
 hipError_t launch_replay_del_full(const PhiArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(replay_del_full, dim3(kPhiGrid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(replay_del_full, dim3(kPhiGrid), dim3(kDelRun), 0, st, a);
     return hipGetLastError();
 }
 
