@@ -45,8 +45,8 @@ hipError_t wave_capacity(int spl, size_t lds, bool fp64, int *blocks_per_cu);
 size_t wave_lds_bytes(int spl, int n_kt, bool fp64);
 int wave_band_words(int spl);
 hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st);
-hipError_t launch_replay_del_full(const PhiArgs &a, hipStream_t st);
-hipError_t launch_replay_del_update(const PhiArgs &a, hipStream_t st);
+hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st);
+hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st);
 hipError_t launch_dense_phi(const DenseArgs &a, hipStream_t st);
 hipError_t launch_dense_decide(const HopArgs &a, int pitch, hipStream_t st);
 hipError_t set_dense_lds_limit(size_t lds_bytes);
@@ -75,7 +75,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
-        rp_a, rp_b, score_log, rdel, hops, hop_ctl, phi, ktiles, dtiles, ctiles, total;
+        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
     size_t wtiles;                    // wave tiling (PTile array)
@@ -220,14 +220,15 @@ Layout layout_for(const kmc_params *p) {
     L.wtiles = take(sizeof(PTile) * (size_t)rails);  // every wave tile is at least one rail
     L.status = take(sizeof(int32_t) * 4);
     // score replay: its own pair of state planes, a discarded event count, the
-    // binary64 Coulomb potential differences across every bond and the list of
-    // a half-step's accepted hops (a longer list falls back to recomputing them)
+    // Coulomb part of every bond's energy change (path precision) and the list
+    // of a half-step's accepted hops (a longer list falls back to recomputing
+    // every bond)
     L.rp_a = take((size_t)pad);
     L.rp_b = take((size_t)pad);
     L.score_log = take(sizeof(int64_t));
     L.hop_cap = std::min<int64_t>(std::max<int64_t>(L.total_sites / 64, 4096), (int64_t)1 << 24);
     if (p->precision != KMC_BF16X2) {
-        L.rdel = take(sizeof(double) * (size_t)L.total_sites);
+        L.rec = take((p->precision == KMC_FP64 ? sizeof(double) : sizeof(float)) * (size_t)L.total_sites);
         L.hops = take(sizeof(uint4) * (size_t)L.hop_cap);
         L.hop_ctl = take(sizeof(int64_t) * 2);
     }
@@ -558,11 +559,10 @@ HopArgs hop_args(kmc_ctx *c) {
     a.nu0 = c->p.nu0_hz;
     a.kappa = c->p.coulomb_kappa_v;
     if (!c->dense) {
-        a.rdel = c->at<double>(c->lay.rdel);
+        a.rec = c->ws + c->lay.rec;
         a.hops = c->at<uint4>(c->lay.hops);
         a.hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
         a.hop_cap = c->lay.hop_cap;
-        a.k01 = c->k01;
     }
     if (c->dense) {
         a.phi = c->at<float>(c->lay.phi);
@@ -1220,8 +1220,9 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     a.log.count = c->at<int64_t>(c->lay.score_log);
     a.log.cap = 0;
     a.score_grad = grad_dev;
-    // the potential differences of the starting state, then per half-step the
-    // replay (which lists its accepted hops) and their update
+    // the Coulomb parts of the starting state, then per half-step the replay
+    // (which lists its accepted hops) and the recomputation of the bonds they
+    // changed
     PhiArgs pa{};
     pa.occ = cur;
     pa.devs = c->at<DevInfo>(c->lay.devs);
@@ -1229,12 +1230,13 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     pa.ktab64 = c->at<double>(c->lay.ktab64);
     pa.cutoff = c->lay.cut;
     pa.rail_range = c->p.rail_range;
-    pa.del = c->at<double>(c->lay.rdel);
+    pa.ec = c->ws + c->lay.rec;
+    pa.k01 = c->k01;
     pa.hops = c->at<uint4>(c->lay.hops);
     pa.hop_cap = c->lay.hop_cap;
     int64_t *hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
     KMC_HIP(c, launch_zero_i64(hop_ctl, 2, c->stream));
-    KMC_HIP(c, launch_replay_del_full(pa, c->stream));
+    KMC_HIP(c, launch_replay_ec_full(pa, c->fp64, c->stream));
     for (int64_t k = 0; k < n_steps; ++k) {
         a.n_abs = step0 + k;
         a.score_w = weight_dev + k * D;
@@ -1245,7 +1247,7 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
             KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
             pa.occ = nxt;  // the new state, for a full recomputation after an overflow
             pa.hop_count = hop_ctl + h;
-            KMC_HIP(c, launch_replay_del_update(pa, c->stream));
+            KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream));
             std::swap(cur, nxt);
         }
     }

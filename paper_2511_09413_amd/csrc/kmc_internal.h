@@ -88,9 +88,8 @@ struct HopArgs {
     // score replay only (hop_half_step<..., 1>)
     int64_t n_abs;             // step index of the launch
     double nu0, kappa;
-    const double *rdel;        // phi(s + 1) - phi(s) of the half-step's state per bond, binary64,
-                               // [device offset + r L + (s odd ? (L + 1) / 2 : 0) + s / 2]
-    double k01;                // K(1, 0) in binary64 (0 when the cutoff is 0)
+    const void *rec;           // Coulomb part of each candidate bond's dE in the half-step's state,
+                               // path precision, [device offset + r L + (s odd ? (L + 1) / 2 : 0) + s / 2]
     uint4 *hops;               // accepted hops of the half-step (device, rail, s, dir), hop_cap entries
     int64_t *hop_ctl;          // [h] entries appended by the half-steps of parity h
     int64_t hop_cap;
@@ -104,15 +103,16 @@ struct HopArgs {
     int32_t n_dtiles;
 };
 
-// Coulomb potential differences across the bonds, for the score replay
-// (binary64), and their update by the accepted hops of a half-step.
+// Coulomb part of every candidate bond's energy change, for the score replay,
+// and its recomputation where the accepted hops of a half-step changed it.
 struct PhiArgs {
     const int8_t *occ;         // padded state (bit 0 = occupied): read by full recomputations
     const DevInfo *devs;
     int32_t n_devices;
     const double *ktab64;      // [(m+1)][(c+1)] kernel table
     int32_t cutoff, rail_range;
-    double *del;               // [device offset + r L + (s odd ? (L + 1) / 2 : 0) + s / 2]
+    double k01;                // K(1, 0) in binary64 (0 when the cutoff is 0)
+    void *ec;                  // path precision, [device offset + r L + (s odd ? (L + 1) / 2 : 0) + s / 2]
     const uint4 *hops;         // (device, rail, s, dir): dir 0 moves the ion at s up
     const int64_t *hop_count;  // entries appended by the half-step (may exceed hop_cap)
     int64_t hop_cap;

@@ -1,6 +1,6 @@
 // HIP kernels of the rail-KMC hop step for gfx950 (MI355X): the half-step
 // kernel (the general path for lattices that are not kept co-resident, and
-// the score replay), the replay's Coulomb-potential differences, and the
+// the score replay), the replay's per-bond Coulomb parts, and the
 // set-up and bookkeeping kernels.  The persistent kernels are in
 // kmc_persistent.hip and kmc_wave.hip.
 //
@@ -30,9 +30,9 @@
 // With kScore the same kernel replays a half-step for the score-function
 // gradient: the decisions are taken exactly as above (so the replay follows the
 // forward trajectory), and in addition every candidate bond gets its hop
-// probability from the Coulomb potential phi of the half-step's state (binary64
-// differences across each bond, kept up to date by replay_del_update: dE_coul
-// = phi(t) - K(1, 0) - phi(o), rounded once to the path precision) and
+// probability from the Coulomb part dE_coul = phi(t) - K(1, 0) - phi(o) of the
+// half-step's state (kept per bond, summed in binary64 and rounded once to the
+// path precision, recomputed by replay_ec_update where hops changed it) and
 // contributes W g (y - p)/(1 - p) to
 // the device's four accumulators, g being the log-derivative of p in (Ea shift,
 // nu0, kappa, alpha).  The accepted hops go to a global list for the potential
@@ -275,12 +275,12 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
 
     // 6. score replay: every candidate's term W g (y - p)/(1 - p), binary64.
     //    The candidates of the tile are listed in LDS (the survivor list is free
-    //    now) and shared round-robin by all lanes.  The Coulomb part of dE is
-    //    phi(t) - K(1, 0) - phi(o) from the potential differences of the
-    //    half-step's state (+-del - K(1, 0)), in binary64, rounded once to the
-    //    path precision for p.  The half-step's accepted hops are appended to
-    //    the global list (device, rail, site, direction) that replay_del_update
-    //    applies before the next half-step.
+    //    now) and shared round-robin by all lanes.  The Coulomb part of dE,
+    //    phi(t) - K(1, 0) - phi(o), is read from the per-bond values of the
+    //    half-step's state (summed in binary64, rounded once to the path
+    //    precision).  The half-step's accepted hops are appended to the global
+    //    list (device, rail, site, direction) from which replay_ec_update
+    //    recomputes the bonds they changed before the next half-step.
     if constexpr (kScore) {
         // the count of the previous half-step's list (the other parity) was
         // consumed by its update kernel: clear it for the next half-step
@@ -331,20 +331,20 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
         // four candidates per lane and pass: their loads are issued together
         constexpr int kBatch = 4;
+        const Real *ec_of = reinterpret_cast<const Real *>(a.rec);
         const int64_t odd_at = (L + 1) / 2;  // start of the odd bonds in a rail's run
         for (int i0 = tid; i0 < n_cand; i0 += kBatch * kBlock) {
-            double dl[kBatch];
-            Real ea_b[kBatch];
+            Real ec_b[kBatch], ea_b[kBatch];
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const int i = i0 + u * kBlock;
-                dl[u] = 0.0;
+                ec_b[u] = (Real)0;
                 ea_b[u] = (Real)a.ea_scalar;
                 if (i < n_cand) {
                     const uint32_t e = clist[i];
                     const int crow = (int)(e >> 14), s = (int)(e & 4095u);
                     const int64_t rail_at = dv.off + (int64_t)(tile.r0 + crow) * L;
-                    dl[u] = a.rdel[rail_at + (H ? odd_at : 0) + (s >> 1)];
+                    ec_b[u] = ec_of[rail_at + (H ? odd_at : 0) + (s >> 1)];
                     if (a.ea) {
                         const int o = ((e >> 12) & 1u) ? s + 1 : s;
                         ea_b[u] = reinterpret_cast<const Real *>(a.ea)[rail_at + o];
@@ -360,8 +360,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                 const int dir = (int)((e >> 12) & 1u);
                 const uint32_t y = (e >> 13) & 1u;
                 const int o = dir ? s + 1 : s, t = dir ? s : s + 1;
-                const double ec64 = (dir ? -dl[u] : dl[u]) - a.k01;
-                const Real ec = (Real)ec64;
+                const Real ec = ec_b[u];
                 const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
                 const Real dE = e_app + ec;
                 Real p = c0_r * exp_r<Real>(-beta_r * (ea_b[u] + (Real)0.5 * dE));
@@ -371,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                     const double ratio = ((double)y - pd) / (1.0 - pd);
                     g0 += w_ea * ratio;
                     g1 += w_nu * ratio;
-                    g2 += (w_k * ec64) * ratio;
+                    g2 += (w_k * (double)ec) * ratio;
                     g3 += (t > o ? w_a : -w_a) * ratio;
                 }
             }
@@ -645,24 +644,32 @@ __global__ void copy_bytes(const uint4 *src, uint4 *dst, int64_t n16) {
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // ------------------------------------------------------------------------
-// Coulomb potential of the score replay, binary64 (main text section 3: the
-// field of the ions; SI Eq. S1 takes its difference between target and
-// origin).  phi(r, s) = sum over the distinct neighbour rails r + off (offsets
-// and minimal-image distances of the device, off = 0 included) and the sites j
-// with |s - j| <= cutoff of occ(r + off, j) K(|s - j|, dist), the site itself
-// excluded.  The replay needs it only as the difference across each bond,
-// del(r, s) = phi(r, s + 1) - phi(r, s), s <= L - 2 (dE_coul = del - K(1, 0)
-// for a hop up, -del - K(1, 0) for a hop down).  del is stored split by bond
-// parity, so that a half-step reads one contiguous run per rail.
+// Coulomb part of the energy change of every candidate bond, for the score
+// replay (main text section 3: the field of the ions; SI Eq. S1 takes its
+// difference between target and origin).  With phi(r, s) the sum over the
+// distinct neighbour rails r + off (offsets and minimal-image distances of
+// the device, off = 0 included) and the sites j with |s - j| <= cutoff of
+// occ(r + off, j) K(|s - j|, dist), the site itself excluded, a candidate bond
+// (s, s+1) with its ion at o and the empty site t has
+//     ec = phi(t) - K(1, 0) - phi(o) = +-(phi(s + 1) - phi(s)) - K(1, 0).
+// It is summed in binary64 in one pass over the bond's window and rounded once
+// to the path precision; a bond that is not a candidate holds 0.  The values
+// are kept for every bond, split by bond parity so that a half-step reads one
+// contiguous run per rail, and recomputed from the new state for every bond
+// whose window an accepted hop changed.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ int64_t del_index(const DevInfo &dv, int r, int s) {
+__device__ __forceinline__ int64_t bond_index(const DevInfo &dv, int r, int s) {
     return dv.off + (int64_t)r * dv.sites + ((s & 1) ? (dv.sites + 1) / 2 : 0) + (s >> 1);
 }
 
-__device__ double replay_phi_site(const PhiArgs &a, const DevInfo &dv, int r, int s) {
+template <typename Real>
+__device__ Real replay_bond_ec(const PhiArgs &a, const DevInfo &dv, int r, int s) {
     const int R = dv.rails, L = dv.sites, cut = a.cutoff;
-    const int lo = s - cut < 0 ? 0 : s - cut, hi = s + cut > L - 1 ? L - 1 : s + cut;
-    double acc = 0.0;
+    const int8_t *own = a.occ + dv.off_pad + (int64_t)r * dv.pitch;
+    const int up = own[s] & 1;
+    if (up == (own[s + 1] & 1)) return (Real)0;
+    const int lo = s - cut < 0 ? 0 : s - cut, hi = s + 1 + cut > L - 1 ? L - 1 : s + 1 + cut;
+    double acc = 0.0;  // phi(s + 1) - phi(s)
     for (int k = 0; k < dv.n_nbr; ++k) {
         const int off = dv.nbr_off[k];
         int rr = (r + off) % R;
@@ -670,15 +677,20 @@ __device__ double replay_phi_site(const PhiArgs &a, const DevInfo &dv, int r, in
         const int8_t *row = a.occ + dv.off_pad + (int64_t)rr * dv.pitch;
         const double *kr = a.ktab64 + dv.nbr_dist[k] * (cut + 1);
         for (int j = lo; j <= hi; ++j) {
-            if (off == 0 && j == s) continue;
-            if (row[j] & 1) acc += kr[j < s ? s - j : j - s];
+            if (!(row[j] & 1)) continue;
+            const int dt = j < s + 1 ? s + 1 - j : j - s - 1, dO = j < s ? s - j : j - s;
+            const double kt = (dt > cut || (off == 0 && j == s + 1)) ? 0.0 : kr[dt];
+            const double ko = (dO > cut || (off == 0 && j == s)) ? 0.0 : kr[dO];
+            acc += kt - ko;
         }
     }
-    return acc;
+    return (Real)((up ? acc : -acc) - a.k01);
 }
 
 // every bond of every device from the state a.occ
-__device__ void replay_del_all(const PhiArgs &a) {
+template <typename Real>
+__device__ void replay_ec_all(const PhiArgs &a) {
+    Real *ec = reinterpret_cast<Real *>(a.ec);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int d = 0; d < a.n_devices; ++d) {
         const DevInfo &dv = a.devs[d];
@@ -686,32 +698,33 @@ __device__ void replay_del_all(const PhiArgs &a) {
         const int64_t n = (int64_t)dv.rails * nb;
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
             const int r = (int)(i / nb), s = (int)(i - (int64_t)r * nb);
-            a.del[del_index(dv, r, s)] = replay_phi_site(a, dv, r, s + 1) - replay_phi_site(a, dv, r, s);
+            ec[bond_index(dv, r, s)] = replay_bond_ec<Real>(a, dv, r, s);
         }
     }
 }
 
-// The starting differences, one workgroup per run of up to 256 bonds of one
-// rail: the occupancy of the run's window on every neighbour rail is staged
-// in LDS (zero outside the rail), and each lane sums its bond's terms over the
-// window in one pass, occ(j) D(dist, j - s + cut) with D the table of
-// K(|s + 1 - j|, dist) - K(|s - j|, dist) (the distance-0 row, the bond's own
-// rail, without the self terms).  Windows wider than kDelMaxCut fall back to
-// replay_del_all.
-constexpr int kDelRun = 256;
-constexpr int kDelMaxCut = 512;
+// The starting values, one workgroup per run of up to 256 bonds of one rail:
+// the occupancy of the run's window on every neighbour rail is staged in LDS
+// (zero outside the rail), and each lane sums its bond's terms in one pass,
+// occ(j) D(dist, j - s + cut) with D the table of K(|s + 1 - j|, dist) -
+// K(|s - j|, dist) (the distance-0 row, the bond's own rail, without the self
+// terms).  Windows wider than kEcMaxCut fall back to replay_ec_all.
+constexpr int kEcRun = 256;
+constexpr int kEcMaxCut = 512;
 
-__global__ __launch_bounds__(kDelRun) void replay_del_full(PhiArgs a) {
+template <typename Real>
+__global__ __launch_bounds__(kEcRun) void replay_ec_full(PhiArgs a) {
     const int cut = a.cutoff;
-    if (cut > kDelMaxCut) {
-        replay_del_all(a);
+    if (cut > kEcMaxCut) {
+        replay_ec_all<Real>(a);
         return;
     }
-    __shared__ uint8_t win[2 * kMaxRailRange + 1][kDelRun + 2 * kDelMaxCut + 2];
-    __shared__ double dtab[(kMaxRailRange + 1) * (2 * kDelMaxCut + 2)];
+    Real *ec = reinterpret_cast<Real *>(a.ec);
+    __shared__ uint8_t win[2 * kMaxRailRange + 1][kEcRun + 2 * kEcMaxCut + 2];
+    __shared__ double dtab[(kMaxRailRange + 1) * (2 * kEcMaxCut + 2)];
     const int wn = 2 * cut + 2;               // window of a bond: sites s - cut .. s + 1 + cut
-    const int width = kDelRun + 2 * cut + 2;  // window of the run: sites b0 - cut .. b0 + kDelRun + cut + 1
-    for (int i = threadIdx.x; i < (a.rail_range + 1) * wn; i += kDelRun) {
+    const int width = kEcRun + 2 * cut + 2;   // window of the run: sites b0 - cut .. b0 + kEcRun + cut + 1
+    for (int i = threadIdx.x; i < (a.rail_range + 1) * wn; i += kEcRun) {
         const int dist = i / wn, x = i - dist * wn;
         const int dt = x - cut - 1 < 0 ? cut + 1 - x : x - cut - 1, dO = x - cut < 0 ? cut - x : x - cut;
         const double *kr = a.ktab64 + dist * (cut + 1);
@@ -722,16 +735,19 @@ __global__ __launch_bounds__(kDelRun) void replay_del_full(PhiArgs a) {
     for (int d = 0; d < a.n_devices; ++d) {
         const DevInfo &dv = a.devs[d];
         const int R = dv.rails, L = dv.sites, nb = L - 1;
-        const int runs = (nb + kDelRun - 1) / kDelRun;
+        const int runs = (nb + kEcRun - 1) / kEcRun;
         const int64_t units = (int64_t)R * runs;
+        int k_own = 0;  // the entry of offset 0 (the bond's own rail)
+        for (int k = 0; k < dv.n_nbr; ++k)
+            if (dv.nbr_off[k] == 0) k_own = k;
         for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
-            const int r = (int)(u / runs), b0 = (int)(u - (int64_t)r * runs) * kDelRun;
+            const int r = (int)(u / runs), b0 = (int)(u - (int64_t)r * runs) * kEcRun;
             __syncthreads();  // the table is written; the previous unit's window is no longer read
             for (int k = 0; k < dv.n_nbr; ++k) {
                 int rr = (r + dv.nbr_off[k]) % R;
                 rr = rr < 0 ? rr + R : rr;
                 const int8_t *row = a.occ + dv.off_pad + (int64_t)rr * dv.pitch;
-                for (int x = threadIdx.x; x < width; x += kDelRun) {
+                for (int x = threadIdx.x; x < width; x += kEcRun) {
                     const int j = b0 - cut + x;
                     win[k][x] = (j >= 0 && j < L) ? (uint8_t)(row[j] & 1) : (uint8_t)0;
                 }
@@ -739,57 +755,109 @@ __global__ __launch_bounds__(kDelRun) void replay_del_full(PhiArgs a) {
             __syncthreads();
             const int s = b0 + (int)threadIdx.x;
             if (s < nb) {
-                double acc = 0.0;
-                for (int k = 0; k < dv.n_nbr; ++k) {
-                    const double *dr = dtab + dv.nbr_dist[k] * wn;
-                    const uint8_t *w = win[k] + (int)threadIdx.x;  // w[x] is site s - cut + x
-                    for (int x = 0; x < wn; ++x) acc = fma((double)w[x], dr[x], acc);
+                const uint8_t *w_own = win[k_own] + (int)threadIdx.x;  // w[x] is site s - cut + x
+                const int up = w_own[cut];
+                Real v = (Real)0;
+                if (up != w_own[cut + 1]) {
+                    double acc = 0.0;
+                    for (int k = 0; k < dv.n_nbr; ++k) {
+                        const double *dr = dtab + dv.nbr_dist[k] * wn;
+                        const uint8_t *w = win[k] + (int)threadIdx.x;
+                        for (int x = 0; x < wn; ++x) acc = fma((double)w[x], dr[x], acc);
+                    }
+                    v = (Real)((up ? acc : -acc) - a.k01);
                 }
-                a.del[del_index(dv, r, s)] = acc;
+                ec[bond_index(dv, r, s)] = v;
             }
         }
     }
 }
 
-// Applies the half-step's accepted hops (device, rail, s, dir; dir 0: o = s,
-// t = s + 1, dir 1: o = s + 1, t = s) to del: the ion's term leaves every site
-// within the cutoff of the origin and enters every site within the cutoff of
-// the target, which changes del on the bonds j = s - cutoff - 1 .. s + 1 +
-// cutoff of each neighbour rail by dphi(j + 1) - dphi(j) (binary64 atomic adds;
-// the hops of one half-step touch disjoint bonds).  A list that overflowed
-// (count > capacity) is replaced by a full recomputation from the new state.
-// The count is cleared by the replay kernel of the next half-step (which
-// appends to the other parity's count).
-__global__ __launch_bounds__(256) void replay_del_update(PhiArgs a) {
+// Recomputes, from the new state a.occ, every bond whose window the
+// half-step's accepted hops changed: for a hop (device, rail r, s, dir; it
+// moved the ion between s and s + 1) the bonds j = s - cutoff - 1 .. s + 1 +
+// cutoff of each neighbour rail r + off.  One workgroup per hop stages the
+// occupancy those bonds' windows read (sites s - 2 cutoff - 1 .. s + 2 cutoff
+// + 2 of the rails r - 2m .. r + 2m) in LDS and sums each bond with the table
+// of kernel differences, as replay_ec_full does.  Bonds reached from several
+// hops are written with the same value.  A list that overflowed (count >
+// capacity) is replaced by a recomputation of every bond.  The count is
+// cleared by the replay kernel of the next half-step (which appends to the
+// other parity's count).
+constexpr int kEcUpdMaxCut = 128;
+
+template <typename Real>
+__global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
     const int64_t cnt = __hip_atomic_load(a.hop_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cnt > a.hop_cap) {
-        replay_del_all(a);
+        replay_ec_all<Real>(a);
         return;
     }
-    const int cut = a.cutoff, w = 2 * cut + 3;  // bonds per rail whose del changes
+    Real *ec = reinterpret_cast<Real *>(a.ec);
+    const int cut = a.cutoff, m = a.rail_range, w = 2 * cut + 3;  // bonds per rail whose window holds s or s + 1
+    if (cut > kEcUpdMaxCut) {  // wide windows: every bond summed from global memory
+        for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
+            const uint4 e = a.hops[i];
+            const int d = (int)e.x, r = (int)e.y, s = (int)e.z;
+            const DevInfo &dv = a.devs[d];
+            const int R = dv.rails, L = dv.sites;
+            for (int q = threadIdx.x; q < dv.n_nbr * w; q += blockDim.x) {
+                const int k = q / w, j = s - cut - 1 + (q - k * w);
+                if (j < 0 || j > L - 2) continue;
+                int rr = (r + dv.nbr_off[k]) % R;
+                rr = rr < 0 ? rr + R : rr;
+                ec[bond_index(dv, rr, j)] = replay_bond_ec<Real>(a, dv, rr, j);
+            }
+        }
+        return;
+    }
+    __shared__ uint8_t win[4 * kMaxRailRange + 1][4 * kEcUpdMaxCut + 4];  // row 2m + o: rail r + o
+    __shared__ double dtab[(kMaxRailRange + 1) * (2 * kEcUpdMaxCut + 2)];
+    const int wn = 2 * cut + 2;     // window of a bond
+    const int width = 4 * cut + 4;  // sites s - 2 cut - 1 .. s + 2 cut + 2
+    const int n_rows = 4 * m + 1;
+    for (int i = threadIdx.x; i < (m + 1) * wn; i += blockDim.x) {
+        const int dist = i / wn, x = i - dist * wn;
+        const int dt = x - cut - 1 < 0 ? cut + 1 - x : x - cut - 1, dO = x - cut < 0 ? cut - x : x - cut;
+        const double *kr = a.ktab64 + dist * (cut + 1);
+        const double kt = (dt > cut || (dist == 0 && dt == 0)) ? 0.0 : kr[dt];
+        const double ko = (dO > cut || (dist == 0 && dO == 0)) ? 0.0 : kr[dO];
+        dtab[i] = kt - ko;
+    }
     for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
         const uint4 e = a.hops[i];
         const int d = (int)e.x, r = (int)e.y, s = (int)e.z;
-        const int o = e.w ? s + 1 : s, t = e.w ? s : s + 1;
         const DevInfo &dv = a.devs[d];
         const int R = dv.rails, L = dv.sites;
-        for (int q = threadIdx.x; q < dv.n_nbr * w; q += blockDim.x) {
-            const int k = q / w, j = s - cut - 1 + (q - k * w);
-            if (j < 0 || j > L - 2) continue;
-            const int off = dv.nbr_off[k];
-            const double *kr = a.ktab64 + dv.nbr_dist[k] * (cut + 1);
-            // change of phi at site x of this rail: + K(x - t) - K(x - o), no self terms
-            auto dphi = [&](int x) {
-                const int dt = x < t ? t - x : x - t, dO = x < o ? o - x : x - o;
-                const double kt = (dt > cut || (off == 0 && x == t)) ? 0.0 : kr[dt];
-                const double ko = (dO > cut || (off == 0 && x == o)) ? 0.0 : kr[dO];
-                return kt - ko;
-            };
-            const double dd = dphi(j + 1) - dphi(j);
-            if (dd == 0.0) continue;
-            int rr = (r + off) % R;
+        const int base = s - 2 * cut - 1;  // site of column 0
+        __syncthreads();  // the table is written; the previous hop's window is no longer read
+        for (int q = threadIdx.x; q < n_rows * width; q += blockDim.x) {
+            const int row = q / width, x = q - row * width, j = base + x;
+            int rr = (r + row - 2 * m) % R;
             rr = rr < 0 ? rr + R : rr;
-            unsafeAtomicAdd(&a.del[del_index(dv, rr, j)], dd);
+            win[row][x] = (j >= 0 && j < L) ? (uint8_t)(a.occ[dv.off_pad + (int64_t)rr * dv.pitch + j] & 1) : (uint8_t)0;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < dv.n_nbr * w; q += blockDim.x) {
+            const int kb = q / w, j = s - cut - 1 + (q - kb * w);  // bond j on rail r + off(kb)
+            if (j < 0 || j > L - 2) continue;
+            const int o1 = dv.nbr_off[kb];
+            const int col = j - cut - base;  // column of site j - cut
+            const uint8_t *w_own = win[2 * m + o1] + col;  // w[x] is site j - cut + x of the bond's rail
+            const int up = w_own[cut];
+            Real v = (Real)0;
+            if (up != w_own[cut + 1]) {
+                double acc = 0.0;
+                for (int k = 0; k < dv.n_nbr; ++k) {
+                    const double *dr = dtab + dv.nbr_dist[k] * wn;
+                    const uint8_t *wk = win[2 * m + o1 + dv.nbr_off[k]] + col;
+                    for (int x = 0; x < wn; ++x) acc = fma((double)wk[x], dr[x], acc);
+                }
+                v = (Real)((up ? acc : -acc) - a.k01);
+            }
+            int rr = (r + o1) % R;
+            rr = rr < 0 ? rr + R : rr;
+            ec[bond_index(dv, rr, j)] = v;
         }
     }
 }
@@ -908,13 +976,15 @@ hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream
 
 constexpr int kPhiGrid = 2048;  // workgroups of the potential kernels
 
-hipError_t launch_replay_del_full(const PhiArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(replay_del_full, dim3(kPhiGrid), dim3(kDelRun), 0, st, a);
+hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st) {
+    if (fp64) hipLaunchKernelGGL(replay_ec_full<double>, dim3(kPhiGrid), dim3(kEcRun), 0, st, a);
+    else hipLaunchKernelGGL(replay_ec_full<float>, dim3(kPhiGrid), dim3(kEcRun), 0, st, a);
     return hipGetLastError();
 }
 
-hipError_t launch_replay_del_update(const PhiArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(replay_del_update, dim3(kPhiGrid), dim3(256), 0, st, a);
+hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st) {
+    if (fp64) hipLaunchKernelGGL(replay_ec_update<double>, dim3(kPhiGrid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(replay_ec_update<float>, dim3(kPhiGrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 

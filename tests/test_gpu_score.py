@@ -4,19 +4,19 @@ replay on the same seeds, and the autograd bridge (needs an MI355X).
 Tolerance.  Both sides take the same decisions (the replay decides as the
 forward does) and sum the terms W g (y - p)/(1 - p) in binary64, in different
 orders.  The score terms take the Coulomb part of dE in binary64 rounded once
-to the path precision: the GPU as phi(t) - K(1, 0) - phi(o) from a potential
-kept up to date hop by hop, the oracle (coul64) as the window sum.  The two
-binary64 values differ by at most (n + 2 H + 8) eps64 B, with n the window's
-terms, H the device's accepted hops (each changes a site's potential at most
-twice) and B = A + |dE| + |dE_coul| + 2 K(1, 0), A the window's sum of
-|K(t - j)| + |K(o - j)| over occupied sites.  After the rounding to the path
+to the path precision: the GPU as +-(phi(s + 1) - phi(s)) - K(1, 0), summed
+in one pass over the bond's window whenever a hop changed it, the oracle
+(coul64) as the window sum.  The two binary64 values differ by at most
+(n + 8) eps64 B, with n the window's terms and B = A + |dE| + |dE_coul| +
+2 K(1, 0), A the window's sum of |K(t - j)| + |K(o - j)| over occupied
+sites.  After the rounding to the path
 precision (eps) the Coulomb parts are equal or one unit apart, so dE differs
 by at most eps B, the exponent's argument by (beta/2) eps B plus the two
 roundings of its evaluation (2 eps |arg|), and the exponential by a few units
 (device libm vs glibc).  A relative change dp/p = x moves a term by
 |W g| p/(1 - p)^2 x (and the kappa term also through dE_coul itself), so
     |grad_gpu - grad_oracle| <= 4 eps sens + 2 eps sens_arg
-                                + (eps + (n + 2 H + 8) eps64) sens_b + 1e-9 mag
+                                + (eps + (n + 8) eps64) sens_b + 1e-9 mag
 with sens = sum |W g| p/(1-p)^2, sens_arg the same weighted by |arg|,
 sens_b the dE-scale sum of the oracle (orc_run_opts) and mag = sum |term|;
 the last part covers the binary64 summation order."""
@@ -38,7 +38,7 @@ EPS = {FP64: 2.0 ** -52, FP32: 2.0 ** -23}
 def _tolerance(ref, ph):
     eps = EPS[ph.precision]
     n_terms = (2 * ph.rail_range + 1) * (2 * ph.cutoff_sites + 2)
-    c_b = eps + (n_terms + 2 * ref["hops"][:, None] + 8) * EPS[FP64]
+    c_b = eps + (n_terms + 8) * EPS[FP64]
     return 4 * eps * ref["sens"] + 2 * eps * ref["sens_arg"] + c_b * ref["sens_b"] + 1e-9 * ref["mag"]
 
 
