@@ -93,8 +93,8 @@ typedef struct {
 } kmc_log_entry;
 
 /* Bytes of device workspace kmc_init_device needs for these parameters
- * (apart from the dense precision, this includes 8 bytes per site for the
- * score replay's Coulomb potential differences). */
+ * (apart from the dense precision, this includes one value of the path's
+ * precision per site for the score replay's per-bond Coulomb parts). */
 kmc_status kmc_workspace_bytes(const kmc_params *params, size_t *bytes);
 
 /* Create a context (paper SI S2.2 "initialization": geometry, filling and
@@ -180,12 +180,12 @@ kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t
  * index).  The context's own state, step counter and tallies are not touched.
  * The hop probability of every candidate is evaluated in full: the Coulomb
  * part of dE is phi(t) - K(1, 0) - phi(o), phi being the window sum of the
- * interaction kernel over the occupied sites.  It comes from binary64
- * differences phi(s + 1) - phi(s) kept for every bond (built from occ0 and
- * updated after each half-step by the accepted hops) and is rounded once to
- * the path's precision; the rest of dE and p are evaluated in the path's
+ * interaction kernel over the occupied sites, summed in binary64 and rounded
+ * once to the path's precision.  It is kept for every bond (computed from
+ * occ0, and recomputed after each half-step for the bonds whose window an
+ * accepted hop changed); the rest of dE and p are evaluated in the path's
  * precision, and the terms are summed in binary64 (sum order not fixed).  The
- * differences and the hop list live in the workspace.
+ * per-bond values and the hop list live in the workspace.
  * Errors: KMC_EINVAL for NULL pointers, negative indices, coulomb_kappa_v == 0
  * or nu0_hz <= 0; KMC_EUNSUPPORTED if step0 + n_steps exceeds 2^32 - 1. */
 kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,

@@ -58,12 +58,12 @@ def test_workspace_scales_with_lattice():
 
 def test_workspace_holds_the_replay_buffers():
     """Outside the dense precision the workspace holds the score replay's
-    binary64 potential differences (8 bytes per site) and its hop list (16
-    bytes per entry, at least 4096 entries)."""
+    per-bond Coulomb parts (one value of the path precision per site) and its
+    hop list (16 bytes per entry, at least 4096 entries)."""
     from workloads import FP32, FP64
-    for prec in (FP32, FP64):
+    for prec, size in ((FP32, 4), (FP64, 8)):
         small = _status(Physics(precision=prec), [64], [128])[1]
         large = _status(Physics(precision=prec), [4096], [1024])[1]
         n_small, n_large = 64 * 128, 4096 * 1024
-        assert large - small >= 8 * (n_large - n_small)
-        assert small >= 8 * n_small + 16 * 4096
+        assert large - small >= size * (n_large - n_small)
+        assert small >= size * n_small + 16 * 4096
