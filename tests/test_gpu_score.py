@@ -104,6 +104,8 @@ def test_replay_many_hops_per_half_step():
     ([1, 2, 3], [40, 33, 57], 2, 16, FP64),   # rings shorter than the rail range: duplicate offsets
     ([4, 2], [19, 64], 1, 0, FP32),           # cutoff 0: no Coulomb term, K(1, 0) = 0
     ([6], [24], 2, 30, FP32),                 # window longer than the rail
+    ([3], [400], 1, 200, FP64),               # recomputation from global memory (cutoff above 128)
+    ([2], [1400], 0, 600, FP32),              # start-up without LDS tiles (cutoff above 512)
 ])
 def test_replay_edge_geometries(rails, sites, m, cut, precision):
     """Replay of small rings, cutoff 0 and windows longer than the rail, with a
