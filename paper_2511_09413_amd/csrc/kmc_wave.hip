@@ -497,26 +497,32 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         const uint32_t thr0 = (uint32_t)__builtin_amdgcn_readlane((int)thr_lane, kw);
         const uint32_t t_lane = __builtin_elementwise_add_sat(__umulhi(thr0, r_lane), 8600u);
         const uint32_t mn = min_word<0>(wd);
+        // the common path decides with one wavefront vote that no lane has a
+        // stage-0 word; only then are the survivor bits and their vote formed
+        const bool stage1 = mn <= t_lane && cand != 0u;
         uint32_t sv = 0;
-        if (mn <= t_lane && cand != 0u) {
-            const double c0 = kargs()->c0;
-            WaveLds<SPL> &wr = *lds_opaque(&w);
-            const double g_step = wr.step_g[kw];
-            uint32_t c = cand;
-            while (c) {
-                const int b = __builtin_ctz(c);
-                c &= c - 1;
-                const uint32_t x = pick_word<0>(wd, b >> 1);
-                if (x <= t_lane) {
-                    const int o = s0 + (((bits >> b) & 1u) ? b : b + 1);
-                    if (x <= threshold_of(c0, wr.cls_a[wr.cls[cls_base + o]], g_step)) sv |= 1u << b;
+        uint64_t any = 0;
+        if (__ballot(stage1)) {
+            if (stage1) {
+                const double c0 = kargs()->c0;
+                WaveLds<SPL> &wr = *lds_opaque(&w);
+                const double g_step = wr.step_g[kw];
+                uint32_t c = cand;
+                while (c) {
+                    const int b = __builtin_ctz(c);
+                    c &= c - 1;
+                    const uint32_t x = pick_word<0>(wd, b >> 1);
+                    if (x <= t_lane) {
+                        const int o = s0 + (((bits >> b) & 1u) ? b : b + 1);
+                        if (x <= threshold_of(c0, wr.cls_a[wr.cls[cls_base + o]], g_step)) sv |= 1u << b;
+                    }
                 }
             }
+            any = __ballot(sv != 0u);
         }
 
         // survivors (rare): one at a time over the whole wavefront
         bool edge_changed = false;
-        const uint64_t any = __ballot(sv != 0u);
         if (any) {
             const KArgs ka = kargs();
             WaveLds<SPL> &wr = *lds_opaque(&w);
