@@ -264,3 +264,38 @@ def test_wave_random_geometries(seed):
     sim.set_protocols(protos)
     st = lockstep(sim, p_or, protos, occ0, 60, 30)
     assert sim.launch_mode == "wave" and st["steps"] == 60
+
+
+@pytest.mark.parametrize("mode", ["half_step", "persistent"])
+@pytest.mark.parametrize("seed", range(6))
+def test_random_geometries_other_strategies(seed, mode):
+    """Seeded random lattices for the half-step and block-tile strategies: rail
+    counts 1..24, sites 2..4096, rail ranges 0..4, cutoffs 0..40, screened and
+    unscreened, both precisions, default or small forced tiles; 40 steps in
+    lockstep with the oracle."""
+    g = np.random.default_rng(2000 + 10 * seed + (mode == "persistent"))
+    n_dev = int(g.integers(1, 4))
+    m = int(g.integers(0, 5))
+    rails = [int(g.integers(1, 25)) for _ in range(n_dev)]
+    sites = [int(g.integers(2, 4097)) for _ in range(n_dev)]
+    cut = int(g.integers(0, 41))
+    lam = float(g.choice([0.0, 2.0, 4.0]))
+    precision = FP64 if seed % 2 == 0 else FP32
+    tile = int(g.choice([0, 512, 1024]))
+    ph = Physics(precision=precision, seed=seed + 50, ea_ev=0.13, coulomb_kappa_v=0.04, screening_sites=lam,
+                 cutoff_sites=cut, rail_range=m)
+    fill = [float(g.uniform(0.05, 0.6)) for _ in range(n_dev)]
+    protos = [triangle(2.0, 120e-12), constant(-0.8), step_then_relax(1.5, 30e-12)][:n_dev]
+    from paper_2511_09413_amd import KmcError, KMC_EUNSUPPORTED
+    try:
+        sim = _sim(ph, rails, sites, mode=mode, tile_sites=tile)
+    except KmcError as e:
+        if e.status != KMC_EUNSUPPORTED:
+            raise
+        pytest.skip(f"the {mode} strategy does not hold {rails} x {sites} with rail range {m}")
+    p_or = oracle.OracleParams(ph, rails, sites)
+    occ0 = oracle.fill(p_or, fill)
+    sim.load_occupancy(occ0)
+    sim.set_protocols(protos)
+    st = lockstep(sim, p_or, protos, occ0, 40, 20)
+    assert sim.launch_mode == mode and st["steps"] == 40

@@ -119,6 +119,29 @@ def test_replay_edge_geometries(rails, sites, m, cut, precision):
     assert np.all(np.abs(grad - ref["grad"]) <= tol), (grad, ref["grad"], tol)
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_replay_random_geometries(seed):
+    """Seeded random lattices: rail counts 1..12, sites 2..300, rail ranges
+    0..3, cutoffs 0..40, screened and unscreened, both precisions, barriers
+    0.08..0.15 eV; 60 steps replayed against the oracle's replay."""
+    g = np.random.default_rng(3000 + seed)
+    n_dev = int(g.integers(1, 4))
+    m = int(g.integers(0, 4))
+    rails = [int(g.integers(1, 13)) for _ in range(n_dev)]
+    sites = [int(g.integers(2, 301)) for _ in range(n_dev)]
+    cut = int(g.integers(0, 41))
+    lam = float(g.choice([0.0, 2.0, 4.0]))
+    precision = FP64 if seed % 2 == 0 else FP32
+    ph = Physics(precision=precision, seed=seed + 70, ea_ev=float(g.uniform(0.08, 0.15)), rail_range=m,
+                 cutoff_sites=cut, screening_sites=lam)
+    protos = [triangle(1.0, 80e-12), constant(0.5), step_then_relax(-1.0, 30e-12)][:n_dev]
+    fill = [float(g.uniform(0.1, 0.5)) for _ in range(n_dev)]
+    sim, grad, ref, net_g, fwd = _forward_and_replay(ph, rails, sites, fill, protos, 60, 11 + seed)
+    assert np.array_equal(net_g, fwd["net"])
+    tol = _tolerance(ref, ph)
+    assert np.all(np.abs(grad - ref["grad"]) <= tol), (grad, ref["grad"], tol)
+
+
 def test_replay_leaves_the_context_alone():
     """Replaying does not change the state, the step counter or the tallies:
     continuing afterwards gives the same trajectory as a context that never
