@@ -974,17 +974,17 @@ hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream
     return hipGetLastError();
 }
 
-constexpr int kPhiGrid = 2048;  // workgroups of the potential kernels
+constexpr int kEcGrid = 2048;  // workgroups of the replay's Coulomb-part kernels
 
 hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st) {
-    if (fp64) hipLaunchKernelGGL(replay_ec_full<double>, dim3(kPhiGrid), dim3(kEcRun), 0, st, a);
-    else hipLaunchKernelGGL(replay_ec_full<float>, dim3(kPhiGrid), dim3(kEcRun), 0, st, a);
+    if (fp64) hipLaunchKernelGGL(replay_ec_full<double>, dim3(kEcGrid), dim3(kEcRun), 0, st, a);
+    else hipLaunchKernelGGL(replay_ec_full<float>, dim3(kEcGrid), dim3(kEcRun), 0, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st) {
-    if (fp64) hipLaunchKernelGGL(replay_ec_update<double>, dim3(kPhiGrid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(replay_ec_update<float>, dim3(kPhiGrid), dim3(256), 0, st, a);
+    if (fp64) hipLaunchKernelGGL(replay_ec_update<double>, dim3(kEcGrid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL(replay_ec_update<float>, dim3(kEcGrid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
