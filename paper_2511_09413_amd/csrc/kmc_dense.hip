@@ -186,7 +186,10 @@ __global__ __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2))
 template <int H>
 __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_rail) {
     __shared__ uint32_t last_hop[256];
+    __shared__ int32_t tally[1 + kDeciles];  // the workgroup's net crossings and decile changes
     const int tid = threadIdx.x;
+    if (tid <= kDeciles) tally[tid] = 0;
+    __syncthreads();
     const Tile tile = a.dtiles[blockIdx.x];
     const int d = tile.d;
     const DevInfo &dv = a.devs[d];
@@ -201,46 +204,47 @@ __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_ra
     uint2 v = make_uint2(0, 0);
     int8_t *dst = a.occ_out + dv.off_pad + (int64_t)r * dv.pitch + s0;
     if (active) {
+        // the occupancy and the potential of the block are loaded together, and
+        // the Philox block drawn while they are in flight (one memory round
+        // trip; blocks without a candidate read their potential needlessly)
         const int8_t *row = a.occ_in + dv.off_pad + (int64_t)r * dv.pitch;
         v = *reinterpret_cast<const uint2 *>(row + s0);
         const uint32_t nxt = (H == 1 && s0 + 8 < dv.pitch) ? (uint32_t)(uint8_t)row[s0 + 8] : 0u;
+        const float *prow = a.phi + (dv.row0 + r) * a.phi_row + s0;
+        const float4 f0 = *reinterpret_cast<const float4 *>(prow);
+        const float4 f1 = *reinterpret_cast<const float4 *>(prow + 4);
+        const float f8 = (H == 1 && s0 + 8 < L) ? prow[8] : 0.0f;  // only bond 3 of parity 1 needs it
+        const uint4 blk = philox4x32_10((uint32_t)b, (uint32_t)r, (uint32_t)n, ((uint32_t)d << 4) | (uint32_t)H,
+                                        a.key0, a.key1);
         const uint32_t bits = (((v.x & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) |
                               ((((v.y & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << 4) | ((nxt & 1u) << 8);
         uint32_t cand = (bits ^ (bits >> 1)) & (H ? 0xAAu : 0x55u);
         const int last = L - 2 - s0;  // bond (s0+k, s0+k+1) exists iff k <= last
         if (last < 7) cand &= last < 0 ? 0u : ((2u << last) - 1u);
         if (cand) {
-            const uint4 blk = philox4x32_10((uint32_t)b, (uint32_t)r, (uint32_t)n, ((uint32_t)d << 4) | (uint32_t)H,
-                                            a.key0, a.key1);
-            const float *prow = a.phi + (dv.row0 + r) * a.phi_row + s0;
-            const float4 f0 = *reinterpret_cast<const float4 *>(prow);
-            const float4 f1 = *reinterpret_cast<const float4 *>(prow + 4);
-            const float f8 = (H == 1 && s0 + 8 < L) ? prow[8] : 0.0f;  // only bond 3 of parity 1 needs it
-            auto phi_at = [&](int k) {  // k = site - s0 in 0..8
-                const float lo = k == 0 ? f0.x : k == 1 ? f0.y : k == 2 ? f0.z : f0.w;
-                const float hi = k == 4 ? f1.x : k == 5 ? f1.y : k == 6 ? f1.z : f1.w;
-                return k == 8 ? f8 : (k < 4 ? lo : hi);
-            };
+            // potential at site s0 + k, k = 0..8, with k known at compile time
+            // (a runtime index would send the nine values through scratch)
+            const float ph[9] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w, f8};
             const float alpha_r = (float)a.alpha, V_r = (float)V, beta_r = (float)a.beta, c0_r = (float)a.c0;
-            while (cand) {
-                const int bit = __builtin_ctz(cand);
-                cand &= cand - 1;
-                const int s = s0 + bit;
-                const bool first = (bits >> bit) & 1u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = H + 2 * i;  // bond (s0 + k, s0 + k + 1)
+                if (!((cand >> k) & 1u)) continue;
+                const int s = s0 + k;
+                const bool first = (bits >> k) & 1u;
                 const int o = first ? s : s + 1, t = first ? s + 1 : s;
-                const float e_coul = (phi_at(t - s0) - a.k10) - phi_at(o - s0);
+                const float phi_o = first ? ph[k] : ph[k + 1], phi_t = first ? ph[k + 1] : ph[k];
+                const float e_coul = (phi_t - a.k10) - phi_o;
                 const float e_app = ((alpha_r * V_r) * (float)(t - o)) / (float)L;
                 const float ea = a.ea ? reinterpret_cast<const float *>(a.ea)[dv.off + (int64_t)r * L + o]
                                       : (float)a.ea_scalar;
-                if (decide_hop<float>(e_app + e_coul, ea, word_of(blk, bit >> 1), beta_r, c0_r, a.log, d, H, n, r,
-                                      s)) {
-                    hopped |= 1u << (bit >> 1);
-                    const int64_t base = (n - a.ctl->tally_base) * a.n_devices + d;
-                    atomicAdd(&a.tally_net[base], t < o ? 1 : -1);
+                if (decide_hop<float>(e_app + e_coul, ea, word_of(blk, i), beta_r, c0_r, a.log, d, H, n, r, s)) {
+                    hopped |= 1u << i;
+                    atomicAdd(&tally[0], t < o ? 1 : -1);
                     const int qo = (10 * o) / L, qt = (10 * t) / L;
                     if (qo != qt) {
-                        atomicAdd(&a.tally_dec[base * kDeciles + qo], -1);
-                        atomicAdd(&a.tally_dec[base * kDeciles + qt], 1);
+                        atomicAdd(&tally[1 + qo], -1);
+                        atomicAdd(&tally[1 + qt], 1);
                     }
                 }
             }
@@ -248,6 +252,10 @@ __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_ra
     }
     last_hop[tid] = hopped;
     __syncthreads();
+    if (tid <= kDeciles && tally[tid] != 0) {  // all rails of the workgroup belong to device d
+        const int64_t base = (n - a.ctl->tally_base) * a.n_devices + d;
+        atomicAdd(tid == 0 ? &a.tally_net[base] : &a.tally_dec[base * kDeciles + tid - 1], tally[tid]);
+    }
     if (!active) return;
     // flip both sites of every bond that moved; bond i starts at 8b + H + 2i
     uint64_t w = (uint64_t)v.x | ((uint64_t)v.y << 32);
