@@ -514,22 +514,43 @@ __global__ void barrier_range_finish(const unsigned long long *kmin, const unsig
 }
 
 // Decile counts of the current state (int64), one workgroup per device.
-__global__ void count_deciles(const int8_t *occ_pad, const DevInfo *devs, int64_t *dec_run) {
+// Occupied sites per decile of every device, from the padded state; dec_run
+// must be zero on entry.  Grid (devices, kDecileBlocks): each thread takes
+// 16-site chunks; a chunk touches few deciles, each counted with one popcount.
+constexpr int kDecileBlocks = 64;
+
+__global__ __launch_bounds__(256) void count_deciles(const int8_t *occ_pad, const DevInfo *devs,
+                                                     unsigned long long *dec_run) {
     __shared__ int cnt[kDeciles];
     const int d = blockIdx.x;
     const DevInfo &dv = devs[d];
     if (threadIdx.x < kDeciles) cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t total = (int64_t)dv.rails * dv.pitch;
-    int local[kDeciles] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t i = threadIdx.x; i < total; i += blockDim.x) {
-        const int s = (int)(i % dv.pitch);
-        if (s < dv.sites && (occ_pad[dv.off_pad + i] & 1)) local[(10 * s) / dv.sites] += 1;
+    const int L = dv.sites, cpr = dv.pitch / 16;
+    const int64_t chunks = (int64_t)dv.rails * cpr;
+    const uint4 *src = reinterpret_cast<const uint4 *>(occ_pad + dv.off_pad);
+    for (int64_t c = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; c < chunks;
+         c += (int64_t)gridDim.y * blockDim.x) {
+        const int s0 = (int)(c % cpr) * 16;
+        if (s0 >= L) continue;
+        const uint4 v = src[c];
+        uint32_t mask = 0;  // bit j: site s0 + j occupied
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) mask |= (((w[k] & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << (4 * k);
+        if (L - s0 < 16) mask &= (1u << (L - s0)) - 1u;
+        if (!mask) continue;
+        const int s_end = min(s0 + 16, L);
+        for (int q = (10 * s0) / L; q <= (10 * (s_end - 1)) / L; ++q) {
+            const int lo = max((q * L + 9) / 10, s0), hi = min(((q + 1) * L + 9) / 10, s_end);
+            const uint32_t range = ((hi - s0 >= 32 ? 0u : (1u << (hi - s0))) - 1u) & ~((1u << (lo - s0)) - 1u);
+            const int n = __popc(mask & range);
+            if (n) atomicAdd(&cnt[q], n);
+        }
     }
-    for (int q = 0; q < kDeciles; ++q)
-        if (local[q]) atomicAdd(&cnt[q], local[q]);
     __syncthreads();
-    if (threadIdx.x < kDeciles) dec_run[d * kDeciles + threadIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < kDeciles && cnt[threadIdx.x])
+        atomicAdd(&dec_run[d * kDeciles + threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
 }
 
 // Install a protocol: knots are passed by value so the update is ordered on the
@@ -934,7 +955,10 @@ hipError_t launch_barrier_range(const void *ea, bool fp64, DevInfo *devs, int n_
 
 hipError_t launch_count_deciles(const int8_t *occ_pad, const DevInfo *devs, int n_dev, int64_t *dec_run,
                                 hipStream_t st) {
-    hipLaunchKernelGGL(count_deciles, dim3(n_dev), dim3(256), 0, st, occ_pad, devs, dec_run);
+    const int64_t n = (int64_t)n_dev * kDeciles;
+    hipLaunchKernelGGL(zero_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dec_run, n);
+    hipLaunchKernelGGL(count_deciles, dim3(n_dev, kDecileBlocks), dim3(256), 0, st, occ_pad, devs,
+                       reinterpret_cast<unsigned long long *>(dec_run));
     return hipGetLastError();
 }
 
