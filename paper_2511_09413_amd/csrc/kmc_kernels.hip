@@ -417,37 +417,73 @@ __device__ __forceinline__ int device_of(const DevInfo *devs, int n_dev, int64_t
     return lo;
 }
 
+// Internal state from the caller's occupancy and per-site barriers: 16 padded
+// bytes per thread, always inside one rail (pitch and device offsets are
+// multiples of 16), written with one 16-byte store.
 template <typename Real>
-__global__ void import_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
-                                 int64_t total_pad, const Real *ea) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total_pad) return;
-    const int d = device_of(devs, n_dev, i, true);
+__global__ __launch_bounds__(256) void import_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs,
+                                                        int n_dev, int64_t total_pad, const Real *ea) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (i0 >= total_pad) return;
+    const int d = device_of(devs, n_dev, i0, true);
     const DevInfo &dv = devs[d];
-    const int64_t loc = i - dv.off_pad;
-    const int r = (int)(loc / dv.pitch), s = (int)(loc - (int64_t)r * dv.pitch);
-    int8_t val = 0;
-    if (s < dv.sites) {
-        const int64_t at = dv.off + (int64_t)r * dv.sites + s;
-        int cls = 0;
-        if (ea && dv.ea_step > 0.0) {
-            const double q = floor(((double)ea[at] - dv.ea_min) / dv.ea_step);
-            cls = q < 0.0 ? 0 : (q > (double)(kClasses - 1) ? kClasses - 1 : (int)q);
+    const int64_t loc = i0 - dv.off_pad;
+    const int r = (int)(loc / dv.pitch), s0 = (int)(loc - (int64_t)r * dv.pitch);
+    const int64_t at = dv.off + (int64_t)r * dv.sites + s0;
+    const bool classes = ea && dv.ea_step > 0.0;
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (s0 + k < dv.sites) {
+            int cls = 0;
+            if (classes) {
+                const double q = floor(((double)ea[at + k] - dv.ea_min) / dv.ea_step);
+                cls = q < 0.0 ? 0 : (q > (double)(kClasses - 1) ? kClasses - 1 : (int)q);
+            }
+            w[k >> 2] |= (uint32_t)((cls << 1) | (src[at + k] != 0 ? 1 : 0)) << (8 * (k & 3));
         }
-        val = (int8_t)((cls << 1) | (src[at] != 0 ? 1 : 0));
     }
-    dst[i] = val;
+    *reinterpret_cast<uint4 *>(dst + i0) = make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__global__ void export_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev,
-                                 int64_t total) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int d = device_of(devs, n_dev, i, false);
-    const DevInfo &dv = devs[d];
-    const int64_t loc = i - dv.off;
-    const int r = (int)(loc / dv.sites), s = (int)(loc - (int64_t)r * dv.sites);
-    dst[i] = src[dv.off_pad + (int64_t)r * dv.pitch + s] & 1;
+// Occupancy bits in the caller's unpadded layout: 16 consecutive output bytes
+// per thread (one 16-byte store when dst allows it), walking rails and devices
+// from the first byte's position (every device has >= 1 rail of >= 2 sites).
+__global__ __launch_bounds__(256) void export_occupancy(const int8_t *src, int8_t *dst, const DevInfo *devs,
+                                                        int n_dev, int64_t total) {
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 16;
+    if (i0 >= total) return;
+    int d = device_of(devs, n_dev, i0, false);
+    int L = devs[d].sites, R = devs[d].rails, pitch = devs[d].pitch;
+    int64_t base = devs[d].off_pad;
+    const int64_t loc = i0 - devs[d].off;
+    int r = (int)(loc / L), s = (int)(loc - (int64_t)r * L);
+    const int n = (int)min((int64_t)16, total - i0);
+    uint64_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        if (k < n) {
+            if (s == L) {  // next rail, or the next device's first rail
+                s = 0;
+                if (++r == R) {
+                    ++d;
+                    L = devs[d].sites, R = devs[d].rails, pitch = devs[d].pitch;
+                    base = devs[d].off_pad;
+                    r = 0;
+                }
+            }
+            const uint64_t b = (uint64_t)(src[base + (int64_t)r * pitch + s] & 1);
+            if (k < 8) lo |= b << (8 * k);
+            else hi |= b << (8 * (k - 8));
+            ++s;
+        }
+    }
+    if (n == 16 && ((uintptr_t)dst & 15u) == 0) {
+        *reinterpret_cast<uint4 *>(dst + i0) =
+            make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+    } else {
+        for (int k = 0; k < n; ++k) dst[i0 + k] = (int8_t)((k < 8 ? lo >> (8 * k) : hi >> (8 * (k - 8))) & 1u);
+    }
 }
 
 // Random placement: floor(f L + 1/2) ions on the sites with the smallest
@@ -919,7 +955,7 @@ hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes) {
 
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
                          const void *ea, bool fp64, hipStream_t st) {
-    const dim3 grid(grid_for(total_pad, 256)), block(256);
+    const dim3 grid(grid_for(total_pad / 16, 256)), block(256);  // total_pad is a multiple of 16
     if (fp64) hipLaunchKernelGGL((import_occupancy<double>), grid, block, 0, st, src, dst, devs, n_dev, total_pad,
                                  (const double *)ea);
     else hipLaunchKernelGGL((import_occupancy<float>), grid, block, 0, st, src, dst, devs, n_dev, total_pad,
@@ -929,8 +965,8 @@ hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, in
 
 hipError_t launch_export(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total,
                          hipStream_t st) {
-    hipLaunchKernelGGL(export_occupancy, dim3(grid_for(total, 256)), dim3(256), 0, st, src, dst, devs, n_dev,
-                       total);
+    hipLaunchKernelGGL(export_occupancy, dim3(grid_for((total + 15) / 16, 256)), dim3(256), 0, st, src, dst, devs,
+                       n_dev, total);
     return hipGetLastError();
 }
 
