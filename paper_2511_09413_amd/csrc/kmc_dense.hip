@@ -187,19 +187,22 @@ template <int H>
 __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_rail) {
     __shared__ uint32_t last_hop[256];
     __shared__ int32_t tally[1 + kDeciles];  // the workgroup's net crossings and decile changes
+    __shared__ double v_wg;                  // the bias of the step (one device per workgroup)
     const int tid = threadIdx.x;
-    if (tid <= kDeciles) tally[tid] = 0;
-    __syncthreads();
     const Tile tile = a.dtiles[blockIdx.x];
     const int d = tile.d;
     const DevInfo &dv = a.devs[d];
+    const int64_t n = a.ctl->n_base + a.step_in_chunk;
+    if (tid <= kDeciles) tally[tid] = 0;
+    if (tid == 0)
+        v_wg = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
+                                (double)(n - dv.n_set) * a.dt);
+    __syncthreads();
+    const double V = v_wg;
     const int slot = tid / blocks_per_rail, b = tid - slot * blocks_per_rail;
     const bool active = slot < tile.nr;
     const int r = tile.r0 + slot;
     const int L = dv.sites, s0 = 8 * b;
-    const int64_t n = a.ctl->n_base + a.step_in_chunk;
-    const double V = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
-                                      (double)(n - dv.n_set) * a.dt);
     uint32_t hopped = 0;  // bit i: bond i of the block moved
     uint2 v = make_uint2(0, 0);
     int8_t *dst = a.occ_out + dv.off_pad + (int64_t)r * dv.pitch + s0;
