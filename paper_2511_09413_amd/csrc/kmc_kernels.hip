@@ -621,51 +621,44 @@ __global__ void begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out) {
 // End of a tally chunk of `steps` steps: per device, prefix-sum the decile
 // deltas into absolute counts, accumulate the int64 net total, copy rows to the
 // caller's buffers, clear the chunk buffers, and advance the step counter.
-// One workgroup per device.
-__global__ __launch_bounds__(256) void finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec,
-                                                    int64_t *dec_run, int64_t *net_total, int n_dev,
-                                                    int steps) {
-    __shared__ int64_t scan[256];
-    const int d = blockIdx.x;
+// One workgroup per series (device, decile or net hops), one thread per step.
+static_assert(kTallySteps <= 1024, "finish_chunk scans a chunk in one workgroup");
+__global__ __launch_bounds__(1024) void finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec,
+                                                     int64_t *dec_run, int64_t *net_total, int n_dev,
+                                                     int steps) {
+    __shared__ int64_t wsum[1024 / 64];
+    const int d = blockIdx.x, q = blockIdx.y;  // q == kDeciles: net hops
+    const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
     const int64_t row0 = ctl->tally_base - ctl->call_base;
     int32_t *net_out = ctl->net_out;
     int32_t *dec_out = ctl->dec_out;
-    for (int q = 0; q <= kDeciles; ++q) {  // q == kDeciles: net hops
-        int64_t carry = (q < kDeciles) ? dec_run[d * kDeciles + q] : 0;
-        for (int k0 = 0; k0 < steps; k0 += 256) {
-            const int k = k0 + threadIdx.x;
-            int64_t val = 0;
-            if (k < steps) {
-                if (q < kDeciles) {
-                    int32_t *p = &tally_dec[((int64_t)k * n_dev + d) * kDeciles + q];
-                    val = *p;
-                    *p = 0;
-                } else {
-                    int32_t *p = &tally_net[(int64_t)k * n_dev + d];
-                    val = *p;
-                    *p = 0;
-                    if (net_out) net_out[(row0 + k) * n_dev + d] = (int32_t)val;
-                }
-            }
-            scan[threadIdx.x] = val;
-            __syncthreads();
-            for (int off = 1; off < 256; off <<= 1) {
-                const int64_t add = threadIdx.x >= off ? scan[threadIdx.x - off] : 0;
-                __syncthreads();
-                scan[threadIdx.x] += add;
-                __syncthreads();
-            }
-            const int64_t incl = carry + scan[threadIdx.x];
-            if (k < steps && q < kDeciles && dec_out)
-                dec_out[((row0 + k) * n_dev + d) * kDeciles + q] = (int32_t)incl;
-            carry += scan[255];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (q < kDeciles) dec_run[d * kDeciles + q] = carry;
-            else net_total[d] += carry;
-        }
-        __syncthreads();
+    const int64_t carry = q < kDeciles ? dec_run[d * kDeciles + q] : 0;  // read before the barrier
+    int64_t x = 0;
+    if (k < steps) {
+        int32_t *p = q < kDeciles ? &tally_dec[((int64_t)k * n_dev + d) * kDeciles + q]
+                                  : &tally_net[(int64_t)k * n_dev + d];
+        x = *p;
+        *p = 0;
+        if (q == kDeciles && net_out) net_out[(row0 + k) * n_dev + d] = (int32_t)x;
+    }
+    // inclusive scan: within the wavefront, then over the wavefront totals
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, off, 64);
+        const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)((uint64_t)x >> 32), off, 64);
+        if (lane >= off) x += (int64_t)(((uint64_t)hi << 32) | lo);
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+    for (int w = 0; w < 1024 / 64; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    if (k < steps && q < kDeciles && dec_out) dec_out[((row0 + k) * n_dev + d) * kDeciles + q] = (int32_t)(carry + before + x);
+    if (k == 0) {
+        if (q < kDeciles) dec_run[d * kDeciles + q] = carry + total;
+        else net_total[d] += total;
     }
 }
 
@@ -1016,8 +1009,10 @@ hipError_t launch_begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out, hipSt
 
 hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec, int64_t *dec_run,
                                int64_t *net_total, int n_dev, int steps, hipStream_t st) {
-    hipLaunchKernelGGL(finish_chunk, dim3(n_dev), dim3(256), 0, st, ctl, tally_net, tally_dec, dec_run, net_total,
-                       n_dev, steps);
+    // one workgroup per series (device, decile or net hops), one thread per step
+    if (steps < 1 || steps > 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finish_chunk, dim3(n_dev, kDeciles + 1), dim3(1024), 0, st, ctl, tally_net, tally_dec,
+                       dec_run, net_total, n_dev, steps);
     hipLaunchKernelGGL(advance_steps, dim3(1), dim3(1), 0, st, ctl, steps);
     return hipGetLastError();
 }
