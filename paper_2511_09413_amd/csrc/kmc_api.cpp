@@ -33,9 +33,7 @@ hipError_t launch_count_deciles(const int8_t *occ_pad, const DevInfo *devs, int 
                                 hipStream_t st);
 hipError_t launch_set_protocol(double *knot_t, double *knot_v, DevInfo *devs, int d0, int d1, int nk,
                                int64_t n_set, const double *t, const double *v, hipStream_t st);
-hipError_t launch_begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out, hipStream_t st);
-hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec, int64_t *dec_run,
-                               int64_t *net_total, int n_dev, int steps, hipStream_t st);
+hipError_t launch_finish_chunk(const FinishArgs &f, hipStream_t st);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t st);
 hipError_t launch_persistent(const PArgs &a, int block, size_t lds, bool fp64, hipStream_t st);
 hipError_t persistent_capacity(int block, size_t lds, bool fp64, int *blocks_per_cu);
@@ -75,7 +73,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
-        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, total;
+        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
     size_t wtiles;                    // wave tiling (PTile array)
@@ -167,7 +165,6 @@ Layout layout_for(const kmc_params *p) {
     L.knot_v = take(sizeof(double) * kMaxKnots * D);
     L.ktab64 = take(sizeof(double) * (m + 1) * (L.cut + 1));
     L.ktab32 = take(sizeof(float) * (m + 1) * (L.cut + 1));
-    L.ctl = take(sizeof(Ctl));
     L.tally_net = take(sizeof(int32_t) * kTallySteps * D);
     L.tally_dec = take(sizeof(int32_t) * kTallySteps * D * kDeciles);
     L.dec_run = take(sizeof(int64_t) * D * kDeciles);
@@ -219,6 +216,7 @@ Layout layout_for(const kmc_params *p) {
                  (size_t)std::max(L.pub_stride * L.max_ptiles, L.wpub_stride * L.max_wtiles));
     L.wtiles = take(sizeof(PTile) * (size_t)rails);  // every wave tile is at least one rail
     L.status = take(sizeof(int32_t) * 4);
+    L.ticket = take(sizeof(uint32_t) * kTicketWords);  // wave kernel: tiles that ended the launch
     // score replay: its own pair of state planes, a discarded event count, the
     // Coulomb part of every bond's energy change (path precision) and the list
     // of a half-step's accepted hops (a longer list falls back to recomputing
@@ -486,10 +484,16 @@ void make_wtiles(kmc_ctx *c) {
     }
     c->w_spl = spl;
     const size_t n_kt = (size_t)(c->p.rail_range + 1) * (c->lay.cut + 1);
-    c->w_lds = wave_lds_bytes(spl, (int)n_kt, c->fp64);
     int per_cu = 0, dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return;
+    // Every workgroup asks for a quarter of the CU's LDS, so that a CU holds
+    // at most four (one wavefront per SIMD each).  A launch of exactly four
+    // workgroups per CU then gives every SIMD the same four tiles; with the
+    // occupancy the registers allow (five), the dispatcher stacks five
+    // workgroups on some CUs and three on others, and the tiles of the fuller
+    // SIMDs set the launch's time.
+    c->w_lds = std::max(wave_lds_bytes(spl, (int)n_kt, c->fp64), (size_t)prop.maxSharedMemoryPerMultiProcessor / 4);
     if (wave_capacity(spl, c->w_lds, c->fp64, &per_cu) != hipSuccess) return;
     // groups of whole devices, each co-resident (and within the publication memory)
     int64_t cap = std::min<int64_t>((int64_t)per_cu * prop.multiProcessorCount * kWaveTilesPerWG, c->lay.max_wtiles);
@@ -549,7 +553,6 @@ HopArgs hop_args(kmc_ctx *c) {
     a.dt = c->p.dt_s;
     a.key0 = (uint32_t)(c->p.seed & 0xffffffffu);
     a.key1 = (uint32_t)(c->p.seed >> 32);
-    a.ctl = c->at<Ctl>(c->lay.ctl);
     a.tally_net = c->at<int32_t>(c->lay.tally_net);
     a.tally_dec = c->at<int32_t>(c->lay.tally_dec);
     a.n_devices = D;
@@ -589,12 +592,35 @@ DenseArgs dense_args(kmc_ctx *c, const int8_t *occ, float *phi, int64_t phi_row)
     return d;
 }
 
-kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
+// Tally rows of a chunk that the wave kernel ends itself: at most five
+// devices (the finishing wavefront's 128 segments) and short chunks (about 64
+// steps per lane); longer chunks get the finish kernel, whose launch costs
+// little against them.
+bool wave_finishes(int d0, int d1, int steps) {
+    const int series = (d1 - d0) * (kDeciles + 1);
+    return series <= 64 && (int64_t)series * steps <= 4096;
+}
+
+// Enqueue n_steps steps.  Returns in *exported whether the launches already
+// wrote the caller's occupancy (the wave kernel does).
+kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_out, int32_t *dec_out, bool *exported) {
     const int D = c->p.n_devices;
     HopArgs a = hop_args(c);
     const int kind = launch_kind(c);
     const bool wave = kind == KMC_LAUNCH_WAVE;
     const bool persistent = wave || kind == KMC_LAUNCH_PERSISTENT;
+    Ctl ctl{};
+    ctl.call_base = c->n;
+    ctl.net_out = net_out;
+    ctl.dec_out = dec_out;
+    FinishArgs fa{};
+    fa.tally_net = a.tally_net;
+    fa.tally_dec = a.tally_dec;
+    fa.dec_run = c->at<int64_t>(c->lay.dec_run);
+    fa.net_total = c->at<int64_t>(c->lay.net_total);
+    fa.n_devices = D;
+    fa.d0 = 0;
+    fa.d1 = D;
     PArgs pa{};
     if (persistent) {
         pa.occ = c->cur;
@@ -615,7 +641,6 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.dt = a.dt;
         pa.key0 = a.key0;
         pa.key1 = a.key1;
-        pa.ctl = a.ctl;
         pa.tally_net = a.tally_net;
         pa.tally_dec = a.tally_dec;
         pa.n_devices = D;
@@ -624,11 +649,20 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
         pa.pub_stride = wave ? c->lay.wpub_stride : c->lay.pub_stride;
         pa.status = c->at<int32_t>(c->lay.status);
         pa.spin_limit = c->spin_limit;
+        pa.occ_user = c->occ_user;
     }
     int64_t done = 0;
     while (done < n_steps) {
         const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
+        ctl.n_base = c->n + done;
+        ctl.tally_base = ctl.n_base;
+        a.ctl = ctl;
+        pa.ctl = ctl;
+        fa.ctl = ctl;
+        fa.steps = chunk;
+        bool all_finished = false;  // every device's rows ended by the launches themselves
         if (persistent) {
+            all_finished = wave;
             for (const auto &g : wave ? c->wgroups : c->pgroups) {
                 // publication tags carry the low 20 bits of the epoch: at every
                 // wrap the ring is cleared so that no stale word can match a new tag
@@ -637,12 +671,28 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
                                                c->stream));
                     ++c->epoch;
                 }
+                const std::vector<PTile> &tl = wave ? c->wtiles : c->ptiles;
                 pa.tiles = c->at<PTile>(wave ? c->lay.wtiles : c->lay.ptiles) + g.first;
                 pa.n_tiles = g.second;
                 pa.epoch = c->epoch;
                 pa.n_steps = chunk;
+                pa.fin = fa;
+                pa.fin.d0 = tl[g.first].d;
+                pa.fin.d1 = tl[g.first + g.second - 1].d + 1;
+                pa.ticket = nullptr;
+                if (wave && wave_finishes(pa.fin.d0, pa.fin.d1, chunk)) pa.ticket = c->at<uint32_t>(c->lay.ticket);
+                else all_finished = false;
                 if (wave) KMC_HIP(c, launch_wave(pa, c->w_spl, c->w_lds, c->fp64, c->stream));
                 else KMC_HIP(c, launch_persistent(pa, c->p_block, c->p_lds, c->fp64, c->stream));
+            }
+            if (wave && !all_finished) {
+                // the groups whose launches did not end their rows
+                for (const auto &g : c->wgroups) {
+                    FinishArgs f = fa;
+                    f.d0 = c->wtiles[g.first].d;
+                    f.d1 = c->wtiles[g.first + g.second - 1].d + 1;
+                    if (!wave_finishes(f.d0, f.d1, chunk)) KMC_HIP(c, launch_finish_chunk(f, c->stream));
+                }
             }
         }
         for (int k = 0; k < chunk && !persistent; ++k) {
@@ -661,10 +711,10 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps) {
                 std::swap(c->cur, c->nxt);
             }
         }
-        KMC_HIP(c, launch_finish_chunk(a.ctl, a.tally_net, a.tally_dec, c->at<int64_t>(c->lay.dec_run),
-                                       c->at<int64_t>(c->lay.net_total), D, chunk, c->stream));
+        if (!wave) KMC_HIP(c, launch_finish_chunk(fa, c->stream));
         done += chunk;
     }
+    *exported = wave;
     return KMC_OK;
 }
 
@@ -824,8 +874,6 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
             rail_dev.push_back(d);
             rail_idx.push_back(r);
         }
-    Ctl ctl{};
-
     hipStream_t st = c->stream;
     auto h2d = [&](size_t at, const void *src, size_t bytes) {
         return hipMemcpyAsync(c->ws + at, src, bytes, hipMemcpyHostToDevice, st);
@@ -847,7 +895,6 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
         chk(h2d(lay.ctiles, c->ctiles.data(), sizeof(Tile) * c->ctiles.size()), "copy decision tiles");
         chk(set_dense_lds_limit((size_t)(kDenseRails + 2 * m) * (lay.dense_nb * 32 + 8)), "LDS limit of the dense kernel");
     }
-    chk(h2d(lay.ctl, &ctl, sizeof(Ctl)), "copy ctl");
     chk(h2d(lay.rail_dev, rail_dev.data(), sizeof(int32_t) * rail_dev.size()), "copy rail table");
     chk(h2d(lay.rail_idx, rail_idx.data(), sizeof(int32_t) * rail_idx.size()), "copy rail table");
     // the host vectors above go out of scope at return: wait for the copies
@@ -858,6 +905,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i64(c->at<int64_t>(lay.log_count), 1, st), "zero log");
     chk(launch_zero_i64(c->at<int64_t>(lay.pub), pub_words(lay), st), "zero publication ring");
     chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
+    chk(launch_zero_i32(c->at<int32_t>(lay.ticket), kTicketWords, st), "zero ticket");
     chk(set_hop_lds_limit(c->hop_lds, c->score_lds), "LDS limit of the hop kernel");
     {
         const double zero_t = 0.0, zero_v = 0.0;
@@ -932,11 +980,12 @@ kmc_status kmc_run_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_hops_dev, int
     if (n_steps < 0) return fail(KMC_EINVAL, "n_steps < 0");
     if (c->n + n_steps > (int64_t)0xffffffffLL) return fail(KMC_EUNSUPPORTED, "step counter would reach 2^32");
     if (n_steps == 0) return KMC_OK;
-    KMC_HIP(c, launch_begin_call(c->at<Ctl>(c->lay.ctl), net_hops_dev, decile_dev, c->stream));
-    s = enqueue_steps(c, n_steps);
+    bool exported = false;
+    s = enqueue_steps(c, n_steps, net_hops_dev, decile_dev, &exported);
     if (s != KMC_OK) return s;
-    KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
-                             c->lay.total_sites, c->stream));
+    if (!exported)
+        KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
+                                 c->lay.total_sites, c->stream));
     c->n += n_steps;
     c->steps_run += n_steps;
     return KMC_OK;
@@ -1069,7 +1118,6 @@ kmc_status kmc_set_tile_sites(kmc_ctx *c, int32_t sites) {
 namespace {
 // Everything a trial run changes, saved so that tuning leaves no trace.
 struct Saved {
-    Ctl ctl;
     std::vector<int64_t> net_total, dec_run;
     int64_t log_count = 0;
     int64_t n = 0, steps_run = 0;
@@ -1081,7 +1129,6 @@ kmc_status save_state(kmc_ctx *c, Saved &sv) {
     sv.dec_run.resize((size_t)D * kDeciles);
     KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.rp_a, c->cur, (size_t)c->lay.total_pad, hipMemcpyDeviceToDevice,
                               c->stream));
-    KMC_HIP(c, hipMemcpyAsync(&sv.ctl, c->ws + c->lay.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
     KMC_HIP(c, hipMemcpyAsync(sv.net_total.data(), c->ws + c->lay.net_total, sizeof(int64_t) * D,
                               hipMemcpyDeviceToHost, c->stream));
     KMC_HIP(c, hipMemcpyAsync(sv.dec_run.data(), c->ws + c->lay.dec_run, sizeof(int64_t) * D * kDeciles,
@@ -1098,7 +1145,6 @@ kmc_status restore_state(kmc_ctx *c, const Saved &sv) {
     const int D = c->p.n_devices;
     KMC_HIP(c, hipMemcpyAsync(c->cur, c->ws + c->lay.rp_a, (size_t)c->lay.total_pad, hipMemcpyDeviceToDevice,
                               c->stream));
-    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.ctl, &sv.ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
     KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.net_total, sv.net_total.data(), sizeof(int64_t) * D,
                               hipMemcpyHostToDevice, c->stream));
     KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.dec_run, sv.dec_run.data(), sizeof(int64_t) * D * kDeciles,
@@ -1106,6 +1152,9 @@ kmc_status restore_state(kmc_ctx *c, const Saved &sv) {
     KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.log_count, &sv.log_count, sizeof(int64_t), hipMemcpyHostToDevice,
                               c->stream));
     KMC_HIP(c, launch_zero_i32(c->at<int32_t>(c->lay.status), 4, c->stream));
+    // a trial in the wave strategy also wrote the caller's occupancy
+    KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
+                             c->lay.total_sites, c->stream));
     KMC_HIP(c, hipStreamSynchronize(c->stream));  // the host copies above are locals of the caller
     c->n = sv.n;
     c->steps_run = sv.steps_run;
@@ -1147,9 +1196,9 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
         for (int rep = 0; rep < 2 && ok; ++rep) {  // the first run pays one-time costs
             s = restore_state(c, sv);
             if (s != KMC_OK) break;
-            KMC_HIP(c, launch_begin_call(c->at<Ctl>(c->lay.ctl), nullptr, nullptr, c->stream));
             KMC_HIP(c, hipEventRecord(e0, c->stream));
-            s = enqueue_steps(c, trial_steps);
+            bool exported = false;
+            s = enqueue_steps(c, trial_steps, nullptr, nullptr, &exported);
             if (s != KMC_OK) break;
             KMC_HIP(c, hipEventRecord(e1, c->stream));
             KMC_HIP(c, hipEventSynchronize(e1));
@@ -1281,3 +1330,8 @@ void kmc_destroy(kmc_ctx *c) {
 }
 
 }  // extern "C"
+
+namespace kmc {
+// The error text of the calling thread, for the other sources of the library.
+kmc_status record_error(kmc_status s, const std::string &msg) { return fail(s, msg); }
+}  // namespace kmc

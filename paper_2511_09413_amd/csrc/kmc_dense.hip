@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_ra
     const Tile tile = a.dtiles[blockIdx.x];
     const int d = tile.d;
     const DevInfo &dv = a.devs[d];
-    const int64_t n = a.ctl->n_base + a.step_in_chunk;
+    const int64_t n = a.ctl.n_base + a.step_in_chunk;
     if (tid <= kDeciles) tally[tid] = 0;
     if (tid == 0)
         v_wg = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_ra
     last_hop[tid] = hopped;
     __syncthreads();
     if (tid <= kDeciles && tally[tid] != 0) {  // all rails of the workgroup belong to device d
-        const int64_t base = (n - a.ctl->tally_base) * a.n_devices + d;
+        const int64_t base = (n - a.ctl.tally_base) * a.n_devices + d;
         atomicAdd(tid == 0 ? &a.tally_net[base] : &a.tally_dec[base * kDeciles + tid - 1], tally[tid]);
     }
     if (!active) return;

@@ -151,4 +151,71 @@ __device__ __forceinline__ uint32_t threshold_of(double c0, double A, double g) 
     return pb >= 1.0 ? 0xFFFFFFFFu : (uint32_t)(ceil(pb * 4294967296.0) - 1.0);
 }
 
+
+// The end of a tally chunk done by one wavefront (the tail of the wave
+// kernel): for the series (device d in [f.d0, f.d1), decile q or net hops) of
+// f.steps steps, the per-step deltas become the caller's rows (absolute decile
+// counts, net hops per step), the running totals advance and the chunk
+// buffers are cleared.  Lane l takes segment l and l + 64 of the series cut
+// into pieces of g steps; needs at most 128 segments (`sums` holds 128
+// values in LDS).  The chunk buffers are read and cleared with device-scope
+// atomics (the launch's tiles added to them with device-scope atomics).
+__device__ inline void finish_tallies_wave(const FinishArgs &f, int lane, int64_t *sums) {
+    const int S = (f.d1 - f.d0) * (kDeciles + 1);
+    const int steps = f.steps, D = f.n_devices;
+    int g = (int)(((int64_t)S * steps + 63) / 64);
+    g = g < 1 ? 1 : (g > steps ? steps : g);
+    const int per = (steps + g - 1) / g;
+    const int n_seg = S * per;
+    const int64_t row0 = f.ctl.tally_base - f.ctl.call_base;
+    auto slot = [&](int q, int d, int k) -> int32_t * {
+        return q < kDeciles ? &f.tally_dec[((int64_t)k * D + d) * kDeciles + q] : &f.tally_net[(int64_t)k * D + d];
+    };
+    int64_t sum_r[2] = {0, 0}, carry_r[2] = {0, 0};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int seg = lane + 64 * r;
+        if (seg < n_seg) {
+            const int s = seg / per, part = seg - s * per;
+            const int d = f.d0 + s / (kDeciles + 1), q = s % (kDeciles + 1);
+            const int k0 = part * g, k1 = k0 + g < steps ? k0 + g : steps;
+            int64_t sum = 0;
+            for (int k = k0; k < k1; ++k) sum += __hip_atomic_load(slot(q, d, k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sum_r[r] = sum;
+            carry_r[r] = q < kDeciles ? f.dec_run[d * kDeciles + q] : 0;
+            sums[seg] = sum;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int seg = lane + 64 * r;
+        if (seg < n_seg) {
+            const int s = seg / per, part = seg - s * per;
+            const int d = f.d0 + s / (kDeciles + 1), q = s % (kDeciles + 1);
+            const int k0 = part * g, k1 = k0 + g < steps ? k0 + g : steps;
+            int64_t before = 0;
+            for (int j = s * per; j < seg; ++j) before += sums[j];
+            int64_t run = carry_r[r] + before;
+            for (int k = k0; k < k1; ++k) {
+                int32_t *p = slot(q, d, k);
+                const int32_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (q == kDeciles) {
+                    if (f.ctl.net_out) f.ctl.net_out[(row0 + k) * D + d] = x;
+                } else {
+                    run += x;
+                    if (f.ctl.dec_out) f.ctl.dec_out[((row0 + k) * D + d) * kDeciles + q] = (int32_t)run;
+                }
+            }
+            if (part == per - 1) {
+                if (q < kDeciles) f.dec_run[d * kDeciles + q] = run;
+                else f.net_total[d] += before + sum_r[r];
+            }
+        }
+    }
+}
+
 }  // namespace kmc

@@ -53,14 +53,30 @@ constexpr int kPubSlots = 2 * kTallySteps + 1;  // publication slots per tile: o
 constexpr int kPMaxBlock = 1024;         // threads per workgroup, persistent kernel
 constexpr int kWaveTilesPerWG = 4;       // wave kernel: tiles (one wavefront each) per workgroup
 constexpr int kSnapSlots = 64;           // wave kernel: edge-row snapshots per tile in a ring
+constexpr int kTicketBuckets = 64;       // wave kernel: end-of-launch counters (one 128-byte line each)
+constexpr int kTicketStride = 32;        // uint32 per counter line
+constexpr int kTicketWords = (kTicketBuckets + 1) * kTicketStride;  // the buckets, then the total
 
-// Step bookkeeping in device memory (lets a captured graph be replayed).
+// Step bookkeeping of one launch, passed by value (the host keeps the step
+// counter).
 struct Ctl {
-    int64_t n_base;        // step index of the next step to run
+    int64_t n_base;        // step index of the launch's first step (chunk start)
     int64_t tally_base;    // step index of row 0 of the tally chunk buffers
     int64_t call_base;     // first step of the current kmc_run_steps call
     int32_t *net_out;      // caller buffers of the current call (may be null)
     int32_t *dec_out;
+};
+
+// End of a tally chunk (either a kernel of its own or the tail of the wave
+// kernel): the per-step tally deltas of devices [d0, d1) are turned into the
+// caller's rows and the running totals.
+struct FinishArgs {
+    Ctl ctl;
+    int32_t *tally_net;        // [kTallySteps][D] net hops per step (cleared here)
+    int32_t *tally_dec;        // [kTallySteps][D][10] decile deltas per step (cleared here)
+    int64_t *dec_run;          // [D][10] decile counts before the chunk, advanced here
+    int64_t *net_total;        // [D] running net-hop totals
+    int32_t n_devices, d0, d1, steps;
 };
 
 // Everything the hop kernel needs, passed by value.
@@ -78,7 +94,7 @@ struct HopArgs {
     int32_t cutoff, rail_range;
     double ea_scalar, beta, c0, alpha, dt;
     uint32_t key0, key1;
-    Ctl *ctl;
+    Ctl ctl;
     int32_t *tally_net;        // [kTallySteps][D]
     int32_t *tally_dec;        // [kTallySteps][D][10]  (deltas)
     int32_t n_devices;
@@ -150,7 +166,7 @@ struct PArgs {
     int32_t cutoff, rail_range;
     double ea_scalar, beta, c0, alpha, dt;
     uint32_t key0, key1;
-    Ctl *ctl;
+    Ctl ctl;
     int32_t *tally_net;
     int32_t *tally_dec;
     int32_t n_devices;
@@ -162,6 +178,15 @@ struct PArgs {
     int32_t n_steps;
     int32_t *status;           // nonzero: a neighbour wait timed out
     int32_t spin_limit;        // polls before a neighbour wait is declared hung (0: at once)
+    // wave kernel only: the launch ends its chunk itself.  Every tile also
+    // writes its rails to the caller's occupancy (occ_user, unpadded layout),
+    // and, when ticket is set, the last tile to finish (counted per bucket of
+    // tiles, then over the buckets: kTicketWords counters) runs the chunk's
+    // tally finish for the launch's devices [fin.d0, fin.d1) and clears the
+    // counters.
+    int8_t *occ_user;
+    uint32_t *ticket;
+    FinishArgs fin;
 };
 
 }  // namespace kmc

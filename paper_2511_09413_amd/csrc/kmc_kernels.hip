@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                                                             : reinterpret_cast<const Real *>(a.ktab32);
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int64_t n = kScore ? a.n_abs : a.ctl->n_base + a.step_in_chunk;
+    const int64_t n = kScore ? a.n_abs : a.ctl.n_base + a.step_in_chunk;
     const int8_t *src_dev = a.occ_in + dv.off_pad;
 
     // 1. issue the loads of the lane's chunk and of one halo chunk
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
         __syncthreads();
     }
     if (!kScore && tid == 0 && sh.n_hop > 0) {
-        const int64_t k = n - a.ctl->tally_base;
+        const int64_t k = n - a.ctl.tally_base;
         const int64_t base = k * a.n_devices + tile.d;
         atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
         for (int q = 0; q < kDeciles; ++q)
@@ -610,33 +610,24 @@ __global__ void set_protocol(double *knot_t, double *knot_v, DevInfo *devs, int 
     }
 }
 
-// Start of a kmc_run_steps call: remember the caller's output buffers.
-__global__ void begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out) {
-    ctl->call_base = ctl->n_base;
-    ctl->tally_base = ctl->n_base;
-    ctl->net_out = net_out;
-    ctl->dec_out = dec_out;
-}
-
 // End of a tally chunk of `steps` steps: per device, prefix-sum the decile
 // deltas into absolute counts, accumulate the int64 net total, copy rows to the
-// caller's buffers, clear the chunk buffers, and advance the step counter.
-// One workgroup per series (device, decile or net hops), one thread per step.
+// caller's buffers and clear the chunk buffers.  One workgroup per series
+// (device, decile or net hops), one thread per step.
 static_assert(kTallySteps <= 1024, "finish_chunk scans a chunk in one workgroup");
-__global__ __launch_bounds__(1024) void finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec,
-                                                     int64_t *dec_run, int64_t *net_total, int n_dev,
-                                                     int steps) {
+__global__ __launch_bounds__(1024) void finish_chunk(FinishArgs f) {
     __shared__ int64_t wsum[1024 / 64];
-    const int d = blockIdx.x, q = blockIdx.y;  // q == kDeciles: net hops
+    const int d = f.d0 + blockIdx.x, q = blockIdx.y;  // q == kDeciles: net hops
     const int k = threadIdx.x, lane = k & 63, wave = k >> 6;
-    const int64_t row0 = ctl->tally_base - ctl->call_base;
-    int32_t *net_out = ctl->net_out;
-    int32_t *dec_out = ctl->dec_out;
-    const int64_t carry = q < kDeciles ? dec_run[d * kDeciles + q] : 0;  // read before the barrier
+    const int n_dev = f.n_devices, steps = f.steps;
+    const int64_t row0 = f.ctl.tally_base - f.ctl.call_base;
+    int32_t *net_out = f.ctl.net_out;
+    int32_t *dec_out = f.ctl.dec_out;
+    const int64_t carry = q < kDeciles ? f.dec_run[d * kDeciles + q] : 0;  // read before the barrier
     int64_t x = 0;
     if (k < steps) {
-        int32_t *p = q < kDeciles ? &tally_dec[((int64_t)k * n_dev + d) * kDeciles + q]
-                                  : &tally_net[(int64_t)k * n_dev + d];
+        int32_t *p = q < kDeciles ? &f.tally_dec[((int64_t)k * n_dev + d) * kDeciles + q]
+                                  : &f.tally_net[(int64_t)k * n_dev + d];
         x = *p;
         *p = 0;
         if (q == kDeciles && net_out) net_out[(row0 + k) * n_dev + d] = (int32_t)x;
@@ -657,14 +648,9 @@ __global__ __launch_bounds__(1024) void finish_chunk(Ctl *ctl, int32_t *tally_ne
     }
     if (k < steps && q < kDeciles && dec_out) dec_out[((row0 + k) * n_dev + d) * kDeciles + q] = (int32_t)(carry + before + x);
     if (k == 0) {
-        if (q < kDeciles) dec_run[d * kDeciles + q] = carry + total;
-        else net_total[d] += total;
+        if (q < kDeciles) f.dec_run[d * kDeciles + q] = carry + total;
+        else f.net_total[d] += total;
     }
-}
-
-__global__ void advance_steps(Ctl *ctl, int steps) {
-    ctl->n_base += steps;
-    ctl->tally_base = ctl->n_base;
 }
 
 __global__ void zero_i32(int32_t *p, int64_t n) {
@@ -1002,18 +988,10 @@ hipError_t launch_set_protocol(double *knot_t, double *knot_v, DevInfo *devs, in
     return hipGetLastError();
 }
 
-hipError_t launch_begin_call(Ctl *ctl, int32_t *net_out, int32_t *dec_out, hipStream_t st) {
-    hipLaunchKernelGGL(begin_call, dim3(1), dim3(1), 0, st, ctl, net_out, dec_out);
-    return hipGetLastError();
-}
-
-hipError_t launch_finish_chunk(Ctl *ctl, int32_t *tally_net, int32_t *tally_dec, int64_t *dec_run,
-                               int64_t *net_total, int n_dev, int steps, hipStream_t st) {
+hipError_t launch_finish_chunk(const FinishArgs &f, hipStream_t st) {
     // one workgroup per series (device, decile or net hops), one thread per step
-    if (steps < 1 || steps > 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(finish_chunk, dim3(n_dev, kDeciles + 1), dim3(1024), 0, st, ctl, tally_net, tally_dec,
-                       dec_run, net_total, n_dev, steps);
-    hipLaunchKernelGGL(advance_steps, dim3(1), dim3(1), 0, st, ctl, steps);
+    if (f.steps < 1 || f.steps > 1024 || f.d1 <= f.d0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(finish_chunk, dim3(f.d1 - f.d0, kDeciles + 1), dim3(1024), 0, st, f);
     return hipGetLastError();
 }
 

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
     const Real *kt = kt_in_lds ? kt_lds : kt_glob;
     const int slot_words = 2 * m * W32;      // 64-bit words of one ring slot
     const uint64_t epoch = a.epoch;
-    const int64_t j0 = 2 * a.ctl->n_base;
+    const int64_t j0 = 2 * a.ctl.n_base;
     const Real beta_r = (Real)a.beta, c0_r = (Real)a.c0, alpha_r = (Real)a.alpha;
 
     // the lane's chunk, fixed for the launch
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
         if (!isolated) publish(nxt, j + 1);
         if (h == 1 && tid == 0) {
             if (sh.n_down | sh.n_up) {
-                const int64_t base = (n - a.ctl->tally_base) * a.n_devices + tile.d;
+                const int64_t base = (n - a.ctl.tally_base) * a.n_devices + tile.d;
                 atomicAdd(&a.tally_net[base], sh.n_down - sh.n_up);
                 for (int q = 0; q < kDeciles; ++q)
                     if (sh.dec[q]) atomicAdd(&a.tally_dec[base * kDeciles + q], sh.dec[q]);

@@ -315,8 +315,8 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             g.dv_off = dv.off;
             g.off_pad = dv.off_pad;
             g.n_set = dv.n_set;
-            g.n_base = a.ctl->n_base;
-            g.tally_base = a.ctl->tally_base;
+            g.n_base = a.ctl.n_base;
+            g.tally_base = a.ctl.tally_base;
             g.coul_bound = dv.coul_bound;
         }
         // the lane's sites, fixed for the launch
@@ -656,33 +656,83 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         PhStep<kNB> ps;
         {
             const KArgs ka = kargs();
-            const uint32_t n_first = (uint32_t)((const __attribute__((address_space(4))) Ctl *)ka->ctl)->n_base;
+            const uint32_t n_first = (uint32_t)ka->ctl.n_base;
             ph_step(ps, phl, rail, n_first + (uint32_t)kstep, ka->key0);
         }
         if (!half_step(std::integral_constant<int, 0>{}, kstep, ps)) break;
         if (!half_step(std::integral_constant<int, 1>{}, kstep, ps)) break;
     }
 
-    // write the tile back
+    // write the tile back: the padded state (bits and barrier classes) and the
+    // caller's occupancy (unpadded, one byte per site)
     {
         const KArgs ka = kargs();
         const WaveGeo &g = lds_opaque(&w)->geo;
-        const int P = rfl(g.P);
+        const int P = rfl(g.P), L = rfl(g.L);
         int8_t *gstate = ka->occ + rfl(g.off_pad) + (int64_t)rfl(g.r0) * P;
         if (lane < rfl(g.nr) * rfl(g.lpr)) {
+            const int row = cls_base / P;
+            int8_t *urow = ka->occ_user + rfl(g.dv_off) + (int64_t)(rfl(g.r0) + row) * L;
 #pragma unroll
             for (int c = 0; c < SPL / 16; ++c) {
                 if (c == 0 || s0 + 16 * c < P) {
                     const uint32_t b16 = (bits >> (16 * c)) & 0xFFFFu;
                     const uint4 cv = *reinterpret_cast<const uint4 *>(w.cls + cls_base + s0 + 16 * c);
-                    uint4 v;
-                    v.x = (((b16 >> 0) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.x << 1);
-                    v.y = (((b16 >> 4) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.y << 1);
-                    v.z = (((b16 >> 8) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.z << 1);
-                    v.w = (((b16 >> 12) & 0xFu) * 0x00204081u & 0x01010101u) | (cv.w << 1);
+                    uint4 o;
+                    o.x = ((b16 >> 0) & 0xFu) * 0x00204081u & 0x01010101u;
+                    o.y = ((b16 >> 4) & 0xFu) * 0x00204081u & 0x01010101u;
+                    o.z = ((b16 >> 8) & 0xFu) * 0x00204081u & 0x01010101u;
+                    o.w = ((b16 >> 12) & 0xFu) * 0x00204081u & 0x01010101u;
+                    const uint4 v = make_uint4(o.x | (cv.x << 1), o.y | (cv.y << 1), o.z | (cv.z << 1), o.w | (cv.w << 1));
                     *reinterpret_cast<uint4 *>(gstate + cls_base + s0 + 16 * c) = v;
+                    const int sc = s0 + 16 * c;
+                    int8_t *u = urow + sc;
+                    if (sc + 16 <= L && (reinterpret_cast<uintptr_t>(u) & 15) == 0) {
+                        *reinterpret_cast<uint4 *>(u) = o;
+                    } else {
+                        for (int k = 0; k < 16 && sc + k < L; ++k) u[k] = (int8_t)((b16 >> k) & 1u);
+                    }
                 }
             }
+        }
+    }
+
+    // The last tile to finish ends the chunk (the launch's tally rows and
+    // totals), when the host asked for it.  The tallies are only ever touched
+    // by device-scope atomics inside the launch: a tile waits until its own
+    // have been performed before it counts itself, and the last tile reads
+    // them with device-scope atomic loads.  (A device-scope release fence per
+    // tile would write back the whole L2 of its XCD.)  Tiles count themselves
+    // in kTicketBuckets counters (tile index modulo the bucket count), and the
+    // tile that completes a bucket counts the bucket in the total, so that no
+    // counter takes more than one atomic per bucket member.
+    if (a.ticket) {
+        const KArgs ka = kargs();
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        const int nt = ka->n_tiles;
+        const int b = ti % kTicketBuckets;
+        const uint32_t members = (uint32_t)(nt / kTicketBuckets + (b < nt % kTicketBuckets ? 1 : 0));
+        const uint32_t buckets = (uint32_t)(nt < kTicketBuckets ? nt : kTicketBuckets);
+        uint32_t last = 0;
+        if (lane == 0) {
+            uint32_t *bucket = ka->ticket + b * kTicketStride;
+            uint32_t *total = ka->ticket + kTicketBuckets * kTicketStride;
+            if (__hip_atomic_fetch_add(bucket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1u) {
+                __hip_atomic_store(bucket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                if (__hip_atomic_fetch_add(total, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == buckets - 1u) {
+                    __hip_atomic_store(total, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    last = 1;
+                }
+            }
+        }
+        last = (uint32_t)__builtin_amdgcn_readfirstlane((int)last);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        if (last) {
+            // the tile's class rows are free now: 128 segment sums
+            const FinishArgs fin = a.fin;
+            finish_tallies_wave(fin, lane, reinterpret_cast<int64_t *>(w.cls));
         }
     }
 }
@@ -705,8 +755,9 @@ hipError_t launch_wave(const PArgs &a, int spl, size_t lds, bool fp64, hipStream
     PArgs args = a;
     void *kargs[] = {&args};
     const int groups = (a.n_tiles + kWaveTilesPerWG - 1) / kWaveTilesPerWG;
-    return hipLaunchCooperativeKernel(wave_fn(spl, fp64), dim3(groups), dim3(64 * kWaveTilesPerWG), kargs,
-                                      (unsigned)lds, st);
+    // An ordinary launch: the grid never exceeds what is co-resident (checked
+    // by the host), and every neighbour wait is bounded.
+    return hipLaunchKernel(wave_fn(spl, fp64), dim3(groups), dim3(64 * kWaveTilesPerWG), kargs, (size_t)lds, st);
 }
 
 hipError_t wave_capacity(int spl, size_t lds, bool fp64, int *blocks_per_cu) {
