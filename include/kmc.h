@@ -141,13 +141,24 @@ kmc_status kmc_set_bias_protocol(kmc_ctx *ctx, int32_t device, const double *t_s
 kmc_status kmc_run_steps(kmc_ctx *ctx, int64_t n_steps, int32_t *net_hops_dev,
                          int32_t *decile_dev);
 
-/* Copy the occupancy to host memory; bytes >= total sites.  Synchronises. */
+/* Copy the occupancy to host memory (paper SI S2.1, "movement acceptance and
+ * position update": the state after the accepted moves of every step; an ion
+ * on each occupied site, the caller's layout above).  dst_host: host memory
+ * of at least `bytes` >= total sites bytes, not owned by the library.
+ * Synchronises the stream.  Errors: KMC_EINVAL for NULL dst_host,
+ * KMC_ETOOSMALL when bytes < total sites (nothing copied), KMC_EHIP when a
+ * persistent launch reported a failed neighbour wait (the context is then
+ * poisoned), KMC_ESTATE on a poisoned context. */
 kmc_status kmc_read_occupancy(kmc_ctx *ctx, int8_t *dst_host, size_t bytes);
 
-/* Electrode current and totals since init (Ramo-Shockley current of blocking
- * electrodes, I = e*net/(L*dt) per step).  Host outputs, each may be NULL:
- *   mean_current_A [n_devices], net_hops_total [n_devices], sim_time_s.
- * Synchronises. */
+/* Electrode current and totals since init (paper SI S3, conversion to
+ * current: the observable is the charge moved through the device; here the
+ * Ramo-Shockley current of blocking electrodes, I = e*net/(L*dt) per step,
+ * with net = hops toward site 0 minus hops toward site L-1).  Host outputs,
+ * each may be NULL: mean_current_A [n_devices] (the mean over every step run
+ * since init), net_hops_total [n_devices], sim_time_s (step counter * dt).
+ * Synchronises the stream.  Errors: as kmc_read_occupancy (KMC_EHIP,
+ * KMC_ESTATE). */
 kmc_status kmc_read_current(kmc_ctx *ctx, double *mean_current_A, int64_t *net_hops_total,
                             double *sim_time_s);
 
@@ -200,6 +211,27 @@ kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0,
  *   phi_dev: device float [total sites], occupancy layout (written).
  * KMC_EUNSUPPORTED unless the context was created with KMC_BF16X2. */
 kmc_status kmc_dense_potential(kmc_ctx *ctx, float *phi_dev);
+
+/* Relaxation time of a decay curve (main text section 4, relaxation decay:
+ * once the bias is removed the fraction of ions in the first decile decays as
+ * a single exponential towards an asymptote every run shares; SI S5, current
+ * relaxation).  Least-squares fit, in binary64 on the host, of
+ *     m(t) = C + A exp(-(t - t0)/tau)
+ * to the n samples (t[i], m[i]) (for example the replica mean of the decile
+ * fraction over the relaxation window, t0 the end of the bias pulse), by
+ * Gauss-Newton iteration.
+ *   t, m:    host [n], n >= 4, finite, not every t equal to t0.
+ *   params:  host [3].  In: a starting point (C, A, tau) when all three are
+ *            finite and tau > 0, else ignored.  Out: the fitted (C, A, tau).
+ *   weights: NULL or host [n]: d tau / d m[i] at the fit, from the
+ *            implicit-function theorem on the fit's stationarity condition
+ *            (the weights that turn a gradient of the samples into a gradient
+ *            of tau).
+ * Touches no context and no device memory.  Errors: KMC_EINVAL for bad
+ * arguments, KMC_EUNSUPPORTED when the iteration finds no minimum with
+ * tau > 0 (params and weights are then left unspecified). */
+kmc_status kmc_fit_decay(const double *t, const double *m, int64_t n, double t0, double *params,
+                         double *weights);
 
 /* Launch strategy of kmc_run_steps.
  *   KMC_LAUNCH_HALF_STEP: one kernel launch per half-step; the state makes a
@@ -276,6 +308,10 @@ kmc_status kmc_autotune(kmc_ctx *ctx, int32_t trial_steps, int32_t *tile_sites, 
 
 /* Current step counter. */
 kmc_status kmc_get_step(kmc_ctx *ctx, int64_t *step);
+
+/* SHA-1 (hex) of the sources and build flags this library was built from,
+ * so that a loader can refuse a library older than its sources. */
+const char *kmc_build_hash(void);
 
 /* Text of the last error of the calling thread ("" if none). */
 const char *kmc_last_error(void);

@@ -6,7 +6,7 @@ There is no CPU fallback: if the HIP library is missing, loading fails loudly.
 
 Module-level functions carry the C names without the `kmc_` prefix
 (init_device, fill_random, set_bias_protocol, run_steps, read_occupancy,
-read_current, read_threshold_log, ...).  `Simulator` bundles them with the
+read_current, read_threshold_log, fit_decay, ...).  `Simulator` bundles them with the
 torch-owned buffers of one context.
 """
 from __future__ import annotations
@@ -52,6 +52,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
         L = C.CDLL(LIB_PATH)
+        L.kmc_build_hash.restype = C.c_char_p
+        built = L.kmc_build_hash().decode()
+        if os.path.isdir(os.path.join(HERE, "csrc")):
+            from .build import source_hash
+            if built != source_hash():
+                raise ImportError(f"{LIB_PATH} was built from other sources than csrc/ holds now "
+                                  f"(run __graft_entry__.build())")
         P, vp = C.POINTER, C.c_void_p
         L.kmc_workspace_bytes.argtypes = [P(kmc_params), P(C.c_size_t)]
         L.kmc_init_device.argtypes = [P(kmc_params), vp, vp, vp, C.c_size_t, vp, P(vp)]
@@ -72,6 +79,8 @@ def lib():
         L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
         L.kmc_dense_potential.argtypes = [vp, vp]
         L.kmc_autotune.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)]
+        L.kmc_fit_decay.argtypes = [P(C.c_double), P(C.c_double), C.c_int64, C.c_double, P(C.c_double),
+                                    P(C.c_double)]
         L.kmc_last_error.restype = C.c_char_p
         L.kmc_destroy.argtypes = [vp]
         L.kmc_destroy.restype = None
@@ -80,7 +89,7 @@ def lib():
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
                      "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential",
-                     "kmc_autotune"):
+                     "kmc_autotune", "kmc_fit_decay"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -184,6 +193,21 @@ def set_tile_sites(ctx: int, sites: int) -> None:
 def score_replay(ctx: int, occ0_ptr: int, step0: int, n_steps: int, weight_ptr: int, grad_ptr: int) -> None:
     _check(lib().kmc_score_replay(C.c_void_p(ctx), C.c_void_p(occ0_ptr), step0, n_steps, C.c_void_p(weight_ptr),
                                   C.c_void_p(grad_ptr)))
+
+
+def fit_decay(t_s: Sequence[float], m: Sequence[float], t0: float, start=None, weights: bool = True):
+    """kmc_fit_decay: least-squares C + A exp(-(t - t0)/tau) through (t_s, m).
+    Returns ((C, A, tau), d tau / d m as an array, or None when weights=False)."""
+    t = np.ascontiguousarray(t_s, dtype=np.float64)
+    mm = np.ascontiguousarray(m, dtype=np.float64)
+    if t.shape != mm.shape or t.ndim != 1:
+        raise ValueError("t_s and m must be 1-D arrays of one length")
+    par = np.full(3, np.nan) if start is None else np.ascontiguousarray(start, dtype=np.float64).copy()
+    w = np.zeros(len(t)) if weights else None
+    PD = C.POINTER(C.c_double)
+    _check(lib().kmc_fit_decay(t.ctypes.data_as(PD), mm.ctypes.data_as(PD), len(t), float(t0),
+                               par.ctypes.data_as(PD), w.ctypes.data_as(PD) if w is not None else PD()))
+    return (float(par[0]), float(par[1]), float(par[2])), w
 
 
 def destroy(ctx: int) -> None:

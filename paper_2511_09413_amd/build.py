@@ -6,6 +6,7 @@ hipcc cross-compiles without a GPU.  Flags:
   -target-feature -packed-fp32-ops
                          no packed FP32 instructions.
 """
+import hashlib
 import os
 import subprocess
 import sys
@@ -15,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libkmc.so")
-SOURCES = ["kmc_kernels.hip", "kmc_persistent.hip", "kmc_wave.hip", "kmc_dense.hip", "kmc_api.cpp"]
+SOURCES = ["kmc_kernels.hip", "kmc_persistent.hip", "kmc_wave.hip", "kmc_dense.hip", "kmc_api.cpp", "kmc_fit.cpp"]
 ARCH = os.environ.get("KMC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -26,13 +27,28 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-command-line-argument"]
+
+
+def source_hash() -> str:
+    """SHA-1 over the build flags and every source and header the library is
+    built from (csrc/ and include/), in sorted order.  build() embeds it; the
+    loader compares it with the library's kmc_build_hash()."""
+    h = hashlib.sha1(" ".join(FLAGS).encode())
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".cpp", ".h")):
+                h.update(f.encode())
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-shared",
-           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-command-line-argument",
-           "-I" + os.path.join(ROOT, "include")]
+    cmd = [hipcc()] + FLAGS + ["-I" + os.path.join(ROOT, "include"), "-DKMC_SOURCE_HASH=\"%s\"" % source_hash()]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     cmd += ["-o", tmp]
     if verbose:

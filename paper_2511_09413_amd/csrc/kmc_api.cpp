@@ -1321,6 +1321,11 @@ kmc_status kmc_calib_copy(const void *src, void *dst, size_t bytes, void *stream
     return KMC_OK;
 }
 
+#ifndef KMC_SOURCE_HASH
+#define KMC_SOURCE_HASH "unknown"
+#endif
+const char *kmc_build_hash(void) { return KMC_SOURCE_HASH; }
+
 const char *kmc_last_error(void) { return g_last_error.c_str(); }
 
 void kmc_destroy(kmc_ctx *c) {

@@ -67,3 +67,44 @@ def test_workspace_holds_the_replay_buffers():
         n_small, n_large = 64 * 128, 4096 * 1024
         assert large - small >= size * (n_large - n_small)
         assert small >= size * n_small + 16 * 4096
+
+
+def test_native_decay_fit_matches_the_oracle_fit():
+    """kmc_fit_decay (host arithmetic in the library, parameterised by the
+    decay rate) against the oracle's Gauss-Newton fit in (C, A, tau): the same
+    least-squares minimum and the same implicit-function weights, on a
+    noise-free curve (exact recovery) and on noisy curves."""
+    import numpy as np
+    from oracle import relaxation as rx
+    t0 = 3e-9
+    t = np.linspace(t0, t0 + 30e-9, 500)
+    exact = rx.decay_model(t, t0, 0.22, 0.31, 5e-9)
+    (c, a, tau), w = kmc.fit_decay(t, exact, t0)
+    assert abs(tau - 5e-9) <= 1e-9 * 5e-9 and abs(c - 0.22) <= 1e-9 and abs(a - 0.31) <= 1e-9
+    for seed in range(4):
+        m = exact + np.random.default_rng(seed).normal(0.0, 0.02, len(t))
+        ref, _ = rx.fit_decay(t, m, t0)
+        w_ref = rx.tau_weights(t, m, t0, ref)
+        got, w = kmc.fit_decay(t, m, t0)
+        assert np.allclose(got, ref, rtol=1e-9, atol=0.0), (got, ref)
+        assert np.abs(w - w_ref).max() <= 1e-8 * np.abs(w_ref).max()
+        # a starting point is used, and gives the same minimum
+        again, _ = kmc.fit_decay(t, m, t0, start=(0.1, 0.5, 2e-9), weights=False)
+        assert np.allclose(again, ref, rtol=1e-9, atol=0.0)
+
+
+def test_native_decay_fit_errors():
+    import numpy as np
+    t = np.linspace(0.0, 1.0, 10)
+    with pytest.raises(kmc.KmcError) as e:
+        kmc.fit_decay(t[:3], t[:3], 0.0)
+    assert e.value.status == kmc.KMC_EINVAL
+    with pytest.raises(kmc.KmcError):
+        kmc.fit_decay(np.zeros(10), t, 0.0)            # every time equals t0
+    bad = t.copy()
+    bad[4] = np.nan
+    with pytest.raises(kmc.KmcError):
+        kmc.fit_decay(t, bad, 0.0)
+    with pytest.raises(kmc.KmcError) as e:
+        kmc.fit_decay(t, np.full(10, 0.3), 0.0)       # a flat curve has no decay time
+    assert e.value.status in (kmc.KMC_EUNSUPPORTED, kmc.KMC_EINVAL)
