@@ -7,8 +7,9 @@ binary32 rates.  A step is one full hop step (both bond parities) of the whole
 lattice.  Inputs are resident in device memory before the timed region.
 
 Prints one JSON line: site-updates/s (value), the roofline of the dominant
-kernel (the hop kernel: VALU-bound by the Philox4x32-10 stream), the effective
-HBM rate of the method's algorithmic traffic, and the CPU oracle timed on a
+kernel (the hop kernel: VALU-bound by the Philox4x32-10 stream), the HBM rate
+the kernel's counters measured, the method's algorithmic bytes as an
+equivalent rate, and the CPU oracle (all host cores, and one core) timed on a
 bounded sample of the same workload.
 """
 import argparse
@@ -87,19 +88,53 @@ def philox_blocks_per_step(rails, sites) -> int:
     return total
 
 
-def cpu_baseline(wl, budget_s):
-    """The oracle as it stands (single thread) on whole steps of the same
-    device, stopping once budget_s of CPU time is spent."""
+def host_cores() -> int:
+    """Threads for the all-core oracle leg: OMP_NUM_THREADS when set (the host's
+    share of a shared machine), else the CPUs this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    return len(os.sched_getaffinity(0))
+
+
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(wl, budget_s, threads):
     import oracle
-    p = oracle.params_for(wl)
-    occ = oracle.fill(p, wl.filling)
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < budget_s:
-        oracle.run(p, wl.protocols, occ, steps, 1, want_dec=False)
-        steps += 1
-    el = time.perf_counter() - t0
-    return {"value": wl.n_sites * steps / el, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} whole steps of the 4096x1024 device, single-threaded C oracle, {el:.1f} s"}
+    oracle.set_threads(threads)
+    try:
+        p = oracle.params_for(wl)
+        occ = oracle.fill(p, wl.filling)
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            oracle.run(p, wl.protocols, occ, steps, 1, want_dec=False)
+            steps += 1
+        el = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(1)
+    return wl.n_sites * steps / el, steps, el
+
+
+def cpu_baseline(wl, budget_s):
+    """The oracle as it stands on whole steps of the same device, stopping once
+    budget_s of wall time is spent: on all of the host's cores (OpenMP over
+    rails inside each half-step, the reported baseline) and on one core."""
+    cores = host_cores()
+    v_all, s_all, e_all = _oracle_rate(wl, budget_s, cores)
+    v_one, s_one, e_one = _oracle_rate(wl, budget_s, 1)
+    return {"value": v_all, "unit": "site-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{s_all} whole steps of the 4096x1024 device, C oracle on {cores} threads, {e_all:.1f} s",
+            "single_core": {"value": v_one, "cores": 1,
+                            "sample": f"{s_one} whole steps, single-threaded, {e_one:.1f} s"},
+            "host": {"nproc": os.cpu_count(), "cpu_model": host_cpu_model()}}
 
 
 def main():
@@ -170,11 +205,16 @@ def main():
         "config": {"workload": wl.name, "rails": 4096, "sites": 1024, "filling": 0.3,
                    "protocol": "triangle +-2 V over 1e5 steps", "barriers": "N(0.3,0.02) eV per site",
                    "coulomb": "lambda=4, cutoff=16, +-1 rail", "launch_mode": mode},
-        "effective_hbm_gbs": BYTES_PER_SITE_UPDATE * value / 1e9,
-        "effective_hbm_frac": BYTES_PER_SITE_UPDATE * value / 1e9 / HBM_PEAK_GBS,
         "roofline": {"bound": "alu", "kernel": kernel, "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                      "avg_launch_us": per_launch_s * 1e6, "launches": launches},
+        # HBM traffic the kernel actually moves (counter record of the same
+        # kernel sources, scaled by the copy-kernel calibration), per second
+        # of this run's launches; the lattice stays in registers for a launch
+        "hbm_measured_gbs": traffic / per_launch_s / 1e9 if traffic is not None else None,
+        # the method's algorithmic bytes (occupancy and barrier read per
+        # half-step) per second: an equivalent rate, not a fraction of a roof
+        "algorithmic_bytes_equivalent_gbs": BYTES_PER_SITE_UPDATE * value / 1e9,
         "wall_s": wall,
         "net_hops_total": int(tot[0]),
         "mean_current_A": float(cur[0]),
@@ -228,7 +268,9 @@ def bench_batch(args):
         "config": {"workload": wl.name, "devices": len(wl.rails), "sites_total": wl.n_sites,
                    "launch_mode": mode, "groups": sim.n_groups,
                    "autotuned": None if tuned is None else {k: tuned[k] for k in ("tile_sites", "mode", "us_per_step")}},
-        "effective_hbm_gbs": BYTES_PER_SITE_UPDATE / 5 * 2 * value / 1e9,
+        # occupancy read per half-step pass (no barrier field here): an
+        # equivalent rate of the method's algorithmic bytes
+        "algorithmic_bytes_equivalent_gbs": BYTES_PER_SITE_UPDATE / 5 * 2 * value / 1e9,
         "roofline": {"bound": "alu",
                      "kernel": {"persistent": "hop_persistent", "wave": "hop_wave"}.get(mode, "hop_half_step"),
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -309,20 +351,12 @@ def bench_gradient(args):
     t_rep = _timed(lambda: grads.append(sim.score_replay(occ0, 0, W)), stream)
     g = grads[0].cpu().numpy()
     value = wl.n_sites * steps / (t_fwd + t_rep)
-    # replay work as the method defines it: the Philox stream plus, for every
-    # candidate bond, a masked add per window site (2 lane-operations) over the
-    # distinct rails in range; candidates per bond 2 f (1 - f) for the fixed ion
-    # count f L per rail.  The kernel reads a maintained Coulomb potential
-    # instead of summing the window, so this is an equivalent rate.
-    ph = wl.physics
-    wn = 2 * ph.cutoff_sites + 2
-    window_ops = 0.0
-    for R, L, f in zip(wl.rails, wl.sites, wl.filling):
-        fr = round(f * L) / L
-        n_nbr = min(2 * ph.rail_range + 1, R)
-        window_ops += R * (L - 1) * 2 * fr * (1 - fr) * n_nbr * wn * 2
-    replay_ops = OPS_PER_PHILOX_BLOCK * philox_blocks_per_step(wl.rails, wl.sites) + window_ops
-    achieved = replay_ops * steps / t_rep / 1e12
+    # The replay kernel's own memory stream, per half-step and site: the
+    # padded occupancy read (1 B) and written (1 B), and the binary32 Coulomb
+    # part of every bond of the half-step's parity (4 B per two sites); the
+    # recomputation after hops touches a few kB.  Against the HBM peak.
+    replay_bytes = 2 * (1 + 1 + 2) * wl.n_sites * steps
+    achieved = replay_bytes / t_rep / 1e9
     out = {
         "metric": "gradient site-updates/s (forward + score replay)", "value": value, "unit": "site-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": (t_fwd + t_rep) * 1e3 / steps,
@@ -333,10 +367,9 @@ def bench_gradient(args):
         "forward_site_updates_per_s": wl.n_sites * steps / t_fwd,
         "replay_site_updates_per_s": wl.n_sites * steps / t_rep,
         "replay_over_forward_time": t_rep / t_fwd,
-        "roofline": {"bound": "alu", "kernel": "hop_half_step<float,h,score>", "achieved": achieved,
-                     "ops": "Philox + 2 per window site of every candidate (expected candidate count); "
-                            "equivalent: the kernel reads a maintained potential instead of the window sum",
-                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+        "roofline": {"bound": "hbm", "kernel": "hop_half_step<float,h,score>", "achieved": achieved,
+                     "bytes": "8 B per site and step: occupancy in and out, one binary32 Coulomb part per bond",
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps,
                      "launch_note": "per half-step: the replay kernel and the potential update"},
         "grad_mean_over_replicas": [float(x) for x in g.mean(axis=0)],

@@ -78,6 +78,8 @@ def lib():
                               P(C.c_int32), P(C.c_int32), P(C.c_int64), C.c_void_p, C.c_int64,
                               P(C.c_int64), P(_Opts)]
         L.orc_run.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -165,6 +167,12 @@ def hop_prob(p: OracleParams, ea: float, dE: float, fp32: bool = False) -> float
     if fp32:
         return float(lib().orc_hop_prob_f32(C.byref(p.s), ea, dE))
     return float(lib().orc_hop_prob_f64(C.byref(p.s), ea, dE))
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the plain run path (rails split inside each
+    half-step; no effect on results, only on the log's entry order)."""
+    lib().orc_set_threads(int(n))
 
 
 def ions_per_rail(filling: float, L: int) -> int:

@@ -17,7 +17,7 @@ LIB = os.path.join(OUT_DIR, "libkmc_oracle.so")
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
+    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp",
            "-Wall", "-Wextra", "-fPIC", "-shared", SRC, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -399,6 +399,82 @@ static void add_score(const orc_params *P, const orc_run_opts *opts, int64_t k, 
     }
 }
 
+/* Threads of orc_run's plain path (no shuffle, no score accumulation): the
+ * rails of a device are split over OpenMP threads inside each half-step.
+ * Every decision reads only the half-step's snapshot and writes only its own
+ * rail, so the result does not depend on the thread count (the threshold
+ * log's entry order may). */
+static int orc_threads = 1;
+
+void orc_set_threads(int n)
+{
+    orc_threads = n < 1 ? 1 : n;
+}
+
+/* One bond (s, s+1) of rail r of device d in half-step h of step n (its k-th
+ * step in this run): candidate test, energy change on the snapshot Sd,
+ * probability, accept, the log, the score terms, and the update of Od.
+ * Returns 1 for a hop toward site 0, 2 toward site L-1, 0 otherwise. */
+static int visit_bond(const orc_params *P, int d, int R, int L, int64_t off, const int8_t *Sd,
+                      int8_t *Od, int h, int64_t n, int64_t k, double V, int r, int s,
+                      orc_log_entry *log, int64_t log_cap, int64_t *n_log, const orc_run_opts *opts,
+                      int threaded)
+{
+    int8_t a0 = Sd[(int64_t)r * L + s], a1 = Sd[(int64_t)r * L + s + 1];
+    if (a0 == a1) return 0;
+    int o = a0 ? s : s + 1;
+    int t = a0 ? s + 1 : s;
+    double ea = P->ea_site ? P->ea_site[off + (int64_t)r * L + o] : P->ea;
+    uint32_t w = orc_hop_word(P->seed, d, n, r, s);
+    int accept, near;
+    double u_log, p_log;
+    double p_score, e_coul_score, de_score, a_abs = 0.0;
+    if (P->fp32) {
+        float e_app, e_coul;
+        delta_energy_parts_f32(P, R, L, Sd, r, o, t, V, &e_app, &e_coul, &a_abs);
+        float dE = e_app + e_coul;
+        float p = orc_hop_prob_f32(P, ea, dE);
+        float u = ldexpf((float)w, -32);
+        accept = u < p;
+        u_log = u; p_log = p;
+        p_score = p; e_coul_score = e_coul; de_score = dE;
+        near = fabsf(u - p) < 1e-6f;
+        if (opts && opts->score_grad && opts->score_coul64) {
+            double e_app64, e_coul64;
+            delta_energy_parts_f64(P, R, L, Sd, r, o, t, V, &e_app64, &e_coul64, &a_abs);
+            float dE_s = e_app + (float)e_coul64;
+            p_score = orc_hop_prob_f32(P, ea, dE_s);
+            e_coul_score = e_coul64;
+            de_score = dE_s;
+        }
+    } else {
+        double e_app, e_coul;
+        delta_energy_parts_f64(P, R, L, Sd, r, o, t, V, &e_app, &e_coul, &a_abs);
+        double dE = e_app + e_coul;
+        double p = orc_hop_prob_f64(P, ea, dE);
+        double u = ldexp((double)w, -32);
+        accept = u < p;
+        u_log = u; p_log = p;
+        p_score = p; e_coul_score = e_coul; de_score = dE;
+        near = fabs(u - p) < 1e-6;
+    }
+    if (near) {
+        if (threaded) {
+#pragma omp critical(orc_log)
+            log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
+        } else {
+            log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
+        }
+    }
+    if (opts && opts->score_grad)
+        add_score(P, opts, k, d, accept, p_score, e_coul_score, V, o, t, L, ea, de_score, a_abs);
+    if (accept && opts && opts->score_hops) ++opts->score_hops[d];
+    if (!accept) return 0;
+    Od[(int64_t)r * L + o] = 0;
+    Od[(int64_t)r * L + t] = 1;
+    return t < o ? 1 : 2;
+}
+
 int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
             int64_t n0, int64_t n_steps, int32_t *net_out, int32_t *dec_out,
             int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,
@@ -414,6 +490,7 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
     double *V = (double *)malloc(sizeof(double) * (size_t)D);
     int32_t *n_down = (int32_t *)calloc((size_t)D, sizeof(int32_t));
     int32_t *n_up = (int32_t *)calloc((size_t)D, sizeof(int32_t));
+    const int threaded = orc_threads > 1 && !(opts && (opts->shuffle_seed || opts->score_grad || opts->score_hops));
 
     for (int64_t k = 0; k < n_steps; ++k) {
         int64_t n = n0 + k;
@@ -436,6 +513,20 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                 }
                 int n_bonds = (L - 1 - h + 1) / 2; /* s = h, h+2, ..., <= L-2 */
                 if (n_bonds < 0) n_bonds = 0;
+                if (threaded) {
+                    int32_t down = 0, up = 0;
+#pragma omp parallel for num_threads(orc_threads) schedule(static) reduction(+ : down, up)
+                    for (int r = r_lo; r < r_hi; ++r)
+                        for (int b = 0; b < n_bonds; ++b) {
+                            int dir = visit_bond(P, d, R, L, off, Sd, Od, h, n, k, V[d], r, h + 2 * b, log,
+                                                 log_cap, n_log, opts, 1);
+                            down += dir == 1;
+                            up += dir == 2;
+                        }
+                    n_down[d] += down;
+                    n_up[d] += up;
+                    continue;
+                }
                 int64_t m = (int64_t)(r_hi - r_lo) * n_bonds;
                 int64_t *perm = NULL;
                 if (opts && opts->shuffle_seed) {
@@ -446,56 +537,10 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                     int64_t b = perm ? perm[idx] : idx;
                     int r = r_lo + (int)(b / n_bonds);
                     int s = h + 2 * (int)(b % n_bonds);
-                    int8_t a0 = Sd[(int64_t)r * L + s], a1 = Sd[(int64_t)r * L + s + 1];
-                    if (a0 == a1) continue;
-                    int o = a0 ? s : s + 1;
-                    int t = a0 ? s + 1 : s;
-                    double ea = P->ea_site ? P->ea_site[off + (int64_t)r * L + o] : P->ea;
-                    uint32_t w = orc_hop_word(P->seed, d, n, r, s);
-                    int accept;
-                    double u_log, p_log;
-                    double p_score, e_coul_score, de_score, a_abs = 0.0;
-                    if (P->fp32) {
-                        float e_app, e_coul;
-                        delta_energy_parts_f32(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul, &a_abs);
-                        float dE = e_app + e_coul;
-                        float p = orc_hop_prob_f32(P, ea, dE);
-                        float u = ldexpf((float)w, -32);
-                        accept = u < p;
-                        u_log = u; p_log = p;
-                        p_score = p; e_coul_score = e_coul; de_score = dE;
-                        if (fabsf(u - p) < 1e-6f)
-                            log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
-                        if (opts && opts->score_grad && opts->score_coul64) {
-                            double e_app64, e_coul64;
-                            delta_energy_parts_f64(P, R, L, Sd, r, o, t, V[d], &e_app64, &e_coul64, &a_abs);
-                            float dE_s = e_app + (float)e_coul64;
-                            p_score = orc_hop_prob_f32(P, ea, dE_s);
-                            e_coul_score = e_coul64;
-                            de_score = dE_s;
-                        }
-                    } else {
-                        double e_app, e_coul;
-                        delta_energy_parts_f64(P, R, L, Sd, r, o, t, V[d], &e_app, &e_coul, &a_abs);
-                        double dE = e_app + e_coul;
-                        double p = orc_hop_prob_f64(P, ea, dE);
-                        double u = ldexp((double)w, -32);
-                        accept = u < p;
-                        u_log = u; p_log = p;
-                        p_score = p; e_coul_score = e_coul; de_score = dE;
-                        if (fabs(u - p) < 1e-6)
-                            log_event(log, log_cap, n_log, d, h, n, r, s, u_log, p_log);
-                    }
-                    if (opts && opts->score_grad)
-                        add_score(P, opts, k, d, accept, p_score, e_coul_score, V[d], o, t, L,
-                                  ea, de_score, a_abs);
-                    if (accept && opts && opts->score_hops) ++opts->score_hops[d];
-                    if (accept) {
-                        Od[(int64_t)r * L + o] = 0;
-                        Od[(int64_t)r * L + t] = 1;
-                        if (t < o) ++n_down[d];
-                        else ++n_up[d];
-                    }
+                    int dir = visit_bond(P, d, R, L, off, Sd, Od, h, n, k, V[d], r, s, log, log_cap, n_log,
+                                         opts, 0);
+                    if (dir == 1) ++n_down[d];
+                    else if (dir == 2) ++n_up[d];
                 }
                 free(perm);
             }
@@ -510,8 +555,8 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                 int32_t *dk = dec_out + (k * D + d) * 10;
                 for (int q = 0; q < 10; ++q) dk[q] = 0;
                 for (int r = 0; r < R; ++r)
-                    for (int s = 0; s < L; ++s)
-                        if (Od[(int64_t)r * L + s]) dk[(10 * s) / L] += 1;
+                    for (int s2 = 0; s2 < L; ++s2)
+                        if (Od[(int64_t)r * L + s2]) dk[(10 * s2) / L] += 1;
             }
         }
     }

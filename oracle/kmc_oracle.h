@@ -82,6 +82,7 @@ double orc_hop_prob_f64(const orc_params *P, double ea, double dE);
 float orc_hop_prob_f32(const orc_params *P, double ea, float dE);
 int orc_ions_per_rail(double filling, int L);
 void orc_fill(const orc_params *P, const double *filling, int8_t *occ);
+void orc_set_threads(int n);
 int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
             int64_t n0, int64_t n_steps, int32_t *net_out, int32_t *dec_out,
             int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,

@@ -8,16 +8,16 @@ times, each by at most 2^-24 of the running sum, which never exceeds
 sum_j occ_j |K| = phi_abs.  So
     |phi_gpu - phi_64| <= (2^-16 + n 2^-24) phi_abs,
 with phi_abs = phi_64 for kappa > 0 (all K > 0).  The decisions then use
-dE = e_app + phi(t) - K(1,0) - phi(o) in binary32: trajectories equal the
-binary64 oracle's except where |u - p| is below the resulting error of p,
-far inside the logged 1e-6 window; the lockstep harness resynchronises only
-there."""
+dE = e_app + phi(t) - K(1,0) - phi(o) in binary32: a decision can differ from
+the binary64 oracle's only where |u - p| is below the resulting error of p
+(in the worst case (beta/2) |dE error| p, about 1e-3 p at the validation
+barrier), so ensembles are compared within their statistical error."""
 import numpy as np
 import pytest
 
 import oracle
-from parity_util import gpu_available, lockstep
-from workloads import BF16X2, FP64, Physics, c4_dense, constant, triangle
+from parity_util import gpu_available
+from workloads import BF16X2, FP64, Physics, c4_dense, step_then_relax
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -47,24 +47,52 @@ def test_dense_potential_matches_oracle(rails, L, m, cut, lam):
     err = np.abs(phi - ref)
     assert np.all(err <= _bound(m, L) * ref + 1e-30), (err.max(), (err / ref).max())
     assert (err / ref).max() < 1e-4
+    print(f"phi error {rails}x{L} m={m}: max rel {(err / ref).max():.3e}, mean rel {(err / ref).mean():.3e}, "
+          f"max abs {err.max():.3e} V (bound {_bound(m, L):.3e} rel)")
 
 
-@pytest.mark.parametrize("R,L,m,protocol", [(16, 64, 4, constant(0.8)), (24, 128, 4, triangle(1.0, 150e-12))])
-def test_dense_trajectory_follows_fp64_oracle(R, L, m, protocol):
-    """Unscreened 1/r over the whole rail and +-m rails, validation barrier:
-    step-by-step equality with the binary64 oracle, resynchronised only in
-    chunks where both logged a near-threshold draw."""
+def test_dense_ensemble_matches_fp64_oracle():
+    """64 replicas of 16 x 64, unscreened 1/r over the whole rail and +-4
+    rails, validation barrier (0.15 eV), a 1 V pulse then relaxation: the
+    BF16X2 path against the binary64 oracle from the same initial states and
+    seeds.  The two ensembles' mean currents (pulse and relaxation windows)
+    and first-decile relaxation curves agree within 3 sigma of the ensemble
+    error (the potential's rounding moves a decision only where u lies within
+    about 1e-3 of p relative; most replicas keep the oracle's trajectory)."""
     from paper_2511_09413_amd import Simulator
-    ph = Physics(precision=BF16X2, seed=8, ea_ev=0.15, screening_sites=0.0, cutoff_sites=L - 1, rail_range=m)
+    D, R, L, n, n_on = 64, 16, 64, 300, 150
+    ph = Physics(precision=BF16X2, seed=8, ea_ev=0.15, screening_sites=0.0, cutoff_sites=L - 1, rail_range=4)
     ph64 = ph.replace(precision=FP64)
-    sim = Simulator(ph, [R, R], [L, L])
-    p_or = oracle.OracleParams(ph64, [R, R], [L, L])
-    occ0 = oracle.fill(p_or, [0.3, 0.2])
+    proto = step_then_relax(1.0, n_on * ph.dt_s)
+    sim = Simulator(ph, [R] * D, [L] * D)
+    p_or = oracle.OracleParams(ph64, [R] * D, [L] * D)
+    occ0 = oracle.fill(p_or, [0.3] * D)
     sim.load_occupancy(occ0)
-    sim.set_protocols([protocol, constant(-0.5)])
-    st = lockstep(sim, p_or, [protocol, constant(-0.5)], occ0, 200, 25, max_resync=3)
-    assert st["hops"] > 100
-    assert st["resyncs"] <= 3
+    sim.set_protocols([proto] * D)
+    net_g, dec_g = sim.run_steps(n, tallies=True)
+    net_g, dec_g = net_g.cpu().numpy(), dec_g.cpu().numpy()
+    occ_g = sim.read_occupancy()
+    occ_o = occ0.copy()
+    out = oracle.run(p_or, [proto] * D, occ_o, 0, n)
+    ions = out["dec"][0].sum(axis=1).astype(np.float64)
+    assert np.array_equal(dec_g[0].sum(axis=1), out["dec"][0].sum(axis=1))
+
+    def check(xg, xo, what):
+        gap = abs(xg.mean() - xo.mean())
+        sig = np.sqrt(xg.var(ddof=1) / D + xo.var(ddof=1) / D)
+        assert gap <= 3.0 * sig + 1e-15, (what, xg.mean(), xo.mean(), sig)
+
+    for w in (slice(0, n_on), slice(n_on, n)):
+        check(net_g[w].mean(axis=0), out["net"][w].mean(axis=0).astype(np.float64), f"current {w}")
+    f_g = dec_g[:, :, 0] / ions
+    f_o = out["dec"][:, :, 0] / ions
+    for k in (50, 100, 149, 200, 250, n - 1):
+        check(f_g[k], f_o[k], f"first-decile fraction at step {k}")
+    same = (occ_g.reshape(D, -1) == occ_o.reshape(D, -1)).all(axis=1)
+    print(f"dense ensemble: {int(same.sum())} of {D} replicas end in the oracle's state; "
+          f"hops {int(np.abs(out['net']).sum())}")
+    assert np.abs(out["net"]).sum() > 1000
+    assert same.sum() >= D // 2
 
 
 def test_c4_full_size_sampled():
@@ -87,3 +115,7 @@ def test_c4_full_size_sampled():
         ref = oracle.dense_potential(p_strip, strip).reshape(17, L)[8]
         err = np.abs(phi[d, r] - ref)
         assert np.all(err <= _bound(4, L) * ref), (d, r, err.max())
+        # the Coulomb part of dE of a bond, phi(s + 1) - phi(s) up to K(1, 0): its error
+        dv = np.abs(np.diff(phi[d, r]) - np.diff(ref))
+        print(f"c4 rail ({d}, {r}): phi max rel err {(err / ref).max():.3e} mean {(err / ref).mean():.3e}; "
+              f"bond dV err max {dv.max():.3e} V mean {dv.mean():.3e} V")

@@ -292,3 +292,29 @@ def test_dense_potential(R, L, m, cut, lam):
                 o, t = (s, s + 1) if S[r, s] else (s + 1, s)
                 e_coul = oracle.delta_energy(p, R, L, S, r, o, t, V) - ph.field_coupling * V * (t - o) / L
                 assert abs(phi[r, t] - k10 - phi[r, o] - e_coul) <= 1e-12 * (abs(phi[r, t]) + abs(phi[r, o]) + 1e-3)
+
+
+def test_threaded_oracle_equals_single_thread():
+    """The oracle's OpenMP path (rails of a device split over threads inside
+    each half-step) gives the single-threaded result: occupancy, per-step net
+    hops and deciles, and the same set of logged near-threshold draws."""
+    from workloads import small_case
+    wl = small_case(24, 96, filling=0.35, precision="fp32", ea_ev=0.05, n_devices=2, seed=9)
+    p = oracle.params_for(wl)
+    occ0 = oracle.fill(p, wl.filling)
+    outs = []
+    for threads in (1, 4):
+        oracle.set_threads(threads)
+        try:
+            outs.append(oracle.run(p, wl.protocols, occ0.copy(), 0, 30, log_cap=65536))
+        finally:
+            oracle.set_threads(1)
+    a, b = outs
+    assert np.abs(a["net"]).sum() > 100
+    for key in ("occ", "net", "dec"):
+        assert np.array_equal(a[key], b[key]), key
+    assert a["n_log"] == b["n_log"] and a["n_log"] <= 65536
+
+    def as_set(log):
+        return {(int(e["d"]), int(e["h"]), int(e["n"]), int(e["r"]), int(e["s"])) for e in log}
+    assert as_set(a["log"]) == as_set(b["log"])
