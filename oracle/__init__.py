@@ -40,6 +40,12 @@ class _Opts(C.Structure):
                 ("score_hops", C.POINTER(C.c_int64)), ("score_coul64", C.c_int)]
 
 
+class _ZoneParams(C.Structure):
+    _fields_ = [("rails", C.c_int), ("ions", C.c_int), ("sites", C.c_int), ("zones", C.c_int),
+                ("p0", C.c_double), ("kT", C.c_double), ("hop_over_thickness", C.c_double),
+                ("v_factor", C.c_double), ("dt", C.c_double), ("seed", C.c_uint64)]
+
+
 LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
                       ("s", np.int32), ("u", np.float64), ("p", np.float64)])
 
@@ -80,6 +86,16 @@ def lib():
         L.orc_run.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = None
+        L.orc_zone_index.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.orc_zone_index.restype = C.c_int
+        L.orc_zone_table.argtypes = [P(_ZoneParams), C.c_double, P(C.c_int64), P(C.c_double), P(C.c_double),
+                                     P(C.c_double)]
+        L.orc_zone_table.restype = None
+        L.orc_zone_words.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int64, P(C.c_uint32), P(C.c_uint32)]
+        L.orc_zone_words.restype = None
+        L.orc_zone_run.argtypes = [P(_ZoneParams), P(_Protocol), P(C.c_int32), C.c_int64, C.c_int64,
+                                   P(C.c_int32), P(C.c_int32), P(C.c_int64)]
+        L.orc_zone_run.restype = C.c_int
         _LIB = L
     return _LIB
 
@@ -264,3 +280,72 @@ def score_replay(p: OracleParams, protocols, occ0: np.ndarray, n0: int, weights:
         raise ValueError("oracle rejected the run (step counter out of range)")
     return {"grad": grad, "mag": mag, "sens": sens, "sens_arg": sens_arg, "sens_b": sens_b, "hops": hops,
             "occ": occ}
+
+
+# ---------------------------------------------------------------- zone model
+class ZoneParams:
+    """Parameters of the paper-literal zone model (kmc_oracle.h, orc_zone_params)."""
+
+    def __init__(self, rails: int, ions: int, sites: int, zones: int = 10, p0: float = 0.5,
+                 kT: float = 8.617333262e-5 * 300.0, hop_over_thickness: Optional[float] = None,
+                 v_factor: float = 5e-5, dt: float = 1e-3, seed: int = 0):
+        self.s = _ZoneParams(rails, ions, sites, zones, p0, kT,
+                             1.0 / sites if hop_over_thickness is None else hop_over_thickness,
+                             v_factor, dt, seed & 0xFFFFFFFFFFFFFFFF)
+        self.rails, self.ions, self.sites, self.zones = rails, ions, sites, zones
+
+
+def zone_index(x: int, sites: int, zones: int = 10) -> int:
+    return int(lib().orc_zone_index(x, sites, zones))
+
+
+def zone_table(p: ZoneParams, V: float, counts: Sequence[int]):
+    """(p_left, p_right, dv_net) of every zone for bias V and zone populations."""
+    c = np.ascontiguousarray(counts, dtype=np.int64)
+    pl, pr, dv = (np.zeros(p.zones) for _ in range(3))
+    lib().orc_zone_table(C.byref(p.s), V, _ptr(c, C.c_int64), _ptr(pl, C.c_double), _ptr(pr, C.c_double),
+                         _ptr(dv, C.c_double))
+    return pl, pr, dv
+
+
+def zone_words(seed: int, rail: int, ion: int, n: int):
+    wr, wl = C.c_uint32(0), C.c_uint32(0)
+    lib().orc_zone_words(seed, rail, ion, n, C.byref(wr), C.byref(wl))
+    return int(wr.value), int(wl.value)
+
+
+def zone_positions(occ: np.ndarray, rails: int, sites: int) -> np.ndarray:
+    """Ion-position matrix X [rails][ions] (1-based columns) of an occupancy
+    [rails][sites] with the same ion count on every rail."""
+    o = np.asarray(occ, dtype=np.int8).reshape(rails, sites)
+    cols = [np.nonzero(r)[0] + 1 for r in o]
+    if len({len(c) for c in cols}) != 1:
+        raise ValueError("every rail needs the same ion count")
+    return np.ascontiguousarray(np.array(cols, dtype=np.int32).reshape(rails, -1))
+
+
+def zone_occupancy(X: np.ndarray, sites: int) -> np.ndarray:
+    X = np.asarray(X)
+    occ = np.zeros((X.shape[0], sites), dtype=np.int8)
+    for i, row in enumerate(X):
+        occ[i, row - 1] = 1
+    return occ.reshape(-1)
+
+
+def zone_run(p: ZoneParams, protocol, X: np.ndarray, n0: int, n_steps: int, n_set: int = 0):
+    """Advance the ion-position matrix X [rails][ions] (modified in place) by
+    n_steps steps from step n0.  Returns net [n], zones [n][Z] and the total."""
+    Xc = np.ascontiguousarray(X, dtype=np.int32)
+    if Xc.shape != (p.rails, p.ions):
+        raise ValueError("X must be [rails][ions]")
+    prot = Protocols([protocol], [n_set])
+    net = np.zeros(n_steps, dtype=np.int32)
+    zones = np.zeros((n_steps, p.zones), dtype=np.int32)
+    tot = C.c_int64(0)
+    rc = lib().orc_zone_run(C.byref(p.s), prot.arr, _ptr(Xc, C.c_int32), n0, n_steps, _ptr(net, C.c_int32),
+                            _ptr(zones, C.c_int32), C.byref(tot))
+    if rc != 0:
+        raise ValueError("oracle rejected the run (step counter out of range)")
+    if Xc is not X:
+        X[...] = Xc
+    return {"X": Xc, "net": net, "zones": zones, "net_total": int(tot.value)}

@@ -566,3 +566,136 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
     free(n_up);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Paper-literal zone model (SI S2.1, "Step-by-Step Explanation of the   */
+/* Markov Chain Monte Carlo Framework").                                 */
+/* ------------------------------------------------------------------ */
+/* Zone of column x (1-based) in a rail of `sites` columns cut into `zones`
+ * zones of equal width: z = ceil(x / (sites / zones)) = ceil(x zones / sites)
+ * (SI S2.1, "Spatial Zones and Local Probabilities"), in 1..zones. */
+int orc_zone_index(int x, int sites, int zones)
+{
+    return (int)(((int64_t)x * zones + sites - 1) / sites);
+}
+
+/* The directional probabilities of every zone for bias V and zone
+ * populations counts[z-1] (ions of all rails in zone z):
+ *   net drop (the implicit space charge: the applied bias less the drop
+ *   across the zone due to the ion imbalance of the zones on either side,
+ *   scaled by the effective voltage difference factor; a reading, SI S2.1
+ *   "Implicit space-charge effects"):
+ *     rho_z   = counts_z - N/Z,
+ *     dV_net  = V - v_factor (sum_{z' < z} rho_z' - sum_{z' > z} rho_z'),
+ *   energy gap (SI Eq. S1):    dE = q dV_net d_hop / t_dev   (q = 1 e),
+ *   Boltzmann factor (Eq. S2): B = exp(-dE / kT),
+ *   probabilities (Eqs. S3, S4):  P_left = P0 / (1 + B),  P_right = B P_left.
+ * "Left" is toward column 1 (the grounded electrode), the direction in
+ * which a positive bias drives the cations. */
+void orc_zone_table(const orc_zone_params *P, double V, const int64_t *counts, double *p_left,
+                    double *p_right, double *dv_net)
+{
+    int Z = P->zones;
+    double total = 0.0;
+    for (int z = 0; z < Z; ++z) total += (double)counts[z];
+    double mean = total / (double)Z;
+    for (int z = 0; z < Z; ++z) {
+        double below = 0.0, above = 0.0;
+        for (int y = 0; y < z; ++y) below += (double)counts[y] - mean;
+        for (int y = z + 1; y < Z; ++y) above += (double)counts[y] - mean;
+        double dv = V - P->v_factor * (below - above);
+        double dE = dv * P->hop_over_thickness;
+        double B = exp(-dE / P->kT);
+        p_left[z] = P->p0 / (1.0 + B);
+        p_right[z] = B * p_left[z];
+        if (dv_net) dv_net[z] = dv;
+    }
+}
+
+/* The two uniforms of ion j of a rail in step n (SI S2.1, "two independent
+ * random matrices"): Philox4x32-10 block at counter (j >> 1, rail, n,
+ * 2 << 1) (stream 2, device 0), words 2 (j & 1) and 2 (j & 1) + 1 for the
+ * right and the left trial. */
+void orc_zone_words(uint64_t seed, int rail, int ion, int64_t n, uint32_t *w_right, uint32_t *w_left)
+{
+    uint32_t ctr[4] = {(uint32_t)(ion >> 1), (uint32_t)rail, (uint32_t)n, 2u << 1};
+    uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    *w_right = out[2 * (ion & 1)];
+    *w_left = out[2 * (ion & 1) + 1];
+}
+
+/* n_steps steps of the zone model from step n0.  X [rails][ions] holds
+ * 1-based columns, strictly increasing along each rail; it is updated in
+ * place.  Per step (SI S2.1, in the paper's order):
+ *   1. zone populations from X, the bias V(t_n), the table of Eqs. S1-S4;
+ *   2. for every ion: its zone, the two uniforms, the gaps to its
+ *      neighbours (a virtual ion at column 0 before the first ion and at
+ *      sites + 1 after the last: moves stay inside the rail), the masks
+ *        M_right = [u_right <= P_right(z) and gap_right > 1],
+ *        M_left  = [u_left <= P_left(z) and gap_left > 1],
+ *      and the move M_right - M_left;
+ *   3. all ions at once: X += move, except that two ions that would land
+ *      on the same column (gap 2, the left one moving right and the right
+ *      one moving left) both stay (the conflict rule of this reading; the
+ *      paper's simultaneous update leaves it open);
+ *   4. tallies: net_out[k] = moves toward column 1 minus moves away,
+ *      zone_out[k][z] = ions in zone z after the step.
+ * Returns 0, or -1 for a step counter beyond 2^32 - 1. */
+int orc_zone_run(const orc_zone_params *P, const orc_protocol *protocol, int32_t *X, int64_t n0,
+                 int64_t n_steps, int32_t *net_out, int32_t *zone_out, int64_t *net_total)
+{
+    if (n0 < 0 || n0 + n_steps > (int64_t)0xffffffffLL) return -1;
+    int Ny = P->rails, Nr = P->ions, Lx = P->sites, Z = P->zones;
+    int64_t *counts = (int64_t *)calloc((size_t)Z, sizeof(int64_t));
+    double *pl = (double *)malloc(sizeof(double) * (size_t)Z);
+    double *pr = (double *)malloc(sizeof(double) * (size_t)Z);
+    int *move = (int *)malloc(sizeof(int) * (size_t)(Nr > 0 ? Nr : 1));
+    for (int64_t k = 0; k < n_steps; ++k) {
+        int64_t n = n0 + k;
+        for (int z = 0; z < Z; ++z) counts[z] = 0;
+        for (int i = 0; i < Ny; ++i)
+            for (int j = 0; j < Nr; ++j) counts[orc_zone_index(X[(int64_t)i * Nr + j], Lx, Z) - 1] += 1;
+        double V = device_voltage(protocol, 0, n, P->dt);
+        orc_zone_table(P, V, counts, pl, pr, NULL);
+        int32_t net = 0;
+        for (int i = 0; i < Ny; ++i) {
+            int32_t *row = X + (int64_t)i * Nr;
+            for (int j = 0; j < Nr; ++j) {
+                int x = row[j];
+                int z = orc_zone_index(x, Lx, Z) - 1;
+                uint32_t wr, wl;
+                orc_zone_words(P->seed, i, j, n, &wr, &wl);
+                double ur = ldexp((double)wr, -32), ul = ldexp((double)wl, -32);
+                int right_nb = j + 1 < Nr ? row[j + 1] : Lx + 1;
+                int left_nb = j > 0 ? row[j - 1] : 0;
+                int m_right = ur <= pr[z] && right_nb - x > 1;
+                int m_left = ul <= pl[z] && x - left_nb > 1;
+                move[j] = m_right - m_left;
+            }
+            for (int j = 0; j + 1 < Nr; ++j)
+                if (move[j] == 1 && move[j + 1] == -1 && row[j + 1] - row[j] == 2) {
+                    move[j] = 0;
+                    move[j + 1] = 0;
+                }
+            for (int j = 0; j < Nr; ++j) {
+                row[j] += move[j];
+                net -= move[j];
+            }
+        }
+        if (net_out) net_out[k] = net;
+        if (net_total) *net_total += net;
+        if (zone_out) {
+            int32_t *zk = zone_out + k * Z;
+            for (int z = 0; z < Z; ++z) zk[z] = 0;
+            for (int i = 0; i < Ny; ++i)
+                for (int j = 0; j < Nr; ++j) zk[orc_zone_index(X[(int64_t)i * Nr + j], Lx, Z) - 1] += 1;
+        }
+    }
+    free(counts);
+    free(pl);
+    free(pr);
+    free(move);
+    return 0;
+}

@@ -88,4 +88,28 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
             int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,
             const orc_run_opts *opts);
 
+/* Paper-literal zone model (SI S2.1): every rail holds `ions` ions at
+ * 1-based columns 1..sites (the ion-position matrix X), the lattice is cut
+ * into `zones` zones of equal width, and each zone has its own pair of
+ * directional hop probabilities per step. */
+typedef struct {
+    int rails;                  /* N_y */
+    int ions;                   /* N_r, ions per rail */
+    int sites;                  /* L_x, columns per rail */
+    int zones;                  /* Z */
+    double p0;                  /* baseline hop probability P0 per ion and step */
+    double kT;                  /* k_B T, eV */
+    double hop_over_thickness;  /* d_hop / t_dev */
+    double v_factor;            /* effective voltage difference factor, V per ion of zone imbalance */
+    double dt;                  /* time per step, s (protocol time t_n = n dt) */
+    uint64_t seed;
+} orc_zone_params;
+
+int orc_zone_index(int x, int sites, int zones);
+void orc_zone_table(const orc_zone_params *P, double V, const int64_t *counts, double *p_left,
+                    double *p_right, double *dv_net);
+void orc_zone_words(uint64_t seed, int rail, int ion, int64_t n, uint32_t *w_right, uint32_t *w_left);
+int orc_zone_run(const orc_zone_params *P, const orc_protocol *protocol, int32_t *X, int64_t n0,
+                 int64_t n_steps, int32_t *net_out, int32_t *zone_out, int64_t *net_total);
+
 #endif
