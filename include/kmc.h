@@ -202,6 +202,22 @@ kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t
 kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
                             const double *weight_dev, double *grad_dev);
 
+/* kmc_score_replay for callers that cannot allocate device memory where they
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same replay, the same arguments and results, but
+ * the replay's own buffers (two state planes, the per-bond Coulomb parts, the
+ * accepted-hop list and its counters) live in a static device array of
+ * 64 MiB per GPU that the library holds until the process ends, instead of
+ * in the context's workspace.  The call allocates nothing.  Call it with the
+ * context's device current.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (on other streams or threads) race.
+ * Errors: as kmc_score_replay, plus KMC_EUNSUPPORTED when the lattice needs
+ * more than the array holds (about 10 million sites in binary32, 6 million
+ * in binary64; the message gives both sizes) and KMC_EHIP when the array's
+ * device address cannot be looked up. */
+kmc_status kmc_score_replay_noalloc(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                                    const double *weight_dev, double *grad_dev);
+
 /* Coulomb potential of the current state at every site, as used by the
  * KMC_BF16X2 step: phi(r, s) = sum over the distinct rails r' within
  * rail_range (r included) and sites j of occ(r', j) K(s - j, dist(r, r')),

@@ -74,6 +74,7 @@ def lib():
         L.kmc_get_launch_mode.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_tile_sites.argtypes = [vp, C.c_int32]
         L.kmc_score_replay.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
+        L.kmc_score_replay_noalloc.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
         L.kmc_get_persistent_groups.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
         L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
@@ -89,7 +90,7 @@ def lib():
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
                      "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential",
-                     "kmc_autotune", "kmc_fit_decay"):
+                     "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -208,6 +209,12 @@ def fit_decay(t_s: Sequence[float], m: Sequence[float], t0: float, start=None, w
     _check(lib().kmc_fit_decay(t.ctypes.data_as(PD), mm.ctypes.data_as(PD), len(t), float(t0),
                                par.ctypes.data_as(PD), w.ctypes.data_as(PD) if w is not None else PD()))
     return (float(par[0]), float(par[1]), float(par[2])), w
+
+
+def score_replay_noalloc(ctx: int, occ0_ptr: int, step0: int, n_steps: int, weight_ptr: int,
+                         grad_ptr: int) -> None:
+    _check(lib().kmc_score_replay_noalloc(C.c_void_p(ctx), C.c_void_p(occ0_ptr), step0, n_steps,
+                                          C.c_void_p(weight_ptr), C.c_void_p(grad_ptr)))
 
 
 def destroy(ctx: int) -> None:

@@ -1247,8 +1247,22 @@ kmc_status kmc_set_persistent_group_limit(kmc_ctx *c, int32_t max_tiles) {
     return retile(c);
 }
 
-kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
-                            const double *weight_dev, double *grad_dev) {
+}  // extern "C"
+
+namespace {
+// The replay's own buffers: its two state planes, the Coulomb part of every
+// bond (path precision), the accepted-hop list with its two counters and the
+// discarded near-threshold event count.
+struct ReplayBufs {
+    int8_t *occ_a, *occ_b;
+    void *rec;
+    uint4 *hops;
+    int64_t *hop_ctl;
+    int64_t *score_log;
+};
+
+kmc_status check_replay_args(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                             const double *weight_dev, double *grad_dev) {
     kmc_status s = usable(c);
     if (s != KMC_OK) return s;
     if (!occ0_dev || !grad_dev) return fail(KMC_EINVAL, "occ0_dev/grad_dev is NULL");
@@ -1259,16 +1273,24 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
         return fail(KMC_EINVAL, "score replay needs coulomb_kappa_v != 0 (the kappa score is dE_coul/kappa)");
     if (!(c->p.nu0_hz > 0.0)) return fail(KMC_EINVAL, "score replay needs nu0_hz > 0");
     if (c->dense) return fail(KMC_EUNSUPPORTED, "score replay runs the binary64/binary32 window paths only");
+    return KMC_OK;
+}
+
+kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                          const double *weight_dev, double *grad_dev, const ReplayBufs &b) {
     const int D = c->p.n_devices;
     KMC_HIP(c, launch_zero_i64(reinterpret_cast<int64_t *>(grad_dev), 4 * (int64_t)D, c->stream));
     if (n_steps == 0) return KMC_OK;
-    int8_t *cur = c->at<int8_t>(c->lay.rp_a), *nxt = c->at<int8_t>(c->lay.rp_b);
+    int8_t *cur = b.occ_a, *nxt = b.occ_b;
     KMC_HIP(c, launch_import(occ0_dev, cur, c->at<DevInfo>(c->lay.devs), D, c->lay.total_pad, c->ea, c->fp64,
                              c->stream));
     HopArgs a = hop_args(c);
-    a.log.count = c->at<int64_t>(c->lay.score_log);
+    a.log.count = b.score_log;
     a.log.cap = 0;
     a.score_grad = grad_dev;
+    a.rec = b.rec;
+    a.hops = b.hops;
+    a.hop_ctl = b.hop_ctl;
     // the Coulomb parts of the starting state, then per half-step the replay
     // (which lists its accepted hops) and the recomputation of the bonds they
     // changed
@@ -1279,12 +1301,11 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     pa.ktab64 = c->at<double>(c->lay.ktab64);
     pa.cutoff = c->lay.cut;
     pa.rail_range = c->p.rail_range;
-    pa.ec = c->ws + c->lay.rec;
+    pa.ec = b.rec;
     pa.k01 = c->k01;
-    pa.hops = c->at<uint4>(c->lay.hops);
+    pa.hops = b.hops;
     pa.hop_cap = c->lay.hop_cap;
-    int64_t *hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
-    KMC_HIP(c, launch_zero_i64(hop_ctl, 2, c->stream));
+    KMC_HIP(c, launch_zero_i64(b.hop_ctl, 2, c->stream));
     KMC_HIP(c, launch_replay_ec_full(pa, c->fp64, c->stream));
     for (int64_t k = 0; k < n_steps; ++k) {
         a.n_abs = step0 + k;
@@ -1295,12 +1316,68 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
             a.h = h;
             KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
             pa.occ = nxt;  // the new state, for a full recomputation after an overflow
-            pa.hop_count = hop_ctl + h;
+            pa.hop_count = b.hop_ctl + h;
             KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream));
             std::swap(cur, nxt);
         }
     }
     return KMC_OK;
+}
+}  // namespace
+
+namespace kmc {
+// Bytes a region needs to hold the replay's buffers for this context.
+size_t replay_region_bytes(const kmc_ctx *c) {
+    const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
+    return align_up((size_t)c->lay.total_pad, 256) * 2 + align_up(real * (size_t)c->lay.total_sites, 256) +
+           align_up(sizeof(uint4) * (size_t)c->lay.hop_cap, 256) + 256;
+}
+
+// kmc_score_replay with the replay's buffers carved from `region` (device
+// memory of region_bytes, 256-byte aligned) instead of the workspace.
+kmc_status score_replay_in_region(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                                  const double *weight_dev, double *grad_dev, unsigned char *region,
+                                  size_t region_bytes) {
+    kmc_status s = check_replay_args(c, occ0_dev, step0, n_steps, weight_dev, grad_dev);
+    if (s != KMC_OK) return s;
+    const size_t need = replay_region_bytes(c);
+    if (need > region_bytes)
+        return fail(KMC_EUNSUPPORTED, "the lattice needs " + std::to_string(need) +
+                                          " bytes of replay buffers; the static scratch holds " +
+                                          std::to_string(region_bytes));
+    const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
+    ReplayBufs b{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = region + off;
+        off += align_up(bytes, 256);
+        return p;
+    };
+    b.occ_a = reinterpret_cast<int8_t *>(take((size_t)c->lay.total_pad));
+    b.occ_b = reinterpret_cast<int8_t *>(take((size_t)c->lay.total_pad));
+    b.rec = take(real * (size_t)c->lay.total_sites);
+    b.hops = reinterpret_cast<uint4 *>(take(sizeof(uint4) * (size_t)c->lay.hop_cap));
+    int64_t *ctl = reinterpret_cast<int64_t *>(take(4 * sizeof(int64_t)));
+    b.hop_ctl = ctl;
+    b.score_log = ctl + 2;
+    return enqueue_replay(c, occ0_dev, step0, n_steps, weight_dev, grad_dev, b);
+}
+}  // namespace kmc
+
+extern "C" {
+
+kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
+                            const double *weight_dev, double *grad_dev) {
+    kmc_status s = check_replay_args(c, occ0_dev, step0, n_steps, weight_dev, grad_dev);
+    if (s != KMC_OK) return s;
+    ReplayBufs b{};
+    b.occ_a = c->at<int8_t>(c->lay.rp_a);
+    b.occ_b = c->at<int8_t>(c->lay.rp_b);
+    b.rec = c->ws + c->lay.rec;
+    b.hops = c->at<uint4>(c->lay.hops);
+    b.hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
+    b.score_log = c->at<int64_t>(c->lay.score_log);
+    return enqueue_replay(c, occ0_dev, step0, n_steps, weight_dev, grad_dev, b);
 }
 
 kmc_status kmc_dense_potential(kmc_ctx *c, float *phi_dev) {
