@@ -42,11 +42,12 @@ def parse():
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent", "wave"])
     ap.add_argument("--tile-sites", type=int, default=0)
     ap.add_argument("--workload", default="large-device",
-                    choices=["large-device", "batch", "gradient", "dense", "small-fp64"],
+                    choices=["large-device", "batch", "gradient", "dense", "small-fp64", "zone"],
                     help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
                          "gradient: forward + score replay of 512 replicas x 256 x 512; "
                          "dense: 64 replicas x 1024 x 512 with the MFMA long-range potential; "
-                         "small-fp64: 64 x 128 in binary64 (latency)")
+                         "small-fp64: 64 x 128 in binary64 (latency); "
+                         "zone: the paper's own zone model at Table S2's largest size (128,000 rails x 200)")
     return ap.parse_args()
 
 
@@ -151,6 +152,8 @@ def main():
         return bench_dense(args)
     if args.workload == "small-fp64":
         return bench_small(args)
+    if args.workload == "zone":
+        return bench_zone(args)
     import torch
     import paper_2511_09413_amd as kmc
     from workloads import c2_large_device
@@ -432,6 +435,68 @@ def bench_dense(args):
     out["dense_over_plain_fp32"] = value / out["plain_fp32_site_updates_per_s"]
     out["plain_fp32_launch_mode"] = plain.launch_mode
     plain.close()
+    print(json.dumps(out), flush=True)
+
+
+# the paper's GPU figure for its zone model at 128,000 rails (SI S4, Table S2):
+# 10,774,101 rail-steps/s on an unnamed GPU
+PAPER_ZONE_RAIL_STEPS_128K = 10_774_101.0
+
+
+def bench_zone(args):
+    """The paper's own zone model (SI S2.1) at Table S2's largest size:
+    128,000 rails x 200 columns, 60 ions per rail (30 %), Table S1's constants
+    (300 K, effective voltage difference factor 5e-5 V), a 5 V polarisation
+    then relaxation; one kernel launch per step.  Value: rail-steps/s, the
+    metric of Table S2."""
+    import torch
+    import paper_2511_09413_amd as kmc
+    from workloads import zone_relaxation
+    steps = args.steps if args.steps != 100_000 else 20_000
+    wl = zone_relaxation(rails=128_000, n_steps=steps)
+    sim = kmc.ZoneSimulator(wl.rails, wl.sites, wl.ions, zones=wl.zones, p0=wl.p0, kT_ev=wl.kT_ev,
+                            v_factor=wl.v_factor, dt_s=wl.dt_s, seed=wl.seed, occ=wl.occupancy())
+    sim.set_bias_protocol(*wl.protocol)
+    sim.run_steps(min(args.warmup, 200))
+    stream = torch.cuda.current_stream()
+    sec = _timed(lambda: sim.run_steps(steps), stream)
+    value = wl.rails * steps / sec
+    ions = wl.rails * wl.ions
+    # per step: the positions read and written (2 B each), one Philox block
+    # per two ions (40 VALU lane-operations)
+    hbm = 4.0 * ions / (sec / steps) / 1e9
+    alu = OPS_PER_PHILOX_BLOCK * (ions / 2) / (sec / steps) / 1e12
+    fr_h, fr_a = hbm / HBM_PEAK_GBS, alu / VALU_PEAK_TOPS
+    roof = ({"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fr_h}
+            if fr_h >= fr_a else
+            {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": fr_a})
+    roof.update({"kernel": "zone_step", "traffic": None, "avg_launch_us": sec / steps * 1e6, "launches": steps,
+                 "other": {"hbm_frac": fr_h, "alu_frac": fr_a}})
+    out = {
+        "metric": "rail-steps/s (zone model, 128,000 rails x 200)", "value": value, "unit": "rail-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 200), "ms_per_step": sec * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak",
+        # the paper's own figure for this metric and workload, on its unnamed GPU
+        "vs_baseline": value / PAPER_ZONE_RAIL_STEPS_128K,
+        "dtype": "fp64 table, u32 draws", "data": "synthetic",
+        "config": {"workload": wl.name, "rails": wl.rails, "sites": wl.sites, "ions_per_rail": wl.ions,
+                   "zones": wl.zones, "protocol": "5 V for 5 s, then 0 V; 0.016 s per step"},
+        "roofline": roof,
+        "paper_rail_steps_per_s": PAPER_ZONE_RAIL_STEPS_128K,
+    }
+    sim.close()
+    if not args.no_cpu_baseline:
+        import oracle
+        p = oracle.ZoneParams(wl.rails, wl.ions, wl.sites, zones=wl.zones, p0=wl.p0, kT=wl.kT_ev,
+                              v_factor=wl.v_factor, dt=wl.dt_s, seed=wl.seed)
+        X = wl.X0.copy()
+        k, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 10.0):
+            oracle.zone_run(p, wl.protocol, X, k, 1)
+            k += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": wl.rails * k / el, "unit": "rail-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{k} whole steps of the 128,000-rail lattice, C oracle, {el:.1f} s"}
     print(json.dumps(out), flush=True)
 
 

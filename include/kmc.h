@@ -325,6 +325,85 @@ kmc_status kmc_autotune(kmc_ctx *ctx, int32_t trial_steps, int32_t *tile_sites, 
 /* Current step counter. */
 kmc_status kmc_get_step(kmc_ctx *ctx, int64_t *step);
 
+/* ------------------------------------------------------------------------
+ * The paper's own zone model (SI S2.1, "Step-by-Step Explanation of the
+ * Markov Chain Monte Carlo Framework"), beside the per-site hop step above.
+ * The state is the ion-position matrix X [rails][ions_per_rail]: the 1-based
+ * column of every ion, strictly increasing along its rail.  The rail of
+ * `sites` columns is cut into `zones` zones of equal width, zone
+ * z = ceil(X / (sites / zones)).  Per step (in this order):
+ *   - the bias V(t_n) of the installed protocol, t_n = (n - n_install) dt_s;
+ *   - per zone the net drop with the implicit space charge (a reading of the
+ *     paper's "effective voltage difference factor"):
+ *       dV_net(z) = V - v_factor (sum_{z'<z} rho_z' - sum_{z'>z} rho_z'),
+ *       rho_z = (ions in zone z, all rails) - (all ions) / zones;
+ *   - the energy gap dE = dV_net hop_over_thickness (Eq. S1 with q = 1 e and
+ *     hop_over_thickness = d_hop / t_dev), B = exp(-dE / kT) (Eq. S2),
+ *     P_left = p0 / (1 + B), P_right = B P_left (Eqs. S3, S4); "left" is
+ *     toward column 1, the grounded electrode;
+ *   - for every ion two uniforms (Philox4x32-10 block at counter
+ *     (j >> 1, rail, n, 4), words 2 (j & 1) and 2 (j & 1) + 1 for the right
+ *     and the left trial), the masks [u <= P] and [gap to the neighbour > 1]
+ *     (a virtual neighbour at column 0 and at sites + 1), the move
+ *     M_right - M_left, all ions at once; two ions that would land on one
+ *     column (gap 2, moving toward each other) both stay.
+ * All arithmetic of the table in binary64.  kmc_zone_ctx is opaque. */
+typedef struct kmc_zone_ctx kmc_zone_ctx;
+
+typedef struct {
+    int32_t rails;               /* N_y >= 1                                  */
+    int32_t sites;               /* L_x in [2, 65534]                         */
+    int32_t ions_per_rail;       /* N_r in [0, min(64, sites)], every rail    */
+    int32_t zones;               /* Z in [1, 64] (the paper: 10)              */
+    double p0;                   /* baseline hop probability, [0, 1]          */
+    double kT_ev;                /* k_B T, eV, > 0                            */
+    double hop_over_thickness;   /* d_hop / t_dev (1 / sites when the rail
+                                    spans the device)                         */
+    double v_factor;             /* effective voltage difference factor, V per
+                                    ion of zone imbalance (the paper: 5e-5)   */
+    double dt_s;                 /* time per step, s (the protocol's clock)   */
+    uint64_t seed;               /* Philox4x32-10 key                         */
+} kmc_zone_params;
+
+/* Device workspace bytes for kmc_zone_init. */
+kmc_status kmc_zone_workspace_bytes(const kmc_zone_params *params, size_t *bytes);
+
+/* Create a zone-model context (paper SI S2.1 "Initialization", SI S2.2).
+ *   occ_dev: device int8 [rails][sites] occupancy, caller-owned; every rail
+ *            must hold exactly ions_per_rail ions (else KMC_EINVAL).  It
+ *            becomes the initial state, and after every kmc_zone_run_steps
+ *            it holds the current state again.
+ *   workspace_dev: device memory of kmc_zone_workspace_bytes, 256-byte
+ *            aligned, caller-owned.
+ * The step counter starts at 0 and the bias is 0 V.  Synchronises. */
+kmc_status kmc_zone_init(const kmc_zone_params *params, int8_t *occ_dev, void *workspace_dev, size_t ws_bytes,
+                         void *stream, kmc_zone_ctx **out);
+
+/* Re-read the state from occ_dev (same rules as at init).  Synchronises. */
+kmc_status kmc_zone_load_occupancy(kmc_zone_ctx *ctx);
+
+/* Install the voltage-vs-time profile (SI S2.2), piecewise linear through the
+ * knots as kmc_set_bias_protocol, times relative to the current step. */
+kmc_status kmc_zone_set_bias_protocol(kmc_zone_ctx *ctx, const double *t_s, const double *v_volt,
+                                      int32_t n_knots);
+
+/* Advance n_steps steps (SI S2.1, the loop; one kernel launch per step).
+ *   net_dev:  NULL or device int32 [n_steps]: moves toward column 1 minus
+ *             moves toward column `sites` in each step.
+ *   zone_dev: NULL or device int32 [n_steps][zones]: ions in each zone after
+ *             each step (with 10 zones, the deciles of SI S3). */
+kmc_status kmc_zone_run_steps(kmc_zone_ctx *ctx, int64_t n_steps, int32_t *net_dev, int32_t *zone_dev);
+
+/* Copy X to host int32 [rails][ions_per_rail] (count >= rails * ions).
+ * Synchronises. */
+kmc_status kmc_zone_read_positions(kmc_zone_ctx *ctx, int32_t *X_host, size_t count);
+
+/* Current step counter of a zone-model context. */
+kmc_status kmc_zone_get_step(kmc_zone_ctx *ctx, int64_t *step);
+
+/* Release a zone-model context (enqueued work is completed first). */
+void kmc_zone_destroy(kmc_zone_ctx *ctx);
+
 /* SHA-1 (hex) of the sources and build flags this library was built from,
  * so that a loader can refuse a library older than its sources. */
 const char *kmc_build_hash(void);

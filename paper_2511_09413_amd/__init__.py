@@ -42,6 +42,12 @@ class kmc_params(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class kmc_zone_params(C.Structure):
+    _fields_ = [("rails", C.c_int32), ("sites", C.c_int32), ("ions_per_rail", C.c_int32), ("zones", C.c_int32),
+                ("p0", C.c_double), ("kT_ev", C.c_double), ("hop_over_thickness", C.c_double),
+                ("v_factor", C.c_double), ("dt_s", C.c_double), ("seed", C.c_uint64)]
+
+
 _LIB = None
 
 
@@ -80,6 +86,15 @@ def lib():
         L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
         L.kmc_dense_potential.argtypes = [vp, vp]
         L.kmc_autotune.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)]
+        L.kmc_zone_workspace_bytes.argtypes = [P(kmc_zone_params), P(C.c_size_t)]
+        L.kmc_zone_init.argtypes = [P(kmc_zone_params), vp, vp, C.c_size_t, vp, P(vp)]
+        L.kmc_zone_load_occupancy.argtypes = [vp]
+        L.kmc_zone_set_bias_protocol.argtypes = [vp, P(C.c_double), P(C.c_double), C.c_int32]
+        L.kmc_zone_run_steps.argtypes = [vp, C.c_int64, vp, vp]
+        L.kmc_zone_read_positions.argtypes = [vp, P(C.c_int32), C.c_size_t]
+        L.kmc_zone_get_step.argtypes = [vp, P(C.c_int64)]
+        L.kmc_zone_destroy.argtypes = [vp]
+        L.kmc_zone_destroy.restype = None
         L.kmc_fit_decay.argtypes = [P(C.c_double), P(C.c_double), C.c_int64, C.c_double, P(C.c_double),
                                     P(C.c_double)]
         L.kmc_last_error.restype = C.c_char_p
@@ -90,7 +105,9 @@ def lib():
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
                      "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential",
-                     "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc"):
+                     "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc", "kmc_zone_workspace_bytes",
+                     "kmc_zone_init", "kmc_zone_load_occupancy", "kmc_zone_set_bias_protocol", "kmc_zone_run_steps",
+                     "kmc_zone_read_positions", "kmc_zone_get_step"):
             getattr(L, name).restype = C.c_int
         _LIB = L
     return _LIB
@@ -196,6 +213,12 @@ def score_replay(ctx: int, occ0_ptr: int, step0: int, n_steps: int, weight_ptr: 
                                   C.c_void_p(grad_ptr)))
 
 
+def score_replay_noalloc(ctx: int, occ0_ptr: int, step0: int, n_steps: int, weight_ptr: int,
+                         grad_ptr: int) -> None:
+    _check(lib().kmc_score_replay_noalloc(C.c_void_p(ctx), C.c_void_p(occ0_ptr), step0, n_steps,
+                                          C.c_void_p(weight_ptr), C.c_void_p(grad_ptr)))
+
+
 def fit_decay(t_s: Sequence[float], m: Sequence[float], t0: float, start=None, weights: bool = True):
     """kmc_fit_decay: least-squares C + A exp(-(t - t0)/tau) through (t_s, m).
     Returns ((C, A, tau), d tau / d m as an array, or None when weights=False)."""
@@ -209,12 +232,6 @@ def fit_decay(t_s: Sequence[float], m: Sequence[float], t0: float, start=None, w
     _check(lib().kmc_fit_decay(t.ctypes.data_as(PD), mm.ctypes.data_as(PD), len(t), float(t0),
                                par.ctypes.data_as(PD), w.ctypes.data_as(PD) if w is not None else PD()))
     return (float(par[0]), float(par[1]), float(par[2])), w
-
-
-def score_replay_noalloc(ctx: int, occ0_ptr: int, step0: int, n_steps: int, weight_ptr: int,
-                         grad_ptr: int) -> None:
-    _check(lib().kmc_score_replay_noalloc(C.c_void_p(ctx), C.c_void_p(occ0_ptr), step0, n_steps,
-                                          C.c_void_p(weight_ptr), C.c_void_p(grad_ptr)))
 
 
 def destroy(ctx: int) -> None:
@@ -390,6 +407,91 @@ class Simulator:
     def close(self) -> None:
         if getattr(self, "ctx", 0):
             destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ zone model
+class ZoneSimulator:
+    """The paper's zone model (kmc_zone_*): one lattice of `rails` rails of
+    `sites` columns with ions_per_rail ions each, torch-owned occupancy and
+    workspace on one GPU and the current torch stream."""
+
+    def __init__(self, rails: int, sites: int, ions_per_rail: int, zones: int = 10, p0: float = 0.5,
+                 kT_ev: float = 8.617333262e-5 * 300.0, hop_over_thickness: Optional[float] = None,
+                 v_factor: float = 5e-5, dt_s: float = 1e-3, seed: int = 0, occ=None, device: str = "cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.rails, self.sites, self.ions, self.zones = int(rails), int(sites), int(ions_per_rail), int(zones)
+        self.params = kmc_zone_params(self.rails, self.sites, self.ions, self.zones, p0, kT_ev,
+                                      1.0 / sites if hop_over_thickness is None else hop_over_thickness,
+                                      v_factor, dt_s, seed & 0xFFFFFFFFFFFFFFFF)
+        if occ is None:
+            raise ValueError("ZoneSimulator needs an initial occupancy [rails][sites]")
+        self.occ = torch.as_tensor(np.asarray(occ, dtype=np.int8).reshape(-1)).to(self.device)
+        if self.occ.numel() != self.rails * self.sites:
+            raise ValueError("occupancy size differs from rails * sites")
+        nbytes = C.c_size_t(0)
+        _check(lib().kmc_zone_workspace_bytes(C.byref(self.params), C.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        ws = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p(0)
+        with torch.cuda.device(self.device):
+            _check(lib().kmc_zone_init(C.byref(self.params), C.c_void_p(self.occ.data_ptr()), C.c_void_p(ws),
+                                       nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.ctx = int(h.value)
+
+    def set_bias_protocol(self, t_s, v_volt) -> None:
+        t = np.ascontiguousarray(t_s, dtype=np.float64)
+        v = np.ascontiguousarray(v_volt, dtype=np.float64)
+        if t.shape != v.shape:
+            raise ValueError("knot arrays differ in length")
+        PD = C.POINTER(C.c_double)
+        _check(lib().kmc_zone_set_bias_protocol(C.c_void_p(self.ctx), t.ctypes.data_as(PD), v.ctypes.data_as(PD),
+                                                len(t)))
+
+    def load_occupancy(self, occ) -> None:
+        self.occ.copy_(self.torch.as_tensor(np.asarray(occ, dtype=np.int8).reshape(-1)).to(self.device))
+        _check(lib().kmc_zone_load_occupancy(C.c_void_p(self.ctx)))
+
+    def run_steps(self, n_steps: int, tallies: bool = False):
+        """Advance n_steps; with tallies=True return (net [n], zones [n, Z]) torch tensors."""
+        torch = self.torch
+        if not tallies:
+            _check(lib().kmc_zone_run_steps(C.c_void_p(self.ctx), n_steps, None, None))
+            return None
+        net = torch.empty(n_steps, dtype=torch.int32, device=self.device)
+        zones = torch.empty((n_steps, self.zones), dtype=torch.int32, device=self.device)
+        _check(lib().kmc_zone_run_steps(C.c_void_p(self.ctx), n_steps, C.c_void_p(net.data_ptr()),
+                                        C.c_void_p(zones.data_ptr())))
+        return net, zones
+
+    def read_positions(self) -> np.ndarray:
+        out = np.zeros((self.rails, self.ions), dtype=np.int32)
+        _check(lib().kmc_zone_read_positions(C.c_void_p(self.ctx), out.ctypes.data_as(C.POINTER(C.c_int32)),
+                                             out.size))
+        return out
+
+    def read_occupancy(self) -> np.ndarray:
+        self.torch.cuda.current_stream(self.device).synchronize()
+        return self.occ.cpu().numpy()
+
+    @property
+    def step(self) -> int:
+        n = C.c_int64(0)
+        _check(lib().kmc_zone_get_step(C.c_void_p(self.ctx), C.byref(n)))
+        return int(n.value)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", 0):
+            lib().kmc_zone_destroy(C.c_void_p(self.ctx))
             self.ctx = 0
 
     def __del__(self):

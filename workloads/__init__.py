@@ -192,3 +192,50 @@ def small_case(rails: int, sites: int, filling: float = 0.3, precision: str = FP
     pr = protocol if protocol is not None else constant(0.5)
     return Workload(f"small_{n_devices}x{rails}x{sites}", ph, [rails] * n_devices,
                     [sites] * n_devices, [filling] * n_devices, [pr] * n_devices, 0)
+
+
+# ------------------------------------------------------------ zone model
+@dataclass
+class ZoneWorkload:
+    """The paper's own zone model at Table S1/S2 shapes: `rails` rails of
+    `sites` columns, `ions` ions per rail at uniformly random columns
+    (seeded), a protocol, and the model's constants."""
+    name: str
+    rails: int
+    sites: int
+    ions: int
+    zones: int
+    p0: float
+    kT_ev: float
+    v_factor: float
+    dt_s: float
+    seed: int
+    protocol: Protocol
+    n_steps: int
+    X0: np.ndarray   # [rails][ions] 1-based columns, increasing
+
+    def occupancy(self) -> np.ndarray:
+        occ = np.zeros((self.rails, self.sites), dtype=np.int8)
+        np.put_along_axis(occ, self.X0.astype(np.int64) - 1, 1, axis=1)
+        return occ.reshape(-1)
+
+
+def zone_positions(rails: int, sites: int, ions: int, seed: int) -> np.ndarray:
+    """ions distinct columns per rail, uniformly random (PCG64), sorted."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    keys = g.random((rails, sites))
+    cols = np.argsort(keys, axis=1)[:, :ions]
+    return (np.sort(cols, axis=1) + 1).astype(np.int32)
+
+
+def zone_relaxation(rails: int = 4000, sites: int = 200, ion_fraction: float = 0.3, n_steps: int = 187_200,
+                    seed: int = 5, p0: float = 0.5, v_factor: float = 5e-5) -> ZoneWorkload:
+    """Table S1 defaults (200 columns, 30 % ions, 300 K, a 5 V polarisation
+    for 5 s then relaxation at 0 V, the effective voltage difference factor
+    5e-5 V) with one step per relaxation time (0.016 s); Table S2 runs 500 to
+    128,000 rails for 187,200 steps."""
+    dt = 0.016
+    ions = int(round(ion_fraction * sites))
+    return ZoneWorkload(f"zone_relaxation_{rails}x{sites}", rails, sites, ions, 10, p0, 8.617333262e-5 * 300.0,
+                        v_factor, dt, seed, step_then_relax(5.0, 5.0), n_steps,
+                        zone_positions(rails, sites, ions, seed + 100))
