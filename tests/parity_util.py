@@ -34,7 +34,8 @@ def lockstep(sim, p_or, protocols, occ0: np.ndarray, n_steps: int, chunk: int,
     draw (device, step, half-step, rail, bond) of the device whose rows diverge
     first, at or before the first diverging step (or anywhere in the chunk
     when only the final occupancy differs).  The GPU is then resynchronised to
-    the oracle state.  Returns a summary dict."""
+    the oracle state.  Returns a summary dict (with the oracle's final state
+    under "occ")."""
     occ_o = occ0.copy().reshape(-1)
     D = len(p_or.rails)
     n0 = sim.step
@@ -78,4 +79,5 @@ def lockstep(sim, p_or, protocols, occ0: np.ndarray, n_steps: int, chunk: int,
         stats["hops"] += int(np.abs(out["net"]).sum())
         stats["steps"] += k
         done += k
+    stats["occ"] = occ_o      # the oracle's state after the run
     return stats

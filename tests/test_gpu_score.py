@@ -204,30 +204,33 @@ def test_autograd_backward_equals_oracle_estimator():
 
 
 def test_c5_full_size_sampled():
-    """512 replicas x 256 x 512 (FP32), the gradient workload's shape: replay 30
-    steps on the GPU; for sampled replicas the oracle computes the same replica
-    alone (the replicas before it shrunk to 1 x 2 sites with zero weight, so the
-    replica index of the random stream is unchanged)."""
+    """512 replicas x 256 x 512 (FP32), the gradient workload's shape: replay
+    256 steps on the GPU; for two sampled replicas (the first and the last)
+    the oracle computes the same replica alone (the replicas before it shrunk
+    to 1 x 2 sites with zero weight, so the replica index of the random stream
+    is unchanged)."""
     import torch
     from paper_2511_09413_amd import Simulator
-    wl = c5_gradient(n_steps=30)
+    n = 256
+    wl = c5_gradient(n_steps=n)
     ph = wl.physics.replace(ea_ev=0.2)
     D = len(wl.rails)
     sim = Simulator(ph, wl.rails, wl.sites)
     sim.fill_random(wl.filling)
     sim.set_protocols(wl.protocols)
     occ0 = sim.snapshot()
-    sim.run_steps(30)
-    W = np.random.default_rng(1).normal(size=(30, D))
+    sim.run_steps(n)
+    W = np.random.default_rng(1).normal(size=(n, D))
     grad = sim.score_replay(occ0, 0, torch.from_numpy(W)).cpu().numpy()
     occ0_h = occ0.cpu().numpy().reshape(D, -1)
-    for d in (0, 137, D - 1):
+    for d in (0, D - 1):
         rails = [1] * d + [wl.rails[d]]
         sites = [2] * d + [wl.sites[d]]
         p_or = oracle.OracleParams(ph, rails, sites)
         occ = np.concatenate([np.zeros(2 * d, dtype=np.int8), occ0_h[d]])
-        Wd = np.zeros((30, d + 1))
+        Wd = np.zeros((n, d + 1))
         Wd[:, d] = W[:, d]
         ref = oracle.score_replay(p_or, [wl.protocols[d]] * (d + 1), occ, 0, Wd, coul64=True)
+        assert ref["hops"][d] > 100
         tol = _tolerance(ref, ph)[d]
         assert np.all(np.abs(grad[d] - ref["grad"][d]) <= tol), (d, grad[d], ref["grad"][d], tol)
