@@ -379,7 +379,9 @@ kmc_status kmc_zone_workspace_bytes(const kmc_zone_params *params, size_t *bytes
 kmc_status kmc_zone_init(const kmc_zone_params *params, int8_t *occ_dev, void *workspace_dev, size_t ws_bytes,
                          void *stream, kmc_zone_ctx **out);
 
-/* Re-read the state from occ_dev (same rules as at init).  Synchronises. */
+/* Re-read the state from occ_dev (same rules as at init).  The ion counts
+ * are checked before anything is written: on KMC_EINVAL the context's state
+ * (positions, populations, step) is unchanged.  Synchronises. */
 kmc_status kmc_zone_load_occupancy(kmc_zone_ctx *ctx);
 
 /* Install the voltage-vs-time profile (SI S2.2), piecewise linear through the

@@ -303,7 +303,7 @@ __global__ void zone_make_table(const int64_t *pop, int Z, const double *knot_t,
 // whose ion count differs from `ions` raise *bad.  The populations of the
 // zones are added to pop.
 __global__ __launch_bounds__(256) void zone_import(const int8_t *occ, uint16_t *X, int rails, int sites, int ions,
-                                                  int zones, int64_t *pop, int32_t *bad) {
+                                                  int zones, int64_t *pop, int32_t *bad, int write) {
     __shared__ int32_t s_pop[kZoneMaxZones];
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < kZoneMaxZones) s_pop[threadIdx.x] = 0;
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void zone_import(const int8_t *occ, uint16_t *
             const bool occd = s < sites && src[s] != 0;
             const uint64_t m = __ballot(occd);
             const int rank = base + __popcll(m & ((1ull << lane) - 1ull));
-            if (occd && rank < ions) {
+            if (write && occd && rank < ions) {
                 X[rail * ions + rank] = (uint16_t)(s + 1);
                 atomicAdd(&s_pop[zone_of(s + 1, sites, zones) - 1], 1);
             }
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(256) void zone_import(const int8_t *occ, uint16_t *
         if (lane == 0 && base != ions) atomicExch(bad, 1);
     }
     __syncthreads();
-    if (threadIdx.x < zones && s_pop[threadIdx.x] != 0)
+    if (write && threadIdx.x < zones && s_pop[threadIdx.x] != 0)
         atomicAdd((unsigned long long *)&pop[threadIdx.x], (unsigned long long)(int64_t)s_pop[threadIdx.x]);
 }
 
@@ -455,20 +455,24 @@ kmc_status zone_refresh_table(kmc_zone_ctx *c) {
 }
 
 // Read the caller's occupancy into X and the populations of the current
-// buffer; synchronises to check the ion counts.
+// buffer.  A first pass only counts the ions of every rail (and synchronises),
+// so a rejected occupancy leaves the context's state as it was.
 kmc_status zone_load(kmc_zone_ctx *c) {
     const int Z = c->p.zones;
     int64_t *pop = c->at<int64_t>(c->off_pop) + c->cur * kZoneMaxZones;
-    ZONE_HIP(c, zone_fill(pop, Z, 0, c->stream));
+    const dim3 grid((unsigned)((c->p.rails + 3) / 4));
     ZONE_HIP(c, zone_fill(reinterpret_cast<int64_t *>(c->at<int32_t>(c->off_bad)), 1, 0, c->stream));
-    hipLaunchKernelGGL(zone_import, dim3((unsigned)((c->p.rails + 3) / 4)), dim3(256), 0, c->stream, c->occ_user,
-                       c->at<uint16_t>(c->off_X), c->p.rails, c->p.sites, c->p.ions_per_rail, Z, pop,
-                       c->at<int32_t>(c->off_bad));
+    hipLaunchKernelGGL(zone_import, grid, dim3(256), 0, c->stream, c->occ_user, c->at<uint16_t>(c->off_X), c->p.rails,
+                       c->p.sites, c->p.ions_per_rail, Z, pop, c->at<int32_t>(c->off_bad), 0);
     ZONE_HIP(c, hipGetLastError());
     int32_t bad = 0;
     ZONE_HIP(c, hipMemcpyAsync(&bad, c->at<int32_t>(c->off_bad), sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     ZONE_HIP(c, hipStreamSynchronize(c->stream));
     if (bad) return record_error(KMC_EINVAL, "a rail of the occupancy does not hold ions_per_rail ions");
+    ZONE_HIP(c, zone_fill(pop, Z, 0, c->stream));
+    hipLaunchKernelGGL(zone_import, grid, dim3(256), 0, c->stream, c->occ_user, c->at<uint16_t>(c->off_X), c->p.rails,
+                       c->p.sites, c->p.ions_per_rail, Z, pop, c->at<int32_t>(c->off_bad), 1);
+    ZONE_HIP(c, hipGetLastError());
     return zone_refresh_table(c);
 }
 
