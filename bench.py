@@ -42,10 +42,11 @@ def parse():
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent", "wave"])
     ap.add_argument("--tile-sites", type=int, default=0)
     ap.add_argument("--workload", default="large-device",
-                    choices=["large-device", "batch", "gradient", "dense", "small-fp64", "zone"],
+                    choices=["large-device", "batch", "gradient", "dense", "dense-fixed", "small-fp64", "zone"],
                     help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
                          "gradient: forward + score replay of 512 replicas x 256 x 512; "
                          "dense: 64 replicas x 1024 x 512 with the MFMA long-range potential; "
+                         "dense-fixed: the same lattice with the potential kept hop by hop in fixed point; "
                          "small-fp64: 64 x 128 in binary64 (latency); "
                          "zone: the paper's own zone model at Table S2's largest size (128,000 rails x 200)")
     return ap.parse_args()
@@ -154,6 +155,8 @@ def main():
         return bench_small(args)
     if args.workload == "zone":
         return bench_zone(args)
+    if args.workload == "dense-fixed":
+        return bench_dense_fixed(args)
     import torch
     import paper_2511_09413_amd as kmc
     from workloads import c2_large_device
@@ -435,6 +438,63 @@ def bench_dense(args):
     out["dense_over_plain_fp32"] = value / out["plain_fp32_site_updates_per_s"]
     out["plain_fp32_launch_mode"] = plain.launch_mode
     plain.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_dense_fixed(args):
+    """The dense workload (64 replicas of 1024 x 512, unscreened 1/r over the
+    whole rail and +-4 rails, 1 V) with the potential kept hop by hop in fixed
+    point (KMC_PHI_FIXED, binary64 decisions): per half-step one decision
+    kernel (occupancy, Philox, the exact prefilter, the potential of the rare
+    survivors) and one update kernel (the half-step's hops).  Compared with the
+    same lattice in the MFMA form (KMC_BF16X2) and in the plain binary32 step
+    (window sums behind the prefilter)."""
+    import torch
+    import paper_2511_09413_amd as kmc
+    from workloads import BF16X2, FP32, PHI_FIXED, c4_dense
+    steps = args.steps if args.steps != 100_000 else 2000
+    wl = c4_dense(n_steps=steps)
+    ph = wl.physics.replace(precision=PHI_FIXED)
+    sim = kmc.Simulator(ph, wl.rails, wl.sites, device="cuda:0")
+    sim.fill_random(wl.filling)
+    sim.set_protocols(wl.protocols)
+    sim.run_steps(min(args.warmup, 50))
+    stream = torch.cuda.current_stream()
+    sec = _timed(lambda: sim.run_steps(steps), stream)
+    sim.read_current()
+    value = wl.n_sites * steps / sec
+    half = sec / steps / 2
+    # per half-step: the occupancy read once (1 B per site), one Philox block
+    # per 8 sites (40 VALU lane-operations)
+    hbm = wl.n_sites * 1.0 / half / 1e9
+    alu = OPS_PER_PHILOX_BLOCK * (wl.n_sites / 8) / half / 1e12
+    fr_h, fr_a = hbm / HBM_PEAK_GBS, alu / VALU_PEAK_TOPS
+    roof = ({"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fr_h}
+            if fr_h >= fr_a else
+            {"bound": "alu", "achieved": alu, "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": fr_a})
+    roof.update({"kernel": "phifix_decide + phifix_update (one half-step)", "traffic": None,
+                 "avg_launch_us": half * 1e6, "launches": 2 * steps, "other": {"hbm_frac": fr_h, "alu_frac": fr_a}})
+    out = {
+        "metric": "site-updates/s (dense long-range potential, fixed point)", "value": value,
+        "unit": "site-updates/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 50),
+        "ms_per_step": sec * 1e3 / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "i64 potential, f64", "data": "synthetic",
+        "config": {"workload": wl.name, "replicas": len(wl.rails), "rails": wl.rails[0], "sites": wl.sites[0],
+                   "rail_range": ph.rail_range, "kernel": "kappa/d, whole rail", "precision": "phi_fixed"},
+        "roofline": roof,
+    }
+    sim.close()
+    for name, prec in (("dense_bf16x2", BF16X2), ("plain_fp32", FP32)):
+        other = kmc.Simulator(wl.physics.replace(precision=prec), wl.rails, wl.sites, device="cuda:0")
+        other.fill_random(wl.filling)
+        other.set_protocols(wl.protocols)
+        other.run_steps(2)
+        k = 20
+        t = _timed(lambda: other.run_steps(k), stream)
+        other.read_current()
+        out[name + "_site_updates_per_s"] = wl.n_sites * k / t
+        out["fixed_over_" + name] = value / out[name + "_site_updates_per_s"]
+        other.close()
     print(json.dumps(out), flush=True)
 
 

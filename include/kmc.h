@@ -48,11 +48,19 @@ typedef enum {
 typedef enum {
     KMC_FP64 = 0,   /* binary64 energies, exponent and probabilities          */
     KMC_FP32 = 1,   /* binary32 energies/probabilities, tables from binary64  */
-    KMC_BF16X2 = 2  /* Coulomb term from the potential of every site computed
+    KMC_BF16X2 = 2, /* Coulomb term from the potential of every site computed
                        as a matrix product on the MFMA units: kernel values
                        split as BF16 hi + lo, FP32 accumulation; energies and
                        probabilities binary32 (needs the same number of sites,
                        at most 1024, on every device)                          */
+    KMC_PHI_FIXED = 3 /* Coulomb term from the potential of every site kept in
+                       fixed point (kernel values rounded once to multiples of
+                       2^-F V, F <= 52 chosen so that no sum can overflow 63
+                       bits; kmc_fixed_potential), updated by every accepted
+                       hop; dE_coul = phi(t) - K(1, 0) - phi(o) exact in those
+                       units, then energies and probabilities in binary64
+                       (per-site barriers are double; at most 2048 sites per
+                       rail)                                                   */
 } kmc_precision;
 
 /* Physical and numerical parameters (paper SI Table S1 for geometry and
@@ -227,6 +235,21 @@ kmc_status kmc_score_replay_noalloc(kmc_ctx *ctx, const int8_t *occ0_dev, int64_
  *   phi_dev: device float [total sites], occupancy layout (written).
  * KMC_EUNSUPPORTED unless the context was created with KMC_BF16X2. */
 kmc_status kmc_dense_potential(kmc_ctx *ctx, float *phi_dev);
+
+/* The potential of the current state at every site, as used by the
+ * KMC_PHI_FIXED step (the ion field of main text section 3, defined as for
+ * kmc_dense_potential), in units of 2^-frac_bits V: phi(r, s) = sum of
+ * round(K(s - j, dist) 2^frac_bits) over the ions j of the distinct rails
+ * within rail_range.  The sum is an exact integer sum, so the potential kept
+ * up to date hop by hop and the one computed from scratch are equal.
+ *   phi_dev:    device int64 [total sites], occupancy layout (written).
+ *   recompute:  0 returns the potential the step uses (kept up to date hop by
+ *               hop); 1 computes it from scratch from the current state
+ *               (the context's own copy is left as it is).
+ *   frac_bits:  host, receives F (may be NULL).
+ * Enqueued on the context's stream (no synchronisation).  KMC_EUNSUPPORTED
+ * unless the context was created with KMC_PHI_FIXED. */
+kmc_status kmc_fixed_potential(kmc_ctx *ctx, int64_t *phi_dev, int32_t recompute, int32_t *frac_bits);
 
 /* Relaxation time of a decay curve (main text section 4, relaxation decay:
  * once the bias is removed the fraction of ions in the first decile decays as

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "_build", "libkmc.so")
 
 KMC_OK, KMC_EINVAL, KMC_EUNSUPPORTED, KMC_EHIP, KMC_ESTATE, KMC_ETOOSMALL = 0, -1, -2, -3, -4, -5
 LAUNCH_MODES = {"auto": 0, "half_step": 1, "persistent": 2, "wave": 3}
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x2": 2, "phi_fixed": 3}
 LOG_DTYPE = np.dtype([("d", np.int32), ("h", np.int32), ("n", np.int64), ("r", np.int32),
                       ("s", np.int32), ("u", np.float64), ("p", np.float64)])
 
@@ -85,6 +85,7 @@ def lib():
         L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
         L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
         L.kmc_dense_potential.argtypes = [vp, vp]
+        L.kmc_fixed_potential.argtypes = [vp, vp, C.c_int32, P(C.c_int32)]
         L.kmc_autotune.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)]
         L.kmc_zone_workspace_bytes.argtypes = [P(kmc_zone_params), P(C.c_size_t)]
         L.kmc_zone_init.argtypes = [P(kmc_zone_params), vp, vp, C.c_size_t, vp, P(vp)]
@@ -104,7 +105,7 @@ def lib():
                      "kmc_set_bias_protocol", "kmc_run_steps", "kmc_read_occupancy", "kmc_read_current",
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
-                     "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential",
+                     "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential", "kmc_fixed_potential",
                      "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc", "kmc_zone_workspace_bytes",
                      "kmc_zone_init", "kmc_zone_load_occupancy", "kmc_zone_set_bias_protocol", "kmc_zone_run_steps",
                      "kmc_zone_read_positions", "kmc_zone_get_step"):
@@ -260,7 +261,7 @@ class Simulator:
             self.occ = torch.as_tensor(np.asarray(occ, dtype=np.int8).reshape(-1)).to(self.device)
         self.ea = None
         if ea is not None:
-            dt = torch.float64 if physics.precision == "fp64" else torch.float32
+            dt = torch.float64 if physics.precision in ("fp64", "phi_fixed") else torch.float32
             self.ea = torch.as_tensor(np.asarray(ea).reshape(-1)).to(self.device, dt).contiguous()
             if self.ea.numel() != self.n_sites:
                 raise ValueError("barrier field size differs from the lattice")
@@ -328,6 +329,16 @@ class Simulator:
         phi = self.torch.empty(self.n_sites, dtype=self.torch.float32, device=self.device)
         _check(lib().kmc_dense_potential(C.c_void_p(self.ctx), C.c_void_p(phi.data_ptr())))
         return phi
+
+    def fixed_potential(self, recompute: bool = False):
+        """(phi, F): the fixed-point potential of every site (int64 device
+        tensor, occupancy layout, units of 2^-F V) of a KMC_PHI_FIXED context;
+        recompute=True computes it from scratch from the current state."""
+        phi = self.torch.empty(self.n_sites, dtype=self.torch.int64, device=self.device)
+        F = C.c_int32(0)
+        _check(lib().kmc_fixed_potential(C.c_void_p(self.ctx), C.c_void_p(phi.data_ptr()), 1 if recompute else 0,
+                                         C.byref(F)))
+        return phi, int(F.value)
 
     def read_occupancy(self) -> np.ndarray:
         return read_occupancy(self.ctx, self.n_sites)

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "kmc_internal.h"
+#include "kmc_phifix.h"
 
 namespace kmc {
 hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
@@ -73,7 +74,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
-        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, total;
+        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, phifix, kfix, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
     size_t wtiles;                    // wave tiling (PTile array)
@@ -113,8 +114,12 @@ kmc_status validate(const kmc_params *p) {
     if (p->cutoff_sites < 0) return fail(KMC_EINVAL, "cutoff_sites must be >= 0");
     if (p->rail_range < 0 || p->rail_range > kMaxRailRange)
         return fail(KMC_EUNSUPPORTED, "rail_range must be in [0, 4]");
-    if (p->precision != KMC_FP64 && p->precision != KMC_FP32 && p->precision != KMC_BF16X2)
+    if (p->precision != KMC_FP64 && p->precision != KMC_FP32 && p->precision != KMC_BF16X2 &&
+        p->precision != KMC_PHI_FIXED)
         return fail(KMC_EINVAL, "unknown precision");
+    if (p->precision == KMC_PHI_FIXED)
+        for (int d = 0; d < p->n_devices; ++d)
+            if (p->sites[d] > kPhiMaxSites) return fail(KMC_EUNSUPPORTED, "KMC_PHI_FIXED supports up to 2048 sites");
     if (p->precision == KMC_BF16X2) {
         for (int d = 1; d < p->n_devices; ++d)
             if (p->sites[d] != p->sites[0])
@@ -226,7 +231,8 @@ Layout layout_for(const kmc_params *p) {
     L.score_log = take(sizeof(int64_t));
     L.hop_cap = std::min<int64_t>(std::max<int64_t>(L.total_sites / 64, 4096), (int64_t)1 << 24);
     if (p->precision != KMC_BF16X2) {
-        L.rec = take((p->precision == KMC_FP64 ? sizeof(double) : sizeof(float)) * (size_t)L.total_sites);
+        const bool f64 = p->precision == KMC_FP64 || p->precision == KMC_PHI_FIXED;
+        L.rec = take((f64 ? sizeof(double) : sizeof(float)) * (size_t)L.total_sites);
         L.hops = take(sizeof(uint4) * (size_t)L.hop_cap);
         L.hop_ctl = take(sizeof(int64_t) * 2);
     }
@@ -238,6 +244,13 @@ Layout layout_for(const kmc_params *p) {
         L.phi = take(sizeof(float) * (size_t)rails * lp);
         L.ktiles = take((size_t)16 * 256 * (m + 1) * (2 * L.dense_nb - 1));
         L.dtiles = take(sizeof(Tile) * (size_t)rails);
+        L.ctiles = take(sizeof(Tile) * (size_t)rails);
+    }
+    if (p->precision == KMC_PHI_FIXED) {
+        // the fixed-point potential of every padded site, the kernel table in
+        // fixed point and the decision tiles
+        L.phifix = take(sizeof(int64_t) * (size_t)pad);
+        L.kfix = take(sizeof(int64_t) * (m + 1) * (L.cut + 1));
         L.ctiles = take(sizeof(Tile) * (size_t)rails);
     }
     L.total = off;
@@ -291,7 +304,10 @@ struct kmc_ctx {
     int mode = 0;                      // KMC_LAUNCH_AUTO / _HALF_STEP / _PERSISTENT
     uint64_t epoch = 0;
     float k10 = 0.0f;                  // K(1, 0) rounded to binary32
-    double k01 = 0.0;                  // K(1, 0) in binary64 (score replay)
+    double k01 = 0.0;                  // K(1, 0) in binary64 (score replay, fixed-point decisions)
+    bool phifix = false;               // KMC_PHI_FIXED: Coulomb term from the fixed-point potential
+    int frac_bits = 0;                 // its units: 2^-frac_bits V
+    int64_t k10fix = 0;                // K(1, 0) in those units
 
     template <typename T>
     T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -524,7 +540,7 @@ void make_wtiles(kmc_ctx *c) {
 
 // The strategy a run uses: KMC_LAUNCH_WAVE, _PERSISTENT or _HALF_STEP.
 int launch_kind(const kmc_ctx *c) {
-    if (c->dense || c->mode == KMC_LAUNCH_HALF_STEP) return KMC_LAUNCH_HALF_STEP;
+    if (c->dense || c->phifix || c->mode == KMC_LAUNCH_HALF_STEP) return KMC_LAUNCH_HALF_STEP;
     if (c->mode == KMC_LAUNCH_WAVE) return c->w_ok ? KMC_LAUNCH_WAVE : KMC_LAUNCH_HALF_STEP;
     if (c->mode == KMC_LAUNCH_PERSISTENT) return c->p_ok ? KMC_LAUNCH_PERSISTENT : KMC_LAUNCH_HALF_STEP;
     // automatic: a persistent kernel whenever one fits co-resident
@@ -571,10 +587,33 @@ HopArgs hop_args(kmc_ctx *c) {
         a.phi = c->at<float>(c->lay.phi);
         a.phi_row = (int64_t)c->lay.dense_nb * 32;
         a.k10 = c->k10;
+    }
+    if (c->dense || c->phifix) {
         a.dtiles = c->at<Tile>(c->lay.ctiles);
         a.n_dtiles = (int32_t)c->ctiles.size();
     }
     return a;
+}
+
+// Arguments of the fixed-point potential kernels (every rail from the state
+// `occ` when full, else the hop list of parity h).
+PhiFixArgs phifix_args(kmc_ctx *c, const int8_t *occ, bool full, int h) {
+    PhiFixArgs f{};
+    f.occ = occ;
+    f.devs = c->at<DevInfo>(c->lay.devs);
+    f.rail_dev = c->at<int32_t>(c->lay.rail_dev);
+    f.rail_idx = c->at<int32_t>(c->lay.rail_idx);
+    f.rails_total = c->lay.rails_total;
+    f.kfix = c->at<int64_t>(c->lay.kfix);
+    f.cutoff = c->lay.cut;
+    f.rail_range = c->p.rail_range;
+    f.phi = c->at<int64_t>(c->lay.phifix);
+    f.out_unpadded = 0;
+    f.hops = c->at<uint4>(c->lay.hops);
+    f.hop_count = c->at<int64_t>(c->lay.hop_ctl) + h;
+    f.hop_cap = c->lay.hop_cap;
+    f.full = full ? 1 : 0;
+    return f;
 }
 
 DenseArgs dense_args(kmc_ctx *c, const int8_t *occ, float *phi, int64_t phi_row) {
@@ -651,6 +690,9 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_out, int32_t 
         pa.spin_limit = c->spin_limit;
         pa.occ_user = c->occ_user;
     }
+    // the fixed-point path's hop counts start at zero (a score replay in
+    // between leaves its own there)
+    if (c->phifix) KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.hop_ctl), 2, c->stream));
     int64_t done = 0;
     while (done < n_steps) {
         const int chunk = (int)std::min<int64_t>(kTallySteps, n_steps - done);
@@ -701,6 +743,15 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_out, int32_t 
                 a.occ_out = c->nxt;
                 a.step_in_chunk = k;
                 a.h = h;
+                if (c->phifix) {
+                    // decisions update the state in place; then the potential
+                    // follows the half-step's hops
+                    a.occ_in = a.occ_out = c->cur;
+                    PhiFixDecide x{c->at<int64_t>(c->lay.phifix), c->frac_bits, c->k10fix};
+                    KMC_HIP(c, launch_phifix_decide(a, x, c->stream));
+                    KMC_HIP(c, launch_phifix_update(phifix_args(c, c->cur, false, h), c->stream));
+                    continue;
+                }
                 if (c->dense) {
                     KMC_HIP(c, launch_dense_phi(dense_args(c, c->cur, c->at<float>(c->lay.phi), a.phi_row),
                                                 c->stream));
@@ -731,6 +782,7 @@ kmc_status check_status(kmc_ctx *c) {
 }
 
 kmc_status after_state_change(kmc_ctx *c) {
+    if (c->phifix) KMC_HIP(c, launch_phifix_update(phifix_args(c, c->cur, true, 0), c->stream));
     KMC_HIP(c, launch_count_deciles(c->cur, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
                                     c->at<int64_t>(c->lay.dec_run), c->stream));
     KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
@@ -774,7 +826,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     c->occ_user = occ_dev;
     c->ea = ea_dev;
     c->stream = static_cast<hipStream_t>(stream);
-    c->fp64 = params->precision == KMC_FP64;
+    c->fp64 = params->precision == KMC_FP64 || params->precision == KMC_PHI_FIXED;
     c->cur = c->at<int8_t>(lay.occ_a);
     c->nxt = c->at<int8_t>(lay.occ_b);
 
@@ -827,6 +879,38 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     make_wtiles(c);
     c->k10 = cut >= 1 ? k32[1] : 0.0f;
     c->k01 = cut >= 1 ? k64[1] : 0.0;
+    // Fixed-point potential (KMC_PHI_FIXED): F fractional bits such that the
+    // largest |phi| any state allows (every site of every window occupied)
+    // stays below 2^61, each kernel value rounded once to a multiple of 2^-F.
+    c->phifix = params->precision == KMC_PHI_FIXED;
+    std::vector<int64_t> kfix_host;
+    if (c->phifix) {
+        double peak = 0.0;
+        for (int d = 0; d < D; ++d) {
+            double sum = 0.0;
+            const int reach = std::min(cut, c->sites[d] - 1);
+            for (int k = 0; k < c->devs[d].n_nbr; ++k)
+                for (int ds = -reach; ds <= reach; ++ds) sum += std::fabs(k64[(size_t)c->devs[d].nbr_dist[k] * (cut + 1) + std::abs(ds)]);
+            peak = std::max(peak, sum);
+        }
+        int F = 52;
+        if (peak > 0.0) F = std::min(52, 61 - (int)std::ceil(std::log2(peak)));
+        if (F < 16) {
+            delete c;
+            return fail(KMC_EUNSUPPORTED, "KMC_PHI_FIXED: the Coulomb kernel sums too large for a 63-bit potential");
+        }
+        c->frac_bits = F;
+        c->k10fix = cut >= 1 ? (int64_t)std::llrint(std::ldexp(k64[1], F)) : 0;
+        kfix_host.resize(k64.size());
+        for (size_t i = 0; i < k64.size(); ++i) kfix_host[i] = (int64_t)std::llrint(std::ldexp(k64[i], F));
+        // decision runs: consecutive rails of one device, eight passes of a
+        // 256-thread workgroup (pitch / 8 threads per rail)
+        for (int d = 0; d < D; ++d) {
+            const int run = 8 * (256 / (c->devs[d].pitch / 8));
+            for (int r0 = 0; r0 < c->rails[d]; r0 += run)
+                c->ctiles.push_back(Tile{d, r0, std::min(run, c->rails[d] - r0), 0});
+        }
+    }
     std::vector<uint16_t> kt_host;
     if (c->dense) {
         auto bf16_rne = [](float f) {
@@ -894,6 +978,10 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
         chk(h2d(lay.dtiles, c->dtiles.data(), sizeof(Tile) * c->dtiles.size()), "copy dense tiles");
         chk(h2d(lay.ctiles, c->ctiles.data(), sizeof(Tile) * c->ctiles.size()), "copy decision tiles");
         chk(set_dense_lds_limit((size_t)(kDenseRails + 2 * m) * (lay.dense_nb * 32 + 8)), "LDS limit of the dense kernel");
+    }
+    if (c->phifix) {
+        chk(h2d(lay.kfix, kfix_host.data(), sizeof(int64_t) * kfix_host.size()), "copy fixed-point kernel table");
+        chk(h2d(lay.ctiles, c->ctiles.data(), sizeof(Tile) * c->ctiles.size()), "copy decision tiles");
     }
     chk(h2d(lay.rail_dev, rail_dev.data(), sizeof(int32_t) * rail_dev.size()), "copy rail table");
     chk(h2d(lay.rail_idx, rail_idx.data(), sizeof(int32_t) * rail_idx.size()), "copy rail table");
@@ -1152,6 +1240,7 @@ kmc_status restore_state(kmc_ctx *c, const Saved &sv) {
     KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.log_count, &sv.log_count, sizeof(int64_t), hipMemcpyHostToDevice,
                               c->stream));
     KMC_HIP(c, launch_zero_i32(c->at<int32_t>(c->lay.status), 4, c->stream));
+    if (c->phifix) KMC_HIP(c, launch_phifix_update(phifix_args(c, c->cur, true, 0), c->stream));
     // a trial in the wave strategy also wrote the caller's occupancy
     KMC_HIP(c, launch_export(c->cur, c->occ_user, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
                              c->lay.total_sites, c->stream));
@@ -1174,7 +1263,7 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
     const int old_tile = c->tile_sites, old_mode = c->mode;
     struct Cand { int mode, tile; };
     std::vector<Cand> cands;
-    if (!c->dense) {
+    if (!c->dense && !c->phifix) {
         for (int t : {1024, 2048}) cands.push_back({KMC_LAUNCH_WAVE, t});
         for (int t : {0, 4096, 8192, 12288, 16384}) cands.push_back({KMC_LAUNCH_PERSISTENT, t});
     }
@@ -1386,6 +1475,26 @@ kmc_status kmc_dense_potential(kmc_ctx *c, float *phi_dev) {
     if (!phi_dev) return fail(KMC_EINVAL, "phi_dev is NULL");
     if (!c->dense) return fail(KMC_EUNSUPPORTED, "the dense potential needs a KMC_BF16X2 context");
     KMC_HIP(c, launch_dense_phi(dense_args(c, c->cur, phi_dev, c->sites[0]), c->stream));
+    return KMC_OK;
+}
+
+kmc_status kmc_fixed_potential(kmc_ctx *c, int64_t *phi_dev, int32_t recompute, int32_t *frac_bits) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (!c->phifix) return fail(KMC_EUNSUPPORTED, "the fixed-point potential needs a KMC_PHI_FIXED context");
+    if (!phi_dev) return fail(KMC_EINVAL, "phi_dev is NULL");
+    if (recompute != 0 && recompute != 1) return fail(KMC_EINVAL, "recompute must be 0 or 1");
+    if (recompute) {
+        PhiFixArgs f = phifix_args(c, c->cur, true, 0);
+        f.phi = phi_dev;
+        f.out_unpadded = 1;
+        KMC_HIP(c, launch_phifix_update(f, c->stream));
+    } else {
+        KMC_HIP(c, launch_phifix_export(c->at<int64_t>(c->lay.phifix), phi_dev, c->at<DevInfo>(c->lay.devs),
+                                        c->at<int32_t>(c->lay.rail_dev), c->at<int32_t>(c->lay.rail_idx),
+                                        c->lay.rails_total, c->stream));
+    }
+    if (frac_bits) *frac_bits = c->frac_bits;
     return KMC_OK;
 }
 

@@ -23,6 +23,7 @@ import numpy as np
 FP64 = "fp64"
 FP32 = "fp32"
 BF16X2 = "bf16x2"
+PHI_FIXED = "phi_fixed"
 
 NS = 1e-9
 
