@@ -236,6 +236,30 @@ kmc_status kmc_score_replay_noalloc(kmc_ctx *ctx, const int8_t *occ0_dev, int64_
  * KMC_EUNSUPPORTED unless the context was created with KMC_BF16X2. */
 kmc_status kmc_dense_potential(kmc_ctx *ctx, float *phi_dev);
 
+/* Open electrodes of one device (device >= 0) or of all devices (-1); an
+ * extension of the paper's model, whose electrodes block ions (SI S1.3) and
+ * whose rails keep their ion count (SI S2.1), in the direction its
+ * conclusion invites (new mechanisms by altering the probabilities at a few
+ * positions).  With open = 1 each rail end is one more bond of the
+ * checkerboard, to a reservoir of ions: the grounded reservoir behind site 0
+ * (bond (-1, 0), half-step 1) and the biased one behind site L-1 (bond
+ * (L-1, L), half-step (L-1) mod 2).  A reservoir ion has the energy mu plus
+ * its bias energy at the virtual site (-1 or L) and no Coulomb interaction.
+ * A transfer between the boundary site x and its reservoir has
+ *     dE = (alpha V (t - o)/L + s phi(x)) - s mu,  s = +1 injection, -1 extraction,
+ * with o, t the origin and target (virtual site included) and phi(x) the
+ * Coulomb potential of the other ions at x (the hop's kernel and window), and
+ * the rate law of a hop with the electrode's barrier ea in place of Ea(o).
+ * Transfers count in the net tallies and the current like hops (toward site
+ * 0's side positive), and in the deciles; the ion count is then free.  Draws:
+ * Philox4x32-10 at counter (0, r, n, 16 d + 6 + h), word 0 (grounded side) or
+ * 1 (biased side).  While any device has open electrodes every run uses the
+ * half-step strategy, and kmc_score_replay returns KMC_EUNSUPPORTED.
+ *   ea_*, mu_*: eV, finite.  open: 0 (blocking, the default) or 1.
+ * KMC_EUNSUPPORTED for KMC_BF16X2 and KMC_PHI_FIXED contexts.  Synchronises. */
+kmc_status kmc_set_electrodes(kmc_ctx *ctx, int32_t device, int32_t open, double ea_ground, double mu_ground,
+                              double ea_bias, double mu_bias);
+
 /* The potential of the current state at every site, as used by the
  * KMC_PHI_FIXED step (the ion field of main text section 3, defined as for
  * kmc_dense_potential), in units of 2^-frac_bits V: phi(r, s) = sum of

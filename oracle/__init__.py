@@ -32,12 +32,18 @@ class _Protocol(C.Structure):
                 ("n_knots", C.c_int), ("n_set", C.c_int64)]
 
 
+class _Electrodes(C.Structure):
+    _fields_ = [("open", C.c_int), ("ea_ground", C.c_double), ("mu_ground", C.c_double),
+                ("ea_bias", C.c_double), ("mu_bias", C.c_double)]
+
+
 class _Opts(C.Structure):
     _fields_ = [("shuffle_seed", C.c_uint64), ("rail_lo", C.c_int), ("rail_hi", C.c_int),
                 ("score_w", C.POINTER(C.c_double)), ("score_grad", C.POINTER(C.c_double)),
                 ("score_mag", C.POINTER(C.c_double)), ("score_sens", C.POINTER(C.c_double)),
                 ("score_sens_arg", C.POINTER(C.c_double)), ("score_sens_b", C.POINTER(C.c_double)),
-                ("score_hops", C.POINTER(C.c_int64)), ("score_coul64", C.c_int)]
+                ("score_hops", C.POINTER(C.c_int64)), ("score_coul64", C.c_int),
+                ("electrodes", C.POINTER(_Electrodes))]
 
 
 class _ZoneParams(C.Structure):
@@ -62,6 +68,11 @@ def lib():
         L.orc_hop_word.restype = C.c_uint32
         L.orc_place_word.argtypes = [C.c_uint64, C.c_int, C.c_int, C.c_int]
         L.orc_place_word.restype = C.c_uint32
+        L.orc_electrode_word.argtypes = [C.c_uint64, C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int]
+        L.orc_electrode_word.restype = C.c_uint32
+        L.orc_electrode_delta_energy.argtypes = [P(_Params), C.c_int, C.c_int, P(C.c_int8), C.c_int, C.c_int,
+                                                 C.c_int, C.c_double, C.c_double]
+        L.orc_electrode_delta_energy.restype = C.c_double
         L.orc_kernel.argtypes = [P(_Params), C.c_int, C.c_int]
         L.orc_kernel.restype = C.c_double
         L.orc_protocol_voltage.argtypes = [P(C.c_double), P(C.c_double), C.c_int, C.c_double]
@@ -152,6 +163,35 @@ def place_word(seed: int, d: int, r: int, s: int) -> int:
     return int(lib().orc_place_word(seed, d, r, s))
 
 
+def electrode_word(seed: int, d: int, n: int, r: int, h: int, side: int) -> int:
+    return int(lib().orc_electrode_word(seed, d, n, r, h, side))
+
+
+def electrode_delta_energy(p: OracleParams, R: int, L: int, S: np.ndarray, r: int, side: int, inject: bool,
+                           V: float, mu: float) -> float:
+    """Energy change of a transfer across the boundary bond of rail r (side 0:
+    grounded, 1: biased) from snapshot S of one device, in p's precision."""
+    S = np.ascontiguousarray(S, dtype=np.int8).reshape(-1)
+    return float(lib().orc_electrode_delta_energy(C.byref(p.s), R, L, _ptr(S, C.c_int8), r, side,
+                                                  1 if inject else 0, V, mu))
+
+
+def _electrodes(electrodes, D):
+    """[D] orc_electrodes from None or a per-device list of None (blocking) or
+    (ea_ground, mu_ground, ea_bias, mu_bias)."""
+    if electrodes is None:
+        return None
+    if len(electrodes) != D:
+        raise ValueError("one electrode entry per device")
+    arr = (_Electrodes * D)()
+    for d, e in enumerate(electrodes):
+        if e is None:
+            arr[d] = _Electrodes(0, 0.0, 0.0, 0.0, 0.0)
+        else:
+            arr[d] = _Electrodes(1, *[float(x) for x in e])
+    return arr
+
+
 def kernel(p: OracleParams, ds: int, dr: int) -> float:
     return float(lib().orc_kernel(C.byref(p.s), ds, dr))
 
@@ -217,7 +257,7 @@ class Protocols:
 def run(p: OracleParams, protocols, occ: np.ndarray, n0: int, n_steps: int,
         n_set: Optional[Sequence[int]] = None, want_dec: bool = True, log_cap: int = 4096,
         shuffle_seed: int = 0, rail_lo: int = 0, rail_hi: int = 0,
-        net_total: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+        net_total: Optional[np.ndarray] = None, electrodes=None) -> Dict[str, np.ndarray]:
     """Advance `occ` (modified in place) by n_steps steps starting at step n0."""
     D = len(p.rails)
     if len(protocols) != D:
@@ -231,7 +271,10 @@ def run(p: OracleParams, protocols, occ: np.ndarray, n0: int, n_steps: int,
     tot = net_total if net_total is not None else np.zeros(D, dtype=np.int64)
     log = np.zeros(max(log_cap, 1), dtype=LOG_DTYPE)
     n_log = C.c_int64(0)
+    el = _electrodes(electrodes, D)
     opts = _Opts(shuffle_seed, rail_lo, rail_hi, None, None, None, None)
+    if el is not None:
+        opts.electrodes = C.cast(el, C.POINTER(_Electrodes))
     rc = lib().orc_run(C.byref(p.s), prot.arr, _ptr(occ_c, C.c_int8), n0, n_steps,
                        _ptr(net, C.c_int32), _ptr(dec, C.c_int32), _ptr(tot, C.c_int64),
                        log.ctypes.data_as(C.c_void_p), log_cap, C.byref(n_log), C.byref(opts))

@@ -33,7 +33,15 @@
  *   hop draw of bond (s, s+1) of rail r, device d, step n, half-step h = s&1:
  *     counter = (s>>3, r, n, d<<4 | 0<<1 | h), key = (seed lo, seed hi),
  *     word (s>>1)&3 of the output block;
- *   placement draw of site s: counter = (s>>2, r, 0, d<<4 | 1<<1), word s&3.
+ *   placement draw of site s: counter = (s>>2, r, 0, d<<4 | 1<<1), word s&3;
+ *   transfer draw of a boundary bond (open electrodes): counter =
+ *     (0, r, n, d<<4 | 3<<1 | h), word 0 (grounded side) or 1 (biased side).
+ *
+ * Open electrodes (optional, orc_electrodes): an extension in the direction
+ * the paper's conclusion invites (new mechanisms by altering probabilities),
+ * not the paper's model, whose electrodes block and whose rails keep their
+ * ion count.  Each rail end is one more bond to a reservoir whose ion has a
+ * set energy and no Coulomb interaction; see orc_electrode_delta_energy.
  *
  * Two precision paths: binary64 everywhere, or binary32 for the energy, the
  * exponent and the probability (tables rounded once from binary64).  Build
@@ -94,6 +102,15 @@ uint32_t orc_place_word(uint64_t seed, int d, int r, int s)
 {
     return philox_word(seed, (uint32_t)(s >> 2), (uint32_t)r, 0u,
                        ((uint32_t)d << 4) | (1u << 1), s & 3);
+}
+
+/* The word of a boundary (electrode) bond: stream 3, the block at counter
+ * (0, r, n, 16 d + 2*3 + h), word 0 for the grounded side, 1 for the biased
+ * side (h is the half-step the bond belongs to). */
+uint32_t orc_electrode_word(uint64_t seed, int d, int64_t n, int r, int h, int side)
+{
+    return philox_word(seed, 0u, (uint32_t)r, (uint32_t)n, ((uint32_t)d << 4) | (3u << 1) | (uint32_t)h,
+                       side);
 }
 
 /* ------------------------------------------------------------------ */
@@ -229,6 +246,75 @@ static void delta_energy_parts_f32(const orc_params *P, int R, int L, const int8
     *e_app_out = e_app;
     *e_coul_out = e_coul;
     if (a_abs_out) *a_abs_out = a_abs;
+}
+
+/* Coulomb potential at site x of rail r from the other ions of the snapshot
+ * (window terms in the same order as the hop's sum), binary64 or, with f32,
+ * summed in binary32 from once-rounded kernel values. */
+static double site_potential_f64(const orc_params *P, int R, int L, const int8_t *S, int r, int x)
+{
+    int rails[64], dists[64];
+    int nr = neighbour_rails(P, R, r, rails, dists);
+    int lo = x - P->cutoff, hi = x + P->cutoff;
+    if (lo < 0) lo = 0;
+    if (hi > L - 1) hi = L - 1;
+    double phi = 0.0;
+    for (int i = 0; i < nr; ++i) {
+        const int8_t *row = S + (int64_t)rails[i] * L;
+        for (int j = lo; j <= hi; ++j) {
+            if (rails[i] == r && j == x) continue;
+            if (row[j]) phi += orc_kernel(P, x - j, dists[i]);
+        }
+    }
+    return phi;
+}
+
+static float site_potential_f32(const orc_params *P, int R, int L, const int8_t *S, int r, int x)
+{
+    int rails[64], dists[64];
+    int nr = neighbour_rails(P, R, r, rails, dists);
+    int lo = x - P->cutoff, hi = x + P->cutoff;
+    if (lo < 0) lo = 0;
+    if (hi > L - 1) hi = L - 1;
+    float phi = 0.0f;
+    for (int i = 0; i < nr; ++i) {
+        const int8_t *row = S + (int64_t)rails[i] * L;
+        for (int j = lo; j <= hi; ++j) {
+            if (rails[i] == r && j == x) continue;
+            if (row[j]) phi += (float)orc_kernel(P, x - j, dists[i]);
+        }
+    }
+    return phi;
+}
+
+/* Energy change of a transfer across the boundary bond of rail r, side 0
+ * (grounded: reservoir at virtual site -1, lattice site 0) or side 1
+ * (biased: lattice site L-1, reservoir at virtual site L).  inject = 1: an
+ * ion leaves the reservoir for the empty boundary site; 0: the ion on the
+ * boundary site leaves for the reservoir.  With o, t the origin and target
+ * (virtual sites included) the bias part is alpha V (t - o) / L, as for any
+ * hop; the Coulomb part is +phi(x) on injection and -phi(x) on extraction
+ * (reservoir ions do not interact); the reservoir's own energy mu leaves on
+ * injection (-mu) and arrives on extraction (+mu):
+ *     dE = (e_app + sgn phi(x)) - sgn mu,   sgn = +1 injection, -1 extraction,
+ * in the path precision (binary32: e_app, phi and mu rounded as the hop's). */
+double orc_electrode_delta_energy(const orc_params *P, int R, int L, const int8_t *S, int r, int side,
+                                  int inject, double V, double mu)
+{
+    int x = side == 0 ? 0 : L - 1;
+    int res = side == 0 ? -1 : L;
+    int o = inject ? res : x, t = inject ? x : res;
+    if (P->fp32) {
+        float a = (float)P->alpha, v = (float)V;
+        float e_app = ((a * v) * (float)(t - o)) / (float)L;
+        float phi = site_potential_f32(P, R, L, S, r, x);
+        float sgn = inject ? 1.0f : -1.0f;
+        return (double)((e_app + sgn * phi) - sgn * (float)mu);
+    }
+    double e_app = ((P->alpha * V) * (double)(t - o)) / (double)L;
+    double phi = site_potential_f64(P, R, L, S, r, x);
+    double sgn = inject ? 1.0 : -1.0;
+    return (e_app + sgn * phi) - sgn * mu;
 }
 
 double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,
@@ -475,6 +561,59 @@ static int visit_bond(const orc_params *P, int d, int R, int L, int64_t off, con
     return t < o ? 1 : 2;
 }
 
+/* The boundary bond of side `side` of rail r in half-step h, when the
+ * device's electrodes are open: a transfer with the rate law of any hop
+ * (barrier ea of that electrode), accepted when u < p; logged like a hop
+ * (bond index -1 for the grounded side, L-1 for the biased side).  Returns 1
+ * for a transfer toward site 0's side (extraction at the grounded electrode,
+ * injection at the biased one), 2 for the opposite direction, 0 for none. */
+static int visit_electrode(const orc_params *P, const orc_electrodes *el, int d, int R, int L, const int8_t *Sd,
+                           int8_t *Od, int h, int64_t n, double V, int r, int side, orc_log_entry *log,
+                           int64_t log_cap, int64_t *n_log, int threaded)
+{
+    int x = side == 0 ? 0 : L - 1;
+    int inject = Sd[(int64_t)r * L + x] == 0;
+    double mu = side == 0 ? el->mu_ground : el->mu_bias;
+    double ea = side == 0 ? el->ea_ground : el->ea_bias;
+    double dE = orc_electrode_delta_energy(P, R, L, Sd, r, side, inject, V, mu);
+    uint32_t w = orc_electrode_word(P->seed, d, n, r, h, side);
+    int accept, near;
+    double u_log, p_log;
+    if (P->fp32) {
+        float p = orc_hop_prob_f32(P, ea, (float)dE);
+        float u = ldexpf((float)w, -32);
+        accept = u < p;
+        near = fabsf(u - p) < 1e-6f;
+        u_log = u; p_log = p;
+    } else {
+        double p = orc_hop_prob_f64(P, ea, dE);
+        double u = ldexp((double)w, -32);
+        accept = u < p;
+        near = fabs(u - p) < 1e-6;
+        u_log = u; p_log = p;
+    }
+    if (near) {
+        int sb = side == 0 ? -1 : L - 1;
+        if (threaded) {
+#pragma omp critical(orc_log)
+            log_event(log, log_cap, n_log, d, h, n, r, sb, u_log, p_log);
+        } else {
+            log_event(log, log_cap, n_log, d, h, n, r, sb, u_log, p_log);
+        }
+    }
+    if (!accept) return 0;
+    Od[(int64_t)r * L + x] = inject ? 1 : 0;
+    /* toward site 0's side: extraction at the grounded end, injection at the biased end */
+    return (side == 0) != inject ? 1 : 2;
+}
+
+/* Whether the boundary bond of `side` belongs to half-step h: bond s = -1
+ * (grounded) is odd, bond s = L - 1 (biased) has the parity of L - 1. */
+static int electrode_in_half_step(int side, int L, int h)
+{
+    return side == 0 ? h == 1 : ((L - 1) & 1) == h;
+}
+
 int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
             int64_t n0, int64_t n_steps, int32_t *net_out, int32_t *dec_out,
             int64_t *net_total, orc_log_entry *log, int64_t log_cap, int64_t *n_log,
@@ -483,6 +622,7 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
     int D = P->n_devices;
     if (n0 < 0 || n0 + n_steps > (int64_t)0xffffffffLL) return -1;
     if (opts && opts->score_grad && (P->kappa == 0.0 || !(P->nu0 > 0.0))) return -2;
+    if (opts && opts->score_grad && opts->electrodes) return -3;
     int64_t total = dev_offset(P, D);
     int8_t *S = (int8_t *)malloc((size_t)total);
     int64_t dummy_log = 0;
@@ -513,16 +653,26 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                 }
                 int n_bonds = (L - 1 - h + 1) / 2; /* s = h, h+2, ..., <= L-2 */
                 if (n_bonds < 0) n_bonds = 0;
+                const orc_electrodes *el =
+                    (opts && opts->electrodes && opts->electrodes[d].open) ? &opts->electrodes[d] : NULL;
                 if (threaded) {
                     int32_t down = 0, up = 0;
 #pragma omp parallel for num_threads(orc_threads) schedule(static) reduction(+ : down, up)
-                    for (int r = r_lo; r < r_hi; ++r)
+                    for (int r = r_lo; r < r_hi; ++r) {
                         for (int b = 0; b < n_bonds; ++b) {
                             int dir = visit_bond(P, d, R, L, off, Sd, Od, h, n, k, V[d], r, h + 2 * b, log,
                                                  log_cap, n_log, opts, 1);
                             down += dir == 1;
                             up += dir == 2;
                         }
+                        for (int side = 0; el && side < 2; ++side) {
+                            if (!electrode_in_half_step(side, L, h)) continue;
+                            int dir = visit_electrode(P, el, d, R, L, Sd, Od, h, n, V[d], r, side, log, log_cap,
+                                                      n_log, 1);
+                            down += dir == 1;
+                            up += dir == 2;
+                        }
+                    }
                     n_down[d] += down;
                     n_up[d] += up;
                     continue;
@@ -543,6 +693,14 @@ int orc_run(const orc_params *P, const orc_protocol *protocols, int8_t *occ,
                     else if (dir == 2) ++n_up[d];
                 }
                 free(perm);
+                for (int r = r_lo; el && r < r_hi; ++r)
+                    for (int side = 0; side < 2; ++side) {
+                        if (!electrode_in_half_step(side, L, h)) continue;
+                        int dir = visit_electrode(P, el, d, R, L, Sd, Od, h, n, V[d], r, side, log, log_cap,
+                                                  n_log, 0);
+                        if (dir == 1) ++n_down[d];
+                        else if (dir == 2) ++n_up[d];
+                    }
             }
         }
         for (int d = 0; d < D; ++d) {

@@ -38,6 +38,19 @@ typedef struct {
     double u, p;
 } orc_log_entry;
 
+/* Open electrodes of one device (NULL electrodes or open == 0: the paper's
+ * blocking electrodes, a fixed ion count per rail).  Each end of a rail is
+ * coupled to a reservoir of ions: the grounded one behind site 0 (a virtual
+ * site -1) and the biased one behind site L-1 (a virtual site L).  An ion
+ * in a reservoir has the energy mu (plus its bias energy at the virtual
+ * site) and no Coulomb interaction; a transfer across the boundary bond
+ * crosses the barrier ea of that electrode. */
+typedef struct {
+    int open;
+    double ea_ground, mu_ground;   /* eV, the grounded electrode (site 0 side) */
+    double ea_bias, mu_bias;       /* eV, the biased electrode (site L-1 side) */
+} orc_electrodes;
+
 typedef struct {
     uint64_t shuffle_seed; /* nonzero: visit bonds in a random order */
     int rail_lo, rail_hi;  /* rail_hi > rail_lo: update only these rails */
@@ -66,11 +79,17 @@ typedef struct {
      * summed in binary64 and rounded once to binary32 (the decisions still
      * use the binary32 sum) */
     int score_coul64;
+    /* NULL, or [n_devices] electrodes (see orc_electrodes); not with the
+     * score accumulation */
+    const orc_electrodes *electrodes;
 } orc_run_opts;
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 uint32_t orc_hop_word(uint64_t seed, int d, int64_t n, int r, int s);
 uint32_t orc_place_word(uint64_t seed, int d, int r, int s);
+uint32_t orc_electrode_word(uint64_t seed, int d, int64_t n, int r, int h, int side);
+double orc_electrode_delta_energy(const orc_params *P, int R, int L, const int8_t *S, int r, int side,
+                                  int inject, double V, double mu);
 double orc_kernel(const orc_params *P, int ds, int dr);
 double orc_protocol_voltage(const double *t_k, const double *v_k, int n_knots, double t_rel);
 double orc_delta_energy_f64(const orc_params *P, int R, int L, const int8_t *S,

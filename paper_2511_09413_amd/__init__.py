@@ -86,6 +86,8 @@ def lib():
         L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
         L.kmc_dense_potential.argtypes = [vp, vp]
         L.kmc_fixed_potential.argtypes = [vp, vp, C.c_int32, P(C.c_int32)]
+        L.kmc_set_electrodes.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                         C.c_double]
         L.kmc_autotune.argtypes = [vp, C.c_int32, P(C.c_int32), P(C.c_int32), P(C.c_double)]
         L.kmc_zone_workspace_bytes.argtypes = [P(kmc_zone_params), P(C.c_size_t)]
         L.kmc_zone_init.argtypes = [P(kmc_zone_params), vp, vp, C.c_size_t, vp, P(vp)]
@@ -106,6 +108,7 @@ def lib():
                      "kmc_read_threshold_log", "kmc_get_step", "kmc_set_launch_mode", "kmc_get_launch_mode",
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
                      "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential", "kmc_fixed_potential",
+                     "kmc_set_electrodes",
                      "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc", "kmc_zone_workspace_bytes",
                      "kmc_zone_init", "kmc_zone_load_occupancy", "kmc_zone_set_bias_protocol", "kmc_zone_run_steps",
                      "kmc_zone_read_positions", "kmc_zone_get_step"):
@@ -329,6 +332,13 @@ class Simulator:
         phi = self.torch.empty(self.n_sites, dtype=self.torch.float32, device=self.device)
         _check(lib().kmc_dense_potential(C.c_void_p(self.ctx), C.c_void_p(phi.data_ptr())))
         return phi
+
+    def set_electrodes(self, ea_ground: float, mu_ground: float, ea_bias: float, mu_bias: float,
+                       device: int = -1, open: bool = True) -> None:
+        """Open (or close again) the electrodes of one device or of all
+        (kmc_set_electrodes): transfer barriers and reservoir energies in eV."""
+        _check(lib().kmc_set_electrodes(C.c_void_p(self.ctx), device, 1 if open else 0, ea_ground, mu_ground,
+                                        ea_bias, mu_bias))
 
     def fixed_potential(self, recompute: bool = False):
         """(phi, F): the fixed-point potential of every site (int64 device

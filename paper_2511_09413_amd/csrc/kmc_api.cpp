@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "kmc_internal.h"
+#include "kmc_electrode.h"
 #include "kmc_phifix.h"
 
 namespace kmc {
@@ -74,7 +75,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
-        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, phifix, kfix, total;
+        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, phifix, kfix, electrodes, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
     size_t wtiles;                    // wave tiling (PTile array)
@@ -222,6 +223,7 @@ Layout layout_for(const kmc_params *p) {
     L.wtiles = take(sizeof(PTile) * (size_t)rails);  // every wave tile is at least one rail
     L.status = take(sizeof(int32_t) * 4);
     L.ticket = take(sizeof(uint32_t) * kTicketWords);  // wave kernel: tiles that ended the launch
+    L.electrodes = take(sizeof(Electrode) * D);       // open-electrode reservoirs per device
     // score replay: its own pair of state planes, a discarded event count, the
     // Coulomb part of every bond's energy change (path precision) and the list
     // of a half-step's accepted hops (a longer list falls back to recomputing
@@ -308,6 +310,8 @@ struct kmc_ctx {
     bool phifix = false;               // KMC_PHI_FIXED: Coulomb term from the fixed-point potential
     int frac_bits = 0;                 // its units: 2^-frac_bits V
     int64_t k10fix = 0;                // K(1, 0) in those units
+    std::vector<Electrode> el;         // reservoirs per device (host copy of the workspace's)
+    bool any_open = false;             // some device has open electrodes: half-step launches only
 
     template <typename T>
     T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -540,7 +544,7 @@ void make_wtiles(kmc_ctx *c) {
 
 // The strategy a run uses: KMC_LAUNCH_WAVE, _PERSISTENT or _HALF_STEP.
 int launch_kind(const kmc_ctx *c) {
-    if (c->dense || c->phifix || c->mode == KMC_LAUNCH_HALF_STEP) return KMC_LAUNCH_HALF_STEP;
+    if (c->dense || c->phifix || c->any_open || c->mode == KMC_LAUNCH_HALF_STEP) return KMC_LAUNCH_HALF_STEP;
     if (c->mode == KMC_LAUNCH_WAVE) return c->w_ok ? KMC_LAUNCH_WAVE : KMC_LAUNCH_HALF_STEP;
     if (c->mode == KMC_LAUNCH_PERSISTENT) return c->p_ok ? KMC_LAUNCH_PERSISTENT : KMC_LAUNCH_HALF_STEP;
     // automatic: a persistent kernel whenever one fits co-resident
@@ -593,6 +597,37 @@ HopArgs hop_args(kmc_ctx *c) {
         a.n_dtiles = (int32_t)c->ctiles.size();
     }
     return a;
+}
+
+// Arguments of the boundary-bond kernel for the half-step described by a.
+ElectrodeArgs electrode_args(kmc_ctx *c, const HopArgs &a) {
+    ElectrodeArgs e{};
+    e.occ_in = a.occ_in;
+    e.occ_out = a.occ_out;
+    e.devs = a.devs;
+    e.rail_dev = c->at<int32_t>(c->lay.rail_dev);
+    e.rail_idx = c->at<int32_t>(c->lay.rail_idx);
+    e.rails_total = c->lay.rails_total;
+    e.el = c->at<Electrode>(c->lay.electrodes);
+    e.knot_t = a.knot_t;
+    e.knot_v = a.knot_v;
+    e.ktab64 = a.ktab64;
+    e.ktab32 = a.ktab32;
+    e.cutoff = a.cutoff;
+    e.beta = a.beta;
+    e.c0 = a.c0;
+    e.alpha = a.alpha;
+    e.dt = a.dt;
+    e.key0 = a.key0;
+    e.key1 = a.key1;
+    e.n = a.ctl.n_base + a.step_in_chunk;
+    e.h = a.h;
+    e.tally_row = e.n - a.ctl.tally_base;
+    e.tally_net = a.tally_net;
+    e.tally_dec = a.tally_dec;
+    e.n_devices = a.n_devices;
+    e.log = a.log;
+    return e;
 }
 
 // Arguments of the fixed-point potential kernels (every rail from the state
@@ -758,6 +793,11 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_out, int32_t 
                     KMC_HIP(c, launch_dense_decide(a, c->devs[0].pitch, c->stream));
                 } else {
                     KMC_HIP(c, launch_hop(a, c->hop_lds, c->fp64, c->stream));
+                    if (c->any_open) {
+                        // boundary bonds of the same half-step, after the interior ones
+                        ElectrodeArgs e = electrode_args(c, a);
+                        KMC_HIP(c, launch_electrodes(e, c->fp64, c->stream));
+                    }
                 }
                 std::swap(c->cur, c->nxt);
             }
@@ -994,6 +1034,9 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
     chk(launch_zero_i64(c->at<int64_t>(lay.pub), pub_words(lay), st), "zero publication ring");
     chk(launch_zero_i32(c->at<int32_t>(lay.status), 4, st), "zero status");
     chk(launch_zero_i32(c->at<int32_t>(lay.ticket), kTicketWords, st), "zero ticket");
+    c->el.assign(D, Electrode{});
+    chk(hipMemcpyAsync(c->ws + lay.electrodes, c->el.data(), sizeof(Electrode) * D, hipMemcpyHostToDevice, st),
+        "closed electrodes");
     chk(set_hop_lds_limit(c->hop_lds, c->score_lds), "LDS limit of the hop kernel");
     {
         const double zero_t = 0.0, zero_v = 0.0;
@@ -1362,6 +1405,7 @@ kmc_status check_replay_args(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, 
         return fail(KMC_EINVAL, "score replay needs coulomb_kappa_v != 0 (the kappa score is dE_coul/kappa)");
     if (!(c->p.nu0_hz > 0.0)) return fail(KMC_EINVAL, "score replay needs nu0_hz > 0");
     if (c->dense) return fail(KMC_EUNSUPPORTED, "score replay runs the binary64/binary32 window paths only");
+    if (c->any_open) return fail(KMC_EUNSUPPORTED, "score replay has no terms for open-electrode transfers");
     return KMC_OK;
 }
 
@@ -1475,6 +1519,34 @@ kmc_status kmc_dense_potential(kmc_ctx *c, float *phi_dev) {
     if (!phi_dev) return fail(KMC_EINVAL, "phi_dev is NULL");
     if (!c->dense) return fail(KMC_EUNSUPPORTED, "the dense potential needs a KMC_BF16X2 context");
     KMC_HIP(c, launch_dense_phi(dense_args(c, c->cur, phi_dev, c->sites[0]), c->stream));
+    return KMC_OK;
+}
+
+kmc_status kmc_set_electrodes(kmc_ctx *c, int32_t device, int32_t open, double ea_ground, double mu_ground,
+                              double ea_bias, double mu_bias) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (device < -1 || device >= c->p.n_devices) return fail(KMC_EINVAL, "device index out of range");
+    if (open != 0 && open != 1) return fail(KMC_EINVAL, "open must be 0 or 1");
+    if (!is_finite(ea_ground) || !is_finite(mu_ground) || !is_finite(ea_bias) || !is_finite(mu_bias))
+        return fail(KMC_EINVAL, "electrode barriers and energies must be finite");
+    if (open && (c->dense || c->phifix))
+        return fail(KMC_EUNSUPPORTED, "open electrodes run the binary64/binary32 window paths only");
+    const int d0 = device < 0 ? 0 : device, d1 = device < 0 ? c->p.n_devices : device + 1;
+    KMC_HIP(c, hipStreamSynchronize(c->stream));  // an earlier copy of the host table may be pending
+    for (int d = d0; d < d1; ++d) {
+        Electrode &e = c->el[d];
+        e.open = open;
+        e.ea_ground = ea_ground;
+        e.mu_ground = mu_ground;
+        e.ea_bias = ea_bias;
+        e.mu_bias = mu_bias;
+    }
+    c->any_open = false;
+    for (const Electrode &e : c->el) c->any_open = c->any_open || e.open;
+    KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.electrodes, c->el.data(), sizeof(Electrode) * c->el.size(),
+                              hipMemcpyHostToDevice, c->stream));
+    KMC_HIP(c, hipStreamSynchronize(c->stream));  // the host copy may change at the next call
     return KMC_OK;
 }
 

@@ -26,7 +26,7 @@ def _first_divergence(net_g, dec_g, net_o, dec_o):
 
 
 def lockstep(sim, p_or, protocols, occ0: np.ndarray, n_steps: int, chunk: int,
-             n_set=None, max_resync: int = 4):
+             n_set=None, max_resync: int = 4, electrodes=None):
     """Run the HIP simulator and the oracle side by side from occ0 in chunks of
     `chunk` steps; compare per-step net hops and deciles and the occupancy after
     every chunk.  A mismatch is accepted only where it can come from a
@@ -48,7 +48,7 @@ def lockstep(sim, p_or, protocols, occ0: np.ndarray, n_steps: int, chunk: int,
         net_g = net_g.cpu().numpy()
         dec_g = dec_g.cpu().numpy()
         occ_g = sim.read_occupancy()
-        out = oracle.run(p_or, protocols, occ_o, n0 + done, k, n_set=n_set, log_cap=65536)
+        out = oracle.run(p_or, protocols, occ_o, n0 + done, k, n_set=n_set, log_cap=65536, electrodes=electrodes)
         log_g, n_gpu_log = sim.read_threshold_log(65536)
         new_gpu_log = n_gpu_log - gpu_log_before
         gpu_entries = log_g[gpu_log_before:n_gpu_log] if n_gpu_log <= len(log_g) else None

@@ -127,6 +127,21 @@ def gaussian_barriers(shape: Sequence[int], mean: float, std: float, seed: int,
     return g.normal(mean, std, size=tuple(shape)).astype(dtype).reshape(-1)
 
 
+def sparse_traps(shape: Sequence[int], base: float, fraction: float, depth: float, seed: int,
+                 dtype=np.float32, field: Optional[np.ndarray] = None) -> np.ndarray:
+    """Per-site barriers with deep traps at a few random positions (the
+    charge-trapping effect of scarce defects the paper's conclusion names):
+    round(fraction x sites) distinct sites, chosen with numpy's PCG64, get
+    `depth` eV more than the rest (`base`, or a given field)."""
+    n = int(np.prod(shape))
+    out = (np.full(n, base, dtype=np.float64) if field is None
+           else np.asarray(field, dtype=np.float64).reshape(-1).copy())
+    g = np.random.Generator(np.random.PCG64(seed))
+    k = int(round(fraction * n))
+    out[g.permutation(n)[:k]] += depth
+    return out.astype(dtype)
+
+
 # --------------------------------------------------------------- workloads
 def c1_plain_fp64(n_steps: int = 10_000) -> Workload:
     ph = Physics(precision=FP64, seed=0)
