@@ -373,11 +373,14 @@ def bench_gradient(args):
         "forward_site_updates_per_s": wl.n_sites * steps / t_fwd,
         "replay_site_updates_per_s": wl.n_sites * steps / t_rep,
         "replay_over_forward_time": t_rep / t_fwd,
-        "roofline": {"bound": "hbm", "kernel": "hop_half_step<float,h,score>", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": "replay_stream<float,h>", "achieved": achieved,
                      "bytes": "8 B per site and step: occupancy in and out, one binary32 Coulomb part per bond",
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None, "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps,
-                     "launch_note": "per half-step: the replay kernel and the potential update"},
+                     "launch_note": "per half-step: the replay kernel and the update of the Coulomb parts",
+                     "limit_note": "the kernel issues about 300 VALU instructions per 8-site block and "
+                                   "half-step and its VALU is about 80 % busy (SQ counters): it is bound by "
+                                   "its instruction count, below the HBM roof"},
         "grad_mean_over_replicas": [float(x) for x in g.mean(axis=0)],
     }
     print(json.dumps(out), flush=True)

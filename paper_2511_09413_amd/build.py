@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libkmc.so")
-SOURCES = ["kmc_kernels.hip", "kmc_persistent.hip", "kmc_wave.hip", "kmc_dense.hip", "kmc_api.cpp", "kmc_fit.cpp", "kmc_noalloc.hip", "kmc_zone.hip", "kmc_phifix.hip", "kmc_electrode.hip"]
+SOURCES = ["kmc_kernels.hip", "kmc_persistent.hip", "kmc_wave.hip", "kmc_dense.hip", "kmc_api.cpp", "kmc_fit.cpp", "kmc_noalloc.hip", "kmc_zone.hip", "kmc_phifix.hip", "kmc_electrode.hip", "kmc_replay.hip"]
 ARCH = os.environ.get("KMC_OFFLOAD_ARCH", "gfx950")
 
 

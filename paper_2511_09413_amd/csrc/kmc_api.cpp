@@ -22,6 +22,8 @@
 namespace kmc {
 hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
 hipError_t launch_score(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
+hipError_t launch_replay_stream(const HopArgs &a, bool fp64, hipStream_t st);
+int replay_run_rails(int pitch);
 hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes);
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
                          const void *ea, bool fp64, hipStream_t st);
@@ -75,7 +77,7 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Layout {
     size_t occ_a, occ_b, devs, tiles, knot_t, knot_v, ktab64, ktab32, ctl, tally_net, tally_dec, dec_run,
         net_total, log_count, log_entries, scratch, rail_dev, rail_idx, n_ions, ptiles, pub, status,
-        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, phifix, kfix, electrodes, total;
+        rp_a, rp_b, score_log, rec, hops, hop_ctl, phi, ktiles, dtiles, ctiles, ticket, phifix, kfix, electrodes, rtiles, total;
     int64_t max_ptiles, pub_stride;  // persistent kernel: tiles per launch (ring slots), words per ring
     int64_t max_wtiles, wpub_stride;  // wave kernel: tiles per launch, publication words per tile
     size_t wtiles;                    // wave tiling (PTile array)
@@ -234,9 +236,12 @@ Layout layout_for(const kmc_params *p) {
     L.hop_cap = std::min<int64_t>(std::max<int64_t>(L.total_sites / 64, 4096), (int64_t)1 << 24);
     if (p->precision != KMC_BF16X2) {
         const bool f64 = p->precision == KMC_FP64 || p->precision == KMC_PHI_FIXED;
-        L.rec = take((f64 ? sizeof(double) : sizeof(float)) * (size_t)L.total_sites);
+        // (16 values of padding: the streaming replay reads four parts per block
+        // and ignores those beyond a rail's end)
+        L.rec = take((f64 ? sizeof(double) : sizeof(float)) * ((size_t)L.total_sites + 16));
         L.hops = take(sizeof(uint4) * (size_t)L.hop_cap);
         L.hop_ctl = take(sizeof(int64_t) * 2);
+        L.rtiles = take(sizeof(Tile) * (size_t)rails);  // runs of the streaming replay
     }
     if (p->precision == KMC_BF16X2) {
         // potential of every site (rows padded to a multiple of 128 sites), the
@@ -311,6 +316,7 @@ struct kmc_ctx {
     int frac_bits = 0;                 // its units: 2^-frac_bits V
     int64_t k10fix = 0;                // K(1, 0) in those units
     std::vector<Electrode> el;         // reservoirs per device (host copy of the workspace's)
+    std::vector<Tile> rtiles;          // runs of rails of the streaming replay (empty: the tile replay)
     bool any_open = false;             // some device has open electrodes: half-step launches only
 
     template <typename T>
@@ -951,6 +957,16 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
                 c->ctiles.push_back(Tile{d, r0, std::min(run, c->rails[d] - r0), 0});
         }
     }
+    // runs of the streaming replay, when every rail fits one workgroup
+    if (!c->dense) {
+        bool fits = true;
+        for (int d = 0; d < D; ++d) fits = fits && replay_run_rails(c->devs[d].pitch) > 0;
+        for (int d = 0; fits && d < D; ++d) {
+            const int run = replay_run_rails(c->devs[d].pitch);
+            for (int r0 = 0; r0 < c->rails[d]; r0 += run)
+                c->rtiles.push_back(Tile{d, r0, std::min(run, c->rails[d] - r0), 0});
+        }
+    }
     std::vector<uint16_t> kt_host;
     if (c->dense) {
         auto bf16_rne = [](float f) {
@@ -1019,6 +1035,7 @@ kmc_status kmc_init_device(const kmc_params *params, int8_t *occ_dev, const void
         chk(h2d(lay.ctiles, c->ctiles.data(), sizeof(Tile) * c->ctiles.size()), "copy decision tiles");
         chk(set_dense_lds_limit((size_t)(kDenseRails + 2 * m) * (lay.dense_nb * 32 + 8)), "LDS limit of the dense kernel");
     }
+    if (!c->rtiles.empty()) chk(h2d(lay.rtiles, c->rtiles.data(), sizeof(Tile) * c->rtiles.size()), "copy replay runs");
     if (c->phifix) {
         chk(h2d(lay.kfix, kfix_host.data(), sizeof(int64_t) * kfix_host.size()), "copy fixed-point kernel table");
         chk(h2d(lay.ctiles, c->ctiles.data(), sizeof(Tile) * c->ctiles.size()), "copy decision tiles");
@@ -1421,6 +1438,8 @@ kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int
     a.log.count = b.score_log;
     a.log.cap = 0;
     a.score_grad = grad_dev;
+    a.dtiles = c->at<Tile>(c->lay.rtiles);
+    a.n_dtiles = (int32_t)c->rtiles.size();
     a.rec = b.rec;
     a.hops = b.hops;
     a.hop_ctl = b.hop_ctl;
@@ -1447,7 +1466,8 @@ kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int
             a.occ_in = cur;
             a.occ_out = nxt;
             a.h = h;
-            KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
+            if (!c->rtiles.empty()) KMC_HIP(c, launch_replay_stream(a, c->fp64, c->stream));
+            else KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
             pa.occ = nxt;  // the new state, for a full recomputation after an overflow
             pa.hop_count = b.hop_ctl + h;
             KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream));
@@ -1462,7 +1482,7 @@ namespace kmc {
 // Bytes a region needs to hold the replay's buffers for this context.
 size_t replay_region_bytes(const kmc_ctx *c) {
     const size_t real = c->fp64 ? sizeof(double) : sizeof(float);
-    return align_up((size_t)c->lay.total_pad, 256) * 2 + align_up(real * (size_t)c->lay.total_sites, 256) +
+    return align_up((size_t)c->lay.total_pad, 256) * 2 + align_up(real * ((size_t)c->lay.total_sites + 16), 256) +
            align_up(sizeof(uint4) * (size_t)c->lay.hop_cap, 256) + 256;
 }
 
@@ -1488,7 +1508,7 @@ kmc_status score_replay_in_region(kmc_ctx *c, const int8_t *occ0_dev, int64_t st
     };
     b.occ_a = reinterpret_cast<int8_t *>(take((size_t)c->lay.total_pad));
     b.occ_b = reinterpret_cast<int8_t *>(take((size_t)c->lay.total_pad));
-    b.rec = take(real * (size_t)c->lay.total_sites);
+    b.rec = take(real * ((size_t)c->lay.total_sites + 16));
     b.hops = reinterpret_cast<uint4 *>(take(sizeof(uint4) * (size_t)c->lay.hop_cap));
     int64_t *ctl = reinterpret_cast<int64_t *>(take(4 * sizeof(int64_t)));
     b.hop_ctl = ctl;

@@ -1,0 +1,342 @@
+// Score replay, one streaming kernel per half-step (kmc_score_replay in
+// include/kmc.h; main text Eq. hop_rate and Eq. 2 for the rate law whose
+// log-derivatives are summed).
+//
+// The replay re-takes the forward's decisions and, for every candidate bond,
+// adds W g (y - p)/(1 - p) (0 when p = 1) to the device's four sums, g the
+// log-derivatives of p with respect to the common barrier shift, nu0, kappa
+// and alpha, y the decision and W the step's weight.  p is evaluated with the
+// Coulomb part of the bond's energy change kept per bond (the exact window sum
+// in binary64 rounded once to the path's precision, maintained by
+// replay_ec_full / replay_ec_update), the rest in the path's precision.
+//
+// A workgroup takes a run of consecutive rails of one device (sixteen passes of
+// 256 / (pitch / 8) rails); a thread owns one Philox block (the four bonds of
+// the parity in eight sites) per pass, and loads the next pass's occupancy and
+// per-bond Coulomb parts before scoring the current one.  Decisions are the
+// forward's: the exact class
+// prefilter settles almost every candidate as rejected on its word alone; a
+// survivor is listed in LDS and decided at the end of its pass with the full
+// window sum over the half-step's snapshot, one wavefront per survivor in the same
+// order as the hop kernels (lanes strided over the window, then a butterfly),
+// so the decision equals the forward's bit for bit.  The kernel never writes
+// the snapshot: accepted hops are marked in an LDS flip mask, each pass writes
+// its blocks' new state to the other plane, and the hops go to the list from
+// which replay_ec_update recomputes the Coulomb parts they changed.  The
+// candidates the prefilter rejects (y = 0) are compacted per wavefront in LDS
+// before their terms are evaluated, 64 per round.
+#include "kmc_device.h"
+#include "kmc_internal.h"
+
+namespace kmc {
+
+namespace {
+
+constexpr int kRBlock = 256;
+constexpr int kRPasses = 16;
+constexpr int kRRing = 2 * kRBlock * 4;  // twice every bond of one pass
+
+template <typename Real>
+__device__ __forceinline__ const Real *ktable(const HopArgs &a) {
+    return std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
+                                             : reinterpret_cast<const Real *>(a.ktab32);
+}
+
+template <typename Real, int H>
+__global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
+    __shared__ double v_wg;
+    __shared__ uint32_t wtab[kClasses];             // prefilter threshold of each barrier class
+    __shared__ int n_surv;                          // survivors listed so far (the list is a ring)
+    __shared__ uint32_t surv[kRRing];               // (rail - r0) << 12 | s
+    __shared__ uint32_t flips[kRBlock];             // bit j: byte s0 + j of the thread's block flips
+    __shared__ double gsum[kRBlock / 64][4];
+    __shared__ Real rec_ec[kRBlock / 64][4 * 64];   // per wavefront: compacted rejected candidates
+    __shared__ Real rec_ea[kRBlock / 64][4 * 64];
+    __shared__ uint32_t rec_aux[kRBlock / 64][4 * 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Tile tile = a.dtiles[blockIdx.x];
+    const int d = tile.d;
+    const DevInfo &dv = a.devs[d];
+    const int L = dv.sites, R = dv.rails, pitch = dv.pitch, bpr = pitch / 8;
+    const int64_t n = a.n_abs;
+    // the count of the previous half-step's list (the other parity) was
+    // consumed by its update kernel: clear it for the next half-step
+    if (blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(a.hop_ctl + (1 - H), (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < kClasses) {  // every thread evaluates the step's bias; one class threshold each
+        const double V = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
+                                          (double)(n - dv.n_set) * a.dt);
+        wtab[tid] = class_threshold(a.c0, a.beta, a.alpha, V, L, dv.ea_min, dv.ea_step, dv.coul_bound, tid);
+        if (tid == 0) {
+            v_wg = V;
+            n_surv = 0;
+        }
+    }
+    flips[tid] = 0u;
+    const int per_pass = kRBlock / bpr;
+    const int slot = tid / bpr, b = tid - slot * bpr, s0 = 8 * b;
+    const bool lane_used = slot < per_pass;
+    const int r_end = tile.r0 + tile.nr;
+    const int8_t *snap = a.occ_in + dv.off_pad;
+    const Real *ec_of = reinterpret_cast<const Real *>(a.rec);
+    const int64_t odd_at = (L + 1) / 2;  // start of the odd bonds in a rail's run
+    const int last = L - 2 - s0;         // bond (s0+k, s0+k+1) exists iff k <= last
+    const uint32_t exist = last >= 7 ? 0xFFu : (last < 0 ? 0u : ((2u << last) - 1u));
+    // a pass's occupancy block and the Coulomb parts of its four bonds.  The
+    // loads are issued unconditionally (a lane without a block of this pass
+    // reads the run's first rail and ignores it; the parts of bonds beyond a
+    // rail's end are read from the array's padding or the next run and
+    // ignored), so that the memory counter of every lane counts the same
+    // loads and the next pass's loads stay in flight while this one is
+    // scored.
+    const int64_t dev_off = dv.off;
+    const int64_t ec_base = dev_off + (H ? odd_at : 0) + 4 * b;
+    const int8_t *snap_s0 = snap + s0;
+    auto load_pass = [&](int r, uint2 &v, uint32_t &nxt, Real *ec) {
+        const int rl = (lane_used && r < r_end) ? r : tile.r0;
+        const int8_t *row = snap_s0 + (int64_t)rl * pitch;
+        v = *reinterpret_cast<const uint2 *>(row);
+        nxt = H == 1 ? (uint32_t)(uint8_t)row[s0 + 8 < pitch ? 8 : 0] : 0u;
+        const Real *e = ec_of + ec_base + (int64_t)rl * L;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ec[i] = e[i];
+    };
+    uint2 v_next;
+    uint32_t nx_next;
+    Real ec_next[4];
+    load_pass(tile.r0 + slot, v_next, nx_next, ec_next);
+    __syncthreads();
+    const double V = v_wg;
+    const uint32_t thr0 = wtab[0];  // the largest threshold (lowest class)
+    const Real alpha_r = (Real)a.alpha, V_r = (Real)V, beta_r = (Real)a.beta, c0_r = (Real)a.c0;
+    const double W = a.score_w[d], beta = a.beta;
+    const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
+    const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
+    // Per thread: S0 = sum of (y - p)/(1 - p) over its candidates (the Ea and
+    // nu0 terms are W g times it, g the same for every candidate), S2 = sum of
+    // dE_coul (y - p)/(1 - p) and S3 = sum of +-(y - p)/(1 - p) (sign of t - o);
+    // the constant factors are applied once at the end.
+    double S0 = 0.0, S2 = 0.0, S3 = 0.0;
+    // the bias part of dE for a hop toward site L - 1 and toward site 0 (the
+    // same expression as the forward's, t - o = +-1)
+    const Real e_up = ((alpha_r * V_r) * (Real)1) / (Real)L;
+    const Real e_down = ((alpha_r * V_r) * (Real)-1) / (Real)L;
+    // score term of one candidate with its decision y
+    auto term = [&](Real ec, Real ea, bool up, uint32_t y) {
+        const Real dE = (up ? e_up : e_down) + ec;
+        Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+        p = p < (Real)1 ? p : (Real)1;
+        if (p < (Real)1) {
+            // (y - p)/(1 - p) with a reciprocal refined by two Newton steps
+            // (within an ulp or two of the rounded quotient; 1 - p lies in (0, 1])
+            const double pd = (double)p;
+            const double den = 1.0 - pd;
+            double rc = __builtin_amdgcn_rcp(den);
+            rc = fma(rc, fma(-den, rc, 1.0), rc);
+            rc = fma(rc, fma(-den, rc, 1.0), rc);
+            const double ratio = ((double)y - pd) * rc;
+            S0 += ratio;
+            S2 += (double)ec * ratio;
+            S3 += up ? ratio : -ratio;
+        }
+    };
+    // the survivors listed in [from, to) of the ring: the forward's decision
+    // from the full window sum over the snapshot, one wavefront each, in the
+    // hop kernels' order; the score term of each with its decision
+    const Real *kt = ktable<Real>(a);
+    const int kt_stride = a.cutoff + 1;
+    const uint32_t ctr3 = ((uint32_t)d << 4) | (uint32_t)H;
+    auto decide_survivors = [&](int from, int to) {
+        for (int i = from + wave; i < to; i += kRBlock / 64) {
+            const uint32_t e = surv[i & (kRRing - 1)];
+            const int rr = tile.r0 + (int)(e >> 12), s = (int)(e & 4095u);
+            const int8_t *rp = snap + (int64_t)rr * pitch;
+            const bool first = rp[s] & 1;
+            const int o = first ? s : s + 1, t = first ? s + 1 : s;
+            int lo = s - a.cutoff, hi = s + 1 + a.cutoff;
+            lo = lo < 0 ? 0 : lo;
+            hi = hi > L - 1 ? L - 1 : hi;
+            Real part = (Real)0;
+            for (int k = 0; k < dv.n_nbr; ++k) {
+                const int off = dv.nbr_off[k];
+                const Real *ktr = kt + dv.nbr_dist[k] * kt_stride;
+                const int8_t *nrow = snap + (int64_t)(((rr + off) % R + R) % R) * pitch;
+                for (int j = lo + lane; j <= hi; j += 64) {
+                    int occ = nrow[j] & 1;
+                    if (off == 0 && (j == o || j == t)) occ = 0;
+                    const int dt_ = t - j < 0 ? j - t : t - j;
+                    const int do_ = o - j < 0 ? j - o : o - j;
+                    const Real kt_v = dt_ > a.cutoff ? (Real)0 : ktr[dt_];
+                    const Real ko_v = do_ > a.cutoff ? (Real)0 : ktr[do_];
+                    part += occ ? (kt_v - ko_v) : (Real)0;
+                }
+            }
+#pragma unroll
+            for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) part += __shfl_xor(part, sh_, 64);
+            if (lane == 0) {
+                const Real e_app = ((alpha_r * V_r) * (Real)(t - o)) / (Real)L;
+                const uint4 blk = philox4x32_10((uint32_t)(s >> 3), (uint32_t)rr, (uint32_t)n, ctr3, a.key0, a.key1);
+                const uint32_t word = word_of(blk, (s >> 1) & 3);
+                const Real ea = a.ea ? reinterpret_cast<const Real *>(a.ea)[dv.off + (int64_t)rr * L + o] : (Real)a.ea_scalar;
+                const bool y = decide_hop<Real>(e_app + part, ea, word, beta_r, c0_r, a.log, d, H, n, rr, s);
+                const Real ec = ec_of[dv.off + (int64_t)rr * L + (H ? odd_at : 0) + (s >> 1)];
+                term(ec, ea, t > o, y ? 1u : 0u);
+                if (y) {
+                    // flip bytes s and s + 1 in the masks of the threads that own them
+                    const int sl = (rr - tile.r0) % per_pass;
+                    atomicOr(&flips[sl * bpr + (s >> 3)], 1u << (s & 7));
+                    atomicOr(&flips[sl * bpr + ((s + 1) >> 3)], 1u << ((s + 1) & 7));
+                    const int64_t kh = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(a.hop_ctl + H), 1ull);
+                    if (kh < a.hop_cap) a.hops[kh] = make_uint4((uint32_t)d, (uint32_t)rr, (uint32_t)s, first ? 0u : 1u);
+                }
+            }
+        }
+    };
+    int listed = 0;  // survivors of the earlier passes (the same value in every thread)
+    for (int p = 0; p < kRPasses; ++p) {
+        const int r = tile.r0 + slot + p * per_pass;
+        const bool valid = lane_used && r < r_end;
+        const uint2 v = v_next;
+        const uint32_t nxt = nx_next;
+        Real ec[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ec[i] = ec_next[i];
+        if (p + 1 < kRPasses) load_pass(r + per_pass, v_next, nx_next, ec_next);  // in flight meanwhile
+        const uint32_t bits = (((v.x & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) |
+                              ((((v.y & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << 4) | ((nxt & 1u) << 8);
+        // (exist drops the last block's bond 7 when site s0 + 8 lies beyond the rail)
+        const uint32_t cand = valid ? (bits ^ (bits >> 1)) & (H ? 0xAAu : 0x55u) & exist : 0u;
+        int pushed = 0;
+        uint32_t rest = 0u;  // bit i: bond i is a candidate rejected by the prefilter (y = 0)
+        if (cand) {
+            const uint4 blk = philox4x32_10((uint32_t)b, (uint32_t)r, (uint32_t)n, ((uint32_t)d << 4) | (uint32_t)H,
+                                            a.key0, a.key1);
+            // stage 0 without branches: bit i when bond i is a candidate whose
+            // word passes the lowest class's threshold
+            uint32_t c4 = 0u, s4 = 0u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t ci = (cand >> (H + 2 * i)) & 1u;
+                c4 |= ci << i;
+                s4 |= (ci & (word_of(blk, i) <= thr0 ? 1u : 0u)) << i;
+            }
+            rest = c4 & ~s4;
+            if (s4) {  // rare: the origin's class decides whether it survives
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (!((s4 >> i) & 1u)) continue;
+                    const int k = H + 2 * i;
+                    const int s = s0 + k;
+                    const int o = ((bits >> k) & 1u) ? s : s + 1;
+                    const int j = o - s0;
+                    const uint32_t ob = j < 8 ? ((j < 4 ? v.x : v.y) >> (8 * (j & 3))) & 0xFFu : nxt;
+                    if (word_of(blk, i) <= wtab[ob >> 1]) {
+                        // decided (and scored) at the end of the pass
+                        const int q = atomicAdd(&n_surv, 1);
+                        surv[q & (kRRing - 1)] = ((uint32_t)(r - tile.r0) << 12) | (uint32_t)s;
+                        pushed = 1;
+                    } else {
+                        rest |= 1u << i;
+                    }
+                }
+            }
+        }
+        // the rejected candidates of the wavefront, compacted: each lane writes
+        // its records from its offset among the wavefront's records (a prefix
+        // count from three ballots of its count's bits), and the wavefront then
+        // scores 64 records per round (a lane's four bond slots would otherwise
+        // cost four rounds whenever any lane has a candidate in each)
+        {
+            const uint32_t cnt = (uint32_t)__builtin_popcount(rest);
+            uint32_t at = 0u, total = 0u;
+#pragma unroll
+            for (int bit = 0; bit < 3; ++bit) {
+                const uint64_t bal = __ballot((cnt >> bit) & 1u);
+                at += __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))
+                      << bit;
+                total += (uint32_t)__popcll(bal) << bit;
+            }
+            uint32_t m = rest;
+            while (m) {
+                const int i = __builtin_ctz(m);
+                m &= m - 1u;
+                const uint32_t up = (bits >> (H + 2 * i)) & 1u;  // 1: toward site L-1
+                rec_ec[wave][at] = ec[i];
+                rec_aux[wave][at] = up;
+                if (a.ea) {
+                    const int s = s0 + H + 2 * i;
+                    rec_ea[wave][at] = reinterpret_cast<const Real *>(a.ea)[dev_off + (int64_t)r * L + (up ? s : s + 1)];
+                }
+                ++at;
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+            for (int j = lane; j < (int)total; j += 64) {
+                const Real ea = a.ea ? rec_ea[wave][j] : (Real)a.ea_scalar;
+                term(rec_ec[wave][j], ea, rec_aux[wave][j] != 0u, 0u);
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+        }
+        uint32_t f = 0u;
+        if (__syncthreads_or(pushed)) {  // uniform: the pass had survivors
+            const int to = n_surv;
+            decide_survivors(listed, to);
+            listed = to;
+            __syncthreads();  // their flips are in the masks
+            f = flips[tid];
+            flips[tid] = 0u;
+        }
+        if (valid) {  // the new state of the pass's block
+            uint2 vn = v;
+            vn.x ^= ((f & 0xFu) * 0x00204081u) & 0x01010101u;
+            vn.y ^= (((f >> 4) & 0xFu) * 0x00204081u) & 0x01010101u;
+            *reinterpret_cast<uint2 *>(a.occ_out + dv.off_pad + (int64_t)r * pitch + s0) = vn;
+        }
+    }
+    // the workgroup's four sums, one atomic each
+    double g0 = w_ea * S0, g1 = w_nu * S0, g2 = w_k * S2, g3 = w_a * S3;
+#pragma unroll
+    for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) {
+        g0 += __shfl_xor(g0, sh_, 64);
+        g1 += __shfl_xor(g1, sh_, 64);
+        g2 += __shfl_xor(g2, sh_, 64);
+        g3 += __shfl_xor(g3, sh_, 64);
+    }
+    if (lane == 0) {
+        gsum[wave][0] = g0;
+        gsum[wave][1] = g1;
+        gsum[wave][2] = g2;
+        gsum[wave][3] = g3;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double sum = 0.0;
+        for (int w = 0; w < kRBlock / 64; ++w) sum += gsum[w][tid];
+        if (sum != 0.0) atomicAdd(&a.score_grad[d * 4 + tid], sum);
+    }
+}
+
+}  // namespace
+
+// Rails of one run of the streaming replay (sixteen passes of a 256-thread
+// workgroup, pitch / 8 threads per rail), or 0 when a rail is longer than
+// one workgroup covers.
+int replay_run_rails(int pitch) {
+    const int bpr = pitch / 8;
+    return bpr > kRBlock ? 0 : kRPasses * (kRBlock / bpr);
+}
+
+hipError_t launch_replay_stream(const HopArgs &a, bool fp64, hipStream_t st) {
+    const dim3 grid(a.n_dtiles), block(kRBlock);
+    if (fp64) {
+        if (a.h == 0) hipLaunchKernelGGL((replay_stream<double, 0>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((replay_stream<double, 1>), grid, block, 0, st, a);
+    } else {
+        if (a.h == 0) hipLaunchKernelGGL((replay_stream<float, 0>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((replay_stream<float, 1>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kmc
