@@ -11,8 +11,10 @@ torch-owned buffers of one context.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -49,6 +51,21 @@ class kmc_zone_params(C.Structure):
 
 
 _LIB = None
+
+# Contexts still open when the interpreter exits are destroyed by an atexit
+# hook, before the interpreter tears down its modules and before the native
+# libraries' own exit handlers run, so that no HIP call comes from a
+# finalizer during teardown.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all() -> None:
+    for sim in list(_LIVE):
+        try:
+            sim.close()
+        except Exception:
+            pass
 
 
 def lib():
@@ -274,6 +291,7 @@ class Simulator:
         self._ws_ptr = (base + 255) // 256 * 256
         self.stream = torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
+            _LIVE.add(self)
             self.ctx = init_device(self._params, self.occ.data_ptr(),
                                    self.ea.data_ptr() if self.ea is not None else None,
                                    self._ws_ptr, nbytes, self.stream.cuda_stream)
@@ -468,6 +486,7 @@ class ZoneSimulator:
             _check(lib().kmc_zone_init(C.byref(self.params), C.c_void_p(self.occ.data_ptr()), C.c_void_p(ws),
                                        nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.ctx = int(h.value)
+        _LIVE.add(self)
 
     def set_bias_protocol(self, t_s, v_volt) -> None:
         t = np.ascontiguousarray(t_s, dtype=np.float64)
