@@ -56,6 +56,7 @@ def parse():
 TRAFFIC = {
     "hop_persistent": ("hop_persistent_c2_traffic.md", "kmc_persistent.hip"),
     "hop_wave": ("hop_wave_c2_traffic.md", "kmc_wave.hip"),
+    "replay_stream": ("replay_stream_c5_traffic.md", "kmc_replay.hip"),
 }
 
 
@@ -363,6 +364,7 @@ def bench_gradient(args):
     # recomputation after hops touches a few kB.  Against the HBM peak.
     replay_bytes = 2 * (1 + 1 + 2) * wl.n_sites * steps
     achieved = replay_bytes / t_rep / 1e9
+    t_meas = measured_traffic("replay_stream")
     out = {
         "metric": "gradient site-updates/s (forward + score replay)", "value": value, "unit": "site-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": (t_fwd + t_rep) * 1e3 / steps,
@@ -376,8 +378,10 @@ def bench_gradient(args):
         "roofline": {"bound": "hbm", "kernel": "replay_stream<float,h>", "achieved": achieved,
                      "bytes": "8 B per site and step: occupancy in and out, one binary32 Coulomb part per bond",
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps,
-                     "launch_note": "per half-step: the replay kernel and the update of the Coulomb parts",
+                     "traffic": t_meas["hbm_bytes_per_launch"] if t_meas is not None else None,
+                     "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps,
+                     "launch_note": "per half-step: the replay kernel and the update of the Coulomb parts; "
+                                    "traffic is the replay kernel's own, per half-step",
                      "limit_note": "the kernel issues about 300 VALU instructions per 8-site block and "
                                    "half-step and its VALU is about 80 % busy (SQ counters): it is bound by "
                                    "its instruction count, below the HBM roof"},
