@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="auto", choices=["auto", "half_step", "persistent", "wave"])
     ap.add_argument("--tile-sites", type=int, default=0)
+    ap.add_argument("--no-record", action="store_true",
+                    help="gradient workload: replay without the forward's recording")
     ap.add_argument("--workload", default="large-device",
                     choices=["large-device", "batch", "gradient", "dense", "dense-fixed", "small-fp64", "zone"],
                     help="large-device: 4096x1024 (default); batch: 256 heterogeneous devices; "
@@ -57,6 +59,7 @@ TRAFFIC = {
     "hop_persistent": ("hop_persistent_c2_traffic.md", "kmc_persistent.hip"),
     "hop_wave": ("hop_wave_c2_traffic.md", "kmc_wave.hip"),
     "replay_stream": ("replay_stream_c5_traffic.md", "kmc_replay.hip"),
+    "replay_logged": ("replay_logged_c5_traffic.md", "kmc_replay.hip"),
 }
 
 
@@ -334,10 +337,22 @@ def bench_small(args):
     sim.close()
 
 
+RECORD_CAP = 4096  # accepted hops per half-step kept by the gradient bench's recording
+LIMIT_NOTE = {
+    "replay_stream": "the kernel issues about 300 VALU instructions per 8-site block and half-step and its VALU "
+                     "is about 80 % busy (SQ counters): it is bound by its instruction count, below the HBM roof",
+    "replay_logged": "no Philox, prefilter or window sums: per candidate one exponential and the binary64 "
+                     "ratio (y - p)/(1 - p); the update of the Coulomb parts after the half-step's hops is "
+                     "a launch of its own",
+}
+
+
 def bench_gradient(args):
     """Forward steps and the score-function replay of 512 replicas of a
     256 x 512 device (1 V for the first half of the run, then 0 V), FP32 step,
-    binary64 accumulators."""
+    binary64 accumulators.  The forward records its accepted hops
+    (kmc_record_hops) and the replay takes its decisions from the recording;
+    --no-record times the replay that draws them again."""
     import numpy as np
     import torch
     import paper_2511_09413_amd as kmc
@@ -353,38 +368,45 @@ def bench_gradient(args):
     D = len(wl.rails)
     W = torch.ones((steps, D), dtype=torch.float64, device="cuda:0")
     sim.score_replay(occ0, 0, W[:min(steps, 64)])      # warm-up of the replay kernels
+    record = not args.no_record
+    if record:
+        sim.record_hops(steps, RECORD_CAP)
     t_fwd = _timed(lambda: sim.run_steps(steps), stream)
     grads = []
     t_rep = _timed(lambda: grads.append(sim.score_replay(occ0, 0, W)), stream)
     g = grads[0].cpu().numpy()
     value = wl.n_sites * steps / (t_fwd + t_rep)
     # The replay kernel's own memory stream, per half-step and site: the
-    # padded occupancy read (1 B) and written (1 B), and the binary32 Coulomb
-    # part of every bond of the half-step's parity (4 B per two sites); the
-    # recomputation after hops touches a few kB.  Against the HBM peak.
-    replay_bytes = 2 * (1 + 1 + 2) * wl.n_sites * steps
+    # padded occupancy read (1 B), written again (1 B) only by the kernel that
+    # draws the decisions (the recorded replay flips the hops' sites in
+    # place), and the binary32 Coulomb part of every bond of the half-step's
+    # parity (4 B per two sites); the recomputation after hops touches a few
+    # kB.  Against the HBM peak.
+    kernel = "replay_logged" if record else "replay_stream"
+    per_site = (1 + 2) if record else (1 + 1 + 2)
+    replay_bytes = 2 * per_site * wl.n_sites * steps
     achieved = replay_bytes / t_rep / 1e9
-    t_meas = measured_traffic("replay_stream")
+    t_meas = measured_traffic(kernel)
     out = {
         "metric": "gradient site-updates/s (forward + score replay)", "value": value, "unit": "site-updates/s",
         "n_gpus": 1, "steps": steps, "warmup": 0, "ms_per_step": (t_fwd + t_rep) * 1e3 / steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32+f64acc",
         "data": "synthetic",
         "config": {"workload": wl.name, "replicas": D, "theta": ["Ea", "nu0", "kappa", "alpha"],
-                   "forward_launch_mode": sim.launch_mode},
+                   "forward_launch_mode": sim.launch_mode, "recorded_decisions": record},
         "forward_site_updates_per_s": wl.n_sites * steps / t_fwd,
         "replay_site_updates_per_s": wl.n_sites * steps / t_rep,
         "replay_over_forward_time": t_rep / t_fwd,
-        "roofline": {"bound": "hbm", "kernel": "replay_stream<float,h>", "achieved": achieved,
-                     "bytes": "8 B per site and step: occupancy in and out, one binary32 Coulomb part per bond",
+        "roofline": {"bound": "hbm", "kernel": kernel + "<float,h>", "achieved": achieved,
+                     "bytes": ("6 B per site and step: occupancy in, one binary32 Coulomb part per bond" if record
+                               else "8 B per site and step: occupancy in and out, one binary32 Coulomb part "
+                                    "per bond"),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": t_meas["hbm_bytes_per_launch"] if t_meas is not None else None,
                      "avg_launch_us": t_rep / (2 * steps) * 1e6, "launches": 2 * steps,
                      "launch_note": "per half-step: the replay kernel and the update of the Coulomb parts; "
                                     "traffic is the replay kernel's own, per half-step",
-                     "limit_note": "the kernel issues about 300 VALU instructions per 8-site block and "
-                                   "half-step and its VALU is about 80 % busy (SQ counters): it is bound by "
-                                   "its instruction count, below the HBM roof"},
+                     "limit_note": LIMIT_NOTE[kernel]},
         "grad_mean_over_replicas": [float(x) for x in g.mean(axis=0)],
     }
     print(json.dumps(out), flush=True)

@@ -205,10 +205,44 @@ kmc_status kmc_read_threshold_log(kmc_ctx *ctx, kmc_log_entry *dst_host, int64_t
  * accepted hop changed); the rest of dE and p are evaluated in the path's
  * precision, and the terms are summed in binary64 (sum order not fixed).  The
  * per-bond values and the hop list live in the workspace.
+ * With a recording (kmc_record_hops) that began at step0, whose steps up to
+ * step0 + n_steps have been run, and whose start state equals occ0 (checked
+ * on the device), each half-step whose list did not overflow takes the
+ * forward's decisions from the recording instead of drawing them again: the
+ * same decisions and the same terms, summed in another order.  The call then
+ * synchronises the stream once (to read the lists' counts).
  * Errors: KMC_EINVAL for NULL pointers, negative indices, coulomb_kappa_v == 0
  * or nu0_hz <= 0; KMC_EUNSUPPORTED if step0 + n_steps exceeds 2^32 - 1. */
 kmc_status kmc_score_replay(kmc_ctx *ctx, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
                             const double *weight_dev, double *grad_dev);
+
+/* Bytes of the caller's buffer for kmc_record_hops(max_steps, cap) (0 when
+ * max_steps is 0).  Errors as kmc_record_hops's argument checks. */
+kmc_status kmc_record_bytes(kmc_ctx *ctx, int64_t max_steps, int64_t cap, size_t *bytes);
+
+/* Records the accepted hops of the next steps for the score replay (the
+ * decisions of SI S2.1, movement acceptance, of the steps that
+ * kmc_run_steps takes), so that kmc_score_replay of those steps need not
+ * draw them again.  From the context's current step n0 and state, every
+ * accepted hop of the steps [n0, n0 + max_steps) that later kmc_run_steps
+ * calls take (in any launch strategy) is appended to the list of its
+ * half-step, cap entries each; a list that overflows is kept as overflowed,
+ * and the replay then draws that half-step's decisions again.
+ *   buf_dev:  device memory of kmc_record_bytes(max_steps, cap) bytes,
+ *             256-byte aligned, owned by the caller, which keeps it until the
+ *             recording ends.  It holds the per-half-step counts, a copy of
+ *             the state at n0 (caller layout) and the lists.
+ *   bytes:    its size.
+ *   max_steps, cap: steps covered and entries per half-step list (>= 1).
+ *   max_steps == 0 or buf_dev == NULL ends the recording.
+ * Installing a protocol, loading, filling or restoring the occupancy,
+ * opening or closing electrodes, autotuning and a new kmc_record_hops end
+ * the recording.  Enqueued on the context's stream.
+ * Errors: KMC_EINVAL for negative sizes, cap < 1, a small or misaligned
+ * buffer or a product max_steps * cap too large; KMC_EUNSUPPORTED for
+ * KMC_BF16X2 and KMC_PHI_FIXED contexts, while any device has open
+ * electrodes, or when n0 + max_steps would reach 2^32. */
+kmc_status kmc_record_hops(kmc_ctx *ctx, void *buf_dev, size_t bytes, int64_t max_steps, int64_t cap);
 
 /* kmc_score_replay for callers that cannot allocate device memory where they
  * call (code under HIP graph capture, tight serving loops, harnesses that

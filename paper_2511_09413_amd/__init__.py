@@ -98,6 +98,8 @@ def lib():
         L.kmc_set_tile_sites.argtypes = [vp, C.c_int32]
         L.kmc_score_replay.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
         L.kmc_score_replay_noalloc.argtypes = [vp, vp, C.c_int64, C.c_int64, vp, vp]
+        L.kmc_record_bytes.argtypes = [vp, C.c_int64, C.c_int64, P(C.c_size_t)]
+        L.kmc_record_hops.argtypes = [vp, vp, C.c_size_t, C.c_int64, C.c_int64]
         L.kmc_get_persistent_groups.argtypes = [vp, P(C.c_int32)]
         L.kmc_set_persistent_group_limit.argtypes = [vp, C.c_int32]
         L.kmc_set_wait_limit.argtypes = [vp, C.c_int32]
@@ -126,7 +128,8 @@ def lib():
                      "kmc_set_tile_sites", "kmc_score_replay", "kmc_get_persistent_groups",
                      "kmc_set_persistent_group_limit", "kmc_set_wait_limit", "kmc_dense_potential", "kmc_fixed_potential",
                      "kmc_set_electrodes",
-                     "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc", "kmc_zone_workspace_bytes",
+                     "kmc_autotune", "kmc_fit_decay", "kmc_score_replay_noalloc", "kmc_record_bytes",
+                     "kmc_record_hops", "kmc_zone_workspace_bytes",
                      "kmc_zone_init", "kmc_zone_load_occupancy", "kmc_zone_set_bias_protocol", "kmc_zone_run_steps",
                      "kmc_zone_read_positions", "kmc_zone_get_step"):
             getattr(L, name).restype = C.c_int
@@ -328,6 +331,22 @@ class Simulator:
     def snapshot(self):
         """Device copy of the current occupancy (the start state of a later replay)."""
         return self.occ.clone()
+
+    def record_hops(self, max_steps: int, cap: int = 1024) -> None:
+        """Record the accepted hops of the next max_steps steps (kmc_record_hops),
+        cap per half-step, so that a score replay of them from the current
+        state takes the decisions from the recording; max_steps = 0 ends it.
+        The buffer is a device tensor this object keeps."""
+        if max_steps == 0:
+            _check(lib().kmc_record_hops(C.c_void_p(self.ctx), None, 0, 0, 0))
+            self._record = None
+            return
+        nbytes = C.c_size_t()
+        _check(lib().kmc_record_bytes(C.c_void_p(self.ctx), max_steps, cap, C.byref(nbytes)))
+        buf = self.torch.empty(nbytes.value + 256, dtype=self.torch.uint8, device=self.device)
+        ptr = (buf.data_ptr() + 255) // 256 * 256
+        _check(lib().kmc_record_hops(C.c_void_p(self.ctx), C.c_void_p(ptr), nbytes.value, max_steps, cap))
+        self._record = buf
 
     def score_replay(self, occ0, step0: int, weights):
         """Score-function terms of the steps [step0, step0 + len(weights)) replayed

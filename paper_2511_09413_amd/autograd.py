@@ -75,12 +75,31 @@ def _observable(sim, spec: ObservableSpec):
     torch = sim.torch
     occ0 = sim.snapshot()
     step0 = sim.step
+    _record(sim, spec.n_steps)
     net, dec = sim.run_steps(spec.n_steps, tallies=True)
     ions = dec[0].sum(dim=1).to(torch.float64).clamp_min(1.0)
     f = dec[:, :, spec.decile].to(torch.float64) / ions
     sites = torch.as_tensor([float(x) for x in spec.sites], dtype=torch.float64, device=f.device)
     cur = net.to(torch.float64) * (ELEMENTARY_CHARGE / spec.physics.dt_s) / sites
     return f, cur, occ0, step0
+
+
+RECORD_CAP = 1024                # accepted hops per half-step kept by the recording
+RECORD_MAX_BYTES = 1 << 30       # larger recordings are not made (the replay then draws again)
+
+
+def _record(sim, n_steps: int) -> None:
+    """Record the forward's hops for the replay where the context supports
+    it and the buffer stays moderate; otherwise the replay draws the decisions
+    again (same result)."""
+    from . import KMC_EUNSUPPORTED, KmcError
+    if 32 * n_steps * RECORD_CAP > RECORD_MAX_BYTES:
+        return
+    try:
+        sim.record_hops(n_steps, RECORD_CAP)
+    except KmcError as err:
+        if err.status != KMC_EUNSUPPORTED:
+            raise
 
 
 def _loo_deviation(x):

@@ -23,6 +23,8 @@ namespace kmc {
 hipError_t launch_hop(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
 hipError_t launch_score(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream_t st);
 hipError_t launch_replay_stream(const HopArgs &a, bool fp64, hipStream_t st);
+hipError_t launch_replay_logged(const HopArgs &a, bool fp64, hipStream_t st);
+hipError_t launch_compare_bytes(const int8_t *x, const int8_t *y, int64_t n, int64_t *flag, hipStream_t st);
 int replay_run_rails(int pitch);
 hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes);
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
@@ -318,6 +320,15 @@ struct kmc_ctx {
     std::vector<Electrode> el;         // reservoirs per device (host copy of the workspace's)
     std::vector<Tile> rtiles;          // runs of rails of the streaming replay (empty: the tile replay)
     bool any_open = false;             // some device has open electrodes: half-step launches only
+    // recording of accepted hops for the score replay (kmc_record_hops), in
+    // the caller's buffer: per half-step counts, then a flag for the replay's
+    // check of its start state; the state at the recording's first step; the
+    // lists
+    bool rec_on = false;
+    int64_t *rec_count = nullptr;      // [rec_n_hs + 1]
+    int8_t *rec_occ = nullptr;         // [total sites], caller layout
+    uint4 *rec_buf = nullptr;          // [rec_n_hs][rec_cap]
+    int64_t rec_cap = 0, rec_n0 = 0, rec_n_hs = 0;
 
     template <typename T>
     T *at(size_t off) { return reinterpret_cast<T *>(ws + off); }
@@ -731,6 +742,11 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_out, int32_t 
         pa.spin_limit = c->spin_limit;
         pa.occ_user = c->occ_user;
     }
+    if (c->rec_on) {
+        HopRecord r{c->rec_buf, c->rec_count, c->rec_cap, c->rec_n0, c->rec_n_hs};
+        a.record = r;
+        pa.record = r;
+    }
     // the fixed-point path's hop counts start at zero (a score replay in
     // between leaves its own there)
     if (c->phifix) KMC_HIP(c, launch_zero_i64(c->at<int64_t>(c->lay.hop_ctl), 2, c->stream));
@@ -828,6 +844,7 @@ kmc_status check_status(kmc_ctx *c) {
 }
 
 kmc_status after_state_change(kmc_ctx *c) {
+    c->rec_on = false;  // a recording describes the trajectory from its own start state
     if (c->phifix) KMC_HIP(c, launch_phifix_update(phifix_args(c, c->cur, true, 0), c->stream));
     KMC_HIP(c, launch_count_deciles(c->cur, c->at<DevInfo>(c->lay.devs), c->p.n_devices,
                                     c->at<int64_t>(c->lay.dec_run), c->stream));
@@ -1117,6 +1134,7 @@ kmc_status kmc_set_bias_protocol(kmc_ctx *c, int32_t device, const double *t_s, 
         if (i > 0 && t_s[i] < t_s[i - 1]) return fail(KMC_EINVAL, "knot times must be nondecreasing");
     }
     const int d0 = device < 0 ? 0 : device, d1 = device < 0 ? c->p.n_devices : device + 1;
+    c->rec_on = false;  // the replay evaluates every step under the installed protocols
     KMC_HIP(c, launch_set_protocol(c->at<double>(c->lay.knot_t), c->at<double>(c->lay.knot_v),
                                    c->at<DevInfo>(c->lay.devs), d0, d1, n_knots, c->n, t_s, v_volt, c->stream));
     return KMC_OK;
@@ -1291,6 +1309,7 @@ kmc_status save_state(kmc_ctx *c, Saved &sv) {
 
 kmc_status restore_state(kmc_ctx *c, const Saved &sv) {
     const int D = c->p.n_devices;
+    c->rec_on = false;  // the trial steps were recorded too
     KMC_HIP(c, hipMemcpyAsync(c->cur, c->ws + c->lay.rp_a, (size_t)c->lay.total_pad, hipMemcpyDeviceToDevice,
                               c->stream));
     KMC_HIP(c, hipMemcpyAsync(c->ws + c->lay.net_total, sv.net_total.data(), sizeof(int64_t) * D,
@@ -1317,6 +1336,7 @@ kmc_status kmc_autotune(kmc_ctx *c, int32_t trial_steps, int32_t *tile_sites, in
     if (trial_steps < 1 || trial_steps > 65536) return fail(KMC_EINVAL, "trial_steps must be in [1, 65536]");
     if (c->n + 2 * (int64_t)trial_steps > (int64_t)0xffffffffLL)
         return fail(KMC_EUNSUPPORTED, "step counter too close to 2^32 for the trials");
+    c->rec_on = false;  // the trials would be recorded
     Saved sv;
     s = save_state(c, sv);
     if (s != KMC_OK) return s;
@@ -1427,10 +1447,28 @@ kmc_status check_replay_args(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, 
 }
 
 kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int64_t n_steps,
-                          const double *weight_dev, double *grad_dev, const ReplayBufs &b) {
+                          const double *weight_dev, double *grad_dev, const ReplayBufs &b, bool use_record) {
     const int D = c->p.n_devices;
     KMC_HIP(c, launch_zero_i64(reinterpret_cast<int64_t *>(grad_dev), 4 * (int64_t)D, c->stream));
     if (n_steps == 0) return KMC_OK;
+    // A recording serves the replay when it began at step0, its steps up to
+    // step0 + n_steps have been run, and occ0 is the state it began from
+    // (checked here); then every half-step whose list did not overflow takes
+    // the forward's decisions from it.
+    std::vector<int64_t> counts;
+    bool recorded = false;
+    if (use_record && c->rec_on && !c->rtiles.empty() && step0 == c->rec_n0 && 2 * n_steps <= c->rec_n_hs &&
+        step0 + n_steps <= c->n) {
+        int64_t *flag = c->rec_count + c->rec_n_hs;
+        KMC_HIP(c, launch_zero_i64(flag, 1, c->stream));
+        KMC_HIP(c, launch_compare_bytes(occ0_dev, c->rec_occ, c->lay.total_sites, flag, c->stream));
+        counts.resize((size_t)(2 * n_steps + 1));
+        KMC_HIP(c, hipMemcpyAsync(counts.data(), c->rec_count, sizeof(int64_t) * (size_t)(2 * n_steps),
+                                  hipMemcpyDeviceToHost, c->stream));
+        KMC_HIP(c, hipMemcpyAsync(&counts.back(), flag, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+        KMC_HIP(c, hipStreamSynchronize(c->stream));
+        recorded = counts.back() == 0;
+    }
     int8_t *cur = b.occ_a, *nxt = b.occ_b;
     KMC_HIP(c, launch_import(occ0_dev, cur, c->at<DevInfo>(c->lay.devs), D, c->lay.total_pad, c->ea, c->fp64,
                              c->stream));
@@ -1463,13 +1501,30 @@ kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int
         a.n_abs = step0 + k;
         a.score_w = weight_dev + k * D;
         for (int h = 0; h < 2; ++h) {
+            a.h = h;
+            const int64_t hs = 2 * k + h;
+            if (recorded && counts[(size_t)hs] <= c->rec_cap) {
+                // the recorded decisions; the state is updated in place
+                a.occ_in = cur;
+                a.occ_out = cur;
+                a.rec_hops = c->rec_buf + hs * c->rec_cap;
+                a.rec_count = c->rec_count + hs;
+                KMC_HIP(c, launch_replay_logged(a, c->fp64, c->stream));
+                pa.occ = cur;
+                pa.hops = a.rec_hops;
+                pa.hop_count = a.rec_count;
+                pa.hop_cap = c->rec_cap;
+                KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream));
+                continue;
+            }
             a.occ_in = cur;
             a.occ_out = nxt;
-            a.h = h;
             if (!c->rtiles.empty()) KMC_HIP(c, launch_replay_stream(a, c->fp64, c->stream));
             else KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
             pa.occ = nxt;  // the new state, for a full recomputation after an overflow
+            pa.hops = b.hops;
             pa.hop_count = b.hop_ctl + h;
+            pa.hop_cap = c->lay.hop_cap;
             KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream));
             std::swap(cur, nxt);
         }
@@ -1513,7 +1568,8 @@ kmc_status score_replay_in_region(kmc_ctx *c, const int8_t *occ0_dev, int64_t st
     int64_t *ctl = reinterpret_cast<int64_t *>(take(4 * sizeof(int64_t)));
     b.hop_ctl = ctl;
     b.score_log = ctl + 2;
-    return enqueue_replay(c, occ0_dev, step0, n_steps, weight_dev, grad_dev, b);
+    // (no recorded decisions: their use synchronises the stream)
+    return enqueue_replay(c, occ0_dev, step0, n_steps, weight_dev, grad_dev, b, false);
 }
 }  // namespace kmc
 
@@ -1530,7 +1586,64 @@ kmc_status kmc_score_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, i
     b.hops = c->at<uint4>(c->lay.hops);
     b.hop_ctl = c->at<int64_t>(c->lay.hop_ctl);
     b.score_log = c->at<int64_t>(c->lay.score_log);
-    return enqueue_replay(c, occ0_dev, step0, n_steps, weight_dev, grad_dev, b);
+    return enqueue_replay(c, occ0_dev, step0, n_steps, weight_dev, grad_dev, b, true);
+}
+
+static size_t record_layout(const kmc_ctx *c, int64_t max_steps, int64_t cap, size_t *occ_at, size_t *buf_at) {
+    const size_t n_hs = (size_t)(2 * max_steps);
+    *occ_at = align_up(sizeof(int64_t) * (n_hs + 1), 256);
+    *buf_at = *occ_at + align_up((size_t)c->lay.total_sites, 256);
+    return *buf_at + sizeof(uint4) * n_hs * (size_t)cap;
+}
+
+static kmc_status check_record_args(kmc_ctx *c, int64_t max_steps, int64_t cap) {
+    if (max_steps < 0 || cap < 0) return fail(KMC_EINVAL, "max_steps and cap must be >= 0");
+    if (max_steps > 0 && cap < 1) return fail(KMC_EINVAL, "cap must be >= 1");
+    if (max_steps > ((int64_t)1 << 31) || cap > ((int64_t)1 << 31) ||
+        (double)max_steps * 2.0 * (double)cap > 9.0e15 / sizeof(uint4))
+        return fail(KMC_EINVAL, "max_steps * cap is too large");
+    if (c->dense || c->phifix) return fail(KMC_EUNSUPPORTED, "the score replay runs the binary64/binary32 window paths only");
+    if (c->any_open) return fail(KMC_EUNSUPPORTED, "the score replay has no terms for open-electrode transfers");
+    return KMC_OK;
+}
+
+kmc_status kmc_record_bytes(kmc_ctx *c, int64_t max_steps, int64_t cap, size_t *bytes) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (!bytes) return fail(KMC_EINVAL, "bytes is NULL");
+    s = check_record_args(c, max_steps, cap);
+    if (s != KMC_OK) return s;
+    size_t occ_at, buf_at;
+    *bytes = max_steps == 0 ? 0 : record_layout(c, max_steps, cap, &occ_at, &buf_at);
+    return KMC_OK;
+}
+
+kmc_status kmc_record_hops(kmc_ctx *c, void *buf_dev, size_t bytes, int64_t max_steps, int64_t cap) {
+    kmc_status s = usable(c);
+    if (s != KMC_OK) return s;
+    if (max_steps == 0 || !buf_dev) {  // stop
+        c->rec_on = false;
+        return KMC_OK;
+    }
+    s = check_record_args(c, max_steps, cap);
+    if (s != KMC_OK) return s;
+    if (reinterpret_cast<uintptr_t>(buf_dev) & 255) return fail(KMC_EINVAL, "buf_dev must be 256-byte aligned");
+    size_t occ_at, buf_at;
+    const size_t need = record_layout(c, max_steps, cap, &occ_at, &buf_at);
+    if (bytes < need) return fail(KMC_EINVAL, "the buffer needs " + std::to_string(need) + " bytes");
+    if (c->n + max_steps > (int64_t)0xffffffffLL) return fail(KMC_EUNSUPPORTED, "step index would reach 2^32");
+    unsigned char *base = static_cast<unsigned char *>(buf_dev);
+    c->rec_count = reinterpret_cast<int64_t *>(base);
+    c->rec_occ = reinterpret_cast<int8_t *>(base + occ_at);
+    c->rec_buf = reinterpret_cast<uint4 *>(base + buf_at);
+    c->rec_cap = cap;
+    c->rec_n0 = c->n;
+    c->rec_n_hs = 2 * max_steps;
+    KMC_HIP(c, launch_zero_i64(c->rec_count, c->rec_n_hs + 1, c->stream));
+    KMC_HIP(c, launch_export(c->cur, c->rec_occ, c->at<DevInfo>(c->lay.devs), c->p.n_devices, c->lay.total_sites,
+                             c->stream));
+    c->rec_on = true;
+    return KMC_OK;
 }
 
 kmc_status kmc_dense_potential(kmc_ctx *c, float *phi_dev) {
@@ -1553,6 +1666,7 @@ kmc_status kmc_set_electrodes(kmc_ctx *c, int32_t device, int32_t open, double e
     if (open && (c->dense || c->phifix))
         return fail(KMC_EUNSUPPORTED, "open electrodes run the binary64/binary32 window paths only");
     const int d0 = device < 0 ? 0 : device, d1 = device < 0 ? c->p.n_devices : device + 1;
+    c->rec_on = false;
     KMC_HIP(c, hipStreamSynchronize(c->stream));  // an earlier copy of the host table may be pending
     for (int d = d0; d < d1; ++d) {
         Electrode &e = c->el[d];

@@ -130,6 +130,16 @@ __device__ inline bool decide_hop(Real dE, Real ea, uint32_t w, Real beta, Real 
     return u < p;
 }
 
+// Appends an accepted hop to the recording (a no-op when nothing is recorded
+// or the step lies outside the recorded run); dir 0 when the ion at s moves up.
+__device__ inline void record_hop(const HopRecord &rec, int d, int h, int64_t n, int rail, int s, int dir) {
+    if (!rec.buf) return;
+    const int64_t hs = 2 * (n - rec.n0) + h;
+    if (hs < 0 || hs >= rec.n_hs) return;
+    const int64_t k = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(rec.count + hs), 1ull);
+    if (k < rec.cap) rec.buf[hs * rec.cap + k] = make_uint4((uint32_t)d, (uint32_t)rail, (uint32_t)s, (uint32_t)dir);
+}
+
 // Inclusive Philox-word threshold of barrier class q: every configuration has
 // dE >= -(|alpha V|/L + coul_bound) and every class-q site a barrier >=
 // ea_min + q ea_step, so p <= pb.  pb is widened by 1e-3 relative and by twice

@@ -79,6 +79,17 @@ struct FinishArgs {
     int32_t n_devices, d0, d1, steps;
 };
 
+// Recording of the accepted hops of a run of steps, for the score replay:
+// the hops of half-step h of step n (n0 <= n < n0 + n_hs / 2) go to list
+// 2 (n - n0) + h, cap entries of (device, rail, s, dir) each (dir 0: the ion
+// at s moves to s + 1), with the list's count (which may exceed cap: the list
+// then overflowed).  buf == nullptr: nothing is recorded.
+struct HopRecord {
+    uint4 *buf;
+    int64_t *count;            // [n_hs]
+    int64_t cap, n0, n_hs;
+};
+
 // Everything the hop kernel needs, passed by value.
 struct HopArgs {
     const int8_t *occ_in;      // padded internal state, read (Jacobi snapshot)
@@ -99,6 +110,7 @@ struct HopArgs {
     int32_t *tally_dec;        // [kTallySteps][D][10]  (deltas)
     int32_t n_devices;
     struct LogBuf { int64_t *count; void *entries; int64_t cap; } log;
+    HopRecord record;          // forward kernels: where accepted hops are recorded
     int32_t step_in_chunk;
     int32_t h;
     // score replay only (hop_half_step<..., 1>)
@@ -117,6 +129,9 @@ struct HopArgs {
     float k10;                 // K(1, 0) in binary32
     const Tile *dtiles;        // decision tiles: whole rails of one device per workgroup
     int32_t n_dtiles;
+    // recorded replay only (replay_logged): the half-step's recorded hops
+    const uint4 *rec_hops;
+    const int64_t *rec_count;
 };
 
 // Coulomb part of every candidate bond's energy change, for the score replay,
@@ -171,6 +186,7 @@ struct PArgs {
     int32_t *tally_dec;
     int32_t n_devices;
     HopArgs::LogBuf log;
+    HopRecord record;
     uint64_t *pub;             // edge-rail publications, pub_stride words per tile
     int64_t pub_stride;        // block tiles: a slot per state; wave tiles: a word per state, then
                                // the snapshot ring

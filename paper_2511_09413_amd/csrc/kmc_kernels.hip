@@ -232,6 +232,7 @@ __global__ __launch_bounds__(kBlock) void hop_half_step(HopArgs a) {
                                      : (Real)a.ea_scalar;
                 const bool accept = decide_hop<Real>(dE, ea, word, beta_r, c0_r, a.log, tile.d, H, n, srail, s);
                 if (accept) {
+                    if (!kScore) record_hop(a.record, tile.d, H, n, srail, s, o == s ? 0 : 1);
                     atomicAdd(&sh.n_hop, 1);
                     surv[i] |= 1u << 31;
                     if (t < o) atomicAdd(&sh.n_down, 1);

@@ -303,6 +303,7 @@ __global__ __launch_bounds__(kPMaxBlock) void hop_persistent(PArgs a) {
                                      : (Real)a.ea_scalar;
                 if (decide_hop<Real>(e_app + part, ea, word_of(blk, (s >> 1) & 3), beta_r, c0_r, a.log, tile.d, h, n,
                                      srail, s)) {
+                    record_hop(a.record, tile.d, h, n, srail, s, o == s ? 0 : 1);
                     atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + (s >> 6)]), 1ull << (s & 63));
                     atomicXor(reinterpret_cast<unsigned long long *>(&nxt[srow * W + ((s + 1) >> 6)]),
                               1ull << ((s + 1) & 63));

@@ -317,7 +317,235 @@ __global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
     }
 }
 
+// The recorded replay of one half-step: the decisions are the forward's, read
+// from the list of hops it recorded for this half-step, so there is no Philox
+// draw, prefilter or window sum; every candidate's term comes from its bond's
+// Coulomb part.  The workgroup takes the same runs of rails as replay_stream,
+// marks the recorded hops of its rails in LDS, scores its sixteen passes
+// (every candidate compacted per wavefront as there), and at the end flips the
+// two sites of each of its hops in the state in place: a workgroup reads only
+// its own rails, so no other workgroup sees a flip before the launch ends.
+template <typename Real, int H>
+__global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
+    __shared__ double v_wg;
+    __shared__ uint32_t taken[kRPasses * kRBlock / 4];  // byte (pass, thread): bit j when the bond at s0 + j hopped
+    __shared__ double gsum[kRBlock / 64][4];
+    __shared__ Real rec_ec[kRBlock / 64][4 * 64];       // per wavefront: compacted candidates
+    __shared__ Real rec_ea[kRBlock / 64][4 * 64];
+    __shared__ uint32_t rec_aux[kRBlock / 64][4 * 64];  // bit 0: toward site L-1, bit 1: hopped
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Tile tile = a.dtiles[blockIdx.x];
+    const int d = tile.d;
+    const DevInfo &dv = a.devs[d];
+    const int L = dv.sites, pitch = dv.pitch, bpr = pitch / 8;
+    const int64_t n = a.n_abs;
+    // the workspace hop list of the other parity was consumed by its update
+    // kernel (a half-step replayed without the recording may follow)
+    if (blockIdx.x == 0 && tid == 0)
+        __hip_atomic_store(a.hop_ctl + (1 - H), (int64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid == 0)
+        v_wg = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
+                                (double)(n - dv.n_set) * a.dt);
+    for (int i = tid; i < kRPasses * kRBlock / 4; i += kRBlock) taken[i] = 0u;
+    const int per_pass = kRBlock / bpr;
+    const int slot = tid / bpr, b = tid - slot * bpr, s0 = 8 * b;
+    const bool lane_used = slot < per_pass;
+    const int r_end = tile.r0 + tile.nr;
+    const int8_t *snap = a.occ_in + dv.off_pad;
+    const Real *ec_of = reinterpret_cast<const Real *>(a.rec);
+    const int64_t odd_at = (L + 1) / 2;
+    const int last = L - 2 - s0;
+    const uint32_t exist = last >= 7 ? 0xFFu : (last < 0 ? 0u : ((2u << last) - 1u));
+    const int64_t dev_off = dv.off;
+    const int64_t ec_base = dev_off + (H ? odd_at : 0) + 4 * b;
+    const int8_t *snap_s0 = snap + s0;
+    // as in replay_stream: unconditional loads, the next pass's in flight
+    auto load_pass = [&](int r, uint2 &v, uint32_t &nxt, Real *ec) {
+        const int rl = (lane_used && r < r_end) ? r : tile.r0;
+        const int8_t *row = snap_s0 + (int64_t)rl * pitch;
+        v = *reinterpret_cast<const uint2 *>(row);
+        nxt = H == 1 ? (uint32_t)(uint8_t)row[s0 + 8 < pitch ? 8 : 0] : 0u;
+        const Real *e = ec_of + ec_base + (int64_t)rl * L;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ec[i] = e[i];
+    };
+    uint2 v_next;
+    uint32_t nx_next;
+    Real ec_next[4];
+    load_pass(tile.r0 + slot, v_next, nx_next, ec_next);
+    __syncthreads();
+    // the recorded hops of this workgroup's rails (the host has checked that
+    // the list did not overflow)
+    const int64_t n_hops = *a.rec_count;
+    auto mine = [&](const uint4 &e) {
+        const int rel = (int)e.y - tile.r0;
+        return (int)e.x == d && rel >= 0 && rel < tile.nr && (int)e.z >= 0 && (int)e.z + 1 < L;
+    };
+    for (int64_t i = tid; i < n_hops; i += kRBlock) {
+        const uint4 e = a.rec_hops[i];
+        if (mine(e)) {
+            const int rel = (int)e.y - tile.r0, s = (int)e.z;
+            const int pp = rel / per_pass, sl = rel - pp * per_pass;
+            const int at = pp * kRBlock + sl * bpr + (s >> 3);
+            atomicOr(&taken[at >> 2], 1u << (8 * (at & 3) + (s & 7)));
+        }
+    }
+    __syncthreads();
+    const double V = v_wg;
+    const Real alpha_r = (Real)a.alpha, V_r = (Real)V, beta_r = (Real)a.beta, c0_r = (Real)a.c0;
+    const double W = a.score_w[d], beta = a.beta;
+    const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
+    const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
+    double S0 = 0.0, S2 = 0.0, S3 = 0.0;
+    // the bias part of dE toward site L - 1 and toward site 0 (the forward's
+    // expression), kept in registers rather than recomputed per candidate
+    Real e_up = ((alpha_r * V_r) * (Real)1) / (Real)L;
+    Real e_down = ((alpha_r * V_r) * (Real)-1) / (Real)L;
+    asm volatile("" : "+v"(e_up), "+v"(e_down));
+    const Real *ea_of = reinterpret_cast<const Real *>(a.ea);
+    const Real ea_scalar = (Real)a.ea_scalar;
+    auto term = [&](Real ec, Real ea, bool up, uint32_t y) {
+        const Real dE = (up ? e_up : e_down) + ec;
+        Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+        if (p < (Real)1) {
+            // (y - p)/(1 - p): the reciprocal refined by Newton steps to within
+            // an ulp or two of binary64 (one step from the hardware estimate
+            // for a binary32 p, two for binary64)
+            const double pd = (double)p;
+            const double den = 1.0 - pd;
+            double rc = __builtin_amdgcn_rcp(den);
+            rc = fma(rc, fma(-den, rc, 1.0), rc);
+            if (std::is_same<Real, double>::value) rc = fma(rc, fma(-den, rc, 1.0), rc);
+            const double ratio = ((double)y - pd) * rc;
+            S0 += ratio;
+            S2 = fma((double)ec, ratio, S2);
+            S3 += up ? ratio : -ratio;
+        }
+    };
+    for (int p = 0; p < kRPasses; ++p) {
+        const int r = tile.r0 + slot + p * per_pass;
+        const bool valid = lane_used && r < r_end;
+        const uint2 v = v_next;
+        const uint32_t nxt = nx_next;
+        Real ec[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ec[i] = ec_next[i];
+        if (p + 1 < kRPasses) load_pass(r + per_pass, v_next, nx_next, ec_next);
+        const uint32_t bits = (((v.x & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) |
+                              ((((v.y & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << 4) | ((nxt & 1u) << 8);
+        const uint32_t cand = valid ? (bits ^ (bits >> 1)) & (H ? 0xAAu : 0x55u) & exist : 0u;
+        const int at_t = p * kRBlock + tid;
+        const uint32_t hopped = (taken[at_t >> 2] >> (8 * (at_t & 3))) & 0xFFu;
+        // bit k: direction (1: toward site L - 1); bit k + 1: the bond hopped
+        // (k of parity H; the masks keep the other parity's bits out)
+        const uint32_t par = H ? 0xAAu : 0x55u;
+        const uint32_t aux_bits = (bits & par) | ((hopped & par) << 1);
+        // the wavefront's candidates, slot-major: slot i of every lane, in
+        // lane order, after those of slots < i
+        uint32_t base = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = H + 2 * i;
+            const bool c = (cand >> k) & 1u;
+            const uint64_t bal = __ballot(c);
+            if (c) {
+                const uint32_t at =
+                    base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                rec_ec[wave][at] = ec[i];
+                rec_aux[wave][at] = (aux_bits >> k) & 3u;
+                if (ea_of) {
+                    const int s = s0 + k;
+                    rec_ea[wave][at] = ea_of[dev_off + (int64_t)r * L + (((bits >> k) & 1u) ? s : s + 1)];
+                }
+            }
+            base += (uint32_t)__popcll(bal);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+        for (int j = lane; j < (int)base; j += 64) {
+            const Real ea = ea_of ? rec_ea[wave][j] : ea_scalar;
+            const uint32_t aux = rec_aux[wave][j];
+            term(rec_ec[wave][j], ea, (aux & 1u) != 0u, aux >> 1);
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
+    }
+    // every pass has read its rails: flip the hops' sites in place
+    __syncthreads();
+    int8_t *state = a.occ_out + dv.off_pad;
+    for (int64_t i = tid; i < n_hops; i += kRBlock) {
+        const uint4 e = a.rec_hops[i];
+        if (mine(e)) {
+            int8_t *row = state + (int64_t)e.y * pitch;
+            if ((row[e.z] ^ row[e.z + 1]) & 1) {  // a hop moves an ion to an empty site
+                row[e.z] ^= 1;
+                row[e.z + 1] ^= 1;
+            }
+        }
+    }
+    double g0 = w_ea * S0, g1 = w_nu * S0, g2 = w_k * S2, g3 = w_a * S3;
+#pragma unroll
+    for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) {
+        g0 += __shfl_xor(g0, sh_, 64);
+        g1 += __shfl_xor(g1, sh_, 64);
+        g2 += __shfl_xor(g2, sh_, 64);
+        g3 += __shfl_xor(g3, sh_, 64);
+    }
+    if (lane == 0) {
+        gsum[wave][0] = g0;
+        gsum[wave][1] = g1;
+        gsum[wave][2] = g2;
+        gsum[wave][3] = g3;
+    }
+    __syncthreads();
+    if (tid < 4) {
+        double sum = 0.0;
+        for (int w = 0; w < kRBlock / 64; ++w) sum += gsum[w][tid];
+        if (sum != 0.0) atomicAdd(&a.score_grad[d * 4 + tid], sum);
+    }
+}
+
+// Sets *flag when the n bytes at x and y differ anywhere.
+__global__ void compare_bytes(const int8_t *x, const int8_t *y, int64_t n, int64_t *flag) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool diff = false;
+    const bool wide = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    int64_t done = 0;
+    if (wide) {
+        const int64_t n16 = n / 16;
+        const uint4 *x4 = reinterpret_cast<const uint4 *>(x), *y4 = reinterpret_cast<const uint4 *>(y);
+        for (int64_t i = t; i < n16; i += stride) {
+            const uint4 u = x4[i], w = y4[i];
+            diff |= ((u.x ^ w.x) | (u.y ^ w.y) | (u.z ^ w.z) | (u.w ^ w.w)) != 0u;
+        }
+        done = n16 * 16;
+    }
+    for (int64_t i = done + t; i < n; i += stride) diff |= x[i] != y[i];
+    if (diff) __hip_atomic_store(flag, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 }  // namespace
+
+hipError_t launch_replay_logged(const HopArgs &a, bool fp64, hipStream_t st) {
+    const dim3 grid(a.n_dtiles), block(kRBlock);
+    if (fp64) {
+        if (a.h == 0) hipLaunchKernelGGL((replay_logged<double, 0>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((replay_logged<double, 1>), grid, block, 0, st, a);
+    } else {
+        if (a.h == 0) hipLaunchKernelGGL((replay_logged<float, 0>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((replay_logged<float, 1>), grid, block, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compare_bytes(const int8_t *x, const int8_t *y, int64_t n, int64_t *flag, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t want = (n + 16 * 256 - 1) / (16 * 256);
+    const int grid = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(compare_bytes, dim3(grid), dim3(256), 0, st, x, y, n, flag);
+    return hipGetLastError();
+}
 
 // Rails of one run of the streaming replay (sixteen passes of a 256-thread
 // workgroup, pitch / 8 threads per rail), or 0 when a rail is longer than

@@ -354,7 +354,10 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         // rho (thr0 + 1) + 2^32 2e-6 with rho = A(q_lo) / A(0); r_lane =
         // ceil(rho 2^32), and the per-step bound is mulhi(thr0, r_lane) +
         // 8600, the addition saturating (the margin covers the widening term,
-        // both ceilings and binary64 rounding).
+        // both ceilings and binary64 rounding).  This holds while thr0 is the
+        // unclipped threshold: a step whose lowest-class bound reaches 1
+        // (thr0 saturated) bounds nothing for the higher classes, and its
+        // window adds 2^32 - 1 instead (every word goes to the exact check).
         if (has && last >= 0) {
             int q_lo = kClasses;
             const int s_hi = s0 + SPL < L - 1 ? s0 + SPL : L - 1;
@@ -375,6 +378,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     // Per-step tables of the window [kb, kb + 64): lane k holds step kb + k's
     // stage-0 threshold in a register, the bias and g go to LDS.
     uint32_t thr_lane = 0;
+    uint32_t t_add = 8600u;  // the stage-0 margin of the window (uniform, kept in a vector register)
     auto refresh = [&](int kb) {
         const KArgs ka = kargs();
         WaveLds<SPL> &wr = *lds_opaque(&w);
@@ -387,6 +391,8 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         wr.step_v[lane] = V;
         wr.step_g[lane] = gg;
         thr_lane = threshold_of(ka->c0, wr.cls_a[0], gg);
+        t_add = __ballot(thr_lane == 0xFFFFFFFFu) != 0 ? 0xFFFFFFFFu : 8600u;
+        asm volatile("" : "+v"(t_add));
         wave_sync();
     };
 
@@ -495,7 +501,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
         // class; stage 1 (rare): each candidate's word against its origin's
         // exact class threshold
         const uint32_t thr0 = (uint32_t)__builtin_amdgcn_readlane((int)thr_lane, kw);
-        const uint32_t t_lane = __builtin_elementwise_add_sat(__umulhi(thr0, r_lane), 8600u);
+        const uint32_t t_lane = __builtin_elementwise_add_sat(__umulhi(thr0, r_lane), t_add);
         const uint32_t mn = min_word<0>(wd);
         // the common path decides with one wavefront vote that no lane has a
         // stage-0 word; only then are the survivor bits and their vote formed
@@ -600,6 +606,13 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
                         log.cap = ka->log.cap;
                         acc = decide_hop<Real>(e_app + part, ea, word, beta_r, c0_r, log, dd, h, n, srail, s);
                         if (acc) {
+                            HopRecord rec;
+                            rec.buf = ka->record.buf;
+                            rec.count = ka->record.count;
+                            rec.cap = ka->record.cap;
+                            rec.n0 = ka->record.n0;
+                            rec.n_hs = ka->record.n_hs;
+                            record_hop(rec, dd, h, n, srail, s, o == s ? 0 : 1);
                             const int64_t base = (n - rfl(g.tally_base)) * ka->n_devices + dd;
                             atomicAdd(&ka->tally_net[base], t < o ? 1 : -1);
                             const int qo = (10 * o) / Lq, qt = (10 * t) / Lq;

@@ -206,6 +206,24 @@ def test_wave_snapshot_ring_wraps_under_many_hops(tile):
     assert st["hops"] > 2000
 
 
+@pytest.mark.parametrize("mode,tile", MODES)
+def test_lowest_class_bound_above_one(mode, tile):
+    """Per-site barriers N(0.08, 0.02) eV with an unscreened window of 40
+    sites over +-2 rails: the prefilter's bound for the lowest barrier class
+    exceeds 1 at every step (its threshold saturates), while lanes whose
+    lowest class is higher keep bounds below 1.  The wave kernel's per-lane
+    stage-0 bound, a scaled copy of the lowest class's threshold, must then
+    pass every word to the exact check (it once rejected hops here: the
+    trajectory left the oracle's at step 96)."""
+    R, L = 16, 96
+    ea = np.random.default_rng(3).normal(0.08, 0.02, size=R * L)
+    ph = Physics(precision=FP64, seed=5, ea_ev=0.08, screening_sites=0.0, cutoff_sites=40, rail_range=2)
+    from workloads import Workload
+    wl = Workload("saturated_bound", ph, [R], [L], [0.3], [constant(0.6)], 0, ea_site=ea)
+    st, _ = _run_parity(wl, 160, 40, mode=mode, tile_sites=tile)
+    assert st["hops"] > 300
+
+
 @pytest.mark.parametrize("mode,tile", [("persistent", 512), ("wave", 0)])
 def test_neighbour_wait_failure_is_reported(mode, tile):
     """A neighbour wait declared hung (the wait limit set to 0 from the host, so
