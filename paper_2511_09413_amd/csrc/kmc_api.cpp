@@ -50,7 +50,7 @@ size_t wave_lds_bytes(int spl, int n_kt, bool fp64);
 int wave_band_words(int spl);
 hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream_t st);
 hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st);
-hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st);
+hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st, int64_t hops_known = -1);
 hipError_t launch_dense_phi(const DenseArgs &a, hipStream_t st);
 hipError_t launch_dense_decide(const HopArgs &a, int pitch, hipStream_t st);
 hipError_t set_dense_lds_limit(size_t lds_bytes);
@@ -1514,7 +1514,7 @@ kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int
                 pa.hops = a.rec_hops;
                 pa.hop_count = a.rec_count;
                 pa.hop_cap = c->rec_cap;
-                KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream));
+                KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream, counts[(size_t)hs]));
                 continue;
             }
             a.occ_in = cur;

@@ -147,6 +147,7 @@ struct PhiArgs {
     const uint4 *hops;         // (device, rail, s, dir): dir 0 moves the ion at s up
     const int64_t *hop_count;  // entries appended by the half-step (may exceed hop_cap)
     int64_t hop_cap;
+    int64_t known_count;       // >= 0: the count, known to be at most hop_cap (hop_count is not read)
 };
 
 // Dense potential (MFMA): every site's Coulomb potential of one state.

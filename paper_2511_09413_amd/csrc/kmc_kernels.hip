@@ -740,6 +740,26 @@ __device__ void replay_ec_all(const PhiArgs &a) {
     }
 }
 
+// acc + sum over x < n of w[x] dr[x] (w in LDS, 0 or 1; dr the LDS table),
+// accumulated in order by binary64 fma; the loads of eight terms are issued
+// before their fmas so that their latencies overlap.
+__device__ __forceinline__ double window_dot(const uint8_t *w, const double *dr, int n, double acc) {
+    int x = 0;
+    for (; x + 8 <= n; x += 8) {
+        uint32_t b[8];
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            b[u] = w[x + u];
+            t[u] = dr[x + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = fma((double)b[u], t[u], acc);
+    }
+    for (; x < n; ++x) acc = fma((double)w[x], dr[x], acc);
+    return acc;
+}
+
 // The starting values, one workgroup per run of up to 256 bonds of one rail:
 // the occupancy of the run's window on every neighbour rail is staged in LDS
 // (zero outside the rail), and each lane sums its bond's terms in one pass,
@@ -800,7 +820,7 @@ __global__ __launch_bounds__(kEcRun) void replay_ec_full(PhiArgs a) {
                     for (int k = 0; k < dv.n_nbr; ++k) {
                         const double *dr = dtab + dv.nbr_dist[k] * wn;
                         const uint8_t *w = win[k] + (int)threadIdx.x;
-                        for (int x = 0; x < wn; ++x) acc = fma((double)w[x], dr[x], acc);
+                        acc = window_dot(w, dr, wn, acc);
                     }
                     v = (Real)((up ? acc : -acc) - a.k01);
                 }
@@ -825,13 +845,15 @@ constexpr int kEcUpdMaxCut = 128;
 
 template <typename Real>
 __global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
-    const int64_t cnt = __hip_atomic_load(a.hop_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t cnt = a.known_count >= 0 ? a.known_count
+                                           : __hip_atomic_load(a.hop_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cnt > a.hop_cap) {
         replay_ec_all<Real>(a);
         return;
     }
     Real *ec = reinterpret_cast<Real *>(a.ec);
     const int cut = a.cutoff, m = a.rail_range, w = 2 * cut + 3;  // bonds per rail whose window holds s or s + 1
+    if (blockIdx.x >= cnt) return;  // no hop for this workgroup
     if (cut > kEcUpdMaxCut) {  // wide windows: every bond summed from global memory
         for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
             const uint4 e = a.hops[i];
@@ -853,6 +875,7 @@ __global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
     const int wn = 2 * cut + 2;     // window of a bond
     const int width = 4 * cut + 4;  // sites s - 2 cut - 1 .. s + 2 cut + 2
     const int n_rows = 4 * m + 1;
+    uint4 e_next = a.hops[blockIdx.x];  // the first hop, loaded while the table is built
     for (int i = threadIdx.x; i < (m + 1) * wn; i += blockDim.x) {
         const int dist = i / wn, x = i - dist * wn;
         const int dt = x - cut - 1 < 0 ? cut + 1 - x : x - cut - 1, dO = x - cut < 0 ? cut - x : x - cut;
@@ -862,7 +885,8 @@ __global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
         dtab[i] = kt - ko;
     }
     for (int64_t i = blockIdx.x; i < cnt; i += gridDim.x) {
-        const uint4 e = a.hops[i];
+        const uint4 e = e_next;
+        if (i + gridDim.x < cnt) e_next = a.hops[i + gridDim.x];
         const int d = (int)e.x, r = (int)e.y, s = (int)e.z;
         const DevInfo &dv = a.devs[d];
         const int R = dv.rails, L = dv.sites;
@@ -888,7 +912,7 @@ __global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
                 for (int k = 0; k < dv.n_nbr; ++k) {
                     const double *dr = dtab + dv.nbr_dist[k] * wn;
                     const uint8_t *wk = win[2 * m + o1 + dv.nbr_off[k]] + col;
-                    for (int x = 0; x < wn; ++x) acc = fma((double)wk[x], dr[x], acc);
+                    acc = window_dot(wk, dr, wn, acc);
                 }
                 v = (Real)((up ? acc : -acc) - a.k01);
             }
@@ -1016,9 +1040,15 @@ hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st) {
-    if (fp64) hipLaunchKernelGGL(replay_ec_update<double>, dim3(kEcGrid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL(replay_ec_update<float>, dim3(kEcGrid), dim3(256), 0, st, a);
+hipError_t launch_replay_ec_update(const PhiArgs &a, bool fp64, hipStream_t st, int64_t hops_known) {
+    // a known hop count (at most the list's capacity) sizes the grid: one
+    // workgroup per hop, none when there is none
+    if (hops_known == 0) return hipSuccess;
+    const int grid = hops_known > 0 && hops_known < kEcGrid ? (int)hops_known : kEcGrid;
+    PhiArgs b = a;
+    b.known_count = hops_known >= 0 && hops_known <= a.hop_cap ? hops_known : -1;
+    if (fp64) hipLaunchKernelGGL(replay_ec_update<double>, dim3(grid), dim3(256), 0, st, b);
+    else hipLaunchKernelGGL(replay_ec_update<float>, dim3(grid), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

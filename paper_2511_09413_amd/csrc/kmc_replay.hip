@@ -36,6 +36,17 @@ constexpr int kRBlock = 256;
 constexpr int kRPasses = 16;
 constexpr int kRRing = 2 * kRBlock * 4;  // twice every bond of one pass
 
+// The exponential of a score term's rate (not of a decision): binary64 as
+// the decisions, binary32 as 2^(x log2 e) on the hardware's base-2
+// exponential (the product's rounding adds |x| eps / 2 to the relative error
+// of p, the base-2 exponential about one unit).
+template <typename Real>
+__device__ __forceinline__ Real score_exp(Real x);
+template <>
+__device__ __forceinline__ double score_exp<double>(double x) { return exp(x); }
+template <>
+__device__ __forceinline__ float score_exp<float>(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+
 template <typename Real>
 __device__ __forceinline__ const Real *ktable(const HopArgs &a) {
     return std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
     // score term of one candidate with its decision y
     auto term = [&](Real ec, Real ea, bool up, uint32_t y) {
         const Real dE = (up ? e_up : e_down) + ec;
-        Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+        Real p = c0_r * score_exp<Real>(-beta_r * (ea + (Real)0.5 * dE));
         p = p < (Real)1 ? p : (Real)1;
         if (p < (Real)1) {
             // (y - p)/(1 - p) with a reciprocal refined by two Newton steps
@@ -325,14 +336,25 @@ __global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
 // (every candidate compacted per wavefront as there), and at the end flips the
 // two sites of each of its hops in the state in place: a workgroup reads only
 // its own rails, so no other workgroup sees a flip before the launch ends.
+constexpr int kLogRec = 64 + 4 * 64;  // a carried partial round and one pass's candidates
+
+// One candidate of the recorded replay: its bond's Coulomb part, and bit 0 the
+// direction (1: toward site L - 1), bit 1 the decision.
+template <typename Real>
+struct alignas(2 * sizeof(Real)) LogRec {
+    Real ec;
+    uint32_t aux;
+};
+
 template <typename Real, int H>
-__global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
+__global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     __shared__ double v_wg;
     __shared__ uint32_t taken[kRPasses * kRBlock / 4];  // byte (pass, thread): bit j when the bond at s0 + j hopped
     __shared__ double gsum[kRBlock / 64][4];
-    __shared__ Real rec_ec[kRBlock / 64][4 * 64];       // per wavefront: compacted candidates
-    __shared__ Real rec_ea[kRBlock / 64][4 * 64];
-    __shared__ uint32_t rec_aux[kRBlock / 64][4 * 64];  // bit 0: toward site L-1, bit 1: hopped
+    // per wavefront: the candidates not yet scored (fewer than 64 carried
+    // over from the earlier passes, then the current pass's)
+    __shared__ LogRec<Real> rec[kRBlock / 64][kLogRec];
+    __shared__ Real rec_ea[kRBlock / 64][kLogRec];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const Tile tile = a.dtiles[blockIdx.x];
     const int d = tile.d;
@@ -396,7 +418,8 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
     const double W = a.score_w[d], beta = a.beta;
     const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
     const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
-    double S0 = 0.0, S2 = 0.0, S3 = 0.0;
+    // S0, S2 as in replay_stream; Su = the ratios toward site L - 1 (S3 = 2 Su - S0)
+    double S0 = 0.0, S2 = 0.0, Su = 0.0;
     // the bias part of dE toward site L - 1 and toward site 0 (the forward's
     // expression), kept in registers rather than recomputed per candidate
     Real e_up = ((alpha_r * V_r) * (Real)1) / (Real)L;
@@ -406,7 +429,7 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
     const Real ea_scalar = (Real)a.ea_scalar;
     auto term = [&](Real ec, Real ea, bool up, uint32_t y) {
         const Real dE = (up ? e_up : e_down) + ec;
-        Real p = c0_r * exp_r<Real>(-beta_r * (ea + (Real)0.5 * dE));
+        Real p = c0_r * score_exp<Real>(-beta_r * (ea + (Real)0.5 * dE));
         if (p < (Real)1) {
             // (y - p)/(1 - p): the reciprocal refined by Newton steps to within
             // an ulp or two of binary64 (one step from the hardware estimate
@@ -419,9 +442,18 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
             const double ratio = ((double)y - pd) * rc;
             S0 += ratio;
             S2 = fma((double)ec, ratio, S2);
-            S3 += up ? ratio : -ratio;
+            Su = fma(up ? 1.0 : 0.0, ratio, Su);
         }
     };
+    // scores the wavefront's records [0, n)
+    auto score_rounds = [&](uint32_t n) {
+        for (int j = lane; j < (int)n; j += 64) {
+            const Real ea = ea_of ? rec_ea[wave][j] : ea_scalar;
+            const LogRec<Real> x = rec[wave][j];
+            term(x.ec, ea, (x.aux & 1u) != 0u, x.aux >> 1);
+        }
+    };
+    uint32_t pending = 0u;  // records carried to the next pass (uniform)
     for (int p = 0; p < kRPasses; ++p) {
         const int r = tile.r0 + slot + p * per_pass;
         const bool valid = lane_used && r < r_end;
@@ -440,9 +472,9 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
         // (k of parity H; the masks keep the other parity's bits out)
         const uint32_t par = H ? 0xAAu : 0x55u;
         const uint32_t aux_bits = (bits & par) | ((hopped & par) << 1);
-        // the wavefront's candidates, slot-major: slot i of every lane, in
-        // lane order, after those of slots < i
-        uint32_t base = 0u;
+        // the wavefront's candidates, slot-major (slot i of every lane, in
+        // lane order, after those of slots < i), after the carried ones
+        uint32_t base = pending;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = H + 2 * i;
@@ -451,8 +483,10 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
             if (c) {
                 const uint32_t at =
                     base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                rec_ec[wave][at] = ec[i];
-                rec_aux[wave][at] = (aux_bits >> k) & 3u;
+                LogRec<Real> x;
+                x.ec = ec[i];
+                x.aux = (aux_bits >> k) & 3u;
+                rec[wave][at] = x;
                 if (ea_of) {
                     const int s = s0 + k;
                     rec_ea[wave][at] = ea_of[dev_off + (int64_t)r * L + (((bits >> k) & 1u) ? s : s + 1)];
@@ -460,12 +494,19 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
             }
             base += (uint32_t)__popcll(bal);
         }
+        // whole rounds of 64 now (all of them after the last pass); the rest
+        // moves to the front for the next pass
+        const uint32_t upto = p + 1 < kRPasses ? (base & ~63u) : base;
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
-        for (int j = lane; j < (int)base; j += 64) {
-            const Real ea = ea_of ? rec_ea[wave][j] : ea_scalar;
-            const uint32_t aux = rec_aux[wave][j];
-            term(rec_ec[wave][j], ea, (aux & 1u) != 0u, aux >> 1);
+        score_rounds(upto);
+        pending = base - upto;
+        if (upto != 0u && (uint32_t)lane < pending) {
+            const uint32_t from = upto + (uint32_t)lane;
+            const LogRec<Real> x = rec[wave][from];
+            const Real ea = ea_of ? rec_ea[wave][from] : (Real)0;
+            rec[wave][lane] = x;
+            if (ea_of) rec_ea[wave][lane] = ea;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
@@ -483,6 +524,7 @@ __global__ __launch_bounds__(kRBlock) void replay_logged(HopArgs a) {
             }
         }
     }
+    const double S3 = 2.0 * Su - S0;
     double g0 = w_ea * S0, g1 = w_nu * S0, g2 = w_k * S2, g3 = w_a * S3;
 #pragma unroll
     for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) {

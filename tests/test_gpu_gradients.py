@@ -145,7 +145,8 @@ def test_fp32_replay_against_fp64_oracle_replay():
     ref = oracle.score_replay(p64, protos, occ0_h, 0, W)
     eps32 = 2.0 ** -23
     n_terms = (2 * ph32.rail_range + 1) * (2 * ph32.cutoff_sites + 2)
-    tol = (4 * eps32 * ref["sens"] + 2 * eps32 * ref["sens_arg"] + (eps32 + (n_terms + 8) * 2.0 ** -52) * ref["sens_b"]
+    # the bound of test_gpu_score.py (binary32 exponential as 2^(arg log2 e))
+    tol = (4 * eps32 * ref["sens"] + 3 * eps32 * ref["sens_arg"] + (eps32 + (n_terms + 8) * 2.0 ** -52) * ref["sens_b"]
            + 1e-9 * ref["mag"])
     assert np.all(np.abs(grad - ref["grad"]) <= tol), (grad, ref["grad"], tol)
     # the binary32 terms do differ from binary64 ones (the comparison is not vacuous)
