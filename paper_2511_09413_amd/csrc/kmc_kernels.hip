@@ -777,10 +777,13 @@ __global__ __launch_bounds__(kEcRun) void replay_ec_full(PhiArgs a) {
         return;
     }
     Real *ec = reinterpret_cast<Real *>(a.ec);
-    __shared__ uint8_t win[2 * kMaxRailRange + 1][kEcRun + 2 * kEcMaxCut + 2];
-    __shared__ double dtab[(kMaxRailRange + 1) * (2 * kEcMaxCut + 2)];
+    // dynamic LDS sized to the window (ec_full_lds): the rows of the run's
+    // window on every neighbour rail, then the table of kernel differences
+    extern __shared__ __align__(16) unsigned char ec_smem[];
     const int wn = 2 * cut + 2;               // window of a bond: sites s - cut .. s + 1 + cut
     const int width = kEcRun + 2 * cut + 2;   // window of the run: sites b0 - cut .. b0 + kEcRun + cut + 1
+    uint8_t *win = ec_smem;                   // row k at k * width
+    double *dtab = reinterpret_cast<double *>(ec_smem + ((size_t)(2 * a.rail_range + 1) * width + 15) / 16 * 16);
     for (int i = threadIdx.x; i < (a.rail_range + 1) * wn; i += kEcRun) {
         const int dist = i / wn, x = i - dist * wn;
         const int dt = x - cut - 1 < 0 ? cut + 1 - x : x - cut - 1, dO = x - cut < 0 ? cut - x : x - cut;
@@ -806,20 +809,20 @@ __global__ __launch_bounds__(kEcRun) void replay_ec_full(PhiArgs a) {
                 const int8_t *row = a.occ + dv.off_pad + (int64_t)rr * dv.pitch;
                 for (int x = threadIdx.x; x < width; x += kEcRun) {
                     const int j = b0 - cut + x;
-                    win[k][x] = (j >= 0 && j < L) ? (uint8_t)(row[j] & 1) : (uint8_t)0;
+                    win[k * width + x] = (j >= 0 && j < L) ? (uint8_t)(row[j] & 1) : (uint8_t)0;
                 }
             }
             __syncthreads();
             const int s = b0 + (int)threadIdx.x;
             if (s < nb) {
-                const uint8_t *w_own = win[k_own] + (int)threadIdx.x;  // w[x] is site s - cut + x
+                const uint8_t *w_own = win + k_own * width + (int)threadIdx.x;  // w[x] is site s - cut + x
                 const int up = w_own[cut];
                 Real v = (Real)0;
                 if (up != w_own[cut + 1]) {
                     double acc = 0.0;
                     for (int k = 0; k < dv.n_nbr; ++k) {
                         const double *dr = dtab + dv.nbr_dist[k] * wn;
-                        const uint8_t *w = win[k] + (int)threadIdx.x;
+                        const uint8_t *w = win + k * width + (int)threadIdx.x;
                         acc = window_dot(w, dr, wn, acc);
                     }
                     v = (Real)((up ? acc : -acc) - a.k01);
@@ -1035,8 +1038,14 @@ hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream
 constexpr int kEcGrid = 2048;  // workgroups of the replay's Coulomb-part kernels
 
 hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st) {
-    if (fp64) hipLaunchKernelGGL(replay_ec_full<double>, dim3(kEcGrid), dim3(kEcRun), 0, st, a);
-    else hipLaunchKernelGGL(replay_ec_full<float>, dim3(kEcGrid), dim3(kEcRun), 0, st, a);
+    // LDS of the window rows and the difference table (none beyond kEcMaxCut,
+    // where every bond is summed from global memory)
+    const int cut = a.cutoff;
+    const size_t lds = cut > kEcMaxCut ? 0
+                                       : ((size_t)(2 * a.rail_range + 1) * (kEcRun + 2 * cut + 2) + 15) / 16 * 16 +
+                                             sizeof(double) * (size_t)(a.rail_range + 1) * (2 * cut + 2);
+    if (fp64) hipLaunchKernelGGL(replay_ec_full<double>, dim3(kEcGrid), dim3(kEcRun), lds, st, a);
+    else hipLaunchKernelGGL(replay_ec_full<float>, dim3(kEcGrid), dim3(kEcRun), lds, st, a);
     return hipGetLastError();
 }
 
