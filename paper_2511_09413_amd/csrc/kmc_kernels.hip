@@ -729,11 +729,15 @@ template <typename Real>
 __device__ void replay_ec_all(const PhiArgs &a) {
     Real *ec = reinterpret_cast<Real *>(a.ec);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t first = 0;  // bonds of the earlier devices: every device's bonds form one sequence
     for (int d = 0; d < a.n_devices; ++d) {
         const DevInfo &dv = a.devs[d];
         const int nb = dv.sites - 1;
         const int64_t n = (int64_t)dv.rails * nb;
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t i0 = ((t - first) % stride + stride) % stride;
+        first += n;
+        for (int64_t i = i0; i < n; i += stride) {
             const int r = (int)(i / nb), s = (int)(i - (int64_t)r * nb);
             ec[bond_index(dv, r, s)] = replay_bond_ec<Real>(a, dv, r, s);
         }
@@ -792,6 +796,9 @@ __global__ __launch_bounds__(kEcRun) void replay_ec_full(PhiArgs a) {
         const double ko = (dO > cut || (dist == 0 && dO == 0)) ? 0.0 : kr[dO];
         dtab[i] = kt - ko;
     }
+    // the units of every device in one sequence (device by device), dealt to
+    // the workgroups in turn, so that no workgroup waits on a small device
+    int64_t first = 0;  // the sequence index of the device's first unit
     for (int d = 0; d < a.n_devices; ++d) {
         const DevInfo &dv = a.devs[d];
         const int R = dv.rails, L = dv.sites, nb = L - 1;
@@ -800,7 +807,10 @@ __global__ __launch_bounds__(kEcRun) void replay_ec_full(PhiArgs a) {
         int k_own = 0;  // the entry of offset 0 (the bond's own rail)
         for (int k = 0; k < dv.n_nbr; ++k)
             if (dv.nbr_off[k] == 0) k_own = k;
-        for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int64_t g = gridDim.x;
+        const int64_t u0 = (((int64_t)blockIdx.x - first) % g + g) % g;  // this workgroup's first unit here
+        first += units;
+        for (int64_t u = u0; u < units; u += g) {
             const int r = (int)(u / runs), b0 = (int)(u - (int64_t)r * runs) * kEcRun;
             __syncthreads();  // the table is written; the previous unit's window is no longer read
             for (int k = 0; k < dv.n_nbr; ++k) {
