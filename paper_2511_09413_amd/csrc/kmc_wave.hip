@@ -664,7 +664,31 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             __hip_atomic_store(pub_at, ((uint64_t)tag_j << 32) | snap_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     };
+    // Wave priority.  A SIMD's issue arbiter prefers the older of its waves,
+    // so the tiles of the workgroups dispatched first would run ahead and the
+    // launch would end with the later ones alone on their SIMDs.  A launch of
+    // up to 128 steps lowers each wave's priority by quarters of its steps (a
+    // wave ahead yields to the ones behind); a longer one rotates the first
+    // place among the workgroups that share a CU (dispatch layers of
+    // gridDim / 4 workgroups) every 10.24 us of the real-time clock.
+    uint32_t layer = (uint32_t)(((int64_t)blockIdx.x * 4) / (int64_t)gridDim.x);
+    asm volatile("" : "+v"(layer));
+    auto set_priority = [&](int kstep) {
+        const int n = kargs()->n_steps;
+        uint32_t pr;
+        if (n <= 128) {
+            pr = 3u - (uint32_t)(kstep >= (n >> 2)) - (uint32_t)(kstep >= (n >> 1)) - (uint32_t)(kstep >= ((3 * n) >> 2));
+        } else {
+            const uint32_t slice = (uint32_t)(__builtin_amdgcn_s_memrealtime() >> 10);
+            pr = (slice + (uint32_t)__builtin_amdgcn_readfirstlane((int)layer)) & 3u;
+        }
+        if (pr == 0u) __builtin_amdgcn_s_setprio(0);
+        else if (pr == 1u) __builtin_amdgcn_s_setprio(1);
+        else if (pr == 2u) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(3);
+    };
     for (int kstep = 0; kstep < a.n_steps; ++kstep) {
+        if ((kstep & 1) == 0) set_priority(kstep);
         if ((kstep & (kWaveWin - 1)) == 0) refresh(kstep);
         PhStep<kNB> ps;
         {
