@@ -181,7 +181,11 @@ __device__ inline void finish_tallies_wave(const FinishArgs &f, int lane, int64_
     auto slot = [&](int q, int d, int k) -> int32_t * {
         return q < kDeciles ? &f.tally_dec[((int64_t)k * D + d) * kDeciles + q] : &f.tally_net[(int64_t)k * D + d];
     };
+    // a segment's values are read eight at a time (their loads in flight
+    // together); segments of at most eight steps keep them for the second pass
+    constexpr int kHeld = 8;
     int64_t sum_r[2] = {0, 0}, carry_r[2] = {0, 0};
+    int32_t held[2][kHeld];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int seg = lane + 64 * r;
@@ -190,7 +194,17 @@ __device__ inline void finish_tallies_wave(const FinishArgs &f, int lane, int64_
             const int d = f.d0 + s / (kDeciles + 1), q = s % (kDeciles + 1);
             const int k0 = part * g, k1 = k0 + g < steps ? k0 + g : steps;
             int64_t sum = 0;
-            for (int k = k0; k < k1; ++k) sum += __hip_atomic_load(slot(q, d, k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int kb = k0; kb < k1; kb += kHeld) {
+                int32_t x[kHeld];
+#pragma unroll
+                for (int u = 0; u < kHeld; ++u)
+                    x[u] = kb + u < k1 ? __hip_atomic_load(slot(q, d, kb + u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+#pragma unroll
+                for (int u = 0; u < kHeld; ++u) {
+                    sum += x[u];
+                    held[r][u] = x[u];
+                }
+            }
             sum_r[r] = sum;
             carry_r[r] = q < kDeciles ? f.dec_run[d * kDeciles + q] : 0;
             sums[seg] = sum;
@@ -211,7 +225,14 @@ __device__ inline void finish_tallies_wave(const FinishArgs &f, int lane, int64_
             int64_t run = carry_r[r] + before;
             for (int k = k0; k < k1; ++k) {
                 int32_t *p = slot(q, d, k);
-                const int32_t x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                int32_t x = 0;
+                if (k1 - k0 <= kHeld) {
+#pragma unroll
+                    for (int u = 0; u < kHeld; ++u)
+                        if (u == k - k0) x = held[r][u];
+                } else {
+                    x = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
                 __hip_atomic_store(p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (q == kDeciles) {
                     if (f.ctl.net_out) f.ctl.net_out[(row0 + k) * D + d] = x;

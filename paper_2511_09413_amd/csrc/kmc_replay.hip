@@ -204,7 +204,12 @@ __global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
         }
     };
     int listed = 0;  // survivors of the earlier passes (the same value in every thread)
+    // wavefront priority lowered by quarters of the passes, as in replay_logged
+    __builtin_amdgcn_s_setprio(3);
     for (int p = 0; p < kRPasses; ++p) {
+        if (p == kRPasses / 4) __builtin_amdgcn_s_setprio(2);
+        if (p == kRPasses / 2) __builtin_amdgcn_s_setprio(1);
+        if (p == 3 * kRPasses / 4) __builtin_amdgcn_s_setprio(0);
         const int r = tile.r0 + slot + p * per_pass;
         const bool valid = lane_used && r < r_end;
         const uint2 v = v_next;
@@ -454,7 +459,14 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
         }
     };
     uint32_t pending = 0u;  // records carried to the next pass (uniform)
+    // The issue arbiter prefers older wavefronts: each wavefront lowers its
+    // priority by quarters of its passes, so that the workgroups dispatched
+    // later are not left alone on their SIMDs at the end of the launch.
+    __builtin_amdgcn_s_setprio(3);
     for (int p = 0; p < kRPasses; ++p) {
+        if (p == kRPasses / 4) __builtin_amdgcn_s_setprio(2);
+        if (p == kRPasses / 2) __builtin_amdgcn_s_setprio(1);
+        if (p == 3 * kRPasses / 4) __builtin_amdgcn_s_setprio(0);
         const int r = tile.r0 + slot + p * per_pass;
         const bool valid = lane_used && r < r_end;
         const uint2 v = v_next;
