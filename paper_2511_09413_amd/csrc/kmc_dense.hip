@@ -87,6 +87,12 @@ __global__ __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2))
 
     const int nd = 2 * a.nb - 1;
     const int half = lane >> 5, col = lane & 31;
+    // the issue arbiter prefers older wavefronts: each lowers its priority by
+    // quarters of its k-steps, so that the workgroups dispatched later are not
+    // left alone on their SIMDs at the end of the launch
+    const int k_steps = (m + 1) * ((a.nb + 3) / 4);
+    int k_done = 0;
+    __builtin_amdgcn_s_setprio(3);
     for (int dd = 0; dd <= m; ++dd) {
         // the distinct rails at this minimal-image distance: none, one or two
         int oa = 127, ob = 127;
@@ -116,7 +122,10 @@ __global__ __launch_bounds__(kDenseBlock) __attribute__((amdgpu_waves_per_eu(2))
         const unsigned char *rowa0 = smem + (m + rail0 + col + oa) * rs;
         const unsigned char *rowb0 = smem + (m + rail0 + col + (ob == 127 ? 0 : ob)) * rs;
         const bool two = ob != 127;
-        for (int jb = 0; jb < a.nb; jb += 4) {
+        for (int jb = 0; jb < a.nb; jb += 4, ++k_done) {
+            if (4 * k_done == k_steps) __builtin_amdgcn_s_setprio(2);
+            if (2 * k_done == k_steps) __builtin_amdgcn_s_setprio(1);
+            if (4 * k_done == 3 * k_steps) __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 // X fragments of the two 32-rail blocks, q = 0, 1
