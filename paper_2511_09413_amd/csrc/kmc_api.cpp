@@ -810,9 +810,12 @@ kmc_status enqueue_steps(kmc_ctx *c, int64_t n_steps, int32_t *net_out, int32_t 
                     continue;
                 }
                 if (c->dense) {
+                    // the decisions update the state in place
                     KMC_HIP(c, launch_dense_phi(dense_args(c, c->cur, c->at<float>(c->lay.phi), a.phi_row),
                                                 c->stream));
+                    a.occ_in = a.occ_out = c->cur;
                     KMC_HIP(c, launch_dense_decide(a, c->devs[0].pitch, c->stream));
+                    continue;
                 } else {
                     KMC_HIP(c, launch_hop(a, c->hop_lds, c->fp64, c->stream));
                     if (c->any_open) {

@@ -278,7 +278,9 @@ __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_ra
             if (k + 1 < 8) w ^= (uint64_t)1 << (8 * (k + 1));
         }
     if (H == 1 && b > 0 && ((last_hop[tid - 1] >> 3) & 1u)) w ^= 1ull;  // previous block's bond (8b-1, 8b)
-    *reinterpret_cast<uint2 *>(dst) = make_uint2((uint32_t)w, (uint32_t)(w >> 32));
+    // the state is updated in place: every read of it precedes the barrier
+    // above, and a workgroup's rails are its own; only changed blocks are written
+    if (w != ((uint64_t)v.x | ((uint64_t)v.y << 32))) *reinterpret_cast<uint2 *>(dst) = make_uint2((uint32_t)w, (uint32_t)(w >> 32));
 }
 
 hipError_t launch_dense_decide(const HopArgs &a, int pitch, hipStream_t st) {
