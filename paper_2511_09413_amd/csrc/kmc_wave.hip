@@ -249,6 +249,12 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: tile data in scalar registers
 
+    const int n_groups = (a.n_tiles + kWaveTilesPerWG - 1) / kWaveTilesPerWG;
+    const int ti = tile_of_block(blockIdx.x, n_groups) * kWaveTilesPerWG + wave;
+    // the tile and its device, loaded before the barrier that the kernel table
+    // needs, so that their latencies overlap the table's
+    const PTile tile = a.tiles[ti < a.n_tiles ? ti : 0];
+    const DevInfo dvc = a.devs[tile.d];
     // the kernel table K(dist, ds), shared by the workgroup's tiles
     {
         const int n_kt = (a.rail_range + 1) * (a.cutoff + 1);
@@ -267,8 +273,6 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     };
     WaveLds<SPL> &w = lds_of(kargs());
 
-    const int n_groups = (a.n_tiles + kWaveTilesPerWG - 1) / kWaveTilesPerWG;
-    const int ti = tile_of_block(blockIdx.x, n_groups) * kWaveTilesPerWG + wave;
     if (ti >= a.n_tiles) return;  // no barrier follows
 
     // ------------------------------------------------------------ set-up
@@ -279,8 +283,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     bool isolated = true;
     uint64_t *own = nullptr;
     {
-        const PTile tile = a.tiles[ti];
-        const DevInfo &dv = a.devs[tile.d];
+        const DevInfo &dv = dvc;
         const int R = dv.rails, L = dv.sites, P = dv.pitch, m = a.rail_range;
         const int lpr = (P + SPL - 1) / SPL;  // lanes per rail
         const int nr = tile.nr;
