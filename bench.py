@@ -342,8 +342,9 @@ LIMIT_NOTE = {
     "replay_stream": "the kernel issues about 300 VALU instructions per 8-site block and half-step and its VALU "
                      "is about 80 % busy (SQ counters): it is bound by its instruction count, below the HBM roof",
     "replay_logged": "no Philox, prefilter or window sums: per candidate one exponential and the binary64 "
-                     "ratio (y - p)/(1 - p); the update of the Coulomb parts after the half-step's hops is "
-                     "a launch of its own",
+                     "ratio (y - p)/(1 - p), about 130 VALU instructions per pass of eight sites (SQ counters: "
+                     "the VALU is near saturation, the HBM at about two thirds); the update of the Coulomb "
+                     "parts after the half-step's hops is a launch of its own",
 }
 
 
@@ -377,13 +378,14 @@ def bench_gradient(args):
     g = grads[0].cpu().numpy()
     value = wl.n_sites * steps / (t_fwd + t_rep)
     # The replay kernel's own memory stream, per half-step and site: the
-    # padded occupancy read (1 B), written again (1 B) only by the kernel that
-    # draws the decisions (the recorded replay flips the hops' sites in
-    # place), and the binary32 Coulomb part of every bond of the half-step's
-    # parity (4 B per two sites); the recomputation after hops touches a few
-    # kB.  Against the HBM peak.
+    # padded occupancy read (1 B; one bit in the recorded replay, which keeps
+    # the state as bits and flips the hops' sites in place), written again
+    # (1 B) only by the kernel that draws the decisions, and the binary32
+    # Coulomb part of every bond of the half-step's parity (4 B per two
+    # sites); the recomputation after hops touches a few kB.  Against the HBM
+    # peak.
     kernel = "replay_logged" if record else "replay_stream"
-    per_site = (1 + 2) if record else (1 + 1 + 2)
+    per_site = (0.125 + 2) if record else (1 + 1 + 2)
     replay_bytes = 2 * per_site * wl.n_sites * steps
     achieved = replay_bytes / t_rep / 1e9
     t_meas = measured_traffic(kernel)
@@ -398,7 +400,8 @@ def bench_gradient(args):
         "replay_site_updates_per_s": wl.n_sites * steps / t_rep,
         "replay_over_forward_time": t_rep / t_fwd,
         "roofline": {"bound": "hbm", "kernel": kernel + "<float,h>", "achieved": achieved,
-                     "bytes": ("6 B per site and step: occupancy in, one binary32 Coulomb part per bond" if record
+                     "bytes": ("4.25 B per site and step: occupancy bits in, one binary32 Coulomb part per bond"
+                               if record
                                else "8 B per site and step: occupancy in and out, one binary32 Coulomb part "
                                     "per bond"),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

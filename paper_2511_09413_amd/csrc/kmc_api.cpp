@@ -25,6 +25,8 @@ hipError_t launch_score(const HopArgs &a, size_t lds_bytes, bool fp64, hipStream
 hipError_t launch_replay_stream(const HopArgs &a, bool fp64, hipStream_t st);
 hipError_t launch_replay_logged(const HopArgs &a, bool fp64, hipStream_t st);
 hipError_t launch_compare_bytes(const int8_t *x, const int8_t *y, int64_t n, int64_t *flag, hipStream_t st);
+hipError_t launch_pack_occ_bits(const int8_t *src, uint8_t *dst, int64_t n_pad, hipStream_t st);
+hipError_t launch_unpack_occ_bits(const uint8_t *src, int8_t *dst, int64_t n_pad, hipStream_t st);
 int replay_run_rails(int pitch);
 hipError_t set_hop_lds_limit(size_t lds_bytes, size_t score_lds_bytes);
 hipError_t launch_import(const int8_t *src, int8_t *dst, const DevInfo *devs, int n_dev, int64_t total_pad,
@@ -1500,6 +1502,10 @@ kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int
     pa.hop_cap = c->lay.hop_cap;
     KMC_HIP(c, launch_zero_i64(b.hop_ctl, 2, c->stream));
     KMC_HIP(c, launch_replay_ec_full(pa, c->fp64, c->stream));
+    // The recorded half-steps keep the state as one bit per site in the plane
+    // not holding it (packed when they begin, unpacked into the byte plane,
+    // whose barrier classes are unchanged, before a half-step drawn again).
+    bool as_bits = false;
     for (int64_t k = 0; k < n_steps; ++k) {
         a.n_abs = step0 + k;
         a.score_w = weight_dev + k * D;
@@ -1508,23 +1514,34 @@ kmc_status enqueue_replay(kmc_ctx *c, const int8_t *occ0_dev, int64_t step0, int
             const int64_t hs = 2 * k + h;
             if (recorded && counts[(size_t)hs] <= c->rec_cap) {
                 // the recorded decisions; the state is updated in place
-                a.occ_in = cur;
-                a.occ_out = cur;
+                if (!as_bits) {
+                    KMC_HIP(c, launch_pack_occ_bits(cur, reinterpret_cast<uint8_t *>(nxt), c->lay.total_pad, c->stream));
+                    as_bits = true;
+                }
+                a.occ_in = nxt;
+                a.occ_out = nxt;
                 a.rec_hops = c->rec_buf + hs * c->rec_cap;
                 a.rec_count = c->rec_count + hs;
                 KMC_HIP(c, launch_replay_logged(a, c->fp64, c->stream));
-                pa.occ = cur;
+                pa.occ = nxt;
+                pa.occ_bits = 1;
                 pa.hops = a.rec_hops;
                 pa.hop_count = a.rec_count;
                 pa.hop_cap = c->rec_cap;
                 KMC_HIP(c, launch_replay_ec_update(pa, c->fp64, c->stream, counts[(size_t)hs]));
                 continue;
             }
+            if (as_bits) {
+                KMC_HIP(c, launch_unpack_occ_bits(reinterpret_cast<const uint8_t *>(nxt), cur, c->lay.total_pad,
+                                                  c->stream));
+                as_bits = false;
+            }
             a.occ_in = cur;
             a.occ_out = nxt;
             if (!c->rtiles.empty()) KMC_HIP(c, launch_replay_stream(a, c->fp64, c->stream));
             else KMC_HIP(c, launch_score(a, c->score_lds, c->fp64, c->stream));
             pa.occ = nxt;  // the new state, for a full recomputation after an overflow
+            pa.occ_bits = 0;
             pa.hops = b.hops;
             pa.hop_count = b.hop_ctl + h;
             pa.hop_cap = c->lay.hop_cap;

@@ -92,7 +92,7 @@ struct HopRecord {
 
 // Everything the hop kernel needs, passed by value.
 struct HopArgs {
-    const int8_t *occ_in;      // padded internal state, read (Jacobi snapshot)
+    const int8_t *occ_in;      // padded internal state, read (Jacobi snapshot); one bit per site in the recorded replay
     int8_t *occ_out;           // padded internal state, written
     const DevInfo *devs;
     const Tile *tiles;
@@ -138,6 +138,7 @@ struct HopArgs {
 // and its recomputation where the accepted hops of a half-step changed it.
 struct PhiArgs {
     const int8_t *occ;         // padded state (bit 0 = occupied): read by full recomputations
+    int32_t occ_bits;          // 1: occ holds one bit per site (site at padded index i: bit i % 8 of byte i / 8)
     const DevInfo *devs;
     int32_t n_devices;
     const double *ktab64;      // [(m+1)][(c+1)] kernel table

@@ -699,22 +699,26 @@ __device__ __forceinline__ int64_t bond_index(const DevInfo &dv, int r, int s) {
     return dv.off + (int64_t)r * dv.sites + ((s & 1) ? (dv.sites + 1) / 2 : 0) + (s >> 1);
 }
 
+// Occupancy of site j of rail r of the state a.occ (a byte or a bit per site).
+__device__ __forceinline__ int occ_site(const PhiArgs &a, const DevInfo &dv, int r, int j) {
+    const int64_t at = dv.off_pad + (int64_t)r * dv.pitch + j;
+    return a.occ_bits ? (reinterpret_cast<const uint8_t *>(a.occ)[at >> 3] >> (at & 7)) & 1 : a.occ[at] & 1;
+}
+
 template <typename Real>
 __device__ Real replay_bond_ec(const PhiArgs &a, const DevInfo &dv, int r, int s) {
     const int R = dv.rails, L = dv.sites, cut = a.cutoff;
-    const int8_t *own = a.occ + dv.off_pad + (int64_t)r * dv.pitch;
-    const int up = own[s] & 1;
-    if (up == (own[s + 1] & 1)) return (Real)0;
+    const int up = occ_site(a, dv, r, s);
+    if (up == occ_site(a, dv, r, s + 1)) return (Real)0;
     const int lo = s - cut < 0 ? 0 : s - cut, hi = s + 1 + cut > L - 1 ? L - 1 : s + 1 + cut;
     double acc = 0.0;  // phi(s + 1) - phi(s)
     for (int k = 0; k < dv.n_nbr; ++k) {
         const int off = dv.nbr_off[k];
         int rr = (r + off) % R;
         rr = rr < 0 ? rr + R : rr;
-        const int8_t *row = a.occ + dv.off_pad + (int64_t)rr * dv.pitch;
         const double *kr = a.ktab64 + dv.nbr_dist[k] * (cut + 1);
         for (int j = lo; j <= hi; ++j) {
-            if (!(row[j] & 1)) continue;
+            if (!occ_site(a, dv, rr, j)) continue;
             const int dt = j < s + 1 ? s + 1 - j : j - s - 1, dO = j < s ? s - j : j - s;
             const double kt = (dt > cut || (off == 0 && j == s + 1)) ? 0.0 : kr[dt];
             const double ko = (dO > cut || (off == 0 && j == s)) ? 0.0 : kr[dO];
@@ -909,7 +913,7 @@ __global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
             const int row = q / width, x = q - row * width, j = base + x;
             int rr = (r + row - 2 * m) % R;
             rr = rr < 0 ? rr + R : rr;
-            win[row][x] = (j >= 0 && j < L) ? (uint8_t)(a.occ[dv.off_pad + (int64_t)rr * dv.pitch + j] & 1) : (uint8_t)0;
+            win[row][x] = (j >= 0 && j < L) ? (uint8_t)occ_site(a, dv, rr, j) : (uint8_t)0;
         }
         __syncthreads();
         for (int q = threadIdx.x; q < dv.n_nbr * w; q += blockDim.x) {
@@ -1048,6 +1052,7 @@ hipError_t launch_copy_bytes(const void *src, void *dst, size_t bytes, hipStream
 constexpr int kEcGrid = 2048;  // workgroups of the replay's Coulomb-part kernels
 
 hipError_t launch_replay_ec_full(const PhiArgs &a, bool fp64, hipStream_t st) {
+    if (a.occ_bits) return hipErrorInvalidValue;  // the start-up reads a byte per site
     // LDS of the window rows and the difference table (none beyond kEcMaxCut,
     // where every bond is summed from global memory)
     const int cut = a.cutoff;

@@ -47,6 +47,25 @@ __device__ __forceinline__ double score_exp<double>(double x) { return exp(x); }
 template <>
 __device__ __forceinline__ float score_exp<float>(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
 
+// A value every lane holds alike, moved to scalar registers.
+__device__ __forceinline__ float uniform(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uniform(double x) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, (uint64_t)hi << 32 | lo);
+}
+
+// x with its sign bit flipped where bit 31 of sign is set.
+__device__ __forceinline__ float flip_sign(float x, uint32_t sign) {
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x) ^ sign);
+}
+__device__ __forceinline__ double flip_sign(double x, uint32_t sign) {
+    return __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, x) ^ ((uint64_t)sign << 32));
+}
+
 template <typename Real>
 __device__ __forceinline__ const Real *ktable(const HopArgs &a) {
     return std::is_same<Real, double>::value ? reinterpret_cast<const Real *>(a.ktab64)
@@ -341,10 +360,15 @@ __global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
 // (every candidate compacted per wavefront as there), and at the end flips the
 // two sites of each of its hops in the state in place: a workgroup reads only
 // its own rails, so no other workgroup sees a flip before the launch ends.
+// The state is one bit per site (pack_occ_bits), a byte per thread's block of
+// eight sites, so that the pass reads an eighth of the bytes it would read as
+// a byte per site; the flips are atomic exclusive-ors of 32-bit words, whose
+// other bits may belong to other hops or to another workgroup's rails.
 constexpr int kLogRec = 64 + 4 * 64;  // a carried partial round and one pass's candidates
 
-// One candidate of the recorded replay: its bond's Coulomb part, and bit 0 the
-// direction (1: toward site L - 1), bit 1 the decision.
+// One candidate of the recorded replay: its bond's Coulomb part, and in aux
+// kDown (the ion moves toward site 0) and kHopped (the decision).
+constexpr uint32_t kDown = 0x80000000u, kHopped = 0x40000000u;
 template <typename Real>
 struct alignas(2 * sizeof(Real)) LogRec {
     Real ec;
@@ -378,26 +402,26 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     const int slot = tid / bpr, b = tid - slot * bpr, s0 = 8 * b;
     const bool lane_used = slot < per_pass;
     const int r_end = tile.r0 + tile.nr;
-    const int8_t *snap = a.occ_in + dv.off_pad;
+    const int rowb = pitch / 8;  // bytes per rail (the pitch is a multiple of 16 sites)
+    const uint8_t *snap = reinterpret_cast<const uint8_t *>(a.occ_in) + dv.off_pad / 8;
     const Real *ec_of = reinterpret_cast<const Real *>(a.rec);
     const int64_t odd_at = (L + 1) / 2;
     const int last = L - 2 - s0;
     const uint32_t exist = last >= 7 ? 0xFFu : (last < 0 ? 0u : ((2u << last) - 1u));
     const int64_t dev_off = dv.off;
     const int64_t ec_base = dev_off + (H ? odd_at : 0) + 4 * b;
-    const int8_t *snap_s0 = snap + s0;
+    const uint8_t *snap_b = snap + b;
     // as in replay_stream: unconditional loads, the next pass's in flight
-    auto load_pass = [&](int r, uint2 &v, uint32_t &nxt, Real *ec) {
+    auto load_pass = [&](int r, uint32_t &v, uint32_t &nxt, Real *ec) {
         const int rl = (lane_used && r < r_end) ? r : tile.r0;
-        const int8_t *row = snap_s0 + (int64_t)rl * pitch;
-        v = *reinterpret_cast<const uint2 *>(row);
-        nxt = H == 1 ? (uint32_t)(uint8_t)row[s0 + 8 < pitch ? 8 : 0] : 0u;
+        const uint8_t *row = snap_b + (int64_t)rl * rowb;
+        v = row[0];
+        nxt = H == 1 ? (uint32_t)row[b + 1 < bpr ? 1 : 0] : 0u;
         const Real *e = ec_of + ec_base + (int64_t)rl * L;
 #pragma unroll
         for (int i = 0; i < 4; ++i) ec[i] = e[i];
     };
-    uint2 v_next;
-    uint32_t nx_next;
+    uint32_t v_next, nx_next;
     Real ec_next[4];
     load_pass(tile.r0 + slot, v_next, nx_next, ec_next);
     __syncthreads();
@@ -418,44 +442,47 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
         }
     }
     __syncthreads();
-    const double V = v_wg;
+    const double V = uniform(v_wg);  // the workgroup's values in scalar registers
     const Real alpha_r = (Real)a.alpha, V_r = (Real)V, beta_r = (Real)a.beta, c0_r = (Real)a.c0;
     const double W = a.score_w[d], beta = a.beta;
     const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
     const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
-    // S0, S2 as in replay_stream; Su = the ratios toward site L - 1 (S3 = 2 Su - S0)
-    double S0 = 0.0, S2 = 0.0, Su = 0.0;
-    // the bias part of dE toward site L - 1 and toward site 0 (the forward's
-    // expression), kept in registers rather than recomputed per candidate
-    Real e_up = ((alpha_r * V_r) * (Real)1) / (Real)L;
-    Real e_down = ((alpha_r * V_r) * (Real)-1) / (Real)L;
-    asm volatile("" : "+v"(e_up), "+v"(e_down));
+    // S0, S2, S3 as in replay_stream
+    double S0 = 0.0, S2 = 0.0, S3 = 0.0;
+    // the bias part of dE toward site L - 1 (the forward's expression; toward
+    // site 0 it is exactly its negative), in scalar registers
+    const Real e_up = uniform(((alpha_r * V_r) * (Real)1) / (Real)L);
     const Real *ea_of = reinterpret_cast<const Real *>(a.ea);
-    const Real ea_scalar = (Real)a.ea_scalar;
-    auto term = [&](Real ec, Real ea, bool up, uint32_t y) {
-        const Real dE = (up ? e_up : e_down) + ec;
-        Real p = c0_r * score_exp<Real>(-beta_r * (ea + (Real)0.5 * dE));
+    const Real ea2_scalar = (Real)a.ea_scalar + (Real)a.ea_scalar;
+    const Real nhb = (Real)-0.5 * beta_r;
+    // The term of one candidate, equal bit for bit to replay_stream's: there
+    // p = c0 exp(-beta (ea + dE / 2)), and (2 ea + dE) (-beta / 2) rounds to
+    // the same argument (scalings by two are exact); (y - p)/(1 - p) with the
+    // reciprocal refined by Newton steps to within an ulp or two of binary64
+    // (one step from the hardware estimate for a binary32 p, two for binary64).
+    auto term = [&](Real ec, Real ea2, uint32_t aux) {
+        const uint32_t dn = aux & kDown;
+        const Real dE = flip_sign(e_up, dn) + ec;
+        const Real p = c0_r * score_exp<Real>((ea2 + dE) * nhb);
         if (p < (Real)1) {
-            // (y - p)/(1 - p): the reciprocal refined by Newton steps to within
-            // an ulp or two of binary64 (one step from the hardware estimate
-            // for a binary32 p, two for binary64)
             const double pd = (double)p;
             const double den = 1.0 - pd;
             double rc = __builtin_amdgcn_rcp(den);
             rc = fma(rc, fma(-den, rc, 1.0), rc);
             if (std::is_same<Real, double>::value) rc = fma(rc, fma(-den, rc, 1.0), rc);
-            const double ratio = ((double)y - pd) * rc;
+            double ratio = -pd * rc;
+            if (aux & kHopped) ratio = den * rc;
             S0 += ratio;
             S2 = fma((double)ec, ratio, S2);
-            Su = fma(up ? 1.0 : 0.0, ratio, Su);
+            S3 += flip_sign(ratio, dn);
         }
     };
     // scores the wavefront's records [0, n)
     auto score_rounds = [&](uint32_t n) {
         for (int j = lane; j < (int)n; j += 64) {
-            const Real ea = ea_of ? rec_ea[wave][j] : ea_scalar;
+            const Real ea2 = ea_of ? rec_ea[wave][j] : ea2_scalar;
             const LogRec<Real> x = rec[wave][j];
-            term(x.ec, ea, (x.aux & 1u) != 0u, x.aux >> 1);
+            term(x.ec, ea2, x.aux);
         }
     };
     uint32_t pending = 0u;  // records carried to the next pass (uniform)
@@ -469,39 +496,37 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
         if (p == 3 * kRPasses / 4) __builtin_amdgcn_s_setprio(0);
         const int r = tile.r0 + slot + p * per_pass;
         const bool valid = lane_used && r < r_end;
-        const uint2 v = v_next;
-        const uint32_t nxt = nx_next;
+        const uint32_t bits = v_next | ((nx_next & 1u) << 8);  // bit j: site s0 + j
         Real ec[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) ec[i] = ec_next[i];
         if (p + 1 < kRPasses) load_pass(r + per_pass, v_next, nx_next, ec_next);
-        const uint32_t bits = (((v.x & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) |
-                              ((((v.y & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << 4) | ((nxt & 1u) << 8);
         const uint32_t cand = valid ? (bits ^ (bits >> 1)) & (H ? 0xAAu : 0x55u) & exist : 0u;
         const int at_t = p * kRBlock + tid;
         const uint32_t hopped = (taken[at_t >> 2] >> (8 * (at_t & 3))) & 0xFFu;
-        // bit k: direction (1: toward site L - 1); bit k + 1: the bond hopped
-        // (k of parity H; the masks keep the other parity's bits out)
+        // bit k: the bond hopped; bit k + 1: toward site 0 (k of parity H; the
+        // masks keep the other parity's bits out), moved to kHopped and kDown
         const uint32_t par = H ? 0xAAu : 0x55u;
-        const uint32_t aux_bits = (bits & par) | ((hopped & par) << 1);
+        const uint32_t aux_bits = (hopped & par) | ((~bits & par) << 1);
         // the wavefront's candidates, slot-major (slot i of every lane, in
-        // lane order, after those of slots < i), after the carried ones
+        // lane order, after those of slots < i), after the carried ones; the
+        // slot's ballot is the branch's lane mask
         uint32_t base = pending;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int k = H + 2 * i;
-            const bool c = (cand >> k) & 1u;
-            const uint64_t bal = __ballot(c);
-            if (c) {
+            const uint64_t bal = __ballot((cand >> k) & 1u);
+            if (__builtin_amdgcn_inverse_ballot_w64(bal)) {
                 const uint32_t at =
-                    base + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, base));
                 LogRec<Real> x;
                 x.ec = ec[i];
-                x.aux = (aux_bits >> k) & 3u;
+                x.aux = aux_bits << (30 - k);  // (the bits below kHopped are not read)
                 rec[wave][at] = x;
                 if (ea_of) {
                     const int s = s0 + k;
-                    rec_ea[wave][at] = ea_of[dev_off + (int64_t)r * L + (((bits >> k) & 1u) ? s : s + 1)];
+                    const Real ea = ea_of[dev_off + (int64_t)r * L + (((bits >> k) & 1u) ? s : s + 1)];
+                    rec_ea[wave][at] = ea + ea;
                 }
             }
             base += (uint32_t)__popcll(bal);
@@ -525,18 +550,27 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     }
     // every pass has read its rails: flip the hops' sites in place
     __syncthreads();
-    int8_t *state = a.occ_out + dv.off_pad;
+    uint32_t *words = reinterpret_cast<uint32_t *>(a.occ_out);
     for (int64_t i = tid; i < n_hops; i += kRBlock) {
         const uint4 e = a.rec_hops[i];
         if (mine(e)) {
-            int8_t *row = state + (int64_t)e.y * pitch;
-            if ((row[e.z] ^ row[e.z + 1]) & 1) {  // a hop moves an ion to an empty site
-                row[e.z] ^= 1;
-                row[e.z + 1] ^= 1;
+            const int64_t at = dv.off_pad + (int64_t)e.y * pitch + e.z;  // bit of site s
+            uint32_t *w0 = words + (at >> 5);
+            const int sh = (int)(at & 31);
+            // the two sites' bits (other bits of the words may be flipping)
+            const uint32_t x0 = __hip_atomic_load(w0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t x1 =
+                sh < 31 ? x0 >> 1 : __hip_atomic_load(w0 + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 31;
+            if (((x0 ^ x1) >> sh) & 1u) {  // a hop moves an ion to an empty site
+                if (sh < 31) {
+                    atomicXor(w0, 3u << sh);
+                } else {
+                    atomicXor(w0, 1u << 31);
+                    atomicXor(w0 + 1, 1u);
+                }
             }
         }
     }
-    const double S3 = 2.0 * Su - S0;
     double g0 = w_ea * S0, g1 = w_nu * S0, g2 = w_k * S2, g3 = w_a * S3;
 #pragma unroll
     for (int sh_ = 32; sh_ >= 1; sh_ >>= 1) {
@@ -579,7 +613,50 @@ __global__ void compare_bytes(const int8_t *x, const int8_t *y, int64_t n, int64
     if (diff) __hip_atomic_store(flag, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One bit per site from a byte per site (bit 0 = occupied): 16 sites per
+// thread, bit i % 8 of byte i / 8 for padded site i.
+__global__ __launch_bounds__(256) void pack_occ_bits(const int8_t *src, uint16_t *dst, int64_t n16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n16) return;
+    const uint4 v = reinterpret_cast<const uint4 *>(src)[i];
+    auto four = [](uint32_t x) { return ((x & 0x01010101u) * 0x01020408u) >> 24 & 0xFu; };
+    dst[i] = (uint16_t)(four(v.x) | four(v.y) << 4 | four(v.z) << 8 | four(v.w) << 12);
+}
+
+// The inverse: bit 0 of every byte of dst from the bits, its other bits
+// (barrier classes) kept.
+__global__ __launch_bounds__(256) void unpack_occ_bits(const uint16_t *src, int8_t *dst, int64_t n16) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n16) return;
+    uint4 v = reinterpret_cast<uint4 *>(dst)[i];
+    const uint32_t b = src[i];
+    auto spread = [](uint32_t q) { return (q & 1u) | (q & 2u) << 7 | (q & 4u) << 14 | (q & 8u) << 21; };
+    v.x = (v.x & 0xFEFEFEFEu) | spread(b & 0xFu);
+    v.y = (v.y & 0xFEFEFEFEu) | spread(b >> 4 & 0xFu);
+    v.z = (v.z & 0xFEFEFEFEu) | spread(b >> 8 & 0xFu);
+    v.w = (v.w & 0xFEFEFEFEu) | spread(b >> 12);
+    reinterpret_cast<uint4 *>(dst)[i] = v;
+}
+
 }  // namespace
+
+// n_pad: padded sites (a multiple of 16); byte planes 16-byte aligned, the
+// bit plane 4-byte aligned.
+hipError_t launch_pack_occ_bits(const int8_t *src, uint8_t *dst, int64_t n_pad, hipStream_t st) {
+    const int64_t n16 = n_pad / 16;
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_occ_bits, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, st, src,
+                       reinterpret_cast<uint16_t *>(dst), n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_occ_bits(const uint8_t *src, int8_t *dst, int64_t n_pad, hipStream_t st) {
+    const int64_t n16 = n_pad / 16;
+    if (n16 <= 0) return hipSuccess;
+    hipLaunchKernelGGL(unpack_occ_bits, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<const uint16_t *>(src), dst, n16);
+    return hipGetLastError();
+}
 
 hipError_t launch_replay_logged(const HopArgs &a, bool fp64, hipStream_t st) {
     const dim3 grid(a.n_dtiles), block(kRBlock);
