@@ -104,6 +104,32 @@ def test_overflowed_lists_are_drawn_again():
     sim.close()
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_many_hops_per_half_step(precision):
+    """A low barrier on 64 x 256 with +-2 rails and cutoff 40: hundreds of
+    hops per half-step, many of them on neighbouring rails and sites, so that
+    the Coulomb-part update rewrites overlapping windows and the in-place
+    flips share state words; against the replay drawn again and the oracle."""
+    ph = Physics(precision=precision, seed=21, ea_ev=0.06, cutoff_sites=40, rail_range=2)
+    rails, sites = [64], [256]
+    protos = [constant(0.5)]
+    sim = _setup(ph, rails, sites, [0.3], protos)
+    n_steps = 40
+    occ0 = sim.snapshot()
+    sim.record_hops(n_steps, cap=4096)
+    sim.run_steps(n_steps)
+    counts = _counts(sim, n_steps).cpu().numpy()
+    assert counts.max() <= 4096 and counts.min() > 100, counts
+    W = np.random.default_rng(2).normal(size=(n_steps, 1))
+    g_rec, g_draw = _replays(sim, occ0, W, n_steps)
+    ref = oracle.score_replay(oracle.OracleParams(ph, rails, sites), protos, occ0.cpu().numpy(), 0, W,
+                              coul64=True)
+    tol = _tolerance(ref, ph)
+    assert np.all(np.abs(g_rec - g_draw) <= 1e-10 * ref["mag"]), (g_rec, g_draw)
+    assert np.all(np.abs(g_rec - ref["grad"]) <= tol), (g_rec, ref["grad"], tol)
+    sim.close()
+
+
 def test_edited_recording_changes_the_result():
     """The replay does take its decisions from the recording: dropping the
     last hop of one list moves the gradient far beyond the summation-order
