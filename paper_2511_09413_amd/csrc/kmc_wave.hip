@@ -51,7 +51,8 @@ struct WaveGeo {
     int32_t n_nbr, n_knots;
     int8_t nbr_off[2 * kMaxRailRange + 1];
     int8_t nbr_dist[2 * kMaxRailRange + 1];
-    int8_t pad_[6];
+    int16_t nr_prev, nr_next;  // rails of the neighbour tiles
+    int8_t pad_[2];
     int64_t dv_off, off_pad, n_set, n_base, tally_base;
     double coul_bound;
 };
@@ -255,6 +256,7 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     // needs, so that their latencies overlap the table's
     const PTile tile = a.tiles[ti < a.n_tiles ? ti : 0];
     const DevInfo dvc = a.devs[tile.d];
+    const int nr_prev = a.tiles[tile.prev].nr, nr_next = a.tiles[tile.next].nr;
     // the kernel table K(dist, ds), shared by the workgroup's tiles
     {
         const int n_kt = (a.rail_range + 1) * (a.cutoff + 1);
@@ -305,6 +307,8 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
             g.d = tile.d;
             g.prev = tile.prev;
             g.next = tile.next;
+            g.nr_prev = (int16_t)nr_prev;
+            g.nr_next = (int16_t)nr_next;
             g.ti = ti;
             g.single = single;
             g.isolated = isolated;
@@ -422,34 +426,36 @@ __global__ __launch_bounds__(64 * kWaveTilesPerWG) void hop_wave(PArgs a) {
     };
     // Neighbour rails of state jrel into band: entry idx * W32 + q holds rail
     // offset idx - m (idx < m, from the previous tile) or nr + idx - m (from
-    // the next tile).  Uniform result.
+    // the next tile).  The lanes take all 2 m W32 words at once (each its own
+    // wait for the owning tile's state, then the word of its snapshot), so
+    // that the round trips to the other tiles' publications overlap.  Uniform
+    // result.
     auto fetch_bands = [&](KArgs ka, WaveLds<SPL> &wr, int64_t jrel) -> bool {
         const WaveGeo &g = wr.geo;
         const int w32 = rfl(g.W32), mm = rfl(g.m), prev = rfl(g.prev), next = rfl(g.next);
-        const PTile *tiles = ka->tiles;
+        const int nr_p = rfl(g.nr_prev), nr_n = rfl(g.nr_next);
         uint64_t *pub = ka->pub;
         const int64_t stride = ka->pub_stride;
         int32_t *status = ka->status;
         const int limit = ka->spin_limit;
         bool ok = true;
-        for (int idx = 0; idx < 2 * mm; ++idx) {
+        for (int i = lane; i < 2 * mm * w32; i += 64) {
+            const int idx = i / w32, q = i - idx * w32;
             const int T = idx < mm ? prev : next;
-            const int nrT = tiles[T].nr;
+            const int nrT = idx < mm ? nr_p : nr_n;
             const int eT = nrT < 2 * mm ? nrT : 2 * mm;
             const int rr = idx < mm ? nrT - mm + idx : idx - mm;  // rail of tile T
             const int sr = rr < mm ? rr : rr - (nrT - eT);        // its row in T's snapshots
             const uint64_t *base = pub + (int64_t)T * stride;
-            for (int q = lane; q < w32; q += 64) {
-                uint64_t st = 0, v = 0;
-                if (ok) ok = poll_tag(base + jrel, tag_hi | (uint32_t)jrel, status, limit, &st);
-                if (ok) {
-                    const int slot = (int)((uint32_t)st >> 12);
-                    const uint32_t snap_rel = (uint32_t)st & 0xFFFu;
-                    ok = poll_tag(base + kPubSlots + (int64_t)slot * (eT * w32) + sr * w32 + q, tag_hi | snap_rel,
-                                  status, limit, &v);
-                }
-                wr.band[idx * w32 + q] = (uint32_t)v;
+            uint64_t st = 0, v = 0;
+            if (ok) ok = poll_tag(base + jrel, tag_hi | (uint32_t)jrel, status, limit, &st);
+            if (ok) {
+                const int slot = (int)((uint32_t)st >> 12);
+                const uint32_t snap_rel = (uint32_t)st & 0xFFFu;
+                ok = poll_tag(base + kPubSlots + (int64_t)slot * (eT * w32) + sr * w32 + q, tag_hi | snap_rel,
+                              status, limit, &v);
             }
+            wr.band[i] = (uint32_t)v;
         }
         return __ballot(!ok) == 0;
     };
