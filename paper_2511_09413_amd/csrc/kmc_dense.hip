@@ -202,32 +202,38 @@ __global__ __launch_bounds__(256) void dense_decide(HopArgs a, int blocks_per_ra
     const int d = tile.d;
     const DevInfo &dv = a.devs[d];
     const int64_t n = a.ctl.n_base + a.step_in_chunk;
+    const int slot = tid / blocks_per_rail, b = tid - slot * blocks_per_rail;
+    const bool active = slot < tile.nr;
+    const int r = tile.r0 + slot;
+    const int L = dv.sites, s0 = 8 * b;
+    // the occupancy and the potential of the block are loaded, and the
+    // Philox block drawn, before the barrier that publishes the step's bias,
+    // so that their latencies overlap the bias's (blocks without a candidate
+    // read their potential needlessly)
+    uint2 v = make_uint2(0, 0);
+    uint32_t nxt = 0u;
+    float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
+    float f8 = 0.0f;
+    uint4 blk = make_uint4(0u, 0u, 0u, 0u);
+    if (active) {
+        const int8_t *row = a.occ_in + dv.off_pad + (int64_t)r * dv.pitch;
+        v = *reinterpret_cast<const uint2 *>(row + s0);
+        nxt = (H == 1 && s0 + 8 < dv.pitch) ? (uint32_t)(uint8_t)row[s0 + 8] : 0u;
+        const float *prow = a.phi + (dv.row0 + r) * a.phi_row + s0;
+        f0 = *reinterpret_cast<const float4 *>(prow);
+        f1 = *reinterpret_cast<const float4 *>(prow + 4);
+        f8 = (H == 1 && s0 + 8 < L) ? prow[8] : 0.0f;  // only bond 3 of parity 1 needs it
+        blk = philox4x32_10((uint32_t)b, (uint32_t)r, (uint32_t)n, ((uint32_t)d << 4) | (uint32_t)H, a.key0, a.key1);
+    }
     if (tid <= kDeciles) tally[tid] = 0;
     if (tid == 0)
         v_wg = protocol_voltage(a.knot_t + d * kMaxKnots, a.knot_v + d * kMaxKnots, dv.n_knots,
                                 (double)(n - dv.n_set) * a.dt);
     __syncthreads();
     const double V = v_wg;
-    const int slot = tid / blocks_per_rail, b = tid - slot * blocks_per_rail;
-    const bool active = slot < tile.nr;
-    const int r = tile.r0 + slot;
-    const int L = dv.sites, s0 = 8 * b;
     uint32_t hopped = 0;  // bit i: bond i of the block moved
-    uint2 v = make_uint2(0, 0);
     int8_t *dst = a.occ_out + dv.off_pad + (int64_t)r * dv.pitch + s0;
     if (active) {
-        // the occupancy and the potential of the block are loaded together, and
-        // the Philox block drawn while they are in flight (one memory round
-        // trip; blocks without a candidate read their potential needlessly)
-        const int8_t *row = a.occ_in + dv.off_pad + (int64_t)r * dv.pitch;
-        v = *reinterpret_cast<const uint2 *>(row + s0);
-        const uint32_t nxt = (H == 1 && s0 + 8 < dv.pitch) ? (uint32_t)(uint8_t)row[s0 + 8] : 0u;
-        const float *prow = a.phi + (dv.row0 + r) * a.phi_row + s0;
-        const float4 f0 = *reinterpret_cast<const float4 *>(prow);
-        const float4 f1 = *reinterpret_cast<const float4 *>(prow + 4);
-        const float f8 = (H == 1 && s0 + 8 < L) ? prow[8] : 0.0f;  // only bond 3 of parity 1 needs it
-        const uint4 blk = philox4x32_10((uint32_t)b, (uint32_t)r, (uint32_t)n, ((uint32_t)d << 4) | (uint32_t)H,
-                                        a.key0, a.key1);
         const uint32_t bits = (((v.x & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) |
                               ((((v.y & 0x01010101u) * 0x01020408u) >> 24 & 0xFu) << 4) | ((nxt & 1u) << 8);
         uint32_t cand = (bits ^ (bits >> 1)) & (H ? 0xAAu : 0x55u);
