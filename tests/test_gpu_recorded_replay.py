@@ -130,6 +130,32 @@ def test_many_hops_per_half_step(precision):
     sim.close()
 
 
+def test_small_ragged_devices():
+    """Three devices of 10, 17 and 33 sites (pitches 16, 32 and 48: rails of
+    two to six bytes in the replay's one-bit state, words shared by rails and
+    devices) and 3, 2 and 5 rails, a low barrier; recorded replay against the
+    replay drawn again and the oracle in both precisions."""
+    for precision in (FP64, FP32):
+        ph = Physics(precision=precision, seed=31, ea_ev=0.08, cutoff_sites=4, screening_sites=2.0)
+        rails, sites = [3, 2, 5], [10, 17, 33]
+        protos = [constant(0.6), triangle(1.0, 100e-12), constant(-0.3)]
+        sim = _setup(ph, rails, sites, [0.3, 0.4, 0.5], protos)
+        n_steps = 200
+        occ0 = sim.snapshot()
+        sim.record_hops(n_steps, cap=256)
+        sim.run_steps(n_steps)
+        counts = _counts(sim, n_steps).cpu().numpy()
+        assert counts.sum() > 50 and counts.max() <= 256
+        W = np.random.default_rng(4).normal(size=(n_steps, 3))
+        g_rec, g_draw = _replays(sim, occ0, W, n_steps)
+        ref = oracle.score_replay(oracle.OracleParams(ph, rails, sites), protos, occ0.cpu().numpy(), 0, W,
+                                  coul64=True)
+        tol = _tolerance(ref, ph)
+        assert np.all(np.abs(g_rec - g_draw) <= 1e-10 * ref["mag"]), (precision, g_rec, g_draw)
+        assert np.all(np.abs(g_rec - ref["grad"]) <= tol), (precision, g_rec, ref["grad"], tol)
+        sim.close()
+
+
 def test_edited_recording_changes_the_result():
     """The replay does take its decisions from the recording: dropping the
     last hop of one list moves the gradient far beyond the summation-order
