@@ -471,7 +471,12 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
             rc = fma(rc, fma(-den, rc, 1.0), rc);
             if (std::is_same<Real, double>::value) rc = fma(rc, fma(-den, rc, 1.0), rc);
             double ratio = -pd * rc;
-            if (aux & kHopped) ratio = den * rc;
+            // the decision y = 1 is rare (about one candidate in 1e5): a
+            // branch no lane takes costs less than a select on every term
+            const bool hop = (aux & kHopped) != 0u;
+            if (__builtin_expect(__ballot(hop) != 0, 0)) {
+                if (hop) ratio = den * rc;
+            }
             S0 += ratio;
             S2 = fma((double)ec, ratio, S2);
             S3 += flip_sign(ratio, dn);
