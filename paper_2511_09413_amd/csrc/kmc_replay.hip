@@ -375,7 +375,7 @@ struct alignas(2 * sizeof(Real)) LogRec {
     uint32_t aux;
 };
 
-template <typename Real, int H>
+template <typename Real, int H, bool kSiteEa>
 __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     __shared__ double v_wg;
     __shared__ uint32_t taken[kRPasses * kRBlock / 4];  // byte (pass, thread): bit j when the bond at s0 + j hopped
@@ -452,6 +452,7 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     // the bias part of dE toward site L - 1 (the forward's expression; toward
     // site 0 it is exactly its negative), in scalar registers
     const Real e_up = uniform(((alpha_r * V_r) * (Real)1) / (Real)L);
+    // per-site barriers (kSiteEa, a.ea not null) or one barrier for all sites
     const Real *ea_of = reinterpret_cast<const Real *>(a.ea);
     const Real ea2_scalar = (Real)a.ea_scalar + (Real)a.ea_scalar;
     const Real nhb = (Real)-0.5 * beta_r;
@@ -485,7 +486,7 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     // scores the wavefront's records [0, n)
     auto score_rounds = [&](uint32_t n) {
         for (int j = lane; j < (int)n; j += 64) {
-            const Real ea2 = ea_of ? rec_ea[wave][j] : ea2_scalar;
+            const Real ea2 = kSiteEa ? rec_ea[wave][j] : ea2_scalar;
             const LogRec<Real> x = rec[wave][j];
             term(x.ec, ea2, x.aux);
         }
@@ -495,6 +496,7 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     // priority by quarters of its passes, so that the workgroups dispatched
     // later are not left alone on their SIMDs at the end of the launch.
     __builtin_amdgcn_s_setprio(3);
+#pragma unroll
     for (int p = 0; p < kRPasses; ++p) {
         if (p == kRPasses / 4) __builtin_amdgcn_s_setprio(2);
         if (p == kRPasses / 2) __builtin_amdgcn_s_setprio(1);
@@ -528,7 +530,7 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
                 x.ec = ec[i];
                 x.aux = aux_bits << (30 - k);  // (the bits below kHopped are not read)
                 rec[wave][at] = x;
-                if (ea_of) {
+                if (kSiteEa) {
                     const int s = s0 + k;
                     const Real ea = ea_of[dev_off + (int64_t)r * L + (((bits >> k) & 1u) ? s : s + 1)];
                     rec_ea[wave][at] = ea + ea;
@@ -546,9 +548,9 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
         if (upto != 0u && (uint32_t)lane < pending) {
             const uint32_t from = upto + (uint32_t)lane;
             const LogRec<Real> x = rec[wave][from];
-            const Real ea = ea_of ? rec_ea[wave][from] : (Real)0;
+            const Real ea = kSiteEa ? rec_ea[wave][from] : (Real)0;
             rec[wave][lane] = x;
-            if (ea_of) rec_ea[wave][lane] = ea;
+            if (kSiteEa) rec_ea[wave][lane] = ea;
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront", "local");
@@ -666,11 +668,21 @@ hipError_t launch_unpack_occ_bits(const uint8_t *src, int8_t *dst, int64_t n_pad
 hipError_t launch_replay_logged(const HopArgs &a, bool fp64, hipStream_t st) {
     const dim3 grid(a.n_dtiles), block(kRBlock);
     if (fp64) {
-        if (a.h == 0) hipLaunchKernelGGL((replay_logged<double, 0>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((replay_logged<double, 1>), grid, block, 0, st, a);
+        if (a.ea) {
+            if (a.h == 0) hipLaunchKernelGGL((replay_logged<double, 0, true>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((replay_logged<double, 1, true>), grid, block, 0, st, a);
+        } else {
+            if (a.h == 0) hipLaunchKernelGGL((replay_logged<double, 0, false>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((replay_logged<double, 1, false>), grid, block, 0, st, a);
+        }
     } else {
-        if (a.h == 0) hipLaunchKernelGGL((replay_logged<float, 0>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((replay_logged<float, 1>), grid, block, 0, st, a);
+        if (a.ea) {
+            if (a.h == 0) hipLaunchKernelGGL((replay_logged<float, 0, true>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((replay_logged<float, 1, true>), grid, block, 0, st, a);
+        } else {
+            if (a.h == 0) hipLaunchKernelGGL((replay_logged<float, 0, false>), grid, block, 0, st, a);
+            else hipLaunchKernelGGL((replay_logged<float, 1, false>), grid, block, 0, st, a);
+        }
     }
     return hipGetLastError();
 }
