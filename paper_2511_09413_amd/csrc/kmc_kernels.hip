@@ -916,26 +916,38 @@ __global__ __launch_bounds__(256) void replay_ec_update(PhiArgs a) {
             win[row][x] = (j >= 0 && j < L) ? (uint8_t)occ_site(a, dv, rr, j) : (uint8_t)0;
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < dv.n_nbr * w; q += blockDim.x) {
-            const int kb = q / w, j = s - cut - 1 + (q - kb * w);  // bond j on rail r + off(kb)
-            if (j < 0 || j > L - 2) continue;
+        // a pair of adjacent lanes per bond, each summing half of every
+        // neighbour rail's window (the first half sites j - cut .. j - cut +
+        // wn/2 - 1, the second the rest), added once at the end
+        const int wh = wn / 2;
+        for (int q = threadIdx.x; q < 2 * dv.n_nbr * w; q += blockDim.x) {
+            const int hf = q & 1, qb = q >> 1;
+            const int kb = qb / w, j = s - cut - 1 + (qb - kb * w);  // bond j on rail r + off(kb)
+            const bool inside = j >= 0 && j <= L - 2;
             const int o1 = dv.nbr_off[kb];
             const int col = j - cut - base;  // column of site j - cut
-            const uint8_t *w_own = win[2 * m + o1] + col;  // w[x] is site j - cut + x of the bond's rail
-            const int up = w_own[cut];
-            Real v = (Real)0;
-            if (up != w_own[cut + 1]) {
-                double acc = 0.0;
-                for (int k = 0; k < dv.n_nbr; ++k) {
-                    const double *dr = dtab + dv.nbr_dist[k] * wn;
-                    const uint8_t *wk = win[2 * m + o1 + dv.nbr_off[k]] + col;
-                    acc = window_dot(wk, dr, wn, acc);
+            int up = 0;
+            bool cand = false;
+            double acc = 0.0;
+            if (inside) {
+                const uint8_t *w_own = win[2 * m + o1] + col;  // w[x] is site j - cut + x of the bond's rail
+                up = w_own[cut];
+                cand = up != w_own[cut + 1];
+                if (cand) {
+                    const int x0 = hf ? wh : 0, nx = hf ? wn - wh : wh;
+                    for (int k = 0; k < dv.n_nbr; ++k) {
+                        const double *dr = dtab + dv.nbr_dist[k] * wn + x0;
+                        const uint8_t *wk = win[2 * m + o1 + dv.nbr_off[k]] + col + x0;
+                        acc = window_dot(wk, dr, nx, acc);
+                    }
                 }
-                v = (Real)((up ? acc : -acc) - a.k01);
             }
-            int rr = (r + o1) % R;
-            rr = rr < 0 ? rr + R : rr;
-            ec[bond_index(dv, rr, j)] = v;
+            const double sum = acc + __shfl_xor(acc, 1, 64);  // both lanes of a pair are here
+            if (inside && hf == 0) {
+                int rr = (r + o1) % R;
+                rr = rr < 0 ? rr + R : rr;
+                ec[bond_index(dv, rr, j)] = cand ? (Real)((up ? sum : -sum) - a.k01) : (Real)0;
+            }
         }
     }
 }

@@ -36,16 +36,23 @@ constexpr int kRBlock = 256;
 constexpr int kRPasses = 16;
 constexpr int kRRing = 2 * kRBlock * 4;  // twice every bond of one pass
 
-// The exponential of a score term's rate (not of a decision): binary64 as
-// the decisions, binary32 as 2^(x log2 e) on the hardware's base-2
-// exponential (the product's rounding adds |x| eps / 2 to the relative error
-// of p, the base-2 exponential about one unit).
+// The exponential factor exp(-beta (Ea + dE/2)) of a score term's rate (not
+// of a decision), from y2 = 2 Ea + dE and the factor k = score_factor: in
+// binary64 as the decisions, exp(y2 (-beta/2)), which rounds -beta (Ea +
+// dE/2) exactly as written (the scalings by two are exact); in binary32 the
+// hardware's base-2 exponential of y2 k with k = -beta log2(e) / 2 rounded
+// once (the constant's and the product's roundings add about |x| eps to the
+// relative error of p, the base-2 exponential about one unit).
 template <typename Real>
-__device__ __forceinline__ Real score_exp(Real x);
+__device__ __forceinline__ Real score_exp(Real y2, Real k);
 template <>
-__device__ __forceinline__ double score_exp<double>(double x) { return exp(x); }
+__device__ __forceinline__ double score_exp<double>(double y2, double k) { return exp(y2 * k); }
 template <>
-__device__ __forceinline__ float score_exp<float>(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896341f); }
+__device__ __forceinline__ float score_exp<float>(float y2, float k) { return __builtin_amdgcn_exp2f(y2 * k); }
+template <typename Real>
+__host__ __device__ __forceinline__ Real score_factor(double beta) {
+    return std::is_same<Real, double>::value ? (Real)(-0.5 * beta) : (Real)(-0.5 * beta * 1.4426950408889634);
+}
 
 // A value every lane holds alike, moved to scalar registers.
 __device__ __forceinline__ float uniform(float x) {
@@ -151,10 +158,11 @@ __global__ __launch_bounds__(kRBlock) void replay_stream(HopArgs a) {
     // same expression as the forward's, t - o = +-1)
     const Real e_up = ((alpha_r * V_r) * (Real)1) / (Real)L;
     const Real e_down = ((alpha_r * V_r) * (Real)-1) / (Real)L;
+    const Real kf = score_factor<Real>(a.beta);
     // score term of one candidate with its decision y
     auto term = [&](Real ec, Real ea, bool up, uint32_t y) {
         const Real dE = (up ? e_up : e_down) + ec;
-        Real p = c0_r * score_exp<Real>(-beta_r * (ea + (Real)0.5 * dE));
+        Real p = c0_r * score_exp<Real>((ea + ea) + dE, kf);
         p = p < (Real)1 ? p : (Real)1;
         if (p < (Real)1) {
             // (y - p)/(1 - p) with a reciprocal refined by two Newton steps
@@ -443,7 +451,7 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     }
     __syncthreads();
     const double V = uniform(v_wg);  // the workgroup's values in scalar registers
-    const Real alpha_r = (Real)a.alpha, V_r = (Real)V, beta_r = (Real)a.beta, c0_r = (Real)a.c0;
+    const Real alpha_r = (Real)a.alpha, V_r = (Real)V, c0_r = (Real)a.c0;
     const double W = a.score_w[d], beta = a.beta;
     const double w_ea = W * -beta, w_nu = W * (1.0 / a.nu0);
     const double w_k = W * (-0.5 * beta / a.kappa), w_a = W * (-0.5 * beta * V / (double)L);
@@ -455,16 +463,15 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
     // per-site barriers (kSiteEa, a.ea not null) or one barrier for all sites
     const Real *ea_of = reinterpret_cast<const Real *>(a.ea);
     const Real ea2_scalar = (Real)a.ea_scalar + (Real)a.ea_scalar;
-    const Real nhb = (Real)-0.5 * beta_r;
-    // The term of one candidate, equal bit for bit to replay_stream's: there
-    // p = c0 exp(-beta (ea + dE / 2)), and (2 ea + dE) (-beta / 2) rounds to
-    // the same argument (scalings by two are exact); (y - p)/(1 - p) with the
-    // reciprocal refined by Newton steps to within an ulp or two of binary64
-    // (one step from the hardware estimate for a binary32 p, two for binary64).
+    const Real kf = score_factor<Real>(a.beta);
+    // The term of one candidate, equal bit for bit to replay_stream's: p =
+    // c0 score_exp(2 ea + dE), and (y - p)/(1 - p) with the reciprocal refined
+    // by Newton steps to within an ulp or two of binary64 (one step from the
+    // hardware estimate for a binary32 p, two for binary64).
     auto term = [&](Real ec, Real ea2, uint32_t aux) {
         const uint32_t dn = aux & kDown;
         const Real dE = flip_sign(e_up, dn) + ec;
-        const Real p = c0_r * score_exp<Real>((ea2 + dE) * nhb);
+        const Real p = c0_r * score_exp<Real>(ea2 + dE, kf);
         if (p < (Real)1) {
             const double pd = (double)p;
             const double den = 1.0 - pd;
@@ -492,6 +499,12 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
         }
     };
     uint32_t pending = 0u;  // records carried to the next pass (uniform)
+    // per lane: the word of the hop table that holds its byte of every pass
+    // (pass p at p kRBlock / 4 words further), the byte's place in it, and the
+    // candidate mask's fixed part (the parity and the bonds the rail has)
+    const uint32_t *taken_at = taken + (tid >> 2);
+    const int taken_sh = 8 * (tid & 3);
+    const uint32_t par_exist = lane_used ? (H ? 0xAAu : 0x55u) & exist : 0u;
     // The issue arbiter prefers older wavefronts: each wavefront lowers its
     // priority by quarters of its passes, so that the workgroups dispatched
     // later are not left alone on their SIMDs at the end of the launch.
@@ -502,15 +515,13 @@ __global__ __launch_bounds__(kRBlock, 8) void replay_logged(HopArgs a) {
         if (p == kRPasses / 2) __builtin_amdgcn_s_setprio(1);
         if (p == 3 * kRPasses / 4) __builtin_amdgcn_s_setprio(0);
         const int r = tile.r0 + slot + p * per_pass;
-        const bool valid = lane_used && r < r_end;
         const uint32_t bits = v_next | ((nx_next & 1u) << 8);  // bit j: site s0 + j
         Real ec[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) ec[i] = ec_next[i];
         if (p + 1 < kRPasses) load_pass(r + per_pass, v_next, nx_next, ec_next);
-        const uint32_t cand = valid ? (bits ^ (bits >> 1)) & (H ? 0xAAu : 0x55u) & exist : 0u;
-        const int at_t = p * kRBlock + tid;
-        const uint32_t hopped = (taken[at_t >> 2] >> (8 * (at_t & 3))) & 0xFFu;
+        const uint32_t cand = r < r_end ? (bits ^ (bits >> 1)) & par_exist : 0u;
+        const uint32_t hopped = (taken_at[p * (kRBlock / 4)] >> taken_sh) & 0xFFu;
         // bit k: the bond hopped; bit k + 1: toward site 0 (k of parity H; the
         // masks keep the other parity's bits out), moved to kHopped and kDown
         const uint32_t par = H ? 0xAAu : 0x55u;
