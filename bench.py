@@ -342,7 +342,7 @@ LIMIT_NOTE = {
     "replay_stream": "the kernel issues about 300 VALU instructions per 8-site block and half-step and its VALU "
                      "is about 80 % busy (SQ counters): it is bound by its instruction count, below the HBM roof",
     "replay_logged": "no Philox, prefilter or window sums: per candidate one exponential and the binary64 "
-                     "ratio (y - p)/(1 - p): VALU-bound (SQ counters: about 2100 VALU per wavefront at 8 "
+                     "ratio (y - p)/(1 - p): VALU-bound (SQ counters: about 2000 VALU per wavefront at 8 "
                      "wavefronts per SIMD fill the VALU for their lifetime; the HBM at about 55 % of its peak); "
                      "the update of the Coulomb parts after the half-step's hops is a launch of its own",
 }
